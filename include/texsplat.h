@@ -1,0 +1,232 @@
+/*
+ * texsplat — C ABI of a gfx950 renderer for textured planar (2D) Gaussian splats.
+ *
+ * What is computed (TextureSplat, arXiv 2506.13348):
+ *   each splat k is a planar Gaussian P(u,v) = p_k + s_u t_u u + s_v t_v v       (Sec. 3.1, Eq. 1)
+ *   a pixel's ray meets the plane at the local (u,v) in closed form             (Sec. 3.1-3.2)
+ *   alpha = min(alpha_max, o_k G(u,v)), G = exp(-(u^2+v^2)/2)                     (Eq. 2, Sec. 3.1)
+ *   material texels T_k, sampled bilinearly at s = (u+S)/(2S), t = (v+S)/(2S)    (Eq. 4-6)
+ *   tangent normals rotated to world space, n = R_k n^t                           (Eq. 7)
+ *   G-buffers X = sum_i x_i alpha_i prod_{j<i}(1 - alpha_j) over the depth order  (Eq. 8-9)
+ *   deferred split-sum shading L_o = L_d + L_s against an environment cubemap    (Eq. 10-12)
+ *   per-primitive textures packed into one atlas addressed through an indirection
+ *   buffer prim -> chart                                                          (Sec. 3.4, Supp. Sec. 1)
+ *
+ * Conventions shared by every call
+ *   - Array pointers are DEVICE pointers owned by the caller, C-contiguous, float32 unless
+ *     noted. Camera and parameter structs marked "host" are read on the host.
+ *   - Every call is ordered on `stream`, never synchronises the host and never allocates:
+ *     scratch memory comes in through `ws`/`ws_bytes` (size it with ts_workspace_size).
+ *   - Return value: TS_OK (0) or a negative TS_E_* code. On a negative return nothing was
+ *     enqueued (argument errors) or a launch failed (TS_E_LAUNCH; the stream state is then the
+ *     caller's to inspect); ts_last_error() gives a message. Conditions found on the device
+ *     (pair-list overflow) go to a device status word instead, so no call needs a host sync.
+ *   - Calls hold no global mutable state and may run concurrently on different streams with
+ *     distinct output and workspace buffers.
+ *   - Screen tiles are 16x16 pixels, row-major; n_tiles = ceil(W/16) * ceil(H/16).
+ *   - A batch of n_views cameras of one resolution is processed per call; per-view arrays
+ *     are laid out view-major ([V][...]).
+ */
+#ifndef TEXSPLAT_H
+#define TEXSPLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TS_OK 0
+#define TS_E_ARG (-1)        /* null pointer, negative or inconsistent size, unsupported T  */
+#define TS_E_WORKSPACE (-2)  /* workspace smaller than ts_workspace_size reports            */
+#define TS_E_LAUNCH (-3)     /* a kernel launch failed (hipGetLastError)                    */
+#define TS_E_UNSUPPORTED (-4)/* feature not available on this device                        */
+
+#define TS_TILE 16
+#define TS_REC_FLOATS 28     /* floats per projected-splat record                          */
+
+/* Pinhole camera, one per view (device array of these for the batched calls).
+   w2c: row-major [R|t] world -> camera, camera axes x right, y down, z forward.
+   A pixel (x,y) has its centre at (x+1/2, y+1/2); its camera ray is
+   ((x+1/2-cx)/fx, (y+1/2-cy)/fy, 1). */
+typedef struct ts_camera {
+    float w2c[12];
+    float fx, fy, cx, cy;
+} ts_camera;
+
+/* Rendering constants (host struct). Defaults in brackets. */
+typedef struct ts_params {
+    float s_sigma;    /* S: kernel support max(|u|,|v|) <= S, texture span [-S,S]^2 [3]    */
+    float alpha_min;  /* splats with alpha below this are skipped                 [1/255] */
+    float alpha_max;  /* alpha is clamped to this                                   [0.99] */
+    float t_min;      /* blending stops before a splat that takes T below this      [1e-4] */
+    float near_z;     /* splats with camera depth <= near_z are dropped              [0.2] */
+    float bg[3];      /* background radiance of empty pixels                           [0] */
+    int32_t tex_res;  /* T: texels per side of each primitive's texture, 1..32        [8] */
+    int32_t reserved;
+} ts_params;
+
+/* Shading tables (device pointers, produced by ts_env_tables / ts_brdf_lut). */
+typedef struct ts_env {
+    const float* spec;     /* specular levels back to back, level l is [6][r_l][r_l][4],
+                              r_l = max(spec_res >> l, 1), rgb + pad; faces +X,-X,+Y,-Y,+Z,-Z,
+                              texel [face][row][col]                                       */
+    int32_t spec_res;
+    int32_t spec_levels;   /* L >= 1: level l prefiltered at roughness l/(L-1)              */
+    const float* irr;      /* diffuse irradiance cube [6][irr_res][irr_res][4]              */
+    int32_t irr_res;
+    const float* lut;      /* split-sum BRDF table [lut_res][lut_res][2]: (A,B), column =
+                              N.V, row = roughness, texel centres at (i+1/2)/lut_res        */
+    int32_t lut_res;
+} ts_env;
+
+/* Workspace sizing (host only). op: TS_OP_BIN_SORT. Writes the byte count to *bytes. */
+#define TS_OP_BIN_SORT 1
+int ts_workspace_size(int32_t op, int32_t n_views, int32_t n, int32_t width, int32_t height,
+                      size_t* bytes);
+
+/*
+ * ts_preprocess — per view and per splat: camera-space frame, depth, facing sign, the
+ * closed-form ray-splat transform used per pixel, and a conservative screen bound.
+ * (Sec. 3.1 Eq. 1-2: the pixel's (u,v) is where its ray meets the splat's plane.)
+ *
+ *   cams      [n_views] ts_camera (device)
+ *   means     [n,3]  splat centres p_k
+ *   quats     [n,4]  rotations (w,x,y,z), any non-zero length (normalised here); the
+ *                    rotation's columns are t_u, t_v and n = t_u x t_v
+ *   scales    [n,2]  (s_u, s_v), linear, > 0
+ *   opac      [n]    o_k in (0,1]
+ *   chart_of  [n]    int32 atlas chart of each primitive (Supp. Sec. 1 indirection buffer)
+ *   rec       [n_views][n][TS_REC_FLOATS] out: projected records read by the rasteriser
+ *   rect      [n_views][n][4] int32 out: tile rectangle [x0,x1) x [y0,y1); empty if the
+ *                    splat cannot contribute to any pixel (behind the near plane, off screen,
+ *                    o < alpha_min)
+ *   depth_key [n_views][n] uint32 out: bits of the camera depth rounded to float32
+ *                    (positive floats sort like their bits); 0xFFFFFFFF for dropped splats
+ * Errors: TS_E_ARG for null pointers, n < 0, n_views < 1, width/height < 1.
+ */
+int ts_preprocess(int32_t n_views, int32_t width, int32_t height, const ts_camera* cams,
+                  const ts_params* params, int32_t n, const float* means, const float* quats,
+                  const float* scales, const float* opac, const int32_t* chart_of,
+                  float* rec, int32_t* rect, uint32_t* depth_key, hipStream_t stream);
+
+/*
+ * ts_bin_sort — the per-view global depth order and per-tile splat lists.
+ * Splats are radix-sorted per view by depth_key (stable, so equal keys keep index order),
+ * then every tile's list holds the splats whose rect covers it, in that depth order
+ * (the global sort the paper's rasteriser inherits from 2DGS, Supp. Sec. 3).
+ *
+ *   rect, depth_key  outputs of ts_preprocess for the same views
+ *   ws, ws_bytes     scratch, at least ts_workspace_size(TS_OP_BIN_SORT, ...) bytes
+ *   pair_capacity    length of pair_ids
+ *   sorted_ids   [n_views][n] int32 out: splat indices in (depth, index) order per view
+ *   tile_ranges  [n_views][n_tiles][2] int32 out: [start, end) of each tile's list in
+ *                pair_ids (global offsets; view v's lists follow view v-1's)
+ *   pair_ids     [pair_capacity] int32 out: splat indices of all tile lists
+ *   n_pairs      [1] int64 out: total list length (also when it exceeds the capacity)
+ *   status       [1] int32 out: 0 ok, 1 = n_pairs > pair_capacity (lists truncated:
+ *                re-run with a larger capacity before rasterising)
+ * Errors: TS_E_ARG, TS_E_WORKSPACE, TS_E_LAUNCH.
+ */
+int ts_bin_sort(int32_t n_views, int32_t width, int32_t height, int32_t n,
+                const int32_t* rect, const uint32_t* depth_key, void* ws, size_t ws_bytes,
+                int64_t pair_capacity, int32_t* sorted_ids, int32_t* tile_ranges,
+                int32_t* pair_ids, int64_t* n_pairs, int32_t* status, hipStream_t stream);
+
+/*
+ * ts_raster_fwd — per pixel, front-to-back over its tile's list: (u,v) -> G -> alpha ->
+ * bilinear texel fetch from the atlas -> normal mapping -> G-buffer blend (Eq. 2-9), with
+ * the split-sum shading of Eq. 10-12 fused into the epilogue when env != NULL.
+ *
+ *   n       splats per view (rec is [n_views][n][TS_REC_FLOATS])
+ *   rec, tile_ranges, pair_ids   from ts_preprocess / ts_bin_sort
+ *   pair_capacity  length of pair_ids; list entries at or beyond it are never read (after
+ *           an overflow reported by ts_bin_sort the image is incomplete, not unsafe)
+ *   atlas   [n_charts][T][T][8] texels, channels (albedo r,g,b, roughness, normal x,y,z,
+ *           metallic); texel [chart][row j (t)][col i (s)]
+ *   env     shading tables, or NULL to skip shading (rgba must then be NULL)
+ *   rgba    [n_views][H][W][4] out or NULL: linear radiance + alpha A = 1 - T
+ *   gbuf    [n_views][8][H][W] out or NULL: blended albedo(3), metallic, roughness,
+ *           normal(3), planar
+ *   t_final [n_views][H][W] out or NULL: final transmittance T
+ *   n_contrib [n_views][H][W] int32 out or NULL: list position (within the tile's list)
+ *           one past the last blended splat, 0 if none
+ *   n_blend [n_views][H][W] int32 out or NULL: number of splats blended into the pixel
+ *           (the contributing splat-pixel evaluations)
+ * Errors: TS_E_ARG (null required pointer, tex_res outside 1..32, rgba without env),
+ *         TS_E_LAUNCH.
+ */
+int ts_raster_fwd(int32_t n_views, int32_t width, int32_t height, const ts_camera* cams,
+                  const ts_params* params, int32_t n, const float* rec, const int32_t* tile_ranges,
+                  const int32_t* pair_ids, int64_t pair_capacity, const float* atlas,
+                  const ts_env* env,
+                  float* rgba, float* gbuf, float* t_final, int32_t* n_contrib,
+                  int32_t* n_blend, hipStream_t stream);
+
+/*
+ * ts_shade — deferred split-sum shading of given G-buffers (Eq. 10-12, V = 1, no indirect
+ * term): with N^ = N/|N| (the view vector if |N| = 0), w_o the unit vector to the camera,
+ * w_r = 2 (N^.w_o) N^ - w_o, level = clamp(R,0,1) (L-1):
+ *   C = albedo/pi (1-M) E(N^) + Lspec(w_r, level) (F0 A + B) + (1 - alpha) bg,
+ *   F0 = 0.04 (1-M) + albedo M, (A,B) = lut(clamp(N^.w_o,0,1), clamp(R,0,1));
+ * pixels with alpha = 0 take bg. Cube lookups pick the face by the major axis (ties X, Y,
+ * Z) and filter bilinearly inside the face at texel centres with clamp-to-edge.
+ *
+ *   gbuf    [n_views][8][H][W] (layout of ts_raster_fwd)
+ *   t_final [n_views][H][W] transmittance, alpha = 1 - T
+ *   rgba    [n_views][H][W][4] out
+ */
+int ts_shade(int32_t n_views, int32_t width, int32_t height, const ts_camera* cams,
+             const ts_params* params, const ts_env* env, const float* gbuf,
+             const float* t_final, float* rgba, hipStream_t stream);
+
+/*
+ * ts_brdf_lut — the split-sum BRDF table (Sec. 3.5.4 precomputed 2D lookup; split sum of
+ * Karis 2013): texel (i,j) at N.V = (i+1/2)/n, roughness r = (j+1/2)/n holds
+ *   A = mean_k (1 - Fc) G_vis,  B = mean_k Fc G_vis,
+ * over `samples` half vectors importance-sampled from GGX (alpha = r^2) at Hammersley
+ * points (k/samples, radical_inverse_2(k)), Fc = (1 - V.H)^5,
+ * G_vis = G V.H / (N.H N.V), G = Smith-Schlick with k = alpha/2; evaluated in double
+ * precision and rounded to float32.
+ *   lut [n][n][2] out.  Errors: TS_E_ARG for n < 1 or samples < 1.
+ */
+int ts_brdf_lut(int32_t n, int32_t samples, float* lut, hipStream_t stream);
+
+/*
+ * ts_env_tables — shading tables of an environment cubemap (Sec. 3.5.4 pre-integrated
+ * diffuse irradiance and roughness-selected specular levels):
+ *   level 0 = the environment;
+ *   level l >= 1 (roughness rho = l/(L-1), alpha = rho^2, resolution r >> l):
+ *     pref(w) = sum_j L_j (w.w_j)^+ D(h_j) dOmega_j / sum_j (w.w_j)^+ D(h_j) dOmega_j,
+ *     h_j = normalize(w + w_j), D the GGX distribution, over all source texels j;
+ *   irradiance E(n) = sum_j L_j (n.w_j)^+ dOmega_j at the irr_res texel centres;
+ * with w_j the source texel centre directions and dOmega_j their exact solid angles.
+ *   env     [6][r][r][3] source radiance
+ *   spec    out: levels back to back, level l [6][r_l][r_l][4]
+ *   irr     out: [6][irr_res][irr_res][4]
+ *   texel_ws scratch of 6*r*r*32 bytes (texel directions and solid angles in double)
+ * The sums run in double precision and are rounded to float32 once.
+ * Errors: TS_E_ARG for null pointers, r < 1, levels < 1, irr_res < 1.
+ */
+int ts_env_tables(const float* env, int32_t r, int32_t levels, int32_t irr_res, float* spec,
+                  float* irr, void* texel_ws, hipStream_t stream);
+
+/*
+ * ts_atlas_pack — copy per-primitive textures [n][T][T][8] into the packed atlas
+ * (chart-major [n][T][T][8]) under a chart permutation: chart perm[k] receives primitive
+ * k's texels and chart_of[k] = perm[k] (Supp. Sec. 1 atlas + indirection buffer).
+ * perm == NULL means the identity. perm must be a permutation of 0..n-1.
+ */
+int ts_atlas_pack(const float* textures, int32_t n, int32_t tex_res, const int32_t* perm,
+                  float* atlas, int32_t* chart_of, hipStream_t stream);
+
+/* Message of the last non-zero return on this thread (never NULL). */
+const char* ts_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TEXSPLAT_H */

@@ -192,7 +192,8 @@ def render(scene, cam, pixels=None, params=None, tabs=None, shade=True):
     """Render the listed pixels ([P,2] x,y; default: the whole frame).
 
     Returns dict with rgba [P,4], gbuf [P,8] (albedo 3, metallic, roughness, normal 3),
-    stat [P,6] (n_blend, n_support, n_ambiguous, grazing, min cube-face gap, n_alt),
+    stat [P,7] (n_blend, n_support, n_ambiguous, grazing, min cube-face gap, n_alt,
+    shading sensitivity = sum over G-buffer channels of max_rgb |dC/dg_c|),
     alt_rgba [P,MAX_ALT,4], alt_gbuf [P,MAX_ALT,8]."""
     if pixels is None:
         pixels = all_pixels(cam["width"], cam["height"])
@@ -202,7 +203,7 @@ def render(scene, cam, pixels=None, params=None, tabs=None, shade=True):
     T = int(scene["textures"].shape[1])
     m, q, s, o, tex = (_f32(scene[k]) for k in ("means", "quats", "scales", "opac", "textures"))
     chart = np.ascontiguousarray(scene["chart_of"], dtype=np.int32)
-    out = {"rgba": np.zeros((P, 4)), "gbuf": np.zeros((P, 8)), "stat": np.zeros((P, 6)),
+    out = {"rgba": np.zeros((P, 4)), "gbuf": np.zeros((P, 8)), "stat": np.zeros((P, 7)),
            "alt_rgba": np.zeros((P, MAX_ALT, 4)), "alt_gbuf": np.zeros((P, MAX_ALT, 8))}
     if shade:
         if tabs is None:

@@ -471,6 +471,7 @@ typedef struct {
     double rgba[4], gbuf[8];
     int n_blend, n_support, graze;
     double min_gap;
+    double sens;       /* sum over G-buffer channels of max_rgb |dC/dg_c| (shading condition) */
     int n_amb;
     flip_t amb[OR_MAX_ALT];
 } pix_out_t;
@@ -561,8 +562,24 @@ static void render_pixel(const scene_t* sc, const splat_t* sp, const cam_t* cam,
     po->rgba[3] = A;
     po->n_blend = nb;
     double gap = 1.0;
-    if (env) gap = shade(env, par, g, A, d, po->rgba);
-    else { po->rgba[0] = po->rgba[1] = po->rgba[2] = 0; }
+    po->sens = 0.0;
+    if (env) {
+        gap = shade(env, par, g, A, d, po->rgba);
+        if (record && A > 0.0) {
+            /* central differences of the shading in each G-buffer channel: how much a rounding
+               of the blended maps moves the shaded radiance */
+            for (int c = 0; c < 8; c++) {
+                double h = 1e-7, gp[8], gm[8], Cp[4], Cm[4];
+                for (int m = 0; m < 8; m++) { gp[m] = g[m]; gm[m] = g[m]; }
+                gp[c] += h; gm[c] -= h;
+                shade(env, par, gp, A, d, Cp);
+                shade(env, par, gm, A, d, Cm);
+                double mx = 0;
+                for (int m = 0; m < 3; m++) mx = fmax(mx, fabs(Cp[m] - Cm[m]) / (2 * h));
+                po->sens += mx;
+            }
+        }
+    } else { po->rgba[0] = po->rgba[1] = po->rgba[2] = 0; }
     po->min_gap = gap;
 }
 
@@ -589,7 +606,8 @@ int or_splat_setup(int n, const float* means, const float* quats, const float* s
 /*
  * Render the listed pixels (pix = [P][2] x,y).
  * out_rgba [P][4], out_gbuf [P][8],
- * out_stat [P][6]: n_blend, n_support, n_amb, grazing flag, min cube-face gap, n_alt,
+ * out_stat [P][7]: n_blend, n_support, n_amb, grazing flag, min cube-face gap, n_alt,
+ *                  shading sensitivity (sum over channels of max_rgb |dC/dg_c|),
  * alt_rgba [P][OR_MAX_ALT][4], alt_gbuf [P][OR_MAX_ALT][8] (the first n_alt are valid).
  * env_spec == NULL renders G-buffers only (rgb = 0).
  */
@@ -626,9 +644,9 @@ int or_render(int n, int T, const float* means, const float* quats, const float*
             for (int m = 0; m < 4; m++) out_rgba[4 * p + m] = po.rgba[m];
             for (int m = 0; m < 8; m++) out_gbuf[8 * p + m] = po.gbuf[m];
             int nalt = po.n_amb < OR_MAX_ALT ? po.n_amb : OR_MAX_ALT;
-            double* st = out_stat + 6 * p;
+            double* st = out_stat + 7 * p;
             st[0] = po.n_blend; st[1] = po.n_support; st[2] = po.n_amb; st[3] = po.graze;
-            st[4] = po.min_gap; st[5] = nalt;
+            st[4] = po.min_gap; st[5] = nalt; st[6] = po.sens;
             for (int a = 0; a < nalt; a++) {
                 pix_out_t pa;
                 render_pixel(&sc, sp, &cam, &par, env, x, y, &po.amb[a], 0, cand, &pa);

@@ -1,0 +1,171 @@
+"""ctypes binding of libtexsplat (argument marshalling only; all work runs in the HIP kernels).
+
+The functions here take torch CUDA tensors and pass raw device pointers and the current
+stream to the C ABI declared in include/texsplat.h. Nothing falls back to another
+implementation: if the library is missing or a call fails, an exception is raised."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtexsplat.so")
+
+TS_OK = 0
+TS_OP_BIN_SORT = 1
+REC_FLOATS = 28
+TILE = 16
+
+c_int32, c_int64, c_float, c_void_p, c_size_t = (ctypes.c_int32, ctypes.c_int64, ctypes.c_float,
+                                                   ctypes.c_void_p, ctypes.c_size_t)
+
+
+class TsParams(ctypes.Structure):
+    _fields_ = [("s_sigma", c_float), ("alpha_min", c_float), ("alpha_max", c_float),
+                ("t_min", c_float), ("near_z", c_float), ("bg", c_float * 3),
+                ("tex_res", c_int32), ("reserved", c_int32)]
+
+
+class TsEnv(ctypes.Structure):
+    _fields_ = [("spec", c_void_p), ("spec_res", c_int32), ("spec_levels", c_int32),
+                ("irr", c_void_p), ("irr_res", c_int32), ("lut", c_void_p), ("lut_res", c_int32)]
+
+
+_SIGS = {
+    "ts_workspace_size": [c_int32, c_int32, c_int32, c_int32, c_int32, ctypes.POINTER(c_size_t)],
+    "ts_preprocess": [c_int32, c_int32, c_int32, c_void_p, ctypes.POINTER(TsParams), c_int32,
+                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                      c_void_p, c_void_p],
+    "ts_bin_sort": [c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_size_t,
+                    c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
+    "ts_raster_fwd": [c_int32, c_int32, c_int32, c_void_p, ctypes.POINTER(TsParams), c_int32,
+                      c_void_p, c_void_p, c_void_p, c_int64, c_void_p, ctypes.POINTER(TsEnv),
+                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
+    "ts_shade": [c_int32, c_int32, c_int32, c_void_p, ctypes.POINTER(TsParams),
+                 ctypes.POINTER(TsEnv), c_void_p, c_void_p, c_void_p, c_void_p],
+    "ts_brdf_lut": [c_int32, c_int32, c_void_p, c_void_p],
+    "ts_env_tables": [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p],
+    "ts_atlas_pack": [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p],
+}
+
+EXPORTS = tuple(_SIGS) + ("ts_last_error",)
+
+_lib = None
+
+
+def lib():
+    """Load libtexsplat.so (built in-tree by __graft_entry__.build); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"texsplat HIP library not built: {LIB_PATH} is missing "
+                               "(run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = c_int32
+        L.ts_last_error.restype = ctypes.c_char_p
+        L.ts_last_error.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _check(rc, name):
+    if rc != TS_OK:
+        msg = lib().ts_last_error().decode()
+        raise RuntimeError(f"{name} failed ({rc}): {msg}")
+
+
+def ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_params(tex_res, s_sigma=3.0, alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4,
+                near_z=0.2, bg=(0.0, 0.0, 0.0)):
+    p = TsParams()
+    p.s_sigma, p.alpha_min, p.alpha_max, p.t_min, p.near_z = s_sigma, alpha_min, alpha_max, t_min, near_z
+    for i in range(3):
+        p.bg[i] = bg[i]
+    p.tex_res = int(tex_res)
+    p.reserved = 0
+    return p
+
+
+def make_env(spec, spec_res, levels, irr, irr_res, lut, lut_res):
+    e = TsEnv()
+    e.spec, e.spec_res, e.spec_levels = spec.data_ptr(), spec_res, levels
+    e.irr, e.irr_res = irr.data_ptr(), irr_res
+    e.lut, e.lut_res = lut.data_ptr(), lut_res
+    return e
+
+
+# --------------------------------------------------------------------------------------
+# one wrapper per C entry point, same names
+# --------------------------------------------------------------------------------------
+
+def ts_workspace_size(op, n_views, n, width, height):
+    out = c_size_t(0)
+    _check(lib().ts_workspace_size(op, n_views, n, width, height, ctypes.byref(out)),
+           "ts_workspace_size")
+    return int(out.value)
+
+
+def ts_preprocess(n_views, width, height, cams, params, n, means, quats, scales, opac, chart_of,
+                  rec, rect, depth_key, stream=None):
+    _check(lib().ts_preprocess(n_views, width, height, ptr(cams), ctypes.byref(params), n,
+                               ptr(means), ptr(quats), ptr(scales), ptr(opac), ptr(chart_of),
+                               ptr(rec), ptr(rect), ptr(depth_key), stream_handle(stream)),
+           "ts_preprocess")
+
+
+def ts_bin_sort(n_views, width, height, n, rect, depth_key, ws, pair_capacity, sorted_ids,
+                tile_ranges, pair_ids, n_pairs, status, stream=None):
+    _check(lib().ts_bin_sort(n_views, width, height, n, ptr(rect), ptr(depth_key), ptr(ws),
+                             ws.numel() * ws.element_size(), pair_capacity, ptr(sorted_ids),
+                             ptr(tile_ranges), ptr(pair_ids), ptr(n_pairs), ptr(status),
+                             stream_handle(stream)), "ts_bin_sort")
+
+
+def ts_raster_fwd(n_views, width, height, cams, params, n, rec, tile_ranges, pair_ids,
+                  pair_capacity, atlas, env, rgba, gbuf, t_final, n_contrib, n_blend=None,
+                  stream=None):
+    _check(lib().ts_raster_fwd(n_views, width, height, ptr(cams), ctypes.byref(params), n,
+                               ptr(rec), ptr(tile_ranges), ptr(pair_ids), pair_capacity, ptr(atlas),
+                               ctypes.byref(env) if env is not None else None, ptr(rgba),
+                               ptr(gbuf), ptr(t_final), ptr(n_contrib), ptr(n_blend),
+                               stream_handle(stream)),
+           "ts_raster_fwd")
+
+
+def ts_shade(n_views, width, height, cams, params, env, gbuf, t_final, rgba, stream=None):
+    _check(lib().ts_shade(n_views, width, height, ptr(cams), ctypes.byref(params),
+                          ctypes.byref(env), ptr(gbuf), ptr(t_final), ptr(rgba),
+                          stream_handle(stream)), "ts_shade")
+
+
+def ts_brdf_lut(n, samples, lut, stream=None):
+    _check(lib().ts_brdf_lut(n, samples, ptr(lut), stream_handle(stream)), "ts_brdf_lut")
+
+
+def ts_env_tables(env, r, levels, irr_res, spec, irr, texel_ws, stream=None):
+    _check(lib().ts_env_tables(ptr(env), r, levels, irr_res, ptr(spec), ptr(irr), ptr(texel_ws),
+                               stream_handle(stream)), "ts_env_tables")
+
+
+def ts_atlas_pack(textures, n, tex_res, perm, atlas, chart_of, stream=None):
+    _check(lib().ts_atlas_pack(ptr(textures), n, tex_res, ptr(perm), ptr(atlas), ptr(chart_of),
+                               stream_handle(stream)), "ts_atlas_pack")

@@ -1,0 +1,307 @@
+// ts_bin_sort: per-view depth order (LSD radix sort of the float32 depth bits, 8 bits per
+// pass, stable) and per-tile splat lists in that order (the global sort of the 2DGS-style
+// rasteriser the paper builds on, Supp. Sec. 3).
+//
+// Tile lists without sorting (tile, depth) pairs: the depth-sorted splats of a view are cut
+// into chunks; one wavefront per chunk counts, in LDS, how many of its splats cover each
+// tile; a column scan over chunks plus a scan over tiles gives every (chunk, tile) its write
+// offset; a second pass over each chunk, in order, writes the splat ids. Each pair is written
+// once (4 bytes) and the order inside every list is the depth order by construction.
+#include "binsort_layout.h"
+#include "ts_internal.h"
+
+namespace ts {
+
+// ---------------------------------------------------------------------------------------
+// radix sort (segmented by view)
+// ---------------------------------------------------------------------------------------
+
+// Per-block digit histogram, written digit-major per view: hist[v][d][b].
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t* __restrict__ keys,
+                                                            int n, int nblk, int shift,
+                                                            uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[kSortBuckets];
+    int b = blockIdx.x, v = blockIdx.y, tid = threadIdx.x;
+    h[tid] = 0;
+    __syncthreads();
+    const uint32_t* kv = keys + (int64_t)v * n;
+    int base = b * kSortItems;
+    for (int r = 0; r < kSortItemsPerThread; r++) {
+        int i = base + r * kSortThreads + tid;
+        if (i < n) atomicAdd(&h[(kv[i] >> shift) & (kSortBuckets - 1)], 1u);
+    }
+    __syncthreads();
+    hist[((int64_t)v * kSortBuckets + tid) * nblk + b] = h[tid];
+}
+
+// Exclusive scan of one view's hist (digit-major, block-minor), in place.
+__global__ __launch_bounds__(1024) void k_sort_scan(uint32_t* __restrict__ hist, int nblk) {
+    __shared__ uint32_t part[1024];
+    int v = blockIdx.x, tid = threadIdx.x;
+    uint32_t* hv = hist + (int64_t)v * kSortBuckets * nblk;
+    int m = kSortBuckets * nblk;
+    int per = (m + 1023) / 1024;
+    int s0 = tid * per, s1 = min(m, s0 + per);
+    uint32_t sum = 0;
+    for (int i = s0; i < s1; i++) sum += hv[i];
+    part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint32_t x = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += x;
+        __syncthreads();
+    }
+    uint32_t run = part[tid] - sum;
+    for (int i = s0; i < s1; i++) {
+        uint32_t x = hv[i];
+        hv[i] = run;
+        run += x;
+    }
+}
+
+// Stable scatter. Wave w of the block owns items [w*1024, (w+1)*1024) of the block's range,
+// taken 64 at a time in order; lanes with equal digits are ranked with ballots, and a
+// per-wave running count per digit (LDS) carries ranks across rounds.
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
+    const uint32_t* __restrict__ keys_in, const int32_t* __restrict__ vals_in, int n, int nblk,
+    int shift, const uint32_t* __restrict__ offsets, uint32_t* __restrict__ keys_out,
+    int32_t* __restrict__ vals_out) {
+    __shared__ uint32_t cnt[kSortThreads / kWave][kSortBuckets];
+    int b = blockIdx.x, v = blockIdx.y, tid = threadIdx.x;
+    int w = tid / kWave, lane = tid % kWave;
+    for (int i = tid; i < (kSortThreads / kWave) * kSortBuckets; i += kSortThreads)
+        (&cnt[0][0])[i] = 0;
+    __syncthreads();
+    const uint32_t* kv = keys_in + (int64_t)v * n;
+    const int32_t* vv = vals_in ? vals_in + (int64_t)v * n : nullptr;
+    int base = b * kSortItems + w * (kSortItemsPerThread * kWave);
+    uint32_t key[kSortItemsPerThread];
+    int32_t val[kSortItemsPerThread];
+    uint32_t loc[kSortItemsPerThread];
+#pragma unroll
+    for (int r = 0; r < kSortItemsPerThread; r++) {
+        int i = base + r * kWave + lane;
+        bool ok = i < n;
+        uint32_t k = ok ? kv[i] : 0u;
+        key[r] = k;
+        val[r] = ok ? (vv ? vv[i] : i) : 0;
+        uint32_t d = (k >> shift) & (kSortBuckets - 1);
+        // lanes holding the same digit (invalid lanes excluded from every peer set)
+        uint64_t peers = __ballot(ok);
+#pragma unroll
+        for (int bit = 0; bit < kSortRadixBits; bit++) {
+            uint64_t m = __ballot((d >> bit) & 1u);
+            peers &= ((d >> bit) & 1u) ? m : ~m;
+        }
+        uint32_t old = ok ? cnt[w][d] : 0u;
+        loc[r] = old + lanes_below(peers);
+        bool leader = ok && ((peers >> lane) == 1ull);
+        if (leader) cnt[w][d] = old + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    // wave offsets inside the block plus the block's global offset per digit
+    {
+        int d = tid;  // kSortThreads == kSortBuckets
+        uint32_t g = offsets[((int64_t)v * kSortBuckets + d) * nblk + b];
+        uint32_t run = g;
+        for (int ww = 0; ww < kSortThreads / kWave; ww++) {
+            uint32_t c = cnt[ww][d];
+            cnt[ww][d] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    uint32_t* ko = keys_out + (int64_t)v * n;
+    int32_t* vo = vals_out + (int64_t)v * n;
+#pragma unroll
+    for (int r = 0; r < kSortItemsPerThread; r++) {
+        int i = base + r * kWave + lane;
+        if (i < n) {
+            uint32_t d = (key[r] >> shift) & (kSortBuckets - 1);
+            uint32_t pos = cnt[w][d] + loc[r];
+            ko[pos] = key[r];
+            vo[pos] = val[r];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// tile lists
+// ---------------------------------------------------------------------------------------
+
+struct BinArgs {
+    int n, n_chunks, chunk, ntx, n_tiles;
+    const int32_t* sorted;   // [V][n]
+    const int4* rect;        // [V][n]
+    uint32_t* counts;        // [V][n_chunks][n_tiles]
+    const int32_t* ranges;   // [V][n_tiles][2] (fill)
+    int32_t* pair_ids;
+    int64_t cap;
+};
+
+// One wavefront per (view, chunk): LDS counters over the view's tiles.
+template <bool kFill>
+__global__ __launch_bounds__(kWave) void k_bin_chunk(BinArgs a) {
+    extern __shared__ uint32_t cnt[];
+    int c = blockIdx.x, v = blockIdx.y, lane = threadIdx.x;
+    uint32_t* row = a.counts + ((int64_t)v * a.n_chunks + c) * a.n_tiles;
+    const int32_t* rg = a.ranges + (int64_t)v * a.n_tiles * 2;
+    for (int t = lane; t < a.n_tiles; t += kWave) cnt[t] = kFill ? (uint32_t)rg[2 * t] + row[t] : 0u;
+    __syncthreads();
+    int i0 = c * a.chunk, i1 = min(a.n, i0 + a.chunk);
+    const int32_t* sv = a.sorted + (int64_t)v * a.n;
+    const int4* rv = a.rect + (int64_t)v * a.n;
+    for (int b = i0; b < i1; b += kWave) {
+        int m = min(kWave, i1 - b);
+        int id = lane < m ? sv[b + lane] : 0;
+        int4 r = lane < m ? rv[id] : make_int4(0, 0, 0, 0);
+        for (int j = 0; j < m; j++) {
+            int x0 = __builtin_amdgcn_readlane(r.x, j), y0 = __builtin_amdgcn_readlane(r.y, j);
+            int x1 = __builtin_amdgcn_readlane(r.z, j), y1 = __builtin_amdgcn_readlane(r.w, j);
+            int wdt = x1 - x0, cntj = wdt * (y1 - y0);
+            if (cntj <= 0) continue;
+            int sid = kFill ? __builtin_amdgcn_readlane(id, j) : 0;
+            for (int e = lane; e < cntj; e += kWave) {
+                int ty = y0 + e / wdt, tx = x0 + e % wdt;
+                int t = ty * a.ntx + tx;
+                uint32_t p = cnt[t];
+                cnt[t] = p + 1;
+                if (kFill && (int64_t)p < a.cap) a.pair_ids[p] = sid;
+            }
+        }
+    }
+    if (!kFill) {
+        __syncthreads();
+        for (int t = lane; t < a.n_tiles; t += kWave) row[t] = cnt[t];
+    }
+}
+
+// Column scan over chunks per (view, tile): counts become exclusive prefixes.
+__global__ __launch_bounds__(256) void k_bin_scan_chunks(uint32_t* __restrict__ counts, int V,
+                                                         int n_chunks, int n_tiles,
+                                                         uint32_t* __restrict__ totals) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)V * n_tiles) return;
+    int v = (int)(i / n_tiles), t = (int)(i % n_tiles);
+    uint32_t* col = counts + (int64_t)v * n_chunks * n_tiles + t;
+    uint32_t run = 0;
+    for (int c = 0; c < n_chunks; c++) {
+        uint32_t x = col[(int64_t)c * n_tiles];
+        col[(int64_t)c * n_tiles] = run;
+        run += x;
+    }
+    totals[i] = run;
+}
+
+// Exclusive scan of all (view, tile) totals -> ranges, total pair count and overflow status.
+__global__ __launch_bounds__(1024) void k_bin_scan_tiles(const uint32_t* __restrict__ totals,
+                                                         int64_t m, int64_t cap,
+                                                         int32_t* __restrict__ ranges,
+                                                         int64_t* __restrict__ n_pairs,
+                                                         int32_t* __restrict__ status) {
+    __shared__ int64_t part[1024];
+    int tid = threadIdx.x;
+    int64_t per = (m + 1023) / 1024;
+    int64_t s0 = tid * per, s1 = min(m, s0 + per);
+    int64_t sum = 0;
+    for (int64_t i = s0; i < s1; i++) sum += totals[i];
+    part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int64_t x = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += x;
+        __syncthreads();
+    }
+    int64_t run = part[tid] - sum;
+    for (int64_t i = s0; i < s1; i++) {
+        int64_t e = run + totals[i];
+        ranges[2 * i] = (int32_t)min(run, (int64_t)0x7FFFFFFF);
+        ranges[2 * i + 1] = (int32_t)min(e, (int64_t)0x7FFFFFFF);
+        run = e;
+    }
+    if (tid == 1023) {
+        n_pairs[0] = part[1023];
+        status[0] = part[1023] > cap ? 1 : 0;
+    }
+}
+
+}  // namespace ts
+
+using namespace ts;
+
+extern "C" int ts_bin_sort(int32_t n_views, int32_t width, int32_t height, int32_t n,
+                           const int32_t* rect, const uint32_t* depth_key, void* ws,
+                           size_t ws_bytes, int64_t pair_capacity, int32_t* sorted_ids,
+                           int32_t* tile_ranges, int32_t* pair_ids, int64_t* n_pairs,
+                           int32_t* status, hipStream_t stream) {
+    if (n_views < 1 || width < 1 || height < 1 || n < 0 || pair_capacity < 0 || !tile_ranges ||
+        !n_pairs || !status || (n > 0 && (!rect || !depth_key || !sorted_ids)) ||
+        (pair_capacity > 0 && !pair_ids)) {
+        set_error("ts_bin_sort: bad argument");
+        return TS_E_ARG;
+    }
+    if (pair_capacity > 0x7FFFFFFFLL) {
+        set_error("ts_bin_sort: pair_capacity above 2^31-1");
+        return TS_E_ARG;
+    }
+    BinSortLayout L = binsort_layout(n_views, n, width, height);
+    if (!ws || ws_bytes < L.total) {
+        set_error("ts_bin_sort: workspace %zu < %zu bytes", ws_bytes, L.total);
+        return TS_E_WORKSPACE;
+    }
+    if ((size_t)L.n_tiles * 4 > 64 * 1024) {
+        set_error("ts_bin_sort: %d tiles exceed the per-view limit of 16384", L.n_tiles);
+        return TS_E_ARG;
+    }
+    char* w = (char*)ws;
+    uint32_t* keys_a = (uint32_t*)(w + L.off_keys_a);
+    uint32_t* keys_b = (uint32_t*)(w + L.off_keys_b);
+    int32_t* vals_a = (int32_t*)(w + L.off_vals_a);
+    uint32_t* hist = (uint32_t*)(w + L.off_hist);
+    uint32_t* counts = (uint32_t*)(w + L.off_counts);
+    uint32_t* totals = (uint32_t*)(w + L.off_totals);
+    int rc;
+    if (n > 0) {
+        // pass p reads (keys_in, vals_in) and writes (keys_out, vals_out); the final pass
+        // writes the splat ids to sorted_ids (also used as the ping-pong value buffer)
+        const uint32_t* kin = depth_key;
+        const int32_t* vin = nullptr;
+        for (int p = 0; p < kSortPasses; p++) {
+            uint32_t* kout = (p & 1) ? keys_b : keys_a;
+            int32_t* vout = (p & 1) ? sorted_ids : vals_a;
+            int shift = p * kSortRadixBits;
+            hipLaunchKernelGGL(k_sort_hist, dim3(L.sort_blocks, n_views), dim3(kSortThreads), 0,
+                               stream, kin, n, L.sort_blocks, shift, hist);
+            hipLaunchKernelGGL(k_sort_scan, dim3(n_views), dim3(1024), 0, stream, hist,
+                               L.sort_blocks);
+            hipLaunchKernelGGL(k_sort_scatter, dim3(L.sort_blocks, n_views), dim3(kSortThreads),
+                               0, stream, kin, vin, n, L.sort_blocks, shift, hist, kout, vout);
+            kin = kout;
+            vin = vout;
+        }
+        static_assert(kSortPasses % 2 == 0, "the last pass must land in sorted_ids");
+        if ((rc = launch_check("ts_bin_sort(sort)")) != TS_OK) return rc;
+    }
+    BinArgs a;
+    a.n = n; a.n_chunks = L.n_chunks; a.chunk = L.chunk; a.ntx = L.ntx; a.n_tiles = L.n_tiles;
+    a.sorted = sorted_ids; a.rect = (const int4*)rect; a.counts = counts; a.ranges = tile_ranges;
+    a.pair_ids = pair_ids; a.cap = pair_capacity;
+    size_t lds = (size_t)L.n_tiles * 4;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_bin_chunk<false>, dim3(L.n_chunks, n_views), dim3(kWave), lds,
+                           stream, a);
+    } else {
+        hipMemsetAsync(counts, 0, (size_t)n_views * L.n_chunks * L.n_tiles * 4, stream);
+    }
+    int64_t m = (int64_t)n_views * L.n_tiles;
+    hipLaunchKernelGGL(k_bin_scan_chunks, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream,
+                       counts, n_views, L.n_chunks, L.n_tiles, totals);
+    hipLaunchKernelGGL(k_bin_scan_tiles, dim3(1), dim3(1024), 0, stream, totals, m, pair_capacity,
+                       tile_ranges, n_pairs, status);
+    if (n > 0)
+        hipLaunchKernelGGL(k_bin_chunk<true>, dim3(L.n_chunks, n_views), dim3(kWave), lds, stream,
+                           a);
+    return launch_check("ts_bin_sort(bin)");
+}

@@ -1,0 +1,288 @@
+// ts_raster_fwd / ts_shade.
+//
+// One 256-thread workgroup per (view, 16x16 tile); wave w covers the 8x8 quadrant
+// (w&1, w>>1), one pixel per lane. The tile's list is walked front to back in batches of 256
+// records staged in LDS (one record per thread, 112 B). A wave skips a splat whose pixel
+// bound misses its quadrant (one scalar test) and leaves the list as soon as all 64 of its
+// pixels have terminated (ballot); the workgroup stops loading batches when all 256 have.
+//
+// Per pixel and splat (Eq. 2-9): closed-form (u,v) from the record, square support
+// max(|u|,|v|) <= S, G = exp(-(u^2+v^2)/2), alpha = min(alpha_max, o G), skip below
+// alpha_min, stop before a splat taking T below t_min; then the texture (Eq. 5-6): bilinear
+// on the primitive's T x T texels in the atlas at s = (u+S)/(2S), t = (v+S)/(2S), texel
+// centres at (i+1/2)/T, clamp-to-edge within the chart; the tangent normal is normalised and
+// rotated by sigma R (Eq. 7); the eight G-buffer channels accumulate with w = alpha T.
+#include "shade.h"
+#include "ts_internal.h"
+
+namespace ts {
+
+struct RasterArgs {
+    int V, W, H, ntx, n_tiles, T, n;
+    const ts_camera* cams;
+    float S, amin, amax, tmin;
+    ShadeConst sc;
+    EnvDev env;
+    bool shade;
+    const float4* rec;
+    const int2* ranges;
+    const int32_t* pair_ids;
+    int64_t cap;
+    const float4* atlas;     // [chart][T][T][2] float4
+    float4* rgba;
+    float* gbuf;
+    float* t_final;
+    int32_t* n_contrib;
+    int32_t* n_blend;
+};
+
+constexpr int kBatch = 256;
+
+__global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
+    __shared__ float4 srec[kBatch * kRec4];
+    const int g = gridDim.x;
+    const int bid = xcd_remap(blockIdx.x, g);
+    const int v = bid / a.n_tiles;
+    const int t = bid - v * a.n_tiles;
+    const int tx = t % a.ntx, ty = t / a.ntx;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int bx = tx * kTile + (w & 1) * 8, by = ty * kTile + (w >> 1) * 8;
+    const int x = bx + (lane & 7), y = by + (lane >> 3);
+    const bool inside = x < a.W && y < a.H;
+    const float X = (float)x + 0.5f, Y = (float)y + 0.5f;
+    const float fbx0 = (float)bx, fbx1 = (float)(bx + 7), fby0 = (float)by, fby1 = (float)(by + 7);
+    int2 range = a.ranges[(int64_t)v * a.n_tiles + t];
+    // lists cut short by a capacity overflow are never read past the buffer
+    range.x = (int)min((int64_t)range.x, a.cap);
+    range.y = (int)min((int64_t)range.y, a.cap);
+    const float4* recv = a.rec;
+    const int T = a.T;
+    const float tscale = (float)T / (2.0f * a.S);
+    const float toff = 0.5f * (float)T - 0.5f;
+    const int chart4 = T * T * 2;
+
+    float Tr = 1.0f;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    bool done = !inside;
+    int last = 0;
+    int nbl = 0;
+
+    for (int b0 = range.x; b0 < range.y; b0 += kBatch) {
+        if (__syncthreads_count(!done) == 0) break;
+        int nb = min(kBatch, range.y - b0);
+        if (tid < nb) {
+            int id = a.pair_ids[b0 + tid];
+            const float4* src = recv + ((int64_t)v * a.n + (int64_t)id) * kRec4;
+#pragma unroll
+            for (int q = 0; q < kRec4; q++) srec[tid * kRec4 + q] = src[q];
+        }
+        __syncthreads();
+        if (__ballot(!done) != 0) {
+            for (int j = 0; j < nb; j++) {
+                const float4* r = srec + j * kRec4;
+                float4 bb = r[0];
+                if (bb.z < fbx0 || bb.x > fbx1 || bb.w < fby0 || bb.y > fby1) continue;
+                float4 c1 = r[1], c2 = r[2], c3 = r[3];
+                float dx = X - c1.x, dy = Y - c1.y;
+                float nu = fmaf(c1.z, dx, fmaf(c1.w, dy, c2.x));
+                float nv = fmaf(c2.y, dx, fmaf(c2.z, dy, c2.w));
+                float den = fmaf(c3.x, dx, fmaf(c3.y, dy, c3.z));
+                float inv = 1.0f / den;
+                float u = nu * inv, vv = nv * inv;
+                float m = fmaxf(fabsf(u), fabsf(vv));
+                float G = __expf(-0.5f * fmaf(u, u, vv * vv));
+                float alpha = fminf(a.amax, c3.w * G);
+                bool ok = !done && den > 0.f && m <= a.S && alpha >= a.amin;
+                float Tn = Tr * (1.0f - alpha);
+                if (ok && Tn < a.tmin) {
+                    done = true;
+                    ok = false;
+                }
+                if (__ballot(ok) != 0) {
+                    if (ok) {
+                        float4 c4 = r[4], c5 = r[5], c6 = r[6];
+                        int chart = __float_as_int(c6.y);
+                        float sx = fmaf(u, tscale, toff), sy = fmaf(vv, tscale, toff);
+                        float fx0 = floorf(sx), fy0 = floorf(sy);
+                        float fx = sx - fx0, fy = sy - fy0;
+                        int i0 = (int)fx0, j0 = (int)fy0;
+                        int i1 = min(max(i0 + 1, 0), T - 1), j1 = min(max(j0 + 1, 0), T - 1);
+                        i0 = min(max(i0, 0), T - 1);
+                        j0 = min(max(j0, 0), T - 1);
+                        const float4* tb = a.atlas + (int64_t)chart * chart4;
+                        float4 p00 = tb[(j0 * T + i0) * 2], q00 = tb[(j0 * T + i0) * 2 + 1];
+                        float4 p10 = tb[(j0 * T + i1) * 2], q10 = tb[(j0 * T + i1) * 2 + 1];
+                        float4 p01 = tb[(j1 * T + i0) * 2], q01 = tb[(j1 * T + i0) * 2 + 1];
+                        float4 p11 = tb[(j1 * T + i1) * 2], q11 = tb[(j1 * T + i1) * 2 + 1];
+                        float w00 = (1.f - fx) * (1.f - fy), w10 = fx * (1.f - fy);
+                        float w01 = (1.f - fx) * fy, w11 = fx * fy;
+                        float t0 = w00 * p00.x + w10 * p10.x + w01 * p01.x + w11 * p11.x;
+                        float t1 = w00 * p00.y + w10 * p10.y + w01 * p01.y + w11 * p11.y;
+                        float t2 = w00 * p00.z + w10 * p10.z + w01 * p01.z + w11 * p11.z;
+                        float t3 = w00 * p00.w + w10 * p10.w + w01 * p01.w + w11 * p11.w;
+                        float t4 = w00 * q00.x + w10 * q10.x + w01 * q01.x + w11 * q11.x;
+                        float t5 = w00 * q00.y + w10 * q10.y + w01 * q01.y + w11 * q11.y;
+                        float t6 = w00 * q00.z + w10 * q10.z + w01 * q01.z + w11 * q11.z;
+                        float t7 = w00 * q00.w + w10 * q10.w + w01 * q01.w + w11 * q11.w;
+                        float nl = t4 * t4 + t5 * t5 + t6 * t6;
+                        float nx, ny, nz;
+                        if (nl > 0.f) {
+                            float il = rsqrtf(nl);
+                            nx = t4 * il; ny = t5 * il; nz = t6 * il;
+                        } else {
+                            nx = 0.f; ny = 0.f; nz = 1.f;
+                        }
+                        float ww = alpha * Tr;
+                        acc[0] = fmaf(ww, t0, acc[0]);
+                        acc[1] = fmaf(ww, t1, acc[1]);
+                        acc[2] = fmaf(ww, t2, acc[2]);
+                        acc[3] = fmaf(ww, t7, acc[3]);   // metallic
+                        acc[4] = fmaf(ww, t3, acc[4]);   // roughness
+                        acc[5] = fmaf(ww, c4.x * nx + c4.y * ny + c4.z * nz, acc[5]);
+                        acc[6] = fmaf(ww, c4.w * nx + c5.x * ny + c5.y * nz, acc[6]);
+                        acc[7] = fmaf(ww, c5.z * nx + c5.w * ny + c6.x * nz, acc[7]);
+                        Tr = Tn;
+                        last = b0 - range.x + j + 1;
+                        nbl++;
+                    }
+                }
+                if (__ballot(!done) == 0) break;
+            }
+        }
+        __syncthreads();
+    }
+    if (!inside) return;
+    int64_t pix = ((int64_t)v * a.H + y) * a.W + x;
+    int64_t plane = (int64_t)a.H * a.W;
+    if (a.gbuf) {
+        float* gb = a.gbuf + (int64_t)v * 8 * plane + (int64_t)y * a.W + x;
+#pragma unroll
+        for (int c = 0; c < 8; c++) gb[c * plane] = acc[c];
+    }
+    if (a.t_final) a.t_final[pix] = Tr;
+    if (a.n_contrib) a.n_contrib[pix] = last;
+    if (a.n_blend) a.n_blend[pix] = nbl;
+    if (a.shade) {
+        float3 d = pixel_ray(a.cams[v], X, Y);
+        float3 C = shade_pixel(a.env, a.sc, acc, Tr, d);
+        a.rgba[pix] = make_float4(C.x, C.y, C.z, 1.0f - Tr);
+    }
+}
+
+struct ShadeArgs {
+    int V, W, H;
+    const ts_camera* cams;
+    ShadeConst sc;
+    EnvDev env;
+    const float* gbuf;
+    const float* t_final;
+    float4* rgba;
+};
+
+__global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t plane = (int64_t)a.H * a.W;
+    if (i >= (int64_t)a.V * plane) return;
+    int v = (int)(i / plane);
+    int64_t p = i - v * plane;
+    int y = (int)(p / a.W), x = (int)(p % a.W);
+    float g[8];
+    const float* gb = a.gbuf + (int64_t)v * 8 * plane + p;
+#pragma unroll
+    for (int c = 0; c < 8; c++) g[c] = gb[c * plane];
+    float T = a.t_final[i];
+    float3 d = pixel_ray(a.cams[v], (float)x + 0.5f, (float)y + 0.5f);
+    float3 C = shade_pixel(a.env, a.sc, g, T, d);
+    a.rgba[i] = make_float4(C.x, C.y, C.z, 1.0f - T);
+}
+
+static int env_from(const ts_env* e, EnvDev& d, const char* who) {
+    if (!e->spec || !e->irr || !e->lut || e->spec_res < 1 || e->spec_levels < 1 || e->irr_res < 1 ||
+        e->lut_res < 1) {
+        set_error("%s: bad ts_env", who);
+        return TS_E_ARG;
+    }
+    d.spec = (const float4*)e->spec;
+    d.irr = (const float4*)e->irr;
+    d.lut = (const float2*)e->lut;
+    d.spec_res = e->spec_res;
+    d.levels = e->spec_levels;
+    d.irr_res = e->irr_res;
+    d.lut_res = e->lut_res;
+    return TS_OK;
+}
+
+}  // namespace ts
+
+using namespace ts;
+
+extern "C" int ts_raster_fwd(int32_t n_views, int32_t width, int32_t height, const ts_camera* cams,
+                             const ts_params* params, int32_t n, const float* rec,
+                             const int32_t* tile_ranges, const int32_t* pair_ids,
+                             int64_t pair_capacity, const float* atlas, const ts_env* env,
+                             float* rgba, float* gbuf, float* t_final, int32_t* n_contrib,
+                             int32_t* n_blend, hipStream_t stream) {
+    if (n_views < 1 || width < 1 || height < 1 || n < 0 || !params || !cams || !tile_ranges ||
+        (n > 0 && (!atlas || !rec || !pair_ids))) {
+        set_error("ts_raster_fwd: bad argument");
+        return TS_E_ARG;
+    }
+    if (params->tex_res < 1 || params->tex_res > 32) {
+        set_error("ts_raster_fwd: tex_res %d outside 1..32", params->tex_res);
+        return TS_E_ARG;
+    }
+    if ((rgba != nullptr) != (env != nullptr)) {
+        set_error("ts_raster_fwd: rgba and env must be given together");
+        return TS_E_ARG;
+    }
+    RasterArgs a = {};
+    a.V = n_views; a.W = width; a.H = height; a.n = n;
+    a.ntx = tiles_x(width);
+    a.n_tiles = a.ntx * tiles_y(height);
+    a.T = params->tex_res;
+    a.cams = cams;
+    a.S = params->s_sigma; a.amin = params->alpha_min; a.amax = params->alpha_max;
+    a.tmin = params->t_min;
+    for (int c = 0; c < 3; c++) a.sc.bg[c] = params->bg[c];
+    a.shade = env != nullptr;
+    if (env) {
+        int rc = env_from(env, a.env, "ts_raster_fwd");
+        if (rc != TS_OK) return rc;
+    }
+    a.rec = (const float4*)rec;
+    a.ranges = (const int2*)tile_ranges;
+    a.pair_ids = pair_ids;
+    a.cap = pair_capacity < 0 ? 0 : pair_capacity;
+    a.atlas = (const float4*)atlas;
+    a.rgba = (float4*)rgba;
+    a.gbuf = gbuf;
+    a.t_final = t_final;
+    a.n_contrib = n_contrib;
+    a.n_blend = n_blend;
+    int64_t blocks = (int64_t)n_views * a.n_tiles;
+    if (blocks > 0x7FFFFFFF) {
+        set_error("ts_raster_fwd: too many tiles");
+        return TS_E_ARG;
+    }
+    hipLaunchKernelGGL(k_raster_fwd, dim3((unsigned)blocks), dim3(256), 0, stream, a);
+    return launch_check("ts_raster_fwd");
+}
+
+extern "C" int ts_shade(int32_t n_views, int32_t width, int32_t height, const ts_camera* cams,
+                        const ts_params* params, const ts_env* env, const float* gbuf,
+                        const float* t_final, float* rgba, hipStream_t stream) {
+    if (n_views < 1 || width < 1 || height < 1 || !params || !cams || !env || !gbuf || !t_final ||
+        !rgba) {
+        set_error("ts_shade: bad argument");
+        return TS_E_ARG;
+    }
+    ShadeArgs a = {};
+    a.V = n_views; a.W = width; a.H = height; a.cams = cams;
+    for (int c = 0; c < 3; c++) a.sc.bg[c] = params->bg[c];
+    int rc = env_from(env, a.env, "ts_shade");
+    if (rc != TS_OK) return rc;
+    a.gbuf = gbuf; a.t_final = t_final; a.rgba = (float4*)rgba;
+    int64_t total = (int64_t)n_views * width * height;
+    hipLaunchKernelGGL(k_shade, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, a);
+    return launch_check("ts_shade");
+}

@@ -1,0 +1,45 @@
+// Internal declarations shared by the texsplat HIP sources (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "texsplat.h"
+
+namespace ts {
+
+constexpr int kTile = TS_TILE;           // 16x16 pixel tiles, one 256-thread workgroup each
+constexpr int kRec = TS_REC_FLOATS;      // floats per projected record (7 float4)
+constexpr int kRec4 = kRec / 4;
+constexpr int kWave = 64;
+constexpr int kXcd = 8;                  // MI355X: 8 XCDs, workgroups dealt round-robin
+
+// record layout (float offsets)
+//  0..3   pixel bounds ix0, iy0, ix1, iy1 (inclusive, pixel indices, as floats)
+//  4..7   px, py (projected centre, float32 head of the double value), ux, uy
+//  8..11  u0, vx, vy, v0
+//  12..15 wx, wy, w0, opacity
+//  16..24 sigma * R (row-major 3x3, world frame), 25 chart id (int bits), 26..27 pad
+// per pixel (X,Y) = pixel centre:   dx = X - px, dy = Y - py
+//   num_u = ux dx + uy dy + u0,  num_v = vx dx + vy dy + v0,  den = wx dx + wy dy + w0
+//   (u,v) = (num_u, num_v) / den, the ray meets the front of the plane iff den > 0
+
+void set_error(const char* fmt, ...);
+int launch_check(const char* what);
+
+inline int tiles_x(int w) { return (w + kTile - 1) / kTile; }
+inline int tiles_y(int h) { return (h + kTile - 1) / kTile; }
+
+// Logical workgroup index such that each XCD receives a contiguous range (spatially adjacent
+// tiles of one view then share that XCD's L2).
+__device__ inline int xcd_remap(int i, int g) {
+    int q = g / kXcd, r = g % kXcd;
+    int x = i % kXcd, k = i / kXcd;
+    return x * q + (x < r ? x : r) + k;
+}
+
+__device__ inline unsigned lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+}  // namespace ts

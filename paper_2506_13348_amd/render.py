@@ -1,0 +1,221 @@
+"""Device-resident scenes and render plans over the texsplat C ABI.
+
+A `DeviceScene` holds one scene on the GPU: splat parameters, the packed texture atlas with
+its indirection buffer (Supp. Sec. 1) and the shading tables of its environment (Sec. 3.5.4).
+A `RenderPlan` preallocates every buffer of a batch of same-resolution views, so `run()`
+enqueues the whole path (preprocess -> bin/sort -> raster with fused shading) on a stream
+without allocating or synchronising; `check()` reads the pair-list status afterwards."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _ffi as F
+
+DEFAULTS = dict(s_sigma=3.0, alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, near_z=0.2,
+                bg=(0.0, 0.0, 0.0))
+IRR_RES = 16
+LUT_RES = 256
+LUT_SAMPLES = 4096
+
+
+def _dev(x, device, dtype=None):
+    t = torch.as_tensor(np.ascontiguousarray(x)) if isinstance(x, np.ndarray) else x
+    t = t.to(device=device)
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.contiguous()
+
+
+def cameras_tensor(cams, device="cuda"):
+    """[V,16] float32: w2c (12, row-major), fx, fy, cx, cy."""
+    if isinstance(cams, torch.Tensor):
+        return cams.to(device=device, dtype=torch.float32).contiguous()
+    if isinstance(cams, np.ndarray):
+        return _dev(cams.astype(np.float32), device)
+    arr = np.zeros((len(cams), 16), np.float32)
+    for i, c in enumerate(cams):
+        arr[i, :12] = np.asarray(c["w2c"], np.float32).reshape(12)
+        arr[i, 12:] = [c["fx"], c["fy"], c["cx"], c["cy"]]
+    return _dev(arr, device)
+
+
+class EnvTables:
+    """Shading tables of one environment cubemap, built by the HIP table kernels."""
+
+    def __init__(self, env, levels, device="cuda", irr_res=IRR_RES, lut_res=LUT_RES,
+                 lut_samples=LUT_SAMPLES, lut=None):
+        env = _dev(np.asarray(env, np.float32) if isinstance(env, np.ndarray) else env, device,
+                   torch.float32)
+        r = int(env.shape[1])
+        self.res, self.levels, self.irr_res, self.lut_res = r, int(levels), irr_res, lut_res
+        n_spec = sum(6 * max(r >> l, 1) ** 2 for l in range(self.levels))
+        self.spec = torch.empty(n_spec * 4, device=device, dtype=torch.float32)
+        self.irr = torch.empty(6 * irr_res * irr_res * 4, device=device, dtype=torch.float32)
+        texel_ws = torch.empty(6 * r * r * 4, device=device, dtype=torch.float64)
+        F.ts_env_tables(env, r, self.levels, irr_res, self.spec, self.irr, texel_ws)
+        if lut is None:
+            lut = torch.empty(lut_res * lut_res * 2, device=device, dtype=torch.float32)
+            F.ts_brdf_lut(lut_res, lut_samples, lut)
+        self.lut = lut
+        self._keep = (env, texel_ws)
+        self.struct = F.make_env(self.spec, r, self.levels, self.irr, irr_res, self.lut, lut_res)
+
+    def spec_levels(self):
+        """Specular levels as a list of [6, r_l, r_l, 3] tensors (views)."""
+        out, off = [], 0
+        for l in range(self.levels):
+            rl = max(self.res >> l, 1)
+            m = 6 * rl * rl * 4
+            out.append(self.spec[off:off + m].view(6, rl, rl, 4)[..., :3])
+            off += m
+        return out
+
+
+class DeviceScene:
+    """Splats + packed atlas + shading tables resident on one device."""
+
+    def __init__(self, means, quats, scales, opac, textures, env=None, env_levels=1,
+                 device="cuda", perm=None, tables=None):
+        self.device = torch.device(device)
+        self.means = _dev(means, device, torch.float32)
+        self.quats = _dev(quats, device, torch.float32)
+        self.scales = _dev(scales, device, torch.float32)
+        self.opac = _dev(opac, device, torch.float32)
+        tex = _dev(textures, device, torch.float32)
+        self.n = int(self.means.shape[0])
+        self.tex_res = int(tex.shape[1])
+        self.atlas = torch.empty_like(tex)
+        self.chart_of = torch.empty(self.n, device=device, dtype=torch.int32)
+        permt = None if perm is None else _dev(np.asarray(perm, np.int32), device, torch.int32)
+        if self.n:
+            F.ts_atlas_pack(tex, self.n, self.tex_res, permt, self.atlas, self.chart_of)
+        del tex
+        if tables is not None:
+            self.tables = tables
+        elif env is not None:
+            self.tables = EnvTables(env, env_levels, device)
+        else:
+            self.tables = None
+
+    @classmethod
+    def from_dict(cls, sc, device="cuda", **kw):
+        return cls(sc["means"], sc["quats"], sc["scales"], sc["opac"], sc["textures"],
+                   sc.get("env"), sc.get("env_levels", 1), device=device, **kw)
+
+    def bytes(self):
+        b = sum(t.numel() * t.element_size() for t in
+                (self.means, self.quats, self.scales, self.opac, self.atlas, self.chart_of))
+        if self.tables is not None:
+            b += sum(t.numel() * 4 for t in (self.tables.spec, self.tables.irr, self.tables.lut))
+        return b
+
+
+class RenderPlan:
+    """All buffers for rendering `cams` (same resolution) of `scene`; run() is alloc-free."""
+
+    def __init__(self, scene: DeviceScene, cams, width, height, params=None, shade=True,
+                 gbuf=False, aux=False, pair_capacity=None, stream=None):
+        p = dict(DEFAULTS)
+        if params:
+            p.update(params)
+        self.scene = scene
+        self.W, self.H = int(width), int(height)
+        self.cams = cameras_tensor(cams, scene.device)
+        self.V = int(self.cams.shape[0])
+        self.params = F.make_params(scene.tex_res, **p)
+        self.ntx = (self.W + F.TILE - 1) // F.TILE
+        self.nty = (self.H + F.TILE - 1) // F.TILE
+        self.n_tiles = self.ntx * self.nty
+        dev, V, n = scene.device, self.V, scene.n
+        i32 = dict(device=dev, dtype=torch.int32)
+        self.rec = torch.empty(V * max(n, 1) * F.REC_FLOATS, device=dev, dtype=torch.float32)
+        self.rect = torch.empty(V * max(n, 1) * 4, **i32)
+        self.depth_key = torch.empty(V * max(n, 1), **i32)
+        ws_bytes = F.ts_workspace_size(F.TS_OP_BIN_SORT, V, n, self.W, self.H)
+        self.ws = torch.empty((ws_bytes + 3) // 4, **i32)
+        self.sorted_ids = torch.empty(V * max(n, 1), **i32)
+        self.tile_ranges = torch.empty(V * self.n_tiles * 2, **i32)
+        self.n_pairs = torch.zeros(1, device=dev, dtype=torch.int64)
+        self.status = torch.zeros(1, **i32)
+        self.shade = bool(shade) and scene.tables is not None
+        plane = V * self.H * self.W
+        self.rgba = torch.empty(plane * 4, device=dev, dtype=torch.float32) if self.shade else None
+        self.gbuf = torch.empty(plane * 8, device=dev, dtype=torch.float32) if (gbuf or not self.shade) else None
+        self.t_final = torch.empty(plane, device=dev, dtype=torch.float32) if (aux or gbuf or not self.shade) else None
+        self.n_contrib = torch.empty(plane, **i32) if aux else None
+        self.n_blend = torch.empty(plane, **i32) if aux else None
+        self.stream = stream
+        if pair_capacity is None:
+            self.pair_ids = torch.empty(1, **i32)
+            self.cap = 0
+            self._front()
+            torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+            need = int(self.n_pairs.item())
+            pair_capacity = need + need // 8 + 4096
+        self.cap = int(pair_capacity)
+        self.pair_ids = torch.empty(max(self.cap, 1), **i32)
+
+    def preprocess(self):
+        sc = self.scene
+        F.ts_preprocess(self.V, self.W, self.H, self.cams, self.params, sc.n, sc.means, sc.quats,
+                        sc.scales, sc.opac, sc.chart_of, self.rec, self.rect, self.depth_key,
+                        self.stream)
+
+    def bin_sort(self):
+        F.ts_bin_sort(self.V, self.W, self.H, self.scene.n, self.rect, self.depth_key, self.ws,
+                      self.cap, self.sorted_ids, self.tile_ranges, self.pair_ids, self.n_pairs,
+                      self.status, self.stream)
+
+    def _front(self):
+        self.preprocess()
+        self.bin_sort()
+
+    def raster(self):
+        sc = self.scene
+        env = sc.tables.struct if self.shade else None
+        F.ts_raster_fwd(self.V, self.W, self.H, self.cams, self.params, sc.n, self.rec,
+                        self.tile_ranges, self.pair_ids, self.cap, sc.atlas, env, self.rgba, self.gbuf,
+                        self.t_final, self.n_contrib, self.n_blend, self.stream)
+
+    def run(self):
+        """Enqueue preprocess, bin/sort and raster(+shade). No host synchronisation."""
+        self._front()
+        self.raster()
+
+    def check(self):
+        """Synchronise and verify the pair lists fit; returns the pair count."""
+        (self.stream or torch.cuda.current_stream()).synchronize()
+        if int(self.status.item()) != 0:
+            raise RuntimeError(f"pair capacity {self.cap} < {int(self.n_pairs.item())}")
+        return int(self.n_pairs.item())
+
+    def outputs(self):
+        V, H, W = self.V, self.H, self.W
+        out = {}
+        if self.rgba is not None:
+            out["rgba"] = self.rgba.view(V, H, W, 4)
+        if self.gbuf is not None:
+            out["gbuf"] = self.gbuf.view(V, 8, H, W)
+        if self.t_final is not None:
+            out["t_final"] = self.t_final.view(V, H, W)
+        if self.n_contrib is not None:
+            out["n_contrib"] = self.n_contrib.view(V, H, W)
+            out["n_blend"] = self.n_blend.view(V, H, W)
+        return out
+
+
+def render(scene: DeviceScene, cams, width, height, params=None, shade=True, gbuf=False,
+           aux=False):
+    """Render a batch of views; grows the pair capacity and re-runs if it overflowed."""
+    plan = RenderPlan(scene, cams, width, height, params, shade=shade, gbuf=gbuf, aux=aux)
+    plan.run()
+    (plan.stream or torch.cuda.current_stream()).synchronize()
+    if int(plan.status.item()) != 0:
+        plan = RenderPlan(scene, cams, width, height, params, shade=shade, gbuf=gbuf, aux=aux,
+                          pair_capacity=2 * int(plan.n_pairs.item()) + 4096)
+        plan.run()
+        plan.check()
+    out = plan.outputs()
+    out["plan"] = plan
+    return out

@@ -1,0 +1,240 @@
+"""HIP forward path against the FP64 oracle (run on an MI355X).
+
+Covers: shading tables, depth keys (bit-exact), the depth sort and tile lists (bit-exact
+against a CPU stable sort of the GPU's own keys and rectangles), G-buffers, alpha and shaded
+RGB per pixel, ragged and degenerate frames, and determinism."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import TOL_A, TOL_G, TOL_RGB, gather, pixel_match, sample_pixels
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _pkg():
+    import paper_2506_13348_amd as P
+    P._ffi.lib()
+    return P
+
+
+def _render(sc, cams, W, H, **kw):
+    P = _pkg()
+    ds = P.DeviceScene.from_dict(sc, device="cuda")
+    out = P.render(ds, cams, W, H, **kw)
+    torch.cuda.synchronize()
+    return ds, out
+
+
+def _print(name, info):
+    print(f"[{name}] " + " ".join(f"{k}={v}" for k, v in info.items()), flush=True)
+
+
+# ------------------------------------------------------------------------------- tables
+
+@pytest.mark.parametrize("r,levels", [(32, 1), (64, 4)])
+def test_env_tables_match_oracle(r, levels):
+    P = _pkg()
+    env = synth.make_env(np.random.default_rng(4), r)
+    tabs = P.EnvTables(env, levels, device="cuda", irr_res=16, lut_res=64, lut_samples=1024)
+    torch.cuda.synchronize()
+    ref_spec = oracle.prefilter(env, levels)
+    ref_irr = oracle.irradiance(env, 16)
+    got = tabs.spec_levels()
+    for l in range(levels):
+        g = got[l].double().cpu().numpy()
+        np.testing.assert_allclose(g, ref_spec[l], rtol=1e-6)
+    g_irr = tabs.irr.view(6, 16, 16, 4)[..., :3].double().cpu().numpy()
+    np.testing.assert_allclose(g_irr, ref_irr, rtol=1e-6)
+    ref_lut = oracle.brdf_lut(64, 1024)
+    np.testing.assert_allclose(tabs.lut.view(64, 64, 2).double().cpu().numpy(), ref_lut, rtol=1e-6, atol=1e-7)
+
+
+def test_brdf_lut_full_size():
+    P = _pkg()
+    lut = torch.empty(256 * 256 * 2, device="cuda")
+    P._ffi.ts_brdf_lut(256, 4096, lut)
+    ref = oracle.brdf_lut(256, 4096)
+    np.testing.assert_allclose(lut.view(256, 256, 2).double().cpu().numpy(), ref, rtol=1e-6, atol=1e-7)
+
+
+# ------------------------------------------------------------------ keys, sort, tile lists
+
+def _check_lists(plan, n):
+    V, nt = plan.V, plan.n_tiles
+    keys = plan.depth_key.view(V, -1)[:, :n].cpu().numpy().view(np.uint32)
+    rect = plan.rect.view(V, -1, 4)[:, :n].cpu().numpy()
+    sorted_ids = plan.sorted_ids.view(V, -1)[:, :n].cpu().numpy()
+    ranges = plan.tile_ranges.view(V, nt, 2).cpu().numpy()
+    npairs = int(plan.n_pairs.item())
+    pairs = plan.pair_ids[:npairs].cpu().numpy()
+    off = 0
+    for v in range(V):
+        order = np.argsort(keys[v], kind="stable")
+        np.testing.assert_array_equal(sorted_ids[v], order)
+        lists = [[] for _ in range(nt)]
+        for k in order:
+            x0, y0, x1, y1 = rect[v, k]
+            for ty in range(y0, y1):
+                for tx in range(x0, x1):
+                    lists[ty * plan.ntx + tx].append(k)
+        for t in range(nt):
+            s, e = ranges[v, t]
+            assert s == off, (v, t, s, off)
+            assert e - s == len(lists[t]), (v, t)
+            np.testing.assert_array_equal(pairs[s:e], np.asarray(lists[t], np.int32))
+            off = e
+    assert off == npairs
+
+
+def test_depth_keys_bit_exact_and_lists():
+    sc = synth.make_scene("shell2k")
+    cams = synth.orbit_cameras(3, 128, 96, dist=3.0, el_deg=15.0)
+    ds, out = _render(sc, cams, 128, 96)
+    plan = out["plan"]
+    keys = plan.depth_key.view(3, -1).cpu().numpy().view(np.uint32)
+    for v, cam in enumerate(cams):
+        d32, keep, _ = oracle.splat_setup(sc, cam)
+        drop = keys[v] == 0xFFFFFFFF
+        kept = ~drop
+        np.testing.assert_array_equal(keys[v][kept], d32[kept].view(np.uint32))
+        assert np.all(keep[kept])
+        assert np.all(~keep[drop] | (sc["opac"][drop] < 1 / 255))
+    _check_lists(plan, len(sc["opac"]))
+
+
+def test_lists_ragged_and_many_views():
+    sc = synth.make_scene("sq100k", n=3000, tex_res=4, env_res=16)
+    cams = synth.orbit_cameras(5, 75, 53, dist=2.6)
+    ds, out = _render(sc, cams, 75, 53)
+    _check_lists(out["plan"], 3000)
+
+
+# --------------------------------------------------------------------------- full frames
+
+def _frame_parity(sc, cam, out, v=0, pixels=None, name="frame", max_fail=0):
+    W, H = cam["width"], cam["height"]
+    if pixels is None:
+        pixels = oracle.all_pixels(W, H)
+    ref = oracle.render(sc, cam, pixels=pixels)
+    rgba, gb = gather(out, v, pixels)
+    ok, info = pixel_match(rgba, gb, ref)
+    if "n_blend" in out:
+        nb = out["n_blend"][v].cpu().numpy()[pixels[:, 1], pixels[:, 0]]
+        clear = ref["stat"][:, 2] == 0
+        info["n_blend_mismatch"] = int((nb[clear] != ref["stat"][clear, 0]).sum())
+        assert info["n_blend_mismatch"] == 0
+    _print(name, info)
+    bad = np.nonzero(~ok)[0][:5]
+    for b in bad:
+        print("  fail", pixels[b], "gpu", rgba[b], "ref", ref["rgba"][b], "stat", ref["stat"][b])
+    assert info["fail"] <= max_fail, info
+    # beyond the first-order G-buffer allowance, the strict 1e-4 holds on all but a few pixels
+    assert info["over_strict_rgb_tol"] <= max(2, 0.005 * info["pixels"]), info
+    return info
+
+
+def test_shell2k_full_frame():
+    """The 2,000-splat shell, 128x128, T = 4: every pixel."""
+    sc = synth.make_scene("shell2k")
+    cam = synth.config_cameras("shell2k")[0]
+    ds, out = _render(sc, [cam], 128, 128, gbuf=True, aux=True)
+    info = _frame_parity(sc, cam, out, name="shell2k")
+    assert info["ambiguous"] < 50
+
+
+def test_ragged_multi_view_frames():
+    sc = synth.make_scene("sq100k", n=4000, tex_res=8, env_res=32)
+    sc["env_levels"] = 3
+    cams = synth.orbit_cameras(3, 61, 47, dist=2.4, el_deg=30.0)
+    ds, out = _render(sc, cams, 61, 47, gbuf=True, aux=True)
+    for v in range(3):
+        _frame_parity(sc, cams[v], out, v=v, name=f"ragged v{v}")
+
+
+@pytest.mark.parametrize("T", [1, 2, 16])
+def test_texture_resolutions(T):
+    sc = synth.make_scene("shell2k", n=800, tex_res=T)
+    cam = synth.crop_camera(synth.config_cameras("shell2k")[0], 24, 24, 80, 80)
+    ds, out = _render(sc, [cam], 80, 80, gbuf=True)
+    _frame_parity(sc, cam, out, name=f"T={T}")
+
+
+def test_sq100k_full_size_sampled():
+    """100,000 splats on the superquadric, 800x800, T = 8, 128^2 env with 4 levels: two of the
+    64 orbit views at sampled pixels (all tiles are rendered; the oracle evaluates a sample)."""
+    sc = synth.make_scene("sq100k")
+    cams = synth.config_cameras("sq100k")
+    pick = [cams[0], cams[21]]
+    ds, out = _render(sc, pick, 800, 800)
+    rng = np.random.default_rng(0)
+    for v in range(2):
+        pix = sample_pixels(rng, 800, 800, 160)
+        _frame_parity(sc, pick[v], out, v=v, pixels=pix, name=f"sq100k v{v}")
+
+
+# ------------------------------------------------------------------------------- shading
+
+def test_shade_on_synthetic_gbuffer():
+    P = _pkg()
+    rng = np.random.default_rng(9)
+    V, H, W = 2, 40, 56
+    g, a = synth.random_gbuffer(rng, V, H, W)
+    env = synth.make_env(rng, 32)
+    tabs_g = P.EnvTables(env, 3, device="cuda")
+    cams = synth.orbit_cameras(V, W, H)
+    plan_cams = P.cameras_tensor(cams)
+    gb = torch.as_tensor(g).cuda().contiguous()
+    tf = torch.as_tensor(1.0 - a).cuda().contiguous()
+    rgba = torch.empty(V * H * W * 4, device="cuda")
+    prm = P._ffi.make_params(8)
+    P._ffi.ts_shade(V, W, H, plan_cams, prm, tabs_g.struct, gb, tf, rgba)
+    torch.cuda.synchronize()
+    rgba = rgba.view(V, H, W, 4).double().cpu().numpy()
+    tabs = oracle.tables(env, 3)
+    pix = oracle.all_pixels(W, H)
+    worst = 0.0
+    for v in range(V):
+        gg = g[v].reshape(8, -1).T.astype(np.float64)
+        aa = (1.0 - (1.0 - a[v].astype(np.float32))).reshape(-1).astype(np.float64)
+        ref, gap = oracle.shade_gbuffer(gg, aa, cams[v], pix, tabs)
+        got = rgba[v].reshape(-1, 4)
+        err = np.abs(got[:, :3] - ref).max(axis=1)
+        tie = gap < 1e-5
+        worst = max(worst, float(err[~tie].max()))
+        assert (err[~tie] <= TOL_RGB).all(), err.max()
+    print(f"[shade] max err {worst:.3e}")
+
+
+# ---------------------------------------------------------------------- degenerate input
+
+def test_empty_scene_and_all_behind():
+    sc = synth.make_scene("shell2k", n=50)
+    cam = synth.config_cameras("shell2k")[0]
+    empty = {k: (v[:0] if isinstance(v, np.ndarray) and v.shape[:1] == (50,) else v)
+             for k, v in sc.items()}
+    ds, out = _render(empty, [cam], 32, 32)
+    assert torch.all(out["rgba"][..., 3] == 0)
+    behind = dict(sc)
+    behind["means"] = sc["means"] + np.float32([0, 0, 10])
+    ds, out = _render(behind, [cam], 32, 32)
+    assert torch.all(out["rgba"][..., 3] == 0)
+    assert int(out["plan"].n_pairs.item()) == 0
+
+
+def test_one_pixel_frame():
+    sc = synth.make_scene("shell2k", n=500)
+    cam = synth.crop_camera(synth.config_cameras("shell2k")[0], 64, 64, 1, 1)
+    ds, out = _render(sc, [cam], 1, 1, gbuf=True)
+    _frame_parity(sc, cam, out, name="1x1")
+
+
+def test_deterministic():
+    sc = synth.make_scene("sq100k", n=5000, env_res=16)
+    cams = synth.orbit_cameras(2, 96, 80)
+    _, a = _render(sc, cams, 96, 80, gbuf=True, aux=True)
+    _, b = _render(sc, cams, 96, 80, gbuf=True, aux=True)
+    for k in ("rgba", "gbuf", "t_final", "n_contrib"):
+        assert torch.equal(a[k], b[k]), k
