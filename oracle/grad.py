@@ -1,0 +1,217 @@
+"""Gradient reference — TEST INFRASTRUCTURE ONLY.
+
+A dense float64 formulation of the same per-pixel definition as oracle.c (Sec. 3.1 Eq. 1-3,
+Sec. 3.2-3.3 Eq. 4-6, Sec. 3.5 Eq. 7-12), written with plain PyTorch CPU ops so that autograd
+gives the gradient of any scalar of the rendered RGBA with respect to the splat centres, the
+(unnormalised) quaternions, the linear scales, the opacities and the texels — the quantities
+the paper optimises (Sec. 3.6).
+
+Discrete decisions are taken from values and carry no gradient, exactly as in the forward
+definition: the near-plane drop, the hit in front of the camera, the square support, the alpha
+cut-off, the termination threshold (a splat blends iff the running transmittance after it
+stays >= t_min), the depth order (float32 depth, then index), the texel taps and the cube
+face. Everything continuous between those decisions is differentiated: alpha = min(alpha_max,
+o G) passes no gradient when clamped.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import DEFAULT_PARAMS, cam16
+
+DT = torch.float64
+
+
+def _quat_rot(q):
+    qn = q / q.norm(dim=1, keepdim=True)
+    w, x, y, z = qn.unbind(1)
+    R = torch.stack([
+        1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+        2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+        2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], 1)
+    return R.view(-1, 3, 3)
+
+
+def _cube_face(d):
+    """Face index and (sc, tc, ma) of directions d [M,3] (OpenGL major-axis rule)."""
+    ad = d.abs().detach()
+    ax, ay, az = ad[:, 0], ad[:, 1], ad[:, 2]
+    isx = (ax >= ay) & (ax >= az)
+    isy = (~isx) & (ay >= az)
+    isz = (~isx) & (~isy)
+    x, y, z = d[:, 0], d[:, 1], d[:, 2]
+    pos = torch.where(isx, x >= 0, torch.where(isy, y >= 0, z >= 0)).detach()
+    face = torch.where(isx, 0, torch.where(isy, 2, 4)) + (~pos).long()
+    sc = torch.where(face == 0, -z, torch.where(face == 1, z, torch.where(face == 5, -x, x)))
+    tc = torch.where(face <= 1, -y, torch.where(face == 2, z, torch.where(face == 3, -z, -y)))
+    ma = torch.where(isx, x.abs(), torch.where(isy, y.abs(), z.abs()))
+    return face, sc, tc, ma
+
+
+def _bilinear(flat, base, H, W, X, Y):
+    """Bilinear sample of images stored in flat [K, C] (row-major H x W each, image m starting
+    at row base[m]) at texel coordinates X, Y [M] (centres at integers), clamp-to-edge."""
+    x0 = torch.floor(X.detach())
+    y0 = torch.floor(Y.detach())
+    fx, fy = X - x0, Y - y0
+    i0 = x0.long().clamp(0, W - 1)
+    i1 = (x0.long() + 1).clamp(0, W - 1)
+    j0 = y0.long().clamp(0, H - 1)
+    j1 = (y0.long() + 1).clamp(0, H - 1)
+    v00, v10 = flat[base + j0 * W + i0], flat[base + j0 * W + i1]
+    v01, v11 = flat[base + j1 * W + i0], flat[base + j1 * W + i1]
+    fx, fy = fx[:, None], fy[:, None]
+    return (1 - fy) * ((1 - fx) * v00 + fx * v10) + fy * ((1 - fx) * v01 + fx * v11)
+
+
+def _cube_lookup(cube, d):
+    """cube [6, r, r, 3] float64 tensor, directions d [M,3] -> [M,3]."""
+    r = cube.shape[1]
+    face, sc, tc, ma = _cube_face(d)
+    X = 0.5 * (sc / ma + 1.0) * r - 0.5
+    Y = 0.5 * (tc / ma + 1.0) * r - 0.5
+    return _bilinear(cube.reshape(-1, 3), face * r * r, r, r, X, Y)
+
+
+def _shade(g, A, dirs, tabs, bg):
+    """Split-sum shading (Eq. 10-12) of blended maps g [P,8] with alpha A [P]."""
+    P = g.shape[0]
+    wo = -dirs / dirs.norm(dim=1, keepdim=True)
+    N = g[:, 5:8]
+    nn = N.norm(dim=1, keepdim=True)
+    zero = (nn[:, 0] == 0).detach()
+    Nh = torch.where(zero[:, None], wo, N / torch.where(zero[:, None], torch.ones_like(nn), nn))
+    ndv = (Nh * wo).sum(1)
+    wr = 2 * ndv[:, None] * Nh - wo
+    M, R = g[:, 3], g[:, 4]
+    irr = torch.as_tensor(tabs["irr"], dtype=DT)
+    E = _cube_lookup(irr, Nh)
+    levels = [torch.as_tensor(l, dtype=DT) for l in tabs["spec"]]
+    L = len(levels)
+    rc = R.clamp(0.0, 1.0)
+    lev = rc * (L - 1)
+    l0 = torch.floor(lev.detach()).long().clamp(max=L - 1)
+    l1 = (l0 + 1).clamp(max=L - 1)
+    fl = lev - l0.to(DT)
+    P0 = torch.zeros(P, 3, dtype=DT)
+    P1 = torch.zeros(P, 3, dtype=DT)
+    for l in range(L):
+        m0 = l0 == l
+        if m0.any():
+            P0 = P0.index_put((m0.nonzero()[:, 0],), _cube_lookup(levels[l], wr[m0]))
+        m1 = l1 == l
+        if m1.any():
+            P1 = P1.index_put((m1.nonzero()[:, 0],), _cube_lookup(levels[l], wr[m1]))
+    Lp = (1 - fl)[:, None] * P0 + fl[:, None] * P1
+    lut = torch.as_tensor(tabs["lut"], dtype=DT)
+    n = lut.shape[0]
+    x = ndv.clamp(0.0, 1.0) * n - 0.5
+    y = rc * n - 0.5
+    ab = _bilinear(lut.reshape(-1, 2), torch.zeros(P, dtype=torch.long), n, n, x, y)
+    F0 = 0.04 * (1 - M)[:, None] + g[:, 0:3] * M[:, None]
+    bgt = torch.as_tensor(bg, dtype=DT)[None]
+    C = (g[:, 0:3] / math.pi * (1 - M)[:, None] * E + Lp * (F0 * ab[:, 0:1] + ab[:, 1:2])
+         + (1 - A)[:, None] * bgt)
+    empty = (A <= 0).detach()
+    return torch.where(empty[:, None], bgt.expand(P, 3), C)
+
+
+def render_dense(means, quats, scales, opac, textures, chart_of, cam, pixels, tabs=None,
+                 params=None):
+    """Differentiable render of pixels [P,2]. Tensors are float64 (leaves may require grad).
+    Returns rgba [P,4] and gbuf [P,8] (albedo 3, metallic, roughness, normal 3)."""
+    p = dict(DEFAULT_PARAMS)
+    if params:
+        p.update(params)
+    f32 = lambda x: float(np.float32(x))
+    S, amin, amax, tmin, near = (f32(p[k]) for k in ("s_sigma", "alpha_min", "alpha_max",
+                                                      "t_min", "near_z"))
+    bg = [f32(b) for b in p["bg"]]
+    c = cam16(cam)
+    Wr = torch.as_tensor(c[:12].reshape(3, 4)[:, :3], dtype=DT)
+    t = torch.as_tensor(c[:12].reshape(3, 4)[:, 3], dtype=DT)
+    fx, fy, cx, cy = (float(v) for v in c[12:16])
+    o = -(Wr.T @ t)
+    R = _quat_rot(quats)
+    tu, tv, nrm = R[:, :, 0], R[:, :, 1], R[:, :, 2]
+    # depth (float32 key) and near-plane drop, from values
+    mu_np = means.detach().numpy()
+    Wn, tn = c[:12].reshape(3, 4)[:, :3], c[:12].reshape(3, 4)[:, 3]
+    z = Wn[2, 0] * mu_np[:, 0] + Wn[2, 1] * mu_np[:, 1] + Wn[2, 2] * mu_np[:, 2] + tn[2]
+    keep = torch.as_tensor(z > near)
+    order = np.lexsort((np.arange(len(z)), z.astype(np.float32)))
+    sigma = torch.where(((nrm * (o[None] - means)).sum(1) >= 0).detach(), 1.0, -1.0).to(DT)
+    pix = torch.as_tensor(np.asarray(pixels, np.float64))
+    dc = torch.stack([(pix[:, 0] + 0.5 - cx) / fx, (pix[:, 1] + 0.5 - cy) / fy,
+                      torch.ones(len(pix), dtype=DT)], 1)
+    dirs = dc @ Wr           # rows: R_c2w d_cam = Wr^T d_cam
+    # dense ray-plane intersection [P,N]
+    den = dirs @ nrm.T
+    mo = means - o[None]
+    num = (mo * nrm).sum(1)
+    safe = torch.where(den == 0, torch.ones_like(den), den)
+    lam = num[None] / safe
+    # P - mu = o + lam d - mu
+    rel_u = (o[None] @ tu.T - (means * tu).sum(1)[None]) + lam * (dirs @ tu.T)
+    rel_v = (o[None] @ tv.T - (means * tv).sum(1)[None]) + lam * (dirs @ tv.T)
+    u = rel_u / scales[None, :, 0]
+    v = rel_v / scales[None, :, 1]
+    valid = (keep[None] & (den != 0) & (lam > 0)).detach()
+    mabs = torch.maximum(u.abs(), v.abs()).detach()
+    valid &= mabs <= S
+    G = torch.exp(-0.5 * (u * u + v * v))
+    oG = opac[None] * G
+    alpha = torch.minimum(oG, torch.full_like(oG, amax))
+    include = valid & (alpha.detach() >= amin)
+    a_inc = torch.where(include, alpha, torch.zeros_like(alpha))
+    # depth order, termination from values
+    a_o = a_inc[:, order]
+    inc_o = include[:, order]
+    trans_after = torch.cumprod(1 - a_o.detach(), dim=1)
+    blended_o = inc_o & (trans_after >= tmin)
+    a_b = torch.where(blended_o, a_o, torch.zeros_like(a_o))
+    one_m = 1 - a_b
+    T_excl = torch.cat([torch.ones(len(pix), 1, dtype=DT), torch.cumprod(one_m, 1)[:, :-1]], 1)
+    w_o = a_b * T_excl
+    T_final = torch.prod(one_m, 1)
+    # texture on the blended pairs only
+    pi, ki = blended_o.nonzero(as_tuple=True)
+    k = torch.as_tensor(order)[ki]
+    uu, vv = u[pi, k], v[pi, k]
+    T = textures.shape[1]
+    X = (uu + S) / (2 * S) * T - 0.5
+    Y = (vv + S) / (2 * S) * T - 0.5
+    chart = torch.as_tensor(np.asarray(chart_of)).long()[k]
+    tx = _bilinear(textures.reshape(-1, 8), chart * T * T, T, T, X, Y)        # [B, 8]
+    nt = tx[:, 4:7]
+    ntl = nt.norm(dim=1, keepdim=True)
+    nth = torch.where(ntl > 0, nt / torch.where(ntl > 0, ntl, torch.ones_like(ntl)),
+                      torch.tensor([0.0, 0.0, 1.0], dtype=DT)[None])
+    nw = sigma[k][:, None] * torch.einsum("bij,bj->bi", R[k], nth)
+    x8 = torch.cat([tx[:, 0:3], tx[:, 7:8], tx[:, 3:4], nw], 1)
+    wb = w_o[pi, ki]
+    gbuf = torch.zeros(len(pix), 8, dtype=DT).index_add(0, pi, wb[:, None] * x8)
+    A = 1 - T_final
+    if tabs is None:
+        rgb = torch.zeros(len(pix), 3, dtype=DT)
+    else:
+        rgb = _shade(gbuf, A, dirs, tabs, bg)
+    rgba = torch.cat([rgb, A[:, None]], 1)
+    return rgba, gbuf
+
+
+def grads(scene, cam, pixels, d_rgba, tabs=None, params=None):
+    """Gradients of sum(d_rgba * rgba) w.r.t. means, quats, scales, opac and textures."""
+    leaves = {k: torch.tensor(np.asarray(scene[k], np.float32), dtype=DT, requires_grad=True)
+              for k in ("means", "quats", "scales", "opac", "textures")}
+    rgba, gbuf = render_dense(leaves["means"], leaves["quats"], leaves["scales"], leaves["opac"],
+                              leaves["textures"], scene["chart_of"], cam, pixels, tabs, params)
+    loss = (rgba * torch.as_tensor(np.asarray(d_rgba), dtype=DT)).sum()
+    loss.backward()
+    out = {k: leaves[k].grad.detach().numpy() for k in leaves}
+    out["rgba"] = rgba.detach().numpy()
+    out["gbuf"] = gbuf.detach().numpy()
+    return out
