@@ -184,6 +184,48 @@ int ts_shade(int32_t n_views, int32_t width, int32_t height, const ts_camera* ca
              const float* t_final, float* rgba, hipStream_t stream);
 
 /*
+ * ts_raster_bwd — gradients of a scalar loss L of the shaded output with respect to the
+ * splat parameters the paper optimises (Sec. 3.6): centres, rotations, scales, opacities and
+ * texels, for the frame rendered by ts_raster_fwd with the same arguments (G-buffers,
+ * t_final and n_contrib requested). Adjoint of Eq. 10-12 per pixel, then of the front-to-back
+ * blend (Eq. 8) back to front from each pixel's last blended splat with T_i recovered as
+ * T_{i+1}/(1-alpha_i), then of Eq. 2-7 and of the projection set-up. Gradients are w.r.t. the
+ * values passed (linear scales, opacities as given, unnormalised quaternions); nothing is
+ * accumulated with floating-point atomics and the result is run-to-run identical.
+ *
+ *   means, quats, scales, chart_of, rec, rect, tile_ranges, pair_ids, pair_capacity, atlas,
+ *   env      as given to ts_preprocess / ts_bin_sort / ts_raster_fwd
+ *   gbuf, t_final, n_contrib   forward outputs of the same frame
+ *   d_rgba   [n_views][H][W][4] dL/d(rgb, alpha)
+ *   ws       scratch, at least ts_raster_bwd_workspace(n_views, n, pair_capacity) bytes
+ *   partials scratch for per-(tile entry, 8x8 block) partial sums, partial_capacity floats;
+ *            if it is too small, *status is set to 2 and the gradients are incomplete
+ *            (re-run with a larger buffer). A frame needs about 24 + 8 * (texels touched)
+ *            floats per (entry, 8x8 block) with a blended pixel.
+ *   status   [1] int32 device word, set to 2 on partial-buffer overflow (never cleared here);
+ *            the gradient outputs are written only if it is 0 once the partials are built,
+ *            so a run that overflowed can be repeated with a larger buffer for any beta
+ *   partial_used [1] int64 device word or NULL: floats the frame asked for (also on overflow)
+ *   beta     0: overwrite the gradient outputs; 1: add to them
+ *   d_means [n,3], d_quats [n,4], d_scales [n,2], d_opac [n], d_atlas [n_charts][T][T][8] out
+ * Errors: TS_E_ARG, TS_E_WORKSPACE, TS_E_LAUNCH.
+ */
+int ts_raster_bwd(int32_t n_views, int32_t width, int32_t height, const ts_camera* cams,
+                  const ts_params* params, int32_t n, const float* means, const float* quats,
+                  const float* scales, const int32_t* chart_of, const float* rec,
+                  const int32_t* rect, const int32_t* tile_ranges, const int32_t* pair_ids,
+                  int64_t pair_capacity, const float* atlas, const ts_env* env,
+                  const float* gbuf, const float* t_final, const int32_t* n_contrib,
+                  const float* d_rgba, void* ws, size_t ws_bytes, float* partials,
+                  int64_t partial_capacity, int32_t* status, int64_t* partial_used, float beta,
+                  float* d_means,
+                  float* d_quats, float* d_scales, float* d_opac, float* d_atlas,
+                  hipStream_t stream);
+
+/* Scratch bytes ts_raster_bwd needs (host only). */
+int ts_raster_bwd_workspace(int32_t n_views, int32_t n, int64_t pair_capacity, size_t* bytes);
+
+/*
  * ts_brdf_lut — the split-sum BRDF table (Sec. 3.5.4 precomputed 2D lookup; split sum of
  * Karis 2013): texel (i,j) at N.V = (i+1/2)/n, roughness r = (j+1/2)/n holds
  *   A = mean_k (1 - Fc) G_vis,  B = mean_k Fc G_vis,

@@ -45,6 +45,13 @@ _SIGS = {
                       c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
     "ts_shade": [c_int32, c_int32, c_int32, c_void_p, ctypes.POINTER(TsParams),
                  ctypes.POINTER(TsEnv), c_void_p, c_void_p, c_void_p, c_void_p],
+    "ts_raster_bwd": [c_int32, c_int32, c_int32, c_void_p, ctypes.POINTER(TsParams), c_int32,
+                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                      c_void_p, c_int64, c_void_p, ctypes.POINTER(TsEnv), c_void_p, c_void_p,
+                      c_void_p, c_void_p, c_void_p, c_size_t, c_void_p, c_int64, c_void_p,
+                      c_void_p, c_float, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                      c_void_p],
+    "ts_raster_bwd_workspace": [c_int32, c_int32, c_int64, ctypes.POINTER(c_size_t)],
     "ts_brdf_lut": [c_int32, c_int32, c_void_p, c_void_p],
     "ts_env_tables": [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p],
     "ts_atlas_pack": [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p],
@@ -149,6 +156,28 @@ def ts_raster_fwd(n_views, width, height, cams, params, n, rec, tile_ranges, pai
                                ptr(gbuf), ptr(t_final), ptr(n_contrib), ptr(n_blend),
                                stream_handle(stream)),
            "ts_raster_fwd")
+
+
+def ts_raster_bwd_workspace(n_views, n, pair_capacity):
+    out = c_size_t(0)
+    _check(lib().ts_raster_bwd_workspace(n_views, n, pair_capacity, ctypes.byref(out)),
+           "ts_raster_bwd_workspace")
+    return int(out.value)
+
+
+def ts_raster_bwd(n_views, width, height, cams, params, n, means, quats, scales, chart_of, rec,
+                  rect, tile_ranges, pair_ids, pair_capacity, atlas, env, gbuf, t_final,
+                  n_contrib, d_rgba, ws, partials, status, partial_used, beta, d_means, d_quats,
+                  d_scales, d_opac, d_atlas, stream=None):
+    _check(lib().ts_raster_bwd(n_views, width, height, ptr(cams), ctypes.byref(params), n,
+                               ptr(means), ptr(quats), ptr(scales), ptr(chart_of), ptr(rec),
+                               ptr(rect), ptr(tile_ranges), ptr(pair_ids), pair_capacity,
+                               ptr(atlas), ctypes.byref(env), ptr(gbuf), ptr(t_final),
+                               ptr(n_contrib), ptr(d_rgba), ptr(ws), ws.numel() * ws.element_size(),
+                               ptr(partials), partials.numel(), ptr(status), ptr(partial_used),
+                               float(beta),
+                               ptr(d_means), ptr(d_quats), ptr(d_scales), ptr(d_opac),
+                               ptr(d_atlas), stream_handle(stream)), "ts_raster_bwd")
 
 
 def ts_shade(n_views, width, height, cams, params, env, gbuf, t_final, rgba, stream=None):

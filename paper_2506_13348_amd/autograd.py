@@ -1,0 +1,90 @@
+"""torch.autograd.Function over ts_raster_fwd / ts_raster_bwd.
+
+`render_rgba(means, quats, scales, opac, atlas, chart_of, cams, width, height, tables)` renders
+a batch of views and, under autograd, returns gradients for the five splat tensors from the
+hand-written HIP backward (deterministic, no floating-point atomics). Python here allocates
+buffers and enqueues the C entry points; it performs none of the rendering arithmetic."""
+from __future__ import annotations
+
+from types import SimpleNamespace
+
+import torch
+
+from . import _ffi as F
+from .render import RenderPlan
+
+
+class _SceneView(SimpleNamespace):
+    pass
+
+
+def _scene_view(means, quats, scales, opac, atlas, chart_of, tables):
+    return _SceneView(device=means.device, n=int(means.shape[0]), tex_res=int(atlas.shape[1]),
+                      means=means.contiguous(), quats=quats.contiguous(),
+                      scales=scales.contiguous(), opac=opac.contiguous(),
+                      atlas=atlas.contiguous(), chart_of=chart_of.contiguous(), tables=tables)
+
+
+class BackwardRunner:
+    """Workspace and partial buffer of ts_raster_bwd for one render plan, grown on demand."""
+
+    def __init__(self, plan: RenderPlan, partial_floats=None):
+        self.plan = plan
+        dev = plan.scene.device
+        ws = F.ts_raster_bwd_workspace(plan.V, plan.scene.n, plan.cap)
+        self.ws = torch.empty((ws + 7) // 8, device=dev, dtype=torch.int64)
+        if partial_floats is None:
+            partial_floats = max(1 << 20, 64 * max(plan.cap, 1))
+        self.partials = torch.empty(int(partial_floats), device=dev, dtype=torch.float32)
+        self.status = torch.zeros(1, device=dev, dtype=torch.int32)
+        self.used = torch.zeros(1, device=dev, dtype=torch.int64)
+
+    def run(self, d_rgba, grads, beta=0.0, retry=True):
+        p, sc = self.plan, self.plan.scene
+        d_means, d_quats, d_scales, d_opac, d_atlas = grads
+        for attempt in range(2):
+            self.status.zero_()
+            F.ts_raster_bwd(p.V, p.W, p.H, p.cams, p.params, sc.n, sc.means, sc.quats, sc.scales,
+                            sc.chart_of, p.rec, p.rect, p.tile_ranges, p.pair_ids, p.cap,
+                            sc.atlas, sc.tables.struct, p.gbuf, p.t_final, p.n_contrib,
+                            d_rgba.contiguous(), self.ws, self.partials, self.status, self.used,
+                            beta, d_means, d_quats, d_scales, d_opac, d_atlas, p.stream)
+            if not retry:
+                return
+            if int(self.status.item()) == 0:
+                return
+            # the counter reports what the frame needed: size to it and run again
+            need = int(self.used.item())
+            self.partials = torch.empty(need + need // 16 + 4096, device=self.partials.device,
+                                        dtype=torch.float32)
+        raise RuntimeError("ts_raster_bwd: partial buffer overflow after resizing")
+
+
+class TexSplatRender(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, means, quats, scales, opac, atlas, chart_of, cams, width, height, tables,
+                params):
+        sv = _scene_view(means.detach(), quats.detach(), scales.detach(), opac.detach(),
+                         atlas.detach(), chart_of, tables)
+        plan = RenderPlan(sv, cams, width, height, params, shade=True, gbuf=True, aux=True)
+        plan.run()
+        plan.check()
+        ctx.plan = plan
+        return plan.rgba.view(plan.V, plan.H, plan.W, 4).clone()
+
+    @staticmethod
+    def backward(ctx, d_rgba):
+        plan = ctx.plan
+        sc = plan.scene
+        grads = (torch.empty_like(sc.means), torch.empty_like(sc.quats),
+                 torch.empty_like(sc.scales), torch.empty_like(sc.opac),
+                 torch.empty_like(sc.atlas))
+        BackwardRunner(plan).run(d_rgba.contiguous(), grads)
+        return (*grads, None, None, None, None, None, None)
+
+
+def render_rgba(means, quats, scales, opac, atlas, chart_of, cams, width, height, tables,
+                params=None):
+    """[V,H,W,4] shaded RGBA + alpha, differentiable w.r.t. the first five tensors."""
+    return TexSplatRender.apply(means, quats, scales, opac, atlas, chart_of, cams, width, height,
+                                tables, params)

@@ -165,7 +165,7 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
             for (int i = 0; i < 9; i++) sR[i] = (float)(sigma * R[i]);
             r4[4] = make_float4(sR[0], sR[1], sR[2], sR[3]);
             r4[5] = make_float4(sR[4], sR[5], sR[6], sR[7]);
-            r4[6] = make_float4(sR[8], __int_as_float(a.chart_of[k]), 0.f, 0.f);
+            r4[6] = make_float4(sR[8], __int_as_float(a.chart_of[k]), (float)px_lo, (float)py_lo);
         }
     }
     a.rect[(int64_t)v * a.n + k] = rect_out;

@@ -12,6 +12,7 @@
 // on the primitive's T x T texels in the atlas at s = (u+S)/(2S), t = (v+S)/(2S), texel
 // centres at (i+1/2)/T, clamp-to-edge within the chart; the tangent normal is normalised and
 // rotated by sigma R (Eq. 7); the eight G-buffer channels accumulate with w = alpha T.
+#include "eval.h"
 #include "shade.h"
 #include "ts_internal.h"
 
@@ -82,17 +83,9 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
                 const float4* r = srec + j * kRec4;
                 float4 bb = r[0];
                 if (bb.z < fbx0 || bb.x > fbx1 || bb.w < fby0 || bb.y > fby1) continue;
-                float4 c1 = r[1], c2 = r[2], c3 = r[3];
-                float dx = X - c1.x, dy = Y - c1.y;
-                float nu = fmaf(c1.z, dx, fmaf(c1.w, dy, c2.x));
-                float nv = fmaf(c2.y, dx, fmaf(c2.z, dy, c2.w));
-                float den = fmaf(c3.x, dx, fmaf(c3.y, dy, c3.z));
-                float inv = 1.0f / den;
-                float u = nu * inv, vv = nv * inv;
-                float m = fmaxf(fabsf(u), fabsf(vv));
-                float G = __expf(-0.5f * fmaf(u, u, vv * vv));
-                float alpha = fminf(a.amax, c3.w * G);
-                bool ok = !done && den > 0.f && m <= a.S && alpha >= a.amin;
+                SplatEval e = eval_splat(r, X, Y, a.S, a.amin, a.amax);
+                float u = e.u, vv = e.v, alpha = e.alpha;
+                bool ok = !done && e.hit;
                 float Tn = Tr * (1.0f - alpha);
                 if (ok && Tn < a.tmin) {
                     done = true;

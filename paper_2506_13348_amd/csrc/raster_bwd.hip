@@ -1,0 +1,641 @@
+// ts_raster_bwd: gradients of a loss on the shaded RGBA with respect to the splat centres,
+// rotations (unnormalised quaternions), scales, opacities and atlas texels (the parameters the
+// paper optimises end to end, Sec. 3.6).
+//
+// 1. k_bwd_pairs: per (view, tile) list entry, the entry's index among its splat's tiles
+//    (splat-major map of the tile lists) and an empty slot per (entry, quadrant).
+// 2. k_raster_bwd: per tile, per pixel: the adjoint of the shading (dL/dX for the 8 G-buffer
+//    channels, dL/dT), then the tile list back to front from the pixel's last blended splat,
+//    recovering T_i = T_{i+1} / (1 - alpha_i), with
+//        dL/dalpha_i = T_i (g . x_i) - (sum_{j>i} w_j g . x_j + dL/dT_final T_final) / (1 - alpha_i)
+//    and the chain through alpha = o G(u,v), the bilinear texture sample at (u,v), the normal
+//    normalisation and rotation (Eq. 2-9), down to the 9 coefficients of the closed-form (u,v),
+//    the opacity and sigma R. Each wave (8x8 pixels) sums its pixels' contributions for one
+//    splat in a fixed lane order and writes one partial — 19 geometric values and the window
+//    of texels it touched — into a slot of a partial buffer. No value is accumulated with
+//    atomics; a single integer atomic hands out slot space.
+// 3. k_bwd_gather: per splat, the partials of its (view, tile, quadrant) entries summed in a
+//    fixed order -> per-view record gradients and the splat's texel gradients.
+// 4. k_bwd_params: per splat, in double precision, the record gradients of every view chained
+//    through the projection set-up to the splat parameters.
+#include "eval.h"
+#include "shade_bwd.h"
+#include "ts_internal.h"
+
+namespace ts {
+
+constexpr int kGeo = 19;          // px py ux uy vx vy wx wy w0 opacity sR[9]
+constexpr int kHdr = 24;          // floats in a partial's header: 19 geometric + window i0 j0 wi wj + pad
+constexpr int kBwdBatch = 128;
+constexpr int kEnt = 36;          // LDS floats per lane entry: taps (4 ints), fx, fy, q[8], pad 2, geo[19], pad 1
+
+struct BwdArgs {
+    int V, W, H, ntx, n_tiles, T, n;
+    const ts_camera* cams;
+    float S, amin, amax, tmin;
+    ShadeConst sc;
+    EnvDev env;
+    const float4* rec;
+    const int2* ranges;
+    const int32_t* pair_ids;
+    int64_t cap;
+    const float4* atlas;
+    const float* gbuf;
+    const float* t_final;
+    const int32_t* n_contrib;
+    const float4* d_rgba;
+    int32_t* slots;          // [cap][4]
+    float* part;             // partial buffer
+    int64_t part_cap;        // floats
+    unsigned long long* part_top;
+    int32_t* status;
+};
+
+__device__ inline float wave_min_f(float v) {
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ inline int wave_min_i(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ inline int wave_max_i(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
+    __shared__ float4 srec[kBwdBatch * kRec4];
+    __shared__ float ent[4][kWave * kEnt];
+    __shared__ int smax[4];
+    const int g = gridDim.x;
+    const int bid = xcd_remap(blockIdx.x, g);
+    const int v = bid / a.n_tiles;
+    const int t = bid - v * a.n_tiles;
+    const int tx = t % a.ntx, ty = t / a.ntx;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int bx = tx * kTile + (w & 1) * 8, by = ty * kTile + (w >> 1) * 8;
+    const int x = bx + (lane & 7), y = by + (lane >> 3);
+    const bool inside = x < a.W && y < a.H;
+    const float X = (float)x + 0.5f, Y = (float)y + 0.5f;
+    const float fbx0 = (float)bx, fbx1 = (float)(bx + 7), fby0 = (float)by, fby1 = (float)(by + 7);
+    int2 range = a.ranges[(int64_t)v * a.n_tiles + t];
+    range.x = (int)min((int64_t)range.x, a.cap);
+    range.y = (int)min((int64_t)range.y, a.cap);
+    const int T = a.T;
+    const float tscale = (float)T / (2.0f * a.S);
+    const float toff = 0.5f * (float)T - 0.5f;
+    const int chart4 = T * T * 2;
+    float* E = ent[w];
+
+    // per-pixel adjoint of the shading
+    int64_t pix = ((int64_t)v * a.H + (inside ? y : 0)) * a.W + (inside ? x : 0);
+    int64_t plane = (int64_t)a.H * a.W;
+    float gx[8];
+    float Tf = 1.f, dLdTf = 0.f;
+    int my_last = 0;
+    if (inside) {
+        float gb[8];
+        const float* gp = a.gbuf + (int64_t)v * 8 * plane + (int64_t)y * a.W + x;
+#pragma unroll
+        for (int c = 0; c < 8; c++) gb[c] = gp[c * plane];
+        Tf = a.t_final[pix];
+        my_last = a.n_contrib[pix];
+        float4 dC = a.d_rgba[pix];
+        float3 dray = pixel_ray(a.cams[v], X, Y);
+        float dT = shade_pixel_bwd(a.env, a.sc, gb, Tf, dray, make_float3(dC.x, dC.y, dC.z), gx);
+        dLdTf = dT - dC.w;   // A = 1 - T_final
+    } else {
+#pragma unroll
+        for (int c = 0; c < 8; c++) gx[c] = 0.f;
+    }
+    int wmax = wave_max_i(my_last);
+    if (lane == 0) smax[w] = wmax;
+    __syncthreads();
+    int tile_max = max(max(smax[0], smax[1]), max(smax[2], smax[3]));
+    float Tr = Tf;
+    float accum = 0.f;
+
+    for (int bend = tile_max; bend > 0; bend -= kBwdBatch) {
+        int bstart = max(0, bend - kBwdBatch);
+        int nb = bend - bstart;
+        __syncthreads();
+        if (tid < nb) {
+            int id = a.pair_ids[range.x + bstart + tid];
+            const float4* src = a.rec + ((int64_t)v * a.n + id) * kRec4;
+#pragma unroll
+            for (int q = 0; q < kRec4; q++) srec[tid * kRec4 + q] = src[q];
+        }
+        __syncthreads();
+        int jtop = min(nb, wmax - bstart);
+        for (int j = jtop - 1; j >= 0; j--) {
+            const float4* r = srec + j * kRec4;
+            float4 bb = r[0];
+            if (bb.z < fbx0 || bb.x > fbx1 || bb.w < fby0 || bb.y > fby1) continue;
+            int pos = bstart + j;
+            SplatEval ev = eval_splat(r, X, Y, a.S, a.amin, a.amax);
+            float u = ev.u, vv = ev.v, alpha = ev.alpha, oG = ev.oG, G = ev.G, inv = ev.inv;
+            bool bl = inside && pos < my_last && ev.hit;
+            uint64_t blm = __ballot(bl);
+            if (blm == 0) continue;
+            float geo[kGeo];
+            if (bl) {
+                float4 c1 = r[1], c2 = r[2], c3 = r[3], c4 = r[4], c5 = r[5], c6 = r[6];
+                int chart = __float_as_int(c6.y);
+                // offsets from the exact projected centre (head + low part)
+                float dx = ev.dx - c6.z, dy = ev.dy - c6.w;
+                float sx = fmaf(u, tscale, toff), sy = fmaf(vv, tscale, toff);
+                float fx0 = floorf(sx), fy0 = floorf(sy);
+                float fx = sx - fx0, fy = sy - fy0;
+                int i0 = (int)fx0, j0 = (int)fy0;
+                int i1 = min(max(i0 + 1, 0), T - 1), j1 = min(max(j0 + 1, 0), T - 1);
+                i0 = min(max(i0, 0), T - 1);
+                j0 = min(max(j0, 0), T - 1);
+                const float4* tb = a.atlas + (int64_t)chart * chart4;
+                float4 p00 = tb[(j0 * T + i0) * 2], q00 = tb[(j0 * T + i0) * 2 + 1];
+                float4 p10 = tb[(j0 * T + i1) * 2], q10 = tb[(j0 * T + i1) * 2 + 1];
+                float4 p01 = tb[(j1 * T + i0) * 2], q01 = tb[(j1 * T + i0) * 2 + 1];
+                float4 p11 = tb[(j1 * T + i1) * 2], q11 = tb[(j1 * T + i1) * 2 + 1];
+                float v00[8] = {p00.x, p00.y, p00.z, p00.w, q00.x, q00.y, q00.z, q00.w};
+                float v10[8] = {p10.x, p10.y, p10.z, p10.w, q10.x, q10.y, q10.z, q10.w};
+                float v01[8] = {p01.x, p01.y, p01.z, p01.w, q01.x, q01.y, q01.z, q01.w};
+                float v11[8] = {p11.x, p11.y, p11.z, p11.w, q11.x, q11.y, q11.z, q11.w};
+                float w00 = (1.f - fx) * (1.f - fy), w10 = fx * (1.f - fy);
+                float w01 = (1.f - fx) * fy, w11 = fx * fy;
+                float tv[8], dtX[8], dtY[8];
+#pragma unroll
+                for (int c = 0; c < 8; c++) {
+                    tv[c] = w00 * v00[c] + w10 * v10[c] + w01 * v01[c] + w11 * v11[c];
+                    dtX[c] = (1.f - fy) * (v10[c] - v00[c]) + fy * (v11[c] - v01[c]);
+                    dtY[c] = (1.f - fx) * (v01[c] - v00[c]) + fx * (v11[c] - v10[c]);
+                }
+                float nl = tv[4] * tv[4] + tv[5] * tv[5] + tv[6] * tv[6];
+                float nh[3], il = 0.f;
+                bool hasn = nl > 0.f;
+                if (hasn) {
+                    il = rsqrtf(nl);
+                    nh[0] = tv[4] * il; nh[1] = tv[5] * il; nh[2] = tv[6] * il;
+                } else {
+                    nh[0] = 0.f; nh[1] = 0.f; nh[2] = 1.f;
+                }
+                float sR[9] = {c4.x, c4.y, c4.z, c4.w, c5.x, c5.y, c5.z, c5.w, c6.x};
+                float nw[3];
+                for (int i = 0; i < 3; i++) nw[i] = sR[3 * i] * nh[0] + sR[3 * i + 1] * nh[1] + sR[3 * i + 2] * nh[2];
+                // transmittance before this splat and dL/dalpha
+                float Tb = Tr / (1.0f - alpha);
+                float wgt = alpha * Tb;
+                float cdot = gx[0] * tv[0] + gx[1] * tv[1] + gx[2] * tv[2] + gx[3] * tv[7] +
+                             gx[4] * tv[3] + gx[5] * nw[0] + gx[6] * nw[1] + gx[7] * nw[2];
+                float dalpha = Tb * cdot - (accum + dLdTf * Tf) / (1.0f - alpha);
+                accum = fmaf(wgt, cdot, accum);
+                Tr = Tb;
+                // texture-sample gradients q[8] (channel order of the texels)
+                float q[8];
+                q[0] = wgt * gx[0]; q[1] = wgt * gx[1]; q[2] = wgt * gx[2];
+                q[3] = wgt * gx[4];                     // roughness
+                q[7] = wgt * gx[3];                     // metallic
+                float dnw[3] = {wgt * gx[5], wgt * gx[6], wgt * gx[7]};
+                float dnh[3];
+                for (int k = 0; k < 3; k++) dnh[k] = sR[k] * dnw[0] + sR[3 + k] * dnw[1] + sR[6 + k] * dnw[2];
+                if (hasn) {
+                    float pp = nh[0] * dnh[0] + nh[1] * dnh[1] + nh[2] * dnh[2];
+                    q[4] = (dnh[0] - nh[0] * pp) * il;
+                    q[5] = (dnh[1] - nh[1] * pp) * il;
+                    q[6] = (dnh[2] - nh[2] * pp) * il;
+                } else {
+                    q[4] = q[5] = q[6] = 0.f;
+                }
+                // d(sigma R): outer(dnw, nh)
+                for (int i = 0; i < 3; i++)
+                    for (int k = 0; k < 3; k++) geo[10 + 3 * i + k] = dnw[i] * nh[k];
+                // (u,v) through alpha and through the texture coordinates
+                float gu = 0.f, gv = 0.f, go = 0.f;
+                if (oG < a.amax) {
+                    go = dalpha * G;
+                    gu = -dalpha * oG * u;
+                    gv = -dalpha * oG * vv;
+                }
+                float gX = 0.f, gY = 0.f;
+#pragma unroll
+                for (int c = 0; c < 8; c++) {
+                    gX = fmaf(q[c], dtX[c], gX);
+                    gY = fmaf(q[c], dtY[c], gY);
+                }
+                gu = fmaf(gX, tscale, gu);
+                gv = fmaf(gY, tscale, gv);
+                // (u,v) = (ux dx + uy dy, vx dx + vy dy) / (wx dx + wy dy + w0), dx = X - px
+                float e = -(gu * u + gv * vv) * inv;
+                geo[2] = gu * dx * inv;                 // ux
+                geo[3] = gu * dy * inv;                 // uy
+                geo[4] = gv * dx * inv;                 // vx
+                geo[5] = gv * dy * inv;                 // vy
+                geo[6] = e * dx;                        // wx
+                geo[7] = e * dy;                        // wy
+                geo[8] = e;                             // w0
+                geo[0] = -(gu * c1.z + gv * c2.y) * inv - e * c3.x;   // px
+                geo[1] = -(gu * c1.w + gv * c2.z) * inv - e * c3.y;   // py
+                geo[9] = go;                            // opacity
+                // lane entry
+                float* me = E + lane * kEnt;
+                me[0] = __int_as_float(i0); me[1] = __int_as_float(i1);
+                me[2] = __int_as_float(j0); me[3] = __int_as_float(j1);
+                me[4] = fx; me[5] = fy;
+#pragma unroll
+                for (int c = 0; c < 8; c++) me[6 + c] = q[c];
+#pragma unroll
+                for (int k = 0; k < kGeo; k++) me[16 + k] = geo[k];
+            }
+            // window of texels touched by this wave
+            int bi0 = bl ? __float_as_int(E[lane * kEnt + 0]) : 0x7fffffff;
+            int bj0 = bl ? __float_as_int(E[lane * kEnt + 2]) : 0x7fffffff;
+            int bi1 = bl ? __float_as_int(E[lane * kEnt + 1]) : -1;
+            int bj1 = bl ? __float_as_int(E[lane * kEnt + 3]) : -1;
+            int wi0 = wave_min_i(bi0), wj0 = wave_min_i(bj0);
+            int wi1 = wave_max_i(bi1), wj1 = wave_max_i(bj1);
+            int wi = wi1 - wi0 + 1, wj = wj1 - wj0 + 1, wt = wi * wj;
+            int64_t need = kHdr + (int64_t)wt * 8;
+            unsigned long long off = 0;
+            if (lane == 0) off = atomicAdd(a.part_top, (unsigned long long)need);
+            off = __shfl(off, 0);
+            bool fits = (int64_t)off + need <= a.part_cap;
+            int64_t slot_idx = ((int64_t)range.x + pos) * 4 + w;
+            if (!fits) {
+                if (lane == 0) {
+                    a.status[0] = 2;
+                    a.slots[slot_idx] = -1;
+                }
+                continue;
+            }
+            float* dst = a.part + off;
+            // geometric sums, lanes 0..18, blended lanes in ascending order
+            float gsum = 0.f;
+            // texel windows: lane owns texels lane, lane+64, ...
+            for (int t0 = 0; t0 < wt; t0 += kWave) {
+                int tt = t0 + lane;
+                int ti = wi0 + (tt % wi), tj = wj0 + (tt / wi);
+                float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                uint64_t mm = blm;
+                while (mm) {
+                    int p = __builtin_ctzll(mm);
+                    mm &= mm - 1;
+                    const float* pe = E + p * kEnt;
+                    int pi0 = __float_as_int(pe[0]), pi1 = __float_as_int(pe[1]);
+                    int pj0 = __float_as_int(pe[2]), pj1 = __float_as_int(pe[3]);
+                    float pfx = pe[4], pfy = pe[5];
+                    float wxp = (ti == pi0 ? 1.f - pfx : 0.f) + (ti == pi1 ? pfx : 0.f);
+                    float wyp = (tj == pj0 ? 1.f - pfy : 0.f) + (tj == pj1 ? pfy : 0.f);
+                    float wq = wxp * wyp;
+#pragma unroll
+                    for (int c = 0; c < 8; c++) acc[c] = fmaf(wq, pe[6 + c], acc[c]);
+                    if (t0 == 0 && lane < kGeo) gsum += pe[16 + lane];
+                }
+                if (tt < wt) {
+                    float4* d4 = (float4*)(dst + kHdr + (int64_t)tt * 8);
+                    d4[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+                    d4[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+                }
+            }
+            if (lane < kGeo) dst[lane] = gsum;
+            if (lane == kGeo) {
+                dst[kGeo + 0] = __int_as_float(wi0);
+                dst[kGeo + 1] = __int_as_float(wj0);
+                dst[kGeo + 2] = __int_as_float(wi);
+                dst[kGeo + 3] = __int_as_float(wj);
+                dst[kGeo + 4] = 0.f;
+            }
+            if (lane == 0) a.slots[slot_idx] = (int32_t)(off / 8);
+        }
+    }
+}
+
+// Splat-major index of the tile lists: for list entry p of tile (tx,ty) holding splat s,
+// pair_pos[start[v][s] + k] = p with k the tile's row-major index inside rect(s); slots of
+// every entry start empty.
+__global__ __launch_bounds__(256) void k_bwd_pairs(int V, int n, int ntx, int n_tiles,
+                                                   const int2* __restrict__ ranges, int64_t cap,
+                                                   const int32_t* __restrict__ pair_ids,
+                                                   const int4* __restrict__ rect,
+                                                   const int64_t* __restrict__ start,
+                                                   int32_t* __restrict__ pair_pos,
+                                                   int32_t* __restrict__ slots) {
+    int vt = blockIdx.x;
+    int v = vt / n_tiles, t = vt % n_tiles;
+    int tx = t % ntx, ty = t / ntx;
+    int2 rg = ranges[vt];
+    int64_t s0 = min((int64_t)rg.x, cap), s1 = min((int64_t)rg.y, cap);
+    for (int64_t p = s0 + threadIdx.x; p < s1; p += blockDim.x) {
+        int s = pair_ids[p];
+        int4 r = rect[(int64_t)v * n + s];
+        int k = (ty - r.y) * (r.z - r.x) + (tx - r.x);
+        pair_pos[start[(int64_t)v * n + s] + k] = (int32_t)p;
+        int4* sl = (int4*)(slots + p * 4);
+        *sl = make_int4(-1, -1, -1, -1);
+    }
+}
+
+// Exclusive scan of rect areas over (view, splat) -> start offsets (int64), single block.
+__global__ __launch_bounds__(1024) void k_area_scan(const int4* __restrict__ rect, int64_t m,
+                                                    int64_t* __restrict__ start) {
+    __shared__ int64_t part[1024];
+    int tid = threadIdx.x;
+    int64_t per = (m + 1023) / 1024;
+    int64_t a0 = tid * per, a1 = min(m, a0 + per);
+    int64_t sum = 0;
+    for (int64_t i = a0; i < a1; i++) {
+        int4 r = rect[i];
+        sum += (int64_t)max(r.z - r.x, 0) * max(r.w - r.y, 0);
+    }
+    part[tid] = sum;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        int64_t x = tid >= o ? part[tid - o] : 0;
+        __syncthreads();
+        part[tid] += x;
+        __syncthreads();
+    }
+    int64_t run = part[tid] - sum;
+    for (int64_t i = a0; i < a1; i++) {
+        start[i] = run;
+        int4 r = rect[i];
+        run += (int64_t)max(r.z - r.x, 0) * max(r.w - r.y, 0);
+    }
+}
+
+__global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
+__global__ void k_copy_u64(const unsigned long long* src, int64_t* dst) { *dst = (int64_t)*src; }
+
+// One wave per splat: views in order, tiles of rect(s) in row-major order, quadrants 0..3.
+// Lane l owns texels l, l+64, ... of the splat's chart; one pass over the partials per group
+// of 64 texels.
+__global__ __launch_bounds__(64) void k_bwd_gather(int V, int n, int T, const int4* __restrict__ rect,
+                                                   const int64_t* __restrict__ start,
+                                                   const int32_t* __restrict__ pair_pos,
+                                                   const int32_t* __restrict__ slots,
+                                                   const float* __restrict__ part,
+                                                   const int32_t* __restrict__ chart_of,
+                                                   const int32_t* __restrict__ status,
+                                                   float beta, float* __restrict__ rec_grad,
+                                                   float* __restrict__ d_atlas) {
+    if (status[0] != 0) return;   // incomplete partials: leave the outputs untouched
+    int s = blockIdx.x, lane = threadIdx.x;
+    int TT = T * T;
+    float4* dst = (float4*)(d_atlas + (int64_t)chart_of[s] * TT * 8);
+    for (int t0 = 0; t0 < TT; t0 += kWave) {
+        int tt = t0 + lane;
+        int ti = tt % T, tj = tt / T;
+        float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        for (int v = 0; v < V; v++) {
+            int4 r = rect[(int64_t)v * n + s];
+            int cnt = max(r.z - r.x, 0) * max(r.w - r.y, 0);
+            int64_t st = start[(int64_t)v * n + s];
+            float gs = 0.f;
+            for (int k = 0; k < cnt; k++) {
+                int p = pair_pos[st + k];
+                for (int q = 0; q < 4; q++) {
+                    int sl = slots[(int64_t)p * 4 + q];
+                    if (sl < 0) continue;
+                    const float* src = part + (int64_t)sl * 8;
+                    if (t0 == 0 && lane < kGeo) gs += src[lane];
+                    int wi0 = __float_as_int(src[kGeo + 0]), wj0 = __float_as_int(src[kGeo + 1]);
+                    int wi = __float_as_int(src[kGeo + 2]), wj = __float_as_int(src[kGeo + 3]);
+                    int li = ti - wi0, lj = tj - wj0;
+                    if (tt < TT && li >= 0 && lj >= 0 && li < wi && lj < wj) {
+                        const float4* s4 = (const float4*)(src + kHdr + (int64_t)(lj * wi + li) * 8);
+                        float4 lo = s4[0], hi = s4[1];
+                        acc[0] += lo.x; acc[1] += lo.y; acc[2] += lo.z; acc[3] += lo.w;
+                        acc[4] += hi.x; acc[5] += hi.y; acc[6] += hi.z; acc[7] += hi.w;
+                    }
+                }
+            }
+            if (t0 == 0 && lane < kGeo) rec_grad[((int64_t)v * n + s) * kGeo + lane] = gs;
+        }
+        if (tt < TT) {
+            float4 lo = make_float4(acc[0], acc[1], acc[2], acc[3]);
+            float4 hi = make_float4(acc[4], acc[5], acc[6], acc[7]);
+            if (beta != 0.f) {
+                float4 o0 = dst[tt * 2], o1 = dst[tt * 2 + 1];
+                lo.x += beta * o0.x; lo.y += beta * o0.y; lo.z += beta * o0.z; lo.w += beta * o0.w;
+                hi.x += beta * o1.x; hi.y += beta * o1.y; hi.z += beta * o1.z; hi.w += beta * o1.w;
+            }
+            dst[tt * 2] = lo;
+            dst[tt * 2 + 1] = hi;
+        }
+    }
+}
+
+__device__ inline void dcross(const double* a, const double* b, double* c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Chain rule of the projection set-up (see k_preprocess), double precision, views in order.
+__global__ __launch_bounds__(256) void k_bwd_params(int V, int n, const ts_camera* __restrict__ cams,
+                                                    const float* __restrict__ means,
+                                                    const float* __restrict__ quats,
+                                                    const float* __restrict__ scales,
+                                                    const int4* __restrict__ rect,
+                                                    const float* __restrict__ rec_grad,
+                                                    const int32_t* __restrict__ status, float beta,
+                                                    float* d_means, float* d_quats, float* d_scales,
+                                                    float* d_opac) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n || status[0] != 0) return;
+    double mu[3] = {means[3 * s], means[3 * s + 1], means[3 * s + 2]};
+    double q[4] = {quats[4 * s], quats[4 * s + 1], quats[4 * s + 2], quats[4 * s + 3]};
+    double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+    double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                   2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                   2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+    double su = scales[2 * s], sv = scales[2 * s + 1];
+    double dmu[3] = {0, 0, 0}, dR[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, dsu = 0, dsv = 0, dop = 0;
+    for (int v = 0; v < V; v++) {
+        int4 rr = rect[(int64_t)v * n + s];
+        if (rr.z <= rr.x || rr.w <= rr.y) continue;
+        const float* gr = rec_grad + ((int64_t)v * n + s) * kGeo;
+        const ts_camera& cam = cams[v];
+        double Wr[9], t[3];
+        for (int i = 0; i < 3; i++) {
+            for (int j = 0; j < 3; j++) Wr[i * 3 + j] = cam.w2c[i * 4 + j];
+            t[i] = cam.w2c[i * 4 + 3];
+        }
+        double mc[3], tu[3], tv[3], nc[3];
+        for (int i = 0; i < 3; i++) {
+            mc[i] = Wr[i * 3] * mu[0] + Wr[i * 3 + 1] * mu[1] + Wr[i * 3 + 2] * mu[2] + t[i];
+            tu[i] = Wr[i * 3] * R[0] + Wr[i * 3 + 1] * R[3] + Wr[i * 3 + 2] * R[6];
+            tv[i] = Wr[i * 3] * R[1] + Wr[i * 3 + 1] * R[4] + Wr[i * 3 + 2] * R[7];
+            nc[i] = Wr[i * 3] * R[2] + Wr[i * 3 + 1] * R[5] + Wr[i * 3 + 2] * R[8];
+        }
+        double fx = cam.fx, fy = cam.fy;
+        double nmu = nc[0] * mc[0] + nc[1] * mc[1] + nc[2] * mc[2];
+        double sg = nmu > 0 ? 1.0 : -1.0;
+        double Au[3], Bv[3];
+        dcross(tv, mc, Au);
+        dcross(mc, tu, Bv);
+        double iz = 1.0 / mc[2];
+        double g_px = gr[0], g_py = gr[1], g_ux = gr[2], g_uy = gr[3], g_vx = gr[4], g_vy = gr[5];
+        double g_wx = gr[6], g_wy = gr[7], g_w0 = gr[8];
+        dop += gr[9];
+        // sigma R -> R (sigma = facing sign, constant)
+        double o[3];
+        for (int i = 0; i < 3; i++) o[i] = -(Wr[0 * 3 + i] * t[0] + Wr[1 * 3 + i] * t[1] + Wr[2 * 3 + i] * t[2]);
+        double nwd = R[2] * (o[0] - mu[0]) + R[5] * (o[1] - mu[1]) + R[8] * (o[2] - mu[2]);
+        double sigma = nwd >= 0.0 ? 1.0 : -1.0;
+        for (int k = 0; k < 9; k++) dR[k] += sigma * gr[10 + k];
+        double dmc[3] = {0, 0, 0}, dtu[3] = {0, 0, 0}, dtv[3] = {0, 0, 0}, dnc[3] = {0, 0, 0};
+        // px = fx mc0/mc2 + cx, py = fy mc1/mc2 + cy
+        dmc[0] += g_px * fx * iz;
+        dmc[1] += g_py * fy * iz;
+        dmc[2] += -(g_px * fx * mc[0] + g_py * fy * mc[1]) * iz * iz;
+        // ux = sg Au0/(su fx), uy = sg Au1/(su fy); vx = sg Bv0/(sv fx), vy = sg Bv1/(sv fy)
+        double dA[3] = {sg * g_ux / (su * fx), sg * g_uy / (su * fy), 0.0};
+        double dB[3] = {sg * g_vx / (sv * fx), sg * g_vy / (sv * fy), 0.0};
+        dsu += -(g_ux * sg * Au[0] / (su * fx) + g_uy * sg * Au[1] / (su * fy)) / su;
+        dsv += -(g_vx * sg * Bv[0] / (sv * fx) + g_vy * sg * Bv[1] / (sv * fy)) / sv;
+        // Au = tv x mc: dtv += mc x dA, dmc += dA x tv ; Bv = mc x tu: dmc += tu x dB, dtu += dB x mc
+        double c[3];
+        dcross(mc, dA, c); for (int i = 0; i < 3; i++) dtv[i] += c[i];
+        dcross(dA, tv, c); for (int i = 0; i < 3; i++) dmc[i] += c[i];
+        dcross(tu, dB, c); for (int i = 0; i < 3; i++) dmc[i] += c[i];
+        dcross(dB, mc, c); for (int i = 0; i < 3; i++) dtu[i] += c[i];
+        // wx = sg nc0/fx, wy = sg nc1/fy, w0 = sg (nc.mc)/mc2
+        dnc[0] += sg * g_wx / fx;
+        dnc[1] += sg * g_wy / fy;
+        for (int i = 0; i < 3; i++) {
+            dnc[i] += sg * g_w0 * mc[i] * iz;
+            dmc[i] += sg * g_w0 * nc[i] * iz;
+        }
+        dmc[2] += -sg * g_w0 * nmu * iz * iz;
+        // camera frame -> world: tu = W R[:,0], ...; mc = W mu + t
+        for (int j = 0; j < 3; j++) {
+            double wtu = 0, wtv = 0, wnc = 0, wmc = 0;
+            for (int i = 0; i < 3; i++) {
+                wtu += Wr[i * 3 + j] * dtu[i];
+                wtv += Wr[i * 3 + j] * dtv[i];
+                wnc += Wr[i * 3 + j] * dnc[i];
+                wmc += Wr[i * 3 + j] * dmc[i];
+            }
+            dR[j * 3 + 0] += wtu;
+            dR[j * 3 + 1] += wtv;
+            dR[j * 3 + 2] += wnc;
+            dmu[j] += wmc;
+        }
+    }
+    // rotation matrix of the unit quaternion -> quaternion
+    double dw = -2 * z * dR[1] + 2 * y * dR[2] + 2 * z * dR[3] - 2 * x * dR[5] - 2 * y * dR[6] + 2 * x * dR[7];
+    double dx = 2 * y * dR[1] + 2 * z * dR[2] + 2 * y * dR[3] - 4 * x * dR[4] - 2 * w * dR[5] + 2 * z * dR[6] + 2 * w * dR[7] - 4 * x * dR[8];
+    double dy = -4 * y * dR[0] + 2 * x * dR[1] + 2 * w * dR[2] + 2 * x * dR[3] + 2 * z * dR[5] - 2 * w * dR[6] + 2 * z * dR[7] - 4 * y * dR[8];
+    double dz = -4 * z * dR[0] - 2 * w * dR[1] + 2 * x * dR[2] + 2 * w * dR[3] - 4 * z * dR[4] + 2 * y * dR[5] + 2 * x * dR[6] + 2 * y * dR[7];
+    double dot = w * dw + x * dx + y * dy + z * dz;
+    double dq[4] = {(dw - w * dot) / qn, (dx - x * dot) / qn, (dy - y * dot) / qn, (dz - z * dot) / qn};
+    float b = beta;
+    for (int i = 0; i < 3; i++) d_means[3 * s + i] = (float)dmu[i] + (b != 0.f ? b * d_means[3 * s + i] : 0.f);
+    for (int i = 0; i < 4; i++) d_quats[4 * s + i] = (float)dq[i] + (b != 0.f ? b * d_quats[4 * s + i] : 0.f);
+    d_scales[2 * s] = (float)dsu + (b != 0.f ? b * d_scales[2 * s] : 0.f);
+    d_scales[2 * s + 1] = (float)dsv + (b != 0.f ? b * d_scales[2 * s + 1] : 0.f);
+    d_opac[s] = (float)dop + (b != 0.f ? b * d_opac[s] : 0.f);
+}
+
+struct BwdLayout {
+    size_t off_start, off_pairpos, off_slots, off_recgrad, off_top, total;
+};
+
+inline BwdLayout bwd_layout(int V, int n, int64_t cap) {
+    BwdLayout L;
+    size_t vn = (size_t)V * (size_t)(n > 0 ? n : 1);
+    size_t c = (size_t)(cap > 0 ? cap : 1);
+    size_t off = 0;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    L.off_start = off; off = al(off + vn * 8);
+    L.off_pairpos = off; off = al(off + c * 4);
+    L.off_slots = off; off = al(off + c * 16);
+    L.off_recgrad = off; off = al(off + vn * kGeo * 4);
+    L.off_top = off; off = al(off + 8);
+    L.total = off;
+    return L;
+}
+
+}  // namespace ts
+
+using namespace ts;
+
+extern "C" int ts_raster_bwd_workspace(int32_t n_views, int32_t n, int64_t pair_capacity,
+                                       size_t* bytes) {
+    if (!bytes || n_views < 1 || n < 0 || pair_capacity < 0) {
+        set_error("ts_raster_bwd_workspace: bad argument");
+        return TS_E_ARG;
+    }
+    *bytes = bwd_layout(n_views, n, pair_capacity).total;
+    return TS_OK;
+}
+
+extern "C" int ts_raster_bwd(int32_t n_views, int32_t width, int32_t height, const ts_camera* cams,
+                             const ts_params* params, int32_t n, const float* means,
+                             const float* quats, const float* scales, const int32_t* chart_of,
+                             const float* rec, const int32_t* rect, const int32_t* tile_ranges,
+                             const int32_t* pair_ids, int64_t pair_capacity, const float* atlas,
+                             const ts_env* env, const float* gbuf, const float* t_final,
+                             const int32_t* n_contrib, const float* d_rgba, void* ws,
+                             size_t ws_bytes, float* partials, int64_t partial_capacity,
+                             int32_t* status, int64_t* partial_used, float beta, float* d_means, float* d_quats,
+                             float* d_scales, float* d_opac, float* d_atlas, hipStream_t stream) {
+    if (n_views < 1 || width < 1 || height < 1 || n < 0 || !params || !cams || !env ||
+        !tile_ranges || !gbuf || !t_final || !n_contrib || !d_rgba || !status ||
+        (n > 0 && (!means || !quats || !scales || !chart_of || !rec || !rect || !pair_ids ||
+                   !atlas || !d_means || !d_quats || !d_scales || !d_opac || !d_atlas ||
+                   !partials))) {
+        set_error("ts_raster_bwd: bad argument");
+        return TS_E_ARG;
+    }
+    if (params->tex_res < 1 || params->tex_res > 32) {
+        set_error("ts_raster_bwd: tex_res %d outside 1..32", params->tex_res);
+        return TS_E_ARG;
+    }
+    BwdLayout L = bwd_layout(n_views, n, pair_capacity);
+    if (!ws || ws_bytes < L.total) {
+        set_error("ts_raster_bwd: workspace %zu < %zu bytes", ws_bytes, L.total);
+        return TS_E_WORKSPACE;
+    }
+    if (n == 0) return TS_OK;
+    char* wsc = (char*)ws;
+    int64_t* start = (int64_t*)(wsc + L.off_start);
+    int32_t* pair_pos = (int32_t*)(wsc + L.off_pairpos);
+    int32_t* slots = (int32_t*)(wsc + L.off_slots);
+    float* rec_grad = (float*)(wsc + L.off_recgrad);
+    unsigned long long* top = (unsigned long long*)(wsc + L.off_top);
+    int ntx = tiles_x(width), n_tiles = ntx * tiles_y(height);
+    int64_t vn = (int64_t)n_views * n;
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, stream, top);
+    hipLaunchKernelGGL(k_area_scan, dim3(1), dim3(1024), 0, stream, (const int4*)rect, vn, start);
+    hipLaunchKernelGGL(k_bwd_pairs, dim3(n_views * n_tiles), dim3(256), 0, stream, n_views, n, ntx,
+                       n_tiles, (const int2*)tile_ranges, pair_capacity, pair_ids,
+                       (const int4*)rect, (const int64_t*)start, pair_pos, slots);
+    BwdArgs a = {};
+    a.V = n_views; a.W = width; a.H = height; a.ntx = ntx; a.n_tiles = n_tiles;
+    a.T = params->tex_res; a.n = n; a.cams = cams;
+    a.S = params->s_sigma; a.amin = params->alpha_min; a.amax = params->alpha_max;
+    a.tmin = params->t_min;
+    for (int c = 0; c < 3; c++) a.sc.bg[c] = params->bg[c];
+    if (!env->spec || !env->irr || !env->lut) {
+        set_error("ts_raster_bwd: bad ts_env");
+        return TS_E_ARG;
+    }
+    a.env.spec = (const float4*)env->spec; a.env.irr = (const float4*)env->irr;
+    a.env.lut = (const float2*)env->lut; a.env.spec_res = env->spec_res;
+    a.env.levels = env->spec_levels; a.env.irr_res = env->irr_res; a.env.lut_res = env->lut_res;
+    a.rec = (const float4*)rec; a.ranges = (const int2*)tile_ranges; a.pair_ids = pair_ids;
+    a.cap = pair_capacity; a.atlas = (const float4*)atlas; a.gbuf = gbuf; a.t_final = t_final;
+    a.n_contrib = n_contrib; a.d_rgba = (const float4*)d_rgba; a.slots = slots;
+    a.part = partials; a.part_cap = partial_capacity; a.part_top = top; a.status = status;
+    hipLaunchKernelGGL(k_raster_bwd, dim3(n_views * n_tiles), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_bwd_gather, dim3(n), dim3(64), 0, stream, n_views, n, params->tex_res,
+                       (const int4*)rect, (const int64_t*)start, (const int32_t*)pair_pos,
+                       (const int32_t*)slots, (const float*)partials, chart_of,
+                       (const int32_t*)status, beta, rec_grad, d_atlas);
+    hipLaunchKernelGGL(k_bwd_params, dim3((n + 255) / 256), dim3(256), 0, stream, n_views, n, cams,
+                       means, quats, scales, (const int4*)rect, (const float*)rec_grad,
+                       (const int32_t*)status, beta, d_means, d_quats, d_scales, d_opac);
+    if (partial_used) hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(1), 0, stream, top, partial_used);
+    return launch_check("ts_raster_bwd");
+}

@@ -19,7 +19,8 @@ constexpr int kXcd = 8;                  // MI355X: 8 XCDs, workgroups dealt rou
 //  4..7   px, py (projected centre, float32 head of the double value), ux, uy
 //  8..11  u0, vx, vy, v0
 //  12..15 wx, wy, w0, opacity
-//  16..24 sigma * R (row-major 3x3, world frame), 25 chart id (int bits), 26..27 pad
+//  16..24 sigma * R (row-major 3x3, world frame), 25 chart id (int bits),
+//  26..27 px - px_head, py - py_head (float low parts of the projected centre)
 // per pixel (X,Y) = pixel centre:   dx = X - px, dy = Y - py
 //   num_u = ux dx + uy dy + u0,  num_v = vx dx + vy dy + v0,  den = wx dx + wy dy + w0
 //   (u,v) = (num_u, num_v) / den, the ray meets the front of the plane iff den > 0

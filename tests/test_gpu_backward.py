@@ -1,0 +1,156 @@
+"""HIP backward (ts_raster_bwd) against the float64 autograd reference (run on an MI355X).
+
+Tolerance per gradient tensor (float32 path vs float64 definition): max |g - g_ref| <=
+1e-3 max |g_ref| + 1e-7 and cosine similarity >= 0.9999. Upstream gradients are zero at pixels
+the oracle marks as near a discrete decision (there both branches are valid renders)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import grad as og
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+NAMES = ("means", "quats", "scales", "opac", "textures")
+
+
+def _pkg():
+    import paper_2506_13348_amd as P
+    P._ffi.lib()
+    return P
+
+
+def _gpu_grads(sc, cams, W, H, d_rgba, partial_floats=None, beta=0.0, grads=None, runner=None):
+    P = _pkg()
+    from paper_2506_13348_amd.autograd import BackwardRunner
+    ds = P.DeviceScene.from_dict(sc, device="cuda")
+    plan = P.RenderPlan(ds, cams, W, H, gbuf=True, aux=True)
+    plan.run()
+    plan.check()
+    if grads is None:
+        grads = (torch.zeros_like(ds.means), torch.zeros_like(ds.quats),
+                 torch.zeros_like(ds.scales), torch.zeros_like(ds.opac),
+                 torch.zeros_like(ds.atlas))
+    run = BackwardRunner(plan, partial_floats)
+    run.run(torch.as_tensor(np.asarray(d_rgba, np.float32)).cuda().contiguous(), grads, beta)
+    torch.cuda.synchronize()
+    return grads, run
+
+
+def _np(grads):
+    return {k: g.double().cpu().numpy() for k, g in zip(NAMES, grads)}
+
+
+def _compare(g, ref, name):
+    out = {}
+    for k in NAMES:
+        a, b = g[k].reshape(-1), ref[k].reshape(-1)
+        scale = np.abs(b).max()
+        err = np.abs(a - b).max()
+        cos = float(a @ b / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-300))
+        out[k] = (err / max(scale, 1e-300), cos)
+        assert err <= 1e-3 * scale + 1e-7, (name, k, err, scale)
+        assert cos >= 0.9999, (name, k, cos)
+    print(f"[{name}] " + " ".join(f"{k}: rel {e:.2e} cos {c:.7f}" for k, (e, c) in out.items()),
+          flush=True)
+
+
+def _upstream(rng, ref, shape):
+    d = rng.normal(size=(ref["rgba"].shape[0], 4))
+    d[ref["stat"][:, 2] > 0] = 0.0
+    return d, d.reshape(shape)
+
+
+@pytest.fixture(scope="module")
+def fd_case():
+    sc = synth.make_scene("sq300k_train", n=20000, env_res=32)
+    sc["env_levels"] = 3
+    cam = synth.config_cameras("sq300k_train")[0]
+    sub, crop = synth.fd_crop_scene(sc, cam, 368, 368, 64, 64, n_keep=500)
+    return sub, crop
+
+
+def test_grads_fd_crop(fd_case):
+    """The 64x64 crop with the 500 front-most splats of the 300k-splat scene."""
+    sub, crop = fd_case
+    tabs = oracle.tables(sub["env"], sub["env_levels"])
+    pix = oracle.all_pixels(64, 64)
+    ref_f = oracle.render(sub, crop, pixels=pix, tabs=tabs)
+    d, d4 = _upstream(np.random.default_rng(1), ref_f, (1, 64, 64, 4))
+    ref = og.grads(sub, crop, pix, d, tabs)
+    g, _ = _gpu_grads(sub, [crop], 64, 64, d4)
+    _compare(_np(g), ref, "fd crop")
+
+
+def test_grads_multi_view_ragged():
+    sc = synth.make_scene("shell2k", n=700, tex_res=4)
+    cams = synth.orbit_cameras(3, 45, 37, dist=2.8, el_deg=10.0)
+    rng = np.random.default_rng(4)
+    tabs = oracle.tables(sc["env"], 1)
+    pix = oracle.all_pixels(45, 37)
+    d_all = np.zeros((3, 37, 45, 4))
+    ref = {k: 0.0 for k in NAMES}
+    for v, cam in enumerate(cams):
+        ref_f = oracle.render(sc, cam, pixels=pix, tabs=tabs)
+        d, d4 = _upstream(rng, ref_f, (37, 45, 4))
+        d_all[v] = d4
+        r = og.grads(sc, cam, pix, d, tabs)
+        for k in NAMES:
+            ref[k] = ref[k] + r[k]
+    g, _ = _gpu_grads(sc, cams, 45, 37, d_all)
+    _compare(_np(g), ref, "3 views")
+
+
+@pytest.mark.parametrize("T", [1, 16])
+def test_grads_texture_resolution(T):
+    sc = synth.make_scene("shell2k", n=500, tex_res=T)
+    cam = synth.crop_camera(synth.config_cameras("shell2k")[0], 40, 40, 40, 40)
+    tabs = oracle.tables(sc["env"], 1)
+    pix = oracle.all_pixels(40, 40)
+    ref_f = oracle.render(sc, cam, pixels=pix, tabs=tabs)
+    d, d4 = _upstream(np.random.default_rng(T), ref_f, (1, 40, 40, 4))
+    ref = og.grads(sc, cam, pix, d, tabs)
+    g, _ = _gpu_grads(sc, [cam], 40, 40, d4)
+    _compare(_np(g), ref, f"T={T}")
+
+
+def test_deterministic_beta_and_overflow_retry():
+    sc = synth.make_scene("sq100k", n=6000, env_res=16)
+    cams = synth.orbit_cameras(2, 80, 64)
+    d = np.random.default_rng(0).normal(size=(2, 64, 80, 4))
+    g1, run1 = _gpu_grads(sc, cams, 80, 64, d)
+    g2, _ = _gpu_grads(sc, cams, 80, 64, d)
+    for a, b in zip(g1, g2):
+        assert torch.equal(a, b)
+    # a 1024-float partial buffer overflows; the retry sized from the reported need matches
+    g3, run3 = _gpu_grads(sc, cams, 80, 64, d, partial_floats=1024)
+    assert run3.partials.numel() > 1024
+    for a, b in zip(g1, g3):
+        assert torch.equal(a, b)
+    # beta = 1 adds onto the previous contents
+    acc = tuple(t.clone() for t in g1)
+    _gpu_grads(sc, cams, 80, 64, d, beta=1.0, grads=acc)
+    for a, b in zip(g1, acc):
+        assert torch.equal(2 * a, b)
+
+
+def test_autograd_function_matches_runner():
+    P = _pkg()
+    from paper_2506_13348_amd.autograd import render_rgba
+    sc = synth.make_scene("shell2k", n=800)
+    cam = synth.config_cameras("shell2k")[0]
+    ds = P.DeviceScene.from_dict(sc, device="cuda")
+    leaves = [t.clone().requires_grad_(True) for t in (ds.means, ds.quats, ds.scales, ds.opac,
+                                                       ds.atlas)]
+    cams = P.cameras_tensor([cam])
+    target = torch.rand(1, 128, 128, 3, device="cuda", generator=torch.Generator("cuda").manual_seed(1))
+    rgba = render_rgba(*leaves, ds.chart_of, cams, 128, 128, ds.tables)
+    loss = (rgba[..., :3] - target).abs().mean()
+    loss.backward()
+    d = (torch.sign(rgba[..., :3].detach() - target) / target.numel())
+    d4 = torch.cat([d, torch.zeros_like(d[..., :1])], -1)
+    g, _ = _gpu_grads(sc, [cam], 128, 128, d4.cpu().numpy())
+    for leaf, ref in zip(leaves, g):
+        torch.testing.assert_close(leaf.grad, ref, rtol=0, atol=0)
