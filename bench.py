@@ -48,12 +48,125 @@ def cpu_baseline(scene, cam, n_pix=40000, seed=0):
             "evals_per_s": round(float(out["stat"][:, 0].sum()) / dt, 1)}
 
 
+def bench_fwd_bwd(steps, warmup):
+    """One training step of the 300k-splat scene: forward of a batch of 8 orbit views at
+    800x800, L1 loss to a seeded target, hand-written backward to all splat parameters."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2506_13348_amd import DeviceScene, RenderPlan
+    from paper_2506_13348_amd.autograd import BackwardRunner
+
+    sc = synth.make_scene("sq300k_train")
+    cams = synth.config_cameras("sq300k_train")
+    V, W, H = len(cams), 800, 800
+    ds = DeviceScene.from_dict(sc, device="cuda")
+    del sc
+    target = torch.as_tensor(synth.target_image(W, H, seed=1, n_views=V)).cuda()
+    plan = RenderPlan(ds, cams, W, H, gbuf=True, aux=True)
+    run = BackwardRunner(plan)
+    grads = (torch.empty_like(ds.means), torch.empty_like(ds.quats), torch.empty_like(ds.scales),
+             torch.empty_like(ds.opac), torch.empty_like(ds.atlas))
+    d_rgba = torch.zeros(V, H, W, 4, device="cuda")
+    inv_n = 1.0 / (V * H * W * 3)
+
+    def step(retry):
+        plan.run()
+        rgb = plan.rgba.view(V, H, W, 4)[..., :3]
+        loss = (rgb - target).abs().sum() * inv_n
+        d_rgba[..., :3] = torch.sign(rgb - target) * inv_n
+        run.run(d_rgba, grads, 0.0, retry=retry)
+        return loss
+
+    for _ in range(max(warmup, 1)):
+        step(True)
+    plan.check()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record()
+        plan.run()
+        ev[k][1].record()
+        rgb = plan.rgba.view(V, H, W, 4)[..., :3]
+        d_rgba[..., :3] = torch.sign(rgb - target) * inv_n
+        run.run(d_rgba, grads, 0.0, retry=False)
+        ev[k][2].record()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    plan.check()
+    if int(run.status.item()) != 0:
+        raise RuntimeError("backward partial buffer overflow in the timed steps")
+    fwd_ms = float(np.mean([ev[k][0].elapsed_time(ev[k][1]) for k in range(steps)]))
+    bwd_ms = float(np.mean([ev[k][1].elapsed_time(ev[k][2]) for k in range(steps)]))
+    return {"value": round(V * W * H / dt / 1e6, 2), "unit": "Mpix/s", "ms_per_step": round(dt * 1e3, 3),
+            "steps": steps, "views_per_step": V, "splats": ds.n,
+            "per_phase_ms": {"forward": round(fwd_ms, 3), "loss_and_backward": round(bwd_ms, 3)},
+            "workload": "sq300k: 300k splats T=8, 8 orbit views 800x800 per step, L1 to a "
+                        "seeded U(0,1) target, gradients to means/quats/scales/opacity/texels",
+            "partial_buffer_floats": int(run.partials.numel())}
+
+
+def bench_serving(duration, rate=200.0, warm=1.0):
+    """Serving: 4 resident scenes (50k, 200k, 500k superquadric splats, 1M height-field
+    splats; T=8), a seeded Poisson stream at `rate` req/s, scene uniform, resolution uniform
+    over {256^2, 512^2, 800^2, 1920x1080}, random orbit cameras. The continuous-batching
+    server (4 stream slots, graph replays) against the plain one-at-a-time renderer."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2506_13348_amd import DeviceScene
+    from paper_2506_13348_amd.serve import Request, Server, latency_report, serve_sequential
+
+    t0 = time.perf_counter()
+    scenes, geos = [], []
+    for i, (geo, n, seed) in enumerate(synth.SERVING_SCENES):
+        raw = synth.serving_scene(i)
+        scenes.append(DeviceScene.from_dict(raw, device="cuda"))
+        geos.append(geo)
+        del raw
+    log(f"serving scenes ready in {time.perf_counter() - t0:.1f}s")
+    rng = np.random.default_rng(7)
+    trace = synth.poisson_requests(rng, rate, duration, len(scenes), synth.SERVING_RESOLUTIONS)
+    cams = [synth.serving_camera(geos[s], wh[0], wh[1], az, el) for (t, s, wh, az, el) in trace]
+    srng = np.random.default_rng(8)
+    samples = {}
+    for s in range(len(scenes)):
+        for (W, H) in synth.SERVING_RESOLUTIONS:
+            samples[(s, W, H)] = [synth.serving_camera(geos[s], W, H, srng.uniform(0, 2 * np.pi),
+                                                       srng.uniform(0, 40)) for _ in range(3)]
+    srv = Server(scenes, slots=4, mem_budget=48 << 30, capacity_samples=samples)
+    srv.prepare([(k, v[0]) for k, v in samples.items()], per_key=2)
+    log(f"serving plans ready in {time.perf_counter() - t0:.1f}s: {srv.stats}")
+
+    def fresh():
+        return [Request(i, t, s, wh[0], wh[1], cams[i]) for i, (t, s, wh, az, el) in enumerate(trace)]
+
+    reqs = srv.serve(fresh())
+    rep = latency_report([r for r in reqs if r.arrival >= warm])
+    log(f"server: {rep}")
+    seq = serve_sequential(scenes, fresh(), srv.capacity)
+    rep_seq = latency_report([r for r in seq if r.arrival >= warm])
+    log(f"sequential: {rep_seq}")
+    return {"workload": f"4 resident scenes (50k/200k/500k/1M splats, T=8), Poisson {rate:g} req/s "
+                        f"for {duration:g} s (first {warm:g} s excluded), resolutions 256^2/512^2/"
+                        "800^2/1920x1080, random orbit cameras",
+            "server": rep, "sequential_plain": rep_seq,
+            "p99_speedup": round(rep_seq["p99_ms"] / rep["p99_ms"], 2),
+            "server_stats": srv.stats}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fwd-bwd", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-seconds", type=float, default=5.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
@@ -136,6 +249,16 @@ def main():
                      "traffic": None,
                      "note": f"{n_blend} blended evaluations x {FLOPS_PER_BLEND} flops per launch"},
     }
+    if not args.no_fwd_bwd:
+        del plan
+        torch.cuda.empty_cache()
+        log("forward+backward ...")
+        result["fwd_bwd"] = bench_fwd_bwd(max(3, K // 2), 1)
+        log(f"fwd+bwd: {result['fwd_bwd']}")
+    if not args.no_serving:
+        torch.cuda.empty_cache()
+        log("serving ...")
+        result["serving"] = bench_serving(args.serving_seconds)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(sc, cams[0])

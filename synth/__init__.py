@@ -28,7 +28,8 @@ import numpy as np
 __all__ = [
     "CONFIGS", "SceneConfig", "make_scene", "make_env", "look_at_camera", "orbit_cameras",
     "config_cameras", "crop_camera", "random_gbuffer", "poisson_requests", "target_image",
-    "cameras_array", "fd_crop_scene",
+    "cameras_array", "fd_crop_scene", "serving_camera", "serving_scene", "SERVING_SCENES",
+    "SERVING_RESOLUTIONS",
 ]
 
 
@@ -90,15 +91,17 @@ def _frames_from_normals(rng, normals):
 
 
 def _textures(rng, n, T):
-    """Per-primitive material textures, drawn albedo, roughness, metallic, normal."""
+    """Per-primitive material textures, drawn albedo, roughness, metallic, normal
+    (float32 draws: millions of texels per scene)."""
     tex = np.empty((n, T, T, 8), np.float32)
-    tex[..., 0:3] = rng.uniform(0.0, 1.0, size=(n, T, T, 3))
-    tex[..., 3] = rng.uniform(0.05, 1.0, size=(n, T, T))
-    tex[..., 7] = (rng.uniform(size=(n, T, T)) < 0.3).astype(np.float32)
-    nt = np.empty((n, T, T, 3))
-    nt[..., 0:2] = rng.normal(0.0, 0.2, size=(n, T, T, 2))
-    nt[..., 2] = 1.0
-    tex[..., 4:7] = _normalize(nt)
+    tex[..., 0:3] = rng.random(size=(n, T, T, 3), dtype=np.float32)
+    tex[..., 3] = np.float32(0.05) + np.float32(0.95) * rng.random(size=(n, T, T), dtype=np.float32)
+    tex[..., 7] = (rng.random(size=(n, T, T), dtype=np.float32) < 0.3).astype(np.float32)
+    nxy = np.float32(0.2) * rng.standard_normal(size=(n, T, T, 2), dtype=np.float32)
+    inv = 1.0 / np.sqrt(1.0 + nxy[..., 0] ** 2 + nxy[..., 1] ** 2)
+    tex[..., 4] = nxy[..., 0] * inv
+    tex[..., 5] = nxy[..., 1] * inv
+    tex[..., 6] = inv
     return tex
 
 
@@ -367,6 +370,28 @@ def config_cameras(cfg: SceneConfig | str, n_views: int | None = None):
     if cfg.name == "sq300k_train":
         return orbit_cameras(V, cfg.width, cfg.height)
     return orbit_cameras(V, cfg.width, cfg.height)
+
+
+def serving_camera(geometry, width, height, az, el_deg):
+    """A random serving view: orbit at distance 3 around the object scenes, or a view from
+    radius 4 at height 1.5 + el/40 towards (0, 0.5, 0) for the height-field scene."""
+    if geometry == "heightfield":
+        eye = (4.0 * math.sin(az), 1.5 + el_deg / 40.0, 4.0 * math.cos(az))
+        return look_at_camera(eye, (0.0, 0.5, 0.0), width, height)
+    el = math.radians(el_deg)
+    eye = 3.0 * np.array([math.cos(el) * math.sin(az), math.sin(el), math.cos(el) * math.cos(az)])
+    return look_at_camera(eye, (0.0, 0.0, 0.0), width, height)
+
+
+SERVING_SCENES = [("superquadric", 50_000, 10), ("superquadric", 200_000, 11),
+                  ("superquadric", 500_000, 12), ("heightfield", 1_000_000, 13)]
+SERVING_RESOLUTIONS = [(256, 256), (512, 512), (800, 800), (1920, 1080)]
+
+
+def serving_scene(i, n=None):
+    geo, count, seed = SERVING_SCENES[i]
+    base = "field1m" if geo == "heightfield" else "sq100k"
+    return make_scene(base, seed=seed, n=count if n is None else n)
 
 
 def target_image(width, height, seed=1, n_views=1):
