@@ -108,6 +108,48 @@ def bench_fwd_bwd(steps, warmup):
             "partial_buffer_floats": int(run.partials.numel())}
 
 
+def bench_tab3(steps=5):
+    """Texture-sampling cost as in the paper's Tab. 3: the same 100k-splat superquadric
+    geometry and 64 orbit views rendered untextured (one attribute per splat) and with
+    software-bilinear textures at T = 2, 4, 8, 16; frame-rate ratios to the untextured run."""
+    import torch
+
+    import synth
+    from paper_2506_13348_amd import DeviceScene, RenderPlan
+
+    cams = synth.config_cameras("sq100k")
+
+    def timed(T, sampler):
+        sc = synth.make_scene("sq100k", tex_res=T)
+        ds = DeviceScene.from_dict(sc, device="cuda")
+        del sc
+        plan = RenderPlan(ds, cams, 800, 800, params={"sampler": sampler})
+        plan.run()
+        plan.check()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            plan.run()
+        e1.record()
+        torch.cuda.synchronize()
+        plan.check()
+        return e0.elapsed_time(e1) / steps
+
+    base = timed(1, 1)
+    out = {"workload": "sq100k geometry, 64 views 800x800 per step", "untextured_ms": round(base, 3),
+           "T": [], "bilinear_ms": [], "fps_ratio_bilinear": []}
+    for T in (2, 4, 8, 16):
+        ms = timed(T, 0)
+        out["T"].append(T)
+        out["bilinear_ms"].append(round(ms, 3))
+        out["fps_ratio_bilinear"].append(round(base / ms, 3))
+        torch.cuda.empty_cache()
+    out["hardware_sampler"] = "unavailable: the gfx950 toolchain has no image/texture instructions"
+    out["paper_tab3_rtx_a6000"] = {"software_bilinear": [0.90, 0.86, 0.85, 0.79],
+                                   "hardware_texture_atlas": [0.92, 0.93, 0.94, 0.91]}
+    return out
+
+
 def bench_serving(duration, rate=200.0, warm=1.0):
     """Serving: 4 resident scenes (50k, 200k, 500k superquadric splats, 1M height-field
     splats; T=8), a seeded Poisson stream at `rate` req/s, scene uniform, resolution uniform
@@ -166,7 +208,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fwd-bwd", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-tab3", action="store_true")
     ap.add_argument("--serving-seconds", type=float, default=5.0)
+    ap.add_argument("--profile-run", action="store_true",
+                    help="only the forward workload (few steps) plus a 256 MiB device copy that "
+                         "calibrates the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
@@ -208,6 +254,14 @@ def main():
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     plan.check()
+    if args.profile_run:
+        src = torch.empty(64 << 20, device=dev, dtype=torch.float32).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)   # calibration: 256 MiB read + 256 MiB written
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_run": True, "steps": K, "views": V,
+                          "calibration_copy_bytes": src.numel() * 4}), flush=True)
+        return
     ms_step = t_total / K * 1e3
     pre_ms = float(np.mean([ev[k][0].elapsed_time(ev[k][1]) for k in range(K)]))
     bin_ms = float(np.mean([ev[k][1].elapsed_time(ev[k][2]) for k in range(K)]))
@@ -255,6 +309,11 @@ def main():
         log("forward+backward ...")
         result["fwd_bwd"] = bench_fwd_bwd(max(3, K // 2), 1)
         log(f"fwd+bwd: {result['fwd_bwd']}")
+    if not args.no_tab3:
+        torch.cuda.empty_cache()
+        log("texture sampling cost (Tab. 3 analog) ...")
+        result["tab3"] = bench_tab3()
+        log(f"tab3: {result['tab3']}")
     if not args.no_serving:
         torch.cuda.empty_cache()
         log("serving ...")

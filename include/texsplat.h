@@ -66,8 +66,16 @@ typedef struct ts_params {
     float near_z;     /* splats with camera depth <= near_z are dropped              [0.2] */
     float bg[3];      /* background radiance of empty pixels                           [0] */
     int32_t tex_res;  /* T: texels per side of each primitive's texture, 1..32        [8] */
-    int32_t reserved;
+    int32_t sampler;  /* TS_SAMPLER_*                                          [BILINEAR] */
 } ts_params;
+
+/* Texture sampling of ts_raster_fwd / ts_raster_bwd (ts_params.sampler). */
+#define TS_SAMPLER_BILINEAR 0   /* software bilinear on the packed atlas (Eq. 5-6)             */
+#define TS_SAMPLER_CONSTANT 1   /* untextured primitives: one attribute per splat (T must be 1),
+                                   the baseline the paper's Tab. 3 compares against            */
+#define TS_SAMPLER_HARDWARE 2   /* texture-unit bilinear on an image atlas (Supp. Sec. 1 Eq.
+                                   S1-S2); the gfx950 toolchain offers no image/texture
+                                   instructions, so this returns TS_E_UNSUPPORTED              */
 
 /* Shading tables (device pointers, produced by ts_env_tables / ts_brdf_lut). */
 typedef struct ts_env {

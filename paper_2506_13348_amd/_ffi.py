@@ -25,7 +25,7 @@ c_int32, c_int64, c_float, c_void_p, c_size_t = (ctypes.c_int32, ctypes.c_int64,
 class TsParams(ctypes.Structure):
     _fields_ = [("s_sigma", c_float), ("alpha_min", c_float), ("alpha_max", c_float),
                 ("t_min", c_float), ("near_z", c_float), ("bg", c_float * 3),
-                ("tex_res", c_int32), ("reserved", c_int32)]
+                ("tex_res", c_int32), ("sampler", c_int32)]
 
 
 class TsEnv(ctypes.Structure):
@@ -101,14 +101,17 @@ def stream_handle(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+SAMPLER_BILINEAR, SAMPLER_CONSTANT, SAMPLER_HARDWARE = 0, 1, 2
+
+
 def make_params(tex_res, s_sigma=3.0, alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4,
-                near_z=0.2, bg=(0.0, 0.0, 0.0)):
+                near_z=0.2, bg=(0.0, 0.0, 0.0), sampler=SAMPLER_BILINEAR):
     p = TsParams()
     p.s_sigma, p.alpha_min, p.alpha_max, p.t_min, p.near_z = s_sigma, alpha_min, alpha_max, t_min, near_z
     for i in range(3):
         p.bg[i] = bg[i]
     p.tex_res = int(tex_res)
-    p.reserved = 0
+    p.sampler = int(sampler)
     return p
 
 

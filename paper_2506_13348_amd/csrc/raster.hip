@@ -39,8 +39,10 @@ struct RasterArgs {
 
 constexpr int kBatch = 256;
 
+template <bool kTextured>
 __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
     __shared__ float4 srec[kBatch * kRec4];
+    __shared__ uint32_t smask[kBatch];
     const int g = gridDim.x;
     const int bid = xcd_remap(blockIdx.x, g);
     const int v = bid / a.n_tiles;
@@ -51,7 +53,6 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
     const int x = bx + (lane & 7), y = by + (lane >> 3);
     const bool inside = x < a.W && y < a.H;
     const float X = (float)x + 0.5f, Y = (float)y + 0.5f;
-    const float fbx0 = (float)bx, fbx1 = (float)(bx + 7), fby0 = (float)by, fby1 = (float)(by + 7);
     int2 range = a.ranges[(int64_t)v * a.n_tiles + t];
     // lists cut short by a capacity overflow are never read past the buffer
     range.x = (int)min((int64_t)range.x, a.cap);
@@ -60,7 +61,7 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
     const int T = a.T;
     const float tscale = (float)T / (2.0f * a.S);
     const float toff = 0.5f * (float)T - 0.5f;
-    const int chart4 = T * T * 2;
+    const unsigned chart4 = (unsigned)(T * T * 2);
 
     float Tr = 1.0f;
     float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -71,56 +72,74 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
     for (int b0 = range.x; b0 < range.y; b0 += kBatch) {
         if (__syncthreads_count(!done) == 0) break;
         int nb = min(kBatch, range.y - b0);
+        uint32_t qm = 0;
         if (tid < nb) {
             int id = a.pair_ids[b0 + tid];
             const float4* src = recv + ((int64_t)v * a.n + (int64_t)id) * kRec4;
 #pragma unroll
             for (int q = 0; q < kRec4; q++) srec[tid * kRec4 + q] = src[q];
+            qm = quad_mask(src[0], tx * kTile, ty * kTile);
         }
+        smask[tid] = qm;
         __syncthreads();
         if (__ballot(!done) != 0) {
-            for (int j = 0; j < nb; j++) {
-                const float4* r = srec + j * kRec4;
-                float4 bb = r[0];
-                if (bb.z < fbx0 || bb.x > fbx1 || bb.w < fby0 || bb.y > fby1) continue;
-                SplatEval e = eval_splat(r, X, Y, a.S, a.amin, a.amax);
-                float u = e.u, vv = e.v, alpha = e.alpha;
-                bool ok = !done && e.hit;
-                float Tn = Tr * (1.0f - alpha);
-                if (ok && Tn < a.tmin) {
-                    done = true;
-                    ok = false;
-                }
-                if (__ballot(ok) != 0) {
+            // splats of this batch whose bounds touch this wave's 8x8 block, in list order
+            for (int r = 0; r < kBatch / kWave; r++) {
+                uint64_t m = __ballot((smask[r * kWave + lane] >> w) & 1u);
+                bool wave_done = false;
+                while (m) {
+                    int j = r * kWave + __builtin_ctzll(m);
+                    m &= m - 1;
+                    const float4* rp = srec + j * kRec4;
+                    SplatEval e = eval_splat(rp, X, Y, a.S, a.amin, a.amax);
+                    float u = e.u, vv = e.v, alpha = e.alpha;
+                    bool ok = !done && e.hit;
+                    float Tn = Tr * (1.0f - alpha);
+                    if (ok && Tn < a.tmin) {
+                        done = true;
+                        ok = false;
+                    }
                     if (ok) {
-                        float4 c4 = r[4], c5 = r[5], c6 = r[6];
-                        int chart = __float_as_int(c6.y);
-                        float sx = fmaf(u, tscale, toff), sy = fmaf(vv, tscale, toff);
-                        float fx0 = floorf(sx), fy0 = floorf(sy);
-                        float fx = sx - fx0, fy = sy - fy0;
-                        int i0 = (int)fx0, j0 = (int)fy0;
-                        int i1 = min(max(i0 + 1, 0), T - 1), j1 = min(max(j0 + 1, 0), T - 1);
-                        i0 = min(max(i0, 0), T - 1);
-                        j0 = min(max(j0, 0), T - 1);
-                        const float4* tb = a.atlas + (int64_t)chart * chart4;
-                        float4 p00 = tb[(j0 * T + i0) * 2], q00 = tb[(j0 * T + i0) * 2 + 1];
-                        float4 p10 = tb[(j0 * T + i1) * 2], q10 = tb[(j0 * T + i1) * 2 + 1];
-                        float4 p01 = tb[(j1 * T + i0) * 2], q01 = tb[(j1 * T + i0) * 2 + 1];
-                        float4 p11 = tb[(j1 * T + i1) * 2], q11 = tb[(j1 * T + i1) * 2 + 1];
-                        float w00 = (1.f - fx) * (1.f - fy), w10 = fx * (1.f - fy);
-                        float w01 = (1.f - fx) * fy, w11 = fx * fy;
-                        float t0 = w00 * p00.x + w10 * p10.x + w01 * p01.x + w11 * p11.x;
-                        float t1 = w00 * p00.y + w10 * p10.y + w01 * p01.y + w11 * p11.y;
-                        float t2 = w00 * p00.z + w10 * p10.z + w01 * p01.z + w11 * p11.z;
-                        float t3 = w00 * p00.w + w10 * p10.w + w01 * p01.w + w11 * p11.w;
-                        float t4 = w00 * q00.x + w10 * q10.x + w01 * q01.x + w11 * q11.x;
-                        float t5 = w00 * q00.y + w10 * q10.y + w01 * q01.y + w11 * q11.y;
-                        float t6 = w00 * q00.z + w10 * q10.z + w01 * q01.z + w11 * q11.z;
-                        float t7 = w00 * q00.w + w10 * q10.w + w01 * q01.w + w11 * q11.w;
+                        float4 c4 = rp[4], c5 = rp[5], c6 = rp[6];
+                        // the chart is the same for the whole wave: scalar base address
+                        int chart = __builtin_amdgcn_readfirstlane(__float_as_int(c6.y));
+                        __amdgpu_buffer_rsrc_t tr = chart_rsrc(a.atlas + (size_t)(unsigned)chart * chart4,
+                                                               chart4 * 16u);
+                        float t0, t1, t2, t3, t4, t5, t6, t7;
+                        if (kTextured) {
+                            float sx = fmaf(u, tscale, toff), sy = fmaf(vv, tscale, toff);
+                            float fx0 = floorf(sx), fy0 = floorf(sy);
+                            float fx = sx - fx0, fy = sy - fy0;
+                            int i0 = (int)fx0, j0 = (int)fy0;
+                            int i1 = min(max(i0 + 1, 0), T - 1), j1 = min(max(j0 + 1, 0), T - 1);
+                            i0 = min(max(i0, 0), T - 1);
+                            j0 = min(max(j0, 0), T - 1);
+                            float4 p00, q00, p10, q10, p01, q01, p11, q11;
+                            load_texel8(tr, (unsigned)(j0 * T + i0), p00, q00);
+                            load_texel8(tr, (unsigned)(j0 * T + i1), p10, q10);
+                            load_texel8(tr, (unsigned)(j1 * T + i0), p01, q01);
+                            load_texel8(tr, (unsigned)(j1 * T + i1), p11, q11);
+                            float w00 = (1.f - fx) * (1.f - fy), w10 = fx * (1.f - fy);
+                            float w01 = (1.f - fx) * fy, w11 = fx * fy;
+                            t0 = w00 * p00.x + w10 * p10.x + w01 * p01.x + w11 * p11.x;
+                            t1 = w00 * p00.y + w10 * p10.y + w01 * p01.y + w11 * p11.y;
+                            t2 = w00 * p00.z + w10 * p10.z + w01 * p01.z + w11 * p11.z;
+                            t3 = w00 * p00.w + w10 * p10.w + w01 * p01.w + w11 * p11.w;
+                            t4 = w00 * q00.x + w10 * q10.x + w01 * q01.x + w11 * q11.x;
+                            t5 = w00 * q00.y + w10 * q10.y + w01 * q01.y + w11 * q11.y;
+                            t6 = w00 * q00.z + w10 * q10.z + w01 * q01.z + w11 * q11.z;
+                            t7 = w00 * q00.w + w10 * q10.w + w01 * q01.w + w11 * q11.w;
+                        } else {
+                            // one attribute per splat (the untextured primitive)
+                            float4 p0, q0;
+                            load_texel8(tr, 0u, p0, q0);
+                            t0 = p0.x; t1 = p0.y; t2 = p0.z; t3 = p0.w;
+                            t4 = q0.x; t5 = q0.y; t6 = q0.z; t7 = q0.w;
+                        }
                         float nl = t4 * t4 + t5 * t5 + t6 * t6;
                         float nx, ny, nz;
                         if (nl > 0.f) {
-                            float il = rsqrtf(nl);
+                            float il = __builtin_amdgcn_rsqf(nl);
                             nx = t4 * il; ny = t5 * il; nz = t6 * il;
                         } else {
                             nx = 0.f; ny = 0.f; nz = 1.f;
@@ -138,8 +157,12 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
                         last = b0 - range.x + j + 1;
                         nbl++;
                     }
+                    if (__ballot(!done) == 0) {
+                        wave_done = true;
+                        break;
+                    }
                 }
-                if (__ballot(!done) == 0) break;
+                if (wave_done) break;
             }
         }
         __syncthreads();
@@ -224,6 +247,19 @@ extern "C" int ts_raster_fwd(int32_t n_views, int32_t width, int32_t height, con
         set_error("ts_raster_fwd: tex_res %d outside 1..32", params->tex_res);
         return TS_E_ARG;
     }
+    if (params->sampler == TS_SAMPLER_HARDWARE) {
+        set_error("ts_raster_fwd: texture-unit sampling is not available on gfx950 (no image "
+                  "instructions for this target)");
+        return TS_E_UNSUPPORTED;
+    }
+    if (params->sampler != TS_SAMPLER_BILINEAR && params->sampler != TS_SAMPLER_CONSTANT) {
+        set_error("ts_raster_fwd: unknown sampler %d", params->sampler);
+        return TS_E_ARG;
+    }
+    if (params->sampler == TS_SAMPLER_CONSTANT && params->tex_res != 1) {
+        set_error("ts_raster_fwd: the constant sampler needs tex_res 1 (got %d)", params->tex_res);
+        return TS_E_ARG;
+    }
     if ((rgba != nullptr) != (env != nullptr)) {
         set_error("ts_raster_fwd: rgba and env must be given together");
         return TS_E_ARG;
@@ -257,7 +293,10 @@ extern "C" int ts_raster_fwd(int32_t n_views, int32_t width, int32_t height, con
         set_error("ts_raster_fwd: too many tiles");
         return TS_E_ARG;
     }
-    hipLaunchKernelGGL(k_raster_fwd, dim3((unsigned)blocks), dim3(256), 0, stream, a);
+    if (params->sampler == TS_SAMPLER_CONSTANT)
+        hipLaunchKernelGGL(k_raster_fwd<false>, dim3((unsigned)blocks), dim3(256), 0, stream, a);
+    else
+        hipLaunchKernelGGL(k_raster_fwd<true>, dim3((unsigned)blocks), dim3(256), 0, stream, a);
     return launch_check("ts_raster_fwd");
 }
 

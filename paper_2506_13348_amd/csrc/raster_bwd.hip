@@ -68,6 +68,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
     __shared__ float4 srec[kBwdBatch * kRec4];
     __shared__ float ent[4][kWave * kEnt];
     __shared__ int smax[4];
+    __shared__ uint32_t smask[kBwdBatch];
     const int g = gridDim.x;
     const int bid = xcd_remap(blockIdx.x, g);
     const int v = bid / a.n_tiles;
@@ -78,7 +79,6 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
     const int x = bx + (lane & 7), y = by + (lane >> 3);
     const bool inside = x < a.W && y < a.H;
     const float X = (float)x + 0.5f, Y = (float)y + 0.5f;
-    const float fbx0 = (float)bx, fbx1 = (float)(bx + 7), fby0 = (float)by, fby1 = (float)(by + 7);
     int2 range = a.ranges[(int64_t)v * a.n_tiles + t];
     range.x = (int)min((int64_t)range.x, a.cap);
     range.y = (int)min((int64_t)range.y, a.cap);
@@ -120,18 +120,25 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
         int bstart = max(0, bend - kBwdBatch);
         int nb = bend - bstart;
         __syncthreads();
+        uint32_t qmask = 0;
         if (tid < nb) {
             int id = a.pair_ids[range.x + bstart + tid];
             const float4* src = a.rec + ((int64_t)v * a.n + id) * kRec4;
 #pragma unroll
             for (int q = 0; q < kRec4; q++) srec[tid * kRec4 + q] = src[q];
+            qmask = quad_mask(src[0], tx * kTile, ty * kTile);
         }
+        if (tid < kBwdBatch) smask[tid] = qmask;
         __syncthreads();
         int jtop = min(nb, wmax - bstart);
-        for (int j = jtop - 1; j >= 0; j--) {
+        // candidates of this wave's 8x8 block below jtop, visited back to front
+        for (int rr = kBwdBatch / kWave - 1; rr >= 0; rr--) {
+          int jb = rr * kWave + lane;
+          uint64_t cand = __ballot(jb < jtop && ((smask[jb] >> w) & 1u));
+          while (cand) {
+            int j = rr * kWave + 63 - __builtin_clzll(cand);
+            cand &= ~(1ull << (j - rr * kWave));
             const float4* r = srec + j * kRec4;
-            float4 bb = r[0];
-            if (bb.z < fbx0 || bb.x > fbx1 || bb.w < fby0 || bb.y > fby1) continue;
             int pos = bstart + j;
             SplatEval ev = eval_splat(r, X, Y, a.S, a.amin, a.amax);
             float u = ev.u, vv = ev.v, alpha = ev.alpha, oG = ev.oG, G = ev.G, inv = ev.inv;
@@ -141,7 +148,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
             float geo[kGeo];
             if (bl) {
                 float4 c1 = r[1], c2 = r[2], c3 = r[3], c4 = r[4], c5 = r[5], c6 = r[6];
-                int chart = __float_as_int(c6.y);
+                int chart = __builtin_amdgcn_readfirstlane(__float_as_int(c6.y));
                 // offsets from the exact projected centre (head + low part)
                 float dx = ev.dx - c6.z, dy = ev.dy - c6.w;
                 float sx = fmaf(u, tscale, toff), sy = fmaf(vv, tscale, toff);
@@ -151,11 +158,13 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
                 int i1 = min(max(i0 + 1, 0), T - 1), j1 = min(max(j0 + 1, 0), T - 1);
                 i0 = min(max(i0, 0), T - 1);
                 j0 = min(max(j0, 0), T - 1);
-                const float4* tb = a.atlas + (int64_t)chart * chart4;
-                float4 p00 = tb[(j0 * T + i0) * 2], q00 = tb[(j0 * T + i0) * 2 + 1];
-                float4 p10 = tb[(j0 * T + i1) * 2], q10 = tb[(j0 * T + i1) * 2 + 1];
-                float4 p01 = tb[(j1 * T + i0) * 2], q01 = tb[(j1 * T + i0) * 2 + 1];
-                float4 p11 = tb[(j1 * T + i1) * 2], q11 = tb[(j1 * T + i1) * 2 + 1];
+                __amdgpu_buffer_rsrc_t tr = chart_rsrc(a.atlas + (size_t)(unsigned)chart * chart4,
+                                                       (unsigned)chart4 * 16u);
+                float4 p00, q00, p10, q10, p01, q01, p11, q11;
+                load_texel8(tr, (unsigned)(j0 * T + i0), p00, q00);
+                load_texel8(tr, (unsigned)(j0 * T + i1), p10, q10);
+                load_texel8(tr, (unsigned)(j1 * T + i0), p01, q01);
+                load_texel8(tr, (unsigned)(j1 * T + i1), p11, q11);
                 float v00[8] = {p00.x, p00.y, p00.z, p00.w, q00.x, q00.y, q00.z, q00.w};
                 float v10[8] = {p10.x, p10.y, p10.z, p10.w, q10.x, q10.y, q10.z, q10.w};
                 float v01[8] = {p01.x, p01.y, p01.z, p01.w, q01.x, q01.y, q01.z, q01.w};
@@ -304,6 +313,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
                 dst[kGeo + 4] = 0.f;
             }
             if (lane == 0) a.slots[slot_idx] = (int32_t)(off / 8);
+          }
         }
     }
 }
@@ -591,6 +601,11 @@ extern "C" int ts_raster_bwd(int32_t n_views, int32_t width, int32_t height, con
     if (params->tex_res < 1 || params->tex_res > 32) {
         set_error("ts_raster_bwd: tex_res %d outside 1..32", params->tex_res);
         return TS_E_ARG;
+    }
+    if (params->sampler != TS_SAMPLER_BILINEAR) {
+        set_error("ts_raster_bwd: only the bilinear sampler is differentiated (T = 1 textures "
+                  "give the untextured primitive)");
+        return params->sampler == TS_SAMPLER_HARDWARE ? TS_E_UNSUPPORTED : TS_E_ARG;
     }
     BwdLayout L = bwd_layout(n_views, n, pair_capacity);
     if (!ws || ws_bytes < L.total) {

@@ -39,6 +39,18 @@ __device__ inline int xcd_remap(int i, int g) {
     return x * q + (x < r ? x : r) + k;
 }
 
+// Buffer descriptor over one chart of the atlas (SGPR base, bounded to the chart's bytes: an
+// out-of-range offset reads 0 instead of faulting). Word 3 = raw 32-bit data, gfx9 layout.
+__device__ inline __amdgpu_buffer_rsrc_t chart_rsrc(const float4* chart_base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)chart_base, (short)0, (int)bytes, 0x00020000);
+}
+
+// The 8 channels of texel t of a chart: two 16-byte loads at byte offset 32 t.
+__device__ inline void load_texel8(__amdgpu_buffer_rsrc_t r, unsigned t, float4& lo, float4& hi) {
+    lo = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, t * 32u, 0, 0));
+    hi = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, t * 32u + 16u, 0, 0));
+}
+
 __device__ inline unsigned lanes_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }

@@ -13,7 +13,7 @@ import torch
 from . import _ffi as F
 
 DEFAULTS = dict(s_sigma=3.0, alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, near_z=0.2,
-                bg=(0.0, 0.0, 0.0))
+                bg=(0.0, 0.0, 0.0), sampler=0)
 IRR_RES = 16
 LUT_RES = 256
 LUT_SAMPLES = 4096

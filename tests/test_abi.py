@@ -47,3 +47,35 @@ def test_host_side_argument_errors():
                            ctypes.c_void_p(16), None, None, None, None, None, None, None) == -1
     assert b"tex_res" in L.ts_last_error()
     assert L.ts_brdf_lut(0, 16, None, None) == -1
+
+
+def test_hardware_sampler_reported_unsupported():
+    """gfx950 has no image/texture instructions: the hardware sampler is refused on the host."""
+    from paper_2506_13348_amd import _ffi
+    L = _ffi.lib()
+    p = _ffi.make_params(8, sampler=_ffi.SAMPLER_HARDWARE)
+    one = ctypes.c_void_p(16)
+    rc = L.ts_raster_fwd(1, 16, 16, one, ctypes.byref(p), 1, one, one, one, 10, one, None, None,
+                         None, None, None, None, None)
+    assert rc == -4 and b"gfx950" in L.ts_last_error()
+    p = _ffi.make_params(4, sampler=_ffi.SAMPLER_CONSTANT)
+    rc = L.ts_raster_fwd(1, 16, 16, one, ctypes.byref(p), 1, one, one, one, 10, one, None, None,
+                         None, None, None, None, None)
+    assert rc == -1 and b"tex_res 1" in L.ts_last_error()
+
+
+def test_texture_api_probe_for_gfx950(tmp_path):
+    """The probe behind TS_SAMPLER_HARDWARE: hipcc refuses tex2D for gfx950."""
+    import shutil
+    import subprocess
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    src = tmp_path / "probe.hip"
+    src.write_text("#include <hip/hip_runtime.h>\n"
+                   "__global__ void k(hipTextureObject_t t, float4* o) {\n"
+                   "  o[threadIdx.x] = tex2D<float4>(t, threadIdx.x + 0.5f, 0.5f);\n}\n")
+    r = subprocess.run([hipcc, "--offload-arch=gfx950", "--cuda-device-only", "-c", str(src),
+                        "-o", str(tmp_path / "probe.o")], capture_output=True, text=True)
+    assert r.returncode != 0
+    assert "not supported on the device" in (r.stdout + r.stderr)

@@ -175,6 +175,19 @@ def test_sq100k_full_size_sampled():
         _frame_parity(sc, pick[v], out, v=v, pixels=pix, name=f"sq100k v{v}")
 
 
+def test_constant_sampler_is_the_untextured_primitive():
+    """Sampler CONSTANT on 1x1 textures equals the oracle's 1x1-texture render."""
+    P = _pkg()
+    sc = synth.make_scene("shell2k", n=900, tex_res=1)
+    cam = synth.crop_camera(synth.config_cameras("shell2k")[0], 30, 30, 70, 60)
+    ds = P.DeviceScene.from_dict(sc, device="cuda")
+    out = P.render(ds, [cam], 70, 60, params={"sampler": 1}, gbuf=True)
+    torch.cuda.synchronize()
+    _frame_parity(sc, cam, out, name="constant sampler")
+    bil = P.render(ds, [cam], 70, 60, gbuf=True)
+    assert float((bil["gbuf"] - out["gbuf"]).abs().max()) <= 1e-6
+
+
 # ------------------------------------------------------------------------------- shading
 
 def test_shade_on_synthetic_gbuffer():
