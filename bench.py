@@ -303,6 +303,25 @@ def main():
                      "traffic": None,
                      "note": f"{n_blend} blended evaluations x {FLOPS_PER_BLEND} flops per launch"},
     }
+    # the same step with charts packed in Morton order of the centres (locality-aware atlas)
+    ds_loc = DeviceScene.from_dict(sc, device=dev, locality=True)
+    plan_loc = RenderPlan(ds_loc, cams, W, H, pair_capacity=plan.cap)
+    for _ in range(2):
+        plan_loc.run()
+    plan_loc.check()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(K):
+        plan_loc.run()
+    e1.record()
+    torch.cuda.synchronize()
+    plan_loc.check()
+    loc_ms = e0.elapsed_time(e1) / K
+    result["locality_packing"] = {"ms_per_step": round(loc_ms, 3),
+                                  "mpix_per_s": round(V * W * H / (loc_ms / 1e3) / 1e6, 2),
+                                  "speedup_vs_identity_packing": round(ms_step / loc_ms, 3)}
+    log(f"locality packing: {result['locality_packing']}")
+    del plan_loc, ds_loc
     if not args.no_fwd_bwd:
         del plan
         torch.cuda.empty_cache()

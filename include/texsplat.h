@@ -273,6 +273,18 @@ int ts_env_tables(const float* env, int32_t r, int32_t levels, int32_t irr_res, 
 int ts_atlas_pack(const float* textures, int32_t n, int32_t tex_res, const int32_t* perm,
                   float* atlas, int32_t* chart_of, hipStream_t stream);
 
+/*
+ * ts_locality_perm — a chart permutation that stores the textures of nearby primitives next to
+ * each other (the packing the paper leaves open, Sec. 4.4): perm[k] = rank of splat k in the
+ * Morton (Z-order) sequence of its centre on a 1024^3 grid over the centres' bounding box,
+ * ties by index. Pass it to ts_atlas_pack. Rendering is unchanged (a pure relabelling of
+ * charts); texel fetches of neighbouring splats share cache lines and DRAM pages more often.
+ *   means [n,3]; ws scratch of ts_locality_perm_workspace(n) bytes; perm [n] int32 out.
+ */
+int ts_locality_perm(const float* means, int32_t n, void* ws, size_t ws_bytes, int32_t* perm,
+                     hipStream_t stream);
+int ts_locality_perm_workspace(int32_t n, size_t* bytes);
+
 /* Message of the last non-zero return on this thread (never NULL). */
 const char* ts_last_error(void);
 

@@ -55,6 +55,8 @@ _SIGS = {
     "ts_brdf_lut": [c_int32, c_int32, c_void_p, c_void_p],
     "ts_env_tables": [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p],
     "ts_atlas_pack": [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p],
+    "ts_locality_perm": [c_void_p, c_int32, c_void_p, c_size_t, c_void_p, c_void_p],
+    "ts_locality_perm_workspace": [c_int32, ctypes.POINTER(c_size_t)],
 }
 
 EXPORTS = tuple(_SIGS) + ("ts_last_error",)
@@ -201,3 +203,11 @@ def ts_env_tables(env, r, levels, irr_res, spec, irr, texel_ws, stream=None):
 def ts_atlas_pack(textures, n, tex_res, perm, atlas, chart_of, stream=None):
     _check(lib().ts_atlas_pack(ptr(textures), n, tex_res, ptr(perm), ptr(atlas), ptr(chart_of),
                                stream_handle(stream)), "ts_atlas_pack")
+
+
+def ts_locality_perm(means, n, perm, stream=None):
+    nb = c_size_t(0)
+    _check(lib().ts_locality_perm_workspace(n, ctypes.byref(nb)), "ts_locality_perm_workspace")
+    ws = torch.empty(max(int(nb.value), 1), device=means.device, dtype=torch.uint8)
+    _check(lib().ts_locality_perm(ptr(means), n, ptr(ws), ws.numel(), ptr(perm),
+                                  stream_handle(stream)), "ts_locality_perm")

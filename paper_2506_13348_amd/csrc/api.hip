@@ -4,6 +4,7 @@
 
 #include "ts_internal.h"
 #include "binsort_layout.h"
+#include "sort_kernels.h"
 
 namespace ts {
 
@@ -40,9 +41,105 @@ __global__ void k_atlas_pack(const float4* __restrict__ tex, int n, int per_prim
     if (o == 0) chart_of[k] = c;
 }
 
+// Bounding box of the centres: one block, strided min/max then a tree in LDS.
+__global__ __launch_bounds__(256) void k_bbox(const float* __restrict__ means, int n,
+                                              float* __restrict__ box) {
+    __shared__ float lo[3][256], hi[3][256];
+    int tid = threadIdx.x;
+    float l[3] = {3.4e38f, 3.4e38f, 3.4e38f}, h[3] = {-3.4e38f, -3.4e38f, -3.4e38f};
+    for (int i = tid; i < n; i += 256)
+        for (int c = 0; c < 3; c++) {
+            float x = means[3 * i + c];
+            l[c] = fminf(l[c], x);
+            h[c] = fmaxf(h[c], x);
+        }
+    for (int c = 0; c < 3; c++) { lo[c][tid] = l[c]; hi[c][tid] = h[c]; }
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o)
+            for (int c = 0; c < 3; c++) {
+                lo[c][tid] = fminf(lo[c][tid], lo[c][tid + o]);
+                hi[c][tid] = fmaxf(hi[c][tid], hi[c][tid + o]);
+            }
+        __syncthreads();
+    }
+    if (tid < 3) { box[tid] = lo[tid][0]; box[3 + tid] = hi[tid][0]; }
+}
+
+__device__ inline uint32_t spread10(uint32_t x) {
+    x &= 0x3ff;
+    x = (x | (x << 16)) & 0x030000ff;
+    x = (x | (x << 8)) & 0x0300f00f;
+    x = (x | (x << 4)) & 0x030c30c3;
+    x = (x | (x << 2)) & 0x09249249;
+    return x;
+}
+
+// 30-bit Morton code of each centre on a 1024^3 grid over the bounding box.
+__global__ __launch_bounds__(256) void k_morton(const float* __restrict__ means, int n,
+                                                const float* __restrict__ box,
+                                                uint32_t* __restrict__ code) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t q[3];
+    for (int c = 0; c < 3; c++) {
+        float ext = fmaxf(box[3 + c] - box[c], 1e-30f);
+        float f = (means[3 * i + c] - box[c]) / ext;
+        q[c] = (uint32_t)fminf(fmaxf(f * 1024.f, 0.f), 1023.f);
+    }
+    code[i] = spread10(q[0]) | (spread10(q[1]) << 1) | (spread10(q[2]) << 2);
+}
+
+__global__ __launch_bounds__(256) void k_rank(const int32_t* __restrict__ order, int n,
+                                              int32_t* __restrict__ perm) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) perm[order[r]] = r;
+}
+
 }  // namespace ts
 
 using namespace ts;
+
+extern "C" int ts_locality_perm_workspace(int32_t n, size_t* bytes) {
+    if (!bytes || n < 0) {
+        set_error("ts_locality_perm_workspace: bad argument");
+        return TS_E_ARG;
+    }
+    size_t m = (size_t)(n > 0 ? n : 1);
+    int nblk = n > 0 ? (n + kSortItems - 1) / kSortItems : 1;
+    *bytes = align256(32) + 4 * align256(m * 4) + align256((size_t)kSortBuckets * nblk * 4);
+    return TS_OK;
+}
+
+extern "C" int ts_locality_perm(const float* means, int32_t n, void* ws, size_t ws_bytes,
+                                int32_t* perm, hipStream_t stream) {
+    size_t need = 0;
+    if (ts_locality_perm_workspace(n, &need) != TS_OK) return TS_E_ARG;
+    if (n > 0 && (!means || !perm)) {
+        set_error("ts_locality_perm: null array");
+        return TS_E_ARG;
+    }
+    if (!ws || ws_bytes < need) {
+        set_error("ts_locality_perm: workspace %zu < %zu bytes", ws_bytes, need);
+        return TS_E_WORKSPACE;
+    }
+    if (n == 0) return TS_OK;
+    char* w = (char*)ws;
+    size_t m4 = align256((size_t)n * 4);
+    float* box = (float*)w;
+    uint32_t* code = (uint32_t*)(w + align256(32));
+    uint32_t* ka = (uint32_t*)(w + align256(32) + m4);
+    uint32_t* kb = (uint32_t*)(w + align256(32) + 2 * m4);
+    int32_t* va = (int32_t*)(w + align256(32) + 3 * m4);
+    uint32_t* hist = (uint32_t*)(w + align256(32) + 4 * m4);
+    hipLaunchKernelGGL(k_bbox, dim3(1), dim3(256), 0, stream, means, n, box);
+    hipLaunchKernelGGL(k_morton, dim3((n + 255) / 256), dim3(256), 0, stream, means, n, box, code);
+    // the codes are read by the first pass only, so the sorted order can land in their buffer
+    int32_t* order = (int32_t*)code;
+    radix_sort_indices(code, n, 1, ka, kb, va, hist, order, stream);
+    hipLaunchKernelGGL(k_rank, dim3((n + 255) / 256), dim3(256), 0, stream, order, n, perm);
+    return launch_check("ts_locality_perm");
+}
 
 extern "C" const char* ts_last_error(void) { return g_err; }
 

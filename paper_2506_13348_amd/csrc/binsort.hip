@@ -8,6 +8,7 @@
 // offset; a second pass over each chunk, in order, writes the splat ids. Each pair is written
 // once (4 bytes) and the order inside every list is the depth order by construction.
 #include "binsort_layout.h"
+#include "sort_kernels.h"
 #include "ts_internal.h"
 
 namespace ts {
@@ -266,21 +267,8 @@ extern "C" int ts_bin_sort(int32_t n_views, int32_t width, int32_t height, int32
     if (n > 0) {
         // pass p reads (keys_in, vals_in) and writes (keys_out, vals_out); the final pass
         // writes the splat ids to sorted_ids (also used as the ping-pong value buffer)
-        const uint32_t* kin = depth_key;
-        const int32_t* vin = nullptr;
-        for (int p = 0; p < kSortPasses; p++) {
-            uint32_t* kout = (p & 1) ? keys_b : keys_a;
-            int32_t* vout = (p & 1) ? sorted_ids : vals_a;
-            int shift = p * kSortRadixBits;
-            hipLaunchKernelGGL(k_sort_hist, dim3(L.sort_blocks, n_views), dim3(kSortThreads), 0,
-                               stream, kin, n, L.sort_blocks, shift, hist);
-            hipLaunchKernelGGL(k_sort_scan, dim3(n_views), dim3(1024), 0, stream, hist,
-                               L.sort_blocks);
-            hipLaunchKernelGGL(k_sort_scatter, dim3(L.sort_blocks, n_views), dim3(kSortThreads),
-                               0, stream, kin, vin, n, L.sort_blocks, shift, hist, kout, vout);
-            kin = kout;
-            vin = vout;
-        }
+        radix_sort_indices(depth_key, n, n_views, keys_a, keys_b, vals_a, hist, sorted_ids,
+                           stream);
         static_assert(kSortPasses % 2 == 0, "the last pass must land in sorted_ids");
         if ((rc = launch_check("ts_bin_sort(sort)")) != TS_OK) return rc;
     }

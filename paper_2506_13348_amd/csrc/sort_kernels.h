@@ -1,0 +1,36 @@
+// Radix-sort kernels of binsort.hip, shared with other entry points of the library.
+#pragma once
+#include "binsort_layout.h"
+
+namespace ts {
+__global__ void k_sort_hist(const uint32_t* __restrict__ keys, int n, int nblk, int shift,
+                            uint32_t* __restrict__ hist);
+__global__ void k_sort_scan(uint32_t* __restrict__ hist, int nblk);
+__global__ void k_sort_scatter(const uint32_t* __restrict__ keys_in,
+                               const int32_t* __restrict__ vals_in, int n, int nblk, int shift,
+                               const uint32_t* __restrict__ offsets, uint32_t* __restrict__ keys_out,
+                               int32_t* __restrict__ vals_out);
+
+// Stable LSD sort of n 32-bit keys per segment (grid.y segments of n keys each):
+// vals_out[s][i] = index of the i-th smallest key of segment s. Scratch: keys_a, keys_b,
+// vals_a of n * segs each and hist of segs * 256 * nblk words.
+inline void radix_sort_indices(const uint32_t* keys, int n, int segs, uint32_t* keys_a,
+                               uint32_t* keys_b, int32_t* vals_a, uint32_t* hist,
+                               int32_t* vals_out, hipStream_t stream) {
+    int nblk = n > 0 ? (n + kSortItems - 1) / kSortItems : 1;
+    const uint32_t* kin = keys;
+    const int32_t* vin = nullptr;
+    for (int p = 0; p < kSortPasses; p++) {
+        uint32_t* kout = (p & 1) ? keys_b : keys_a;
+        int32_t* vout = (p & 1) ? vals_out : vals_a;
+        int shift = p * kSortRadixBits;
+        hipLaunchKernelGGL(k_sort_hist, dim3(nblk, segs), dim3(kSortThreads), 0, stream, kin, n,
+                           nblk, shift, hist);
+        hipLaunchKernelGGL(k_sort_scan, dim3(segs), dim3(1024), 0, stream, hist, nblk);
+        hipLaunchKernelGGL(k_sort_scatter, dim3(nblk, segs), dim3(kSortThreads), 0, stream, kin,
+                           vin, n, nblk, shift, hist, kout, vout);
+        kin = kout;
+        vin = vout;
+    }
+}
+}  // namespace ts

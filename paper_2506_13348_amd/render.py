@@ -76,7 +76,7 @@ class DeviceScene:
     """Splats + packed atlas + shading tables resident on one device."""
 
     def __init__(self, means, quats, scales, opac, textures, env=None, env_levels=1,
-                 device="cuda", perm=None, tables=None):
+                 device="cuda", perm=None, tables=None, locality=False):
         self.device = torch.device(device)
         self.means = _dev(means, device, torch.float32)
         self.quats = _dev(quats, device, torch.float32)
@@ -88,6 +88,10 @@ class DeviceScene:
         self.atlas = torch.empty_like(tex)
         self.chart_of = torch.empty(self.n, device=device, dtype=torch.int32)
         permt = None if perm is None else _dev(np.asarray(perm, np.int32), device, torch.int32)
+        if locality and perm is None and self.n:
+            # charts in Morton order of the centres: neighbouring splats share cache lines
+            permt = torch.empty(self.n, device=device, dtype=torch.int32)
+            F.ts_locality_perm(self.means, self.n, permt)
         if self.n:
             F.ts_atlas_pack(tex, self.n, self.tex_res, permt, self.atlas, self.chart_of)
         del tex

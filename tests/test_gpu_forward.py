@@ -251,3 +251,22 @@ def test_deterministic():
     _, b = _render(sc, cams, 96, 80, gbuf=True, aux=True)
     for k in ("rgba", "gbuf", "t_final", "n_contrib"):
         assert torch.equal(a[k], b[k]), k
+
+
+def test_locality_packing_is_a_relabelling():
+    """Charts in Morton order: a permutation of 0..n-1, and the same image bit for bit."""
+    P = _pkg()
+    sc = synth.make_scene("sq100k", n=20000, env_res=16)
+    cams = synth.orbit_cameras(2, 160, 120)
+    a = P.DeviceScene.from_dict(sc, device="cuda")
+    b = P.DeviceScene.from_dict(sc, device="cuda", locality=True)
+    perm = b.chart_of.cpu().numpy()
+    assert np.array_equal(np.sort(perm), np.arange(20000))
+    assert not np.array_equal(perm, np.arange(20000))
+    # neighbouring charts hold nearby splats
+    m = sc["means"][np.argsort(perm)]
+    assert np.linalg.norm(np.diff(m, axis=0), axis=1).mean() < 0.2 * np.linalg.norm(
+        np.diff(sc["means"], axis=0), axis=1).mean()
+    ra = P.render(a, cams, 160, 120)["rgba"]
+    rb = P.render(b, cams, 160, 120)["rgba"]
+    assert torch.equal(ra, rb)
