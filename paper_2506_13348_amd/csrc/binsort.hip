@@ -141,18 +141,59 @@ struct BinArgs {
     int64_t cap;
 };
 
-// One wavefront per (view, chunk): LDS counters over the view's tiles.
-template <bool kFill>
-__global__ __launch_bounds__(kWave) void k_bin_chunk(BinArgs a) {
+// Counts per (view, chunk, tile): one wavefront per chunk adds each splat's rectangle into an
+// LDS difference grid ((ntx+1) x (nty+1): +1 at (x0,y0) and (x1,y1), -1 at (x1,y0) and (x0,y1);
+// integer adds, so the order does not matter), then a 2D prefix sum turns it into coverage
+// counts.
+__global__ __launch_bounds__(kWave) void k_bin_count(BinArgs a, int nty) {
     extern __shared__ uint32_t cnt[];
     int c = blockIdx.x, v = blockIdx.y, lane = threadIdx.x;
-    uint32_t* row = a.counts + ((int64_t)v * a.n_chunks + c) * a.n_tiles;
-    const int32_t* rg = a.ranges + (int64_t)v * a.n_tiles * 2;
-    for (int t = lane; t < a.n_tiles; t += kWave) cnt[t] = kFill ? (uint32_t)rg[2 * t] + row[t] : 0u;
+    int gw = a.ntx + 1, gh = nty + 1;
+    for (int t = lane; t < gw * gh; t += kWave) cnt[t] = 0u;
     __syncthreads();
     int i0 = c * a.chunk, i1 = min(a.n, i0 + a.chunk);
     const int32_t* sv = a.sorted + (int64_t)v * a.n;
     const int4* rv = a.rect + (int64_t)v * a.n;
+    for (int b = i0 + lane; b < i1; b += kWave) {
+        int4 r = rv[sv[b]];
+        if (r.z <= r.x || r.w <= r.y) continue;
+        atomicAdd(&cnt[r.y * gw + r.x], 1u);
+        atomicAdd(&cnt[r.w * gw + r.z], 1u);
+        atomicSub(&cnt[r.y * gw + r.z], 1u);
+        atomicSub(&cnt[r.w * gw + r.x], 1u);
+    }
+    __syncthreads();
+    // prefix along rows, then along columns (wrap-around arithmetic is exact)
+    for (int y = lane; y < gh; y += kWave) {
+        uint32_t run = 0;
+        for (int x = 0; x < gw; x++) { run += cnt[y * gw + x]; cnt[y * gw + x] = run; }
+    }
+    __syncthreads();
+    for (int x = lane; x < gw; x += kWave) {
+        uint32_t run = 0;
+        for (int y = 0; y < gh; y++) { run += cnt[y * gw + x]; cnt[y * gw + x] = run; }
+    }
+    __syncthreads();
+    uint32_t* row = a.counts + ((int64_t)v * a.n_chunks + c) * a.n_tiles;
+    for (int t = lane; t < a.n_tiles; t += kWave) {
+        int ty = t / a.ntx, tx = t - ty * a.ntx;
+        row[t] = cnt[ty * gw + tx];
+    }
+}
+
+// Ordered fill: one wavefront per (view, chunk) walks its splats in depth order; the lanes
+// cover the splat's rectangle in 8x8 tile blocks; LDS cursors per tile give each entry its slot.
+__global__ __launch_bounds__(kWave) void k_bin_fill(BinArgs a) {
+    extern __shared__ uint32_t cur[];
+    int c = blockIdx.x, v = blockIdx.y, lane = threadIdx.x;
+    const uint32_t* row = a.counts + ((int64_t)v * a.n_chunks + c) * a.n_tiles;
+    const int32_t* rg = a.ranges + (int64_t)v * a.n_tiles * 2;
+    for (int t = lane; t < a.n_tiles; t += kWave) cur[t] = (uint32_t)rg[2 * t] + row[t];
+    __syncthreads();
+    int i0 = c * a.chunk, i1 = min(a.n, i0 + a.chunk);
+    const int32_t* sv = a.sorted + (int64_t)v * a.n;
+    const int4* rv = a.rect + (int64_t)v * a.n;
+    const int lx = lane & 7, ly = lane >> 3;
     for (int b = i0; b < i1; b += kWave) {
         int m = min(kWave, i1 - b);
         int id = lane < m ? sv[b + lane] : 0;
@@ -160,21 +201,20 @@ __global__ __launch_bounds__(kWave) void k_bin_chunk(BinArgs a) {
         for (int j = 0; j < m; j++) {
             int x0 = __builtin_amdgcn_readlane(r.x, j), y0 = __builtin_amdgcn_readlane(r.y, j);
             int x1 = __builtin_amdgcn_readlane(r.z, j), y1 = __builtin_amdgcn_readlane(r.w, j);
-            int wdt = x1 - x0, cntj = wdt * (y1 - y0);
-            if (cntj <= 0) continue;
-            int sid = kFill ? __builtin_amdgcn_readlane(id, j) : 0;
-            for (int e = lane; e < cntj; e += kWave) {
-                int ty = y0 + e / wdt, tx = x0 + e % wdt;
-                int t = ty * a.ntx + tx;
-                uint32_t p = cnt[t];
-                cnt[t] = p + 1;
-                if (kFill && (int64_t)p < a.cap) a.pair_ids[p] = sid;
+            if (x1 <= x0 || y1 <= y0) continue;
+            int sid = __builtin_amdgcn_readlane(id, j);
+            for (int by = y0; by < y1; by += 8) {
+                for (int bx = x0; bx < x1; bx += 8) {
+                    int tx = bx + lx, ty = by + ly;
+                    if (tx < x1 && ty < y1) {
+                        int t = ty * a.ntx + tx;
+                        uint32_t p = cur[t];
+                        cur[t] = p + 1;
+                        if ((int64_t)p < a.cap) a.pair_ids[p] = sid;
+                    }
+                }
             }
         }
-    }
-    if (!kFill) {
-        __syncthreads();
-        for (int t = lane; t < a.n_tiles; t += kWave) row[t] = cnt[t];
     }
 }
 
@@ -195,36 +235,73 @@ __global__ __launch_bounds__(256) void k_bin_scan_chunks(uint32_t* __restrict__ 
     totals[i] = run;
 }
 
-// Exclusive scan of all (view, tile) totals -> ranges, total pair count and overflow status.
-__global__ __launch_bounds__(1024) void k_bin_scan_tiles(const uint32_t* __restrict__ totals,
-                                                         int64_t m, int64_t cap,
-                                                         int32_t* __restrict__ ranges,
-                                                         int64_t* __restrict__ n_pairs,
-                                                         int32_t* __restrict__ status) {
-    __shared__ int64_t part[1024];
-    int tid = threadIdx.x;
-    int64_t per = (m + 1023) / 1024;
-    int64_t s0 = tid * per, s1 = min(m, s0 + per);
-    int64_t sum = 0;
-    for (int64_t i = s0; i < s1; i++) sum += totals[i];
-    part[tid] = sum;
+// Exclusive scan of all (view, tile) totals in three steps: block sums, a scan of the block
+// sums, then each block's own scan plus its offset -> ranges, total count, overflow status.
+constexpr int kScanBlock = 1024;
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_block_sums(const uint32_t* __restrict__ x,
+                                                                int64_t m,
+                                                                int64_t* __restrict__ sums) {
+    __shared__ int64_t red[kScanBlock];
+    int64_t i = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+    red[threadIdx.x] = i < m ? (int64_t)x[i] : 0;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        int64_t x = tid >= off ? part[tid - off] : 0;
-        __syncthreads();
-        part[tid] += x;
+    for (int o = kScanBlock / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
-    int64_t run = part[tid] - sum;
-    for (int64_t i = s0; i < s1; i++) {
-        int64_t e = run + totals[i];
-        ranges[2 * i] = (int32_t)min(run, (int64_t)0x7FFFFFFF);
-        ranges[2 * i + 1] = (int32_t)min(e, (int64_t)0x7FFFFFFF);
-        run = e;
+    if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
+}
+
+__device__ inline int64_t block_exclusive_scan(int64_t v, int64_t* sh) {
+    int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int o = 1; o < kScanBlock; o <<= 1) {
+        int64_t y = tid >= o ? sh[tid - o] : 0;
+        __syncthreads();
+        sh[tid] += y;
+        __syncthreads();
     }
-    if (tid == 1023) {
-        n_pairs[0] = part[1023];
-        status[0] = part[1023] > cap ? 1 : 0;
+    int64_t incl = sh[tid];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_sums(int64_t* __restrict__ sums, int nb,
+                                                          int64_t cap,
+                                                          int64_t* __restrict__ n_pairs,
+                                                          int32_t* __restrict__ status) {
+    __shared__ int64_t sh[kScanBlock];
+    int64_t carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += kScanBlock) {
+        int i = b0 + threadIdx.x;
+        int64_t v = i < nb ? sums[i] : 0;
+        int64_t ex = block_exclusive_scan(v, sh);
+        if (i < nb) sums[i] = carry + ex;
+        __syncthreads();
+        if (threadIdx.x == kScanBlock - 1) sh[0] = ex + v;
+        __syncthreads();
+        carry += sh[0];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        n_pairs[0] = carry;
+        status[0] = carry > cap ? 1 : 0;
+    }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_ranges(const uint32_t* __restrict__ x,
+                                                            int64_t m,
+                                                            const int64_t* __restrict__ sums,
+                                                            int32_t* __restrict__ ranges) {
+    __shared__ int64_t sh[kScanBlock];
+    int64_t i = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+    int64_t v = i < m ? (int64_t)x[i] : 0;
+    int64_t ex = block_exclusive_scan(v, sh) + sums[blockIdx.x];
+    if (i < m) {
+        ranges[2 * i] = (int32_t)min(ex, (int64_t)0x7FFFFFFF);
+        ranges[2 * i + 1] = (int32_t)min(ex + v, (int64_t)0x7FFFFFFF);
     }
 }
 
@@ -252,8 +329,8 @@ extern "C" int ts_bin_sort(int32_t n_views, int32_t width, int32_t height, int32
         set_error("ts_bin_sort: workspace %zu < %zu bytes", ws_bytes, L.total);
         return TS_E_WORKSPACE;
     }
-    if ((size_t)L.n_tiles * 4 > 64 * 1024) {
-        set_error("ts_bin_sort: %d tiles exceed the per-view limit of 16384", L.n_tiles);
+    if ((size_t)(L.ntx + 1) * (L.nty + 1) * 4 > 64 * 1024) {
+        set_error("ts_bin_sort: %d x %d tiles exceed the per-view limit", L.ntx, L.nty);
         return TS_E_ARG;
     }
     char* w = (char*)ws;
@@ -263,6 +340,7 @@ extern "C" int ts_bin_sort(int32_t n_views, int32_t width, int32_t height, int32
     uint32_t* hist = (uint32_t*)(w + L.off_hist);
     uint32_t* counts = (uint32_t*)(w + L.off_counts);
     uint32_t* totals = (uint32_t*)(w + L.off_totals);
+    int64_t* block_sums = (int64_t*)(w + L.off_blocksums);
     int rc;
     if (n > 0) {
         // pass p reads (keys_in, vals_in) and writes (keys_out, vals_out); the final pass
@@ -276,20 +354,25 @@ extern "C" int ts_bin_sort(int32_t n_views, int32_t width, int32_t height, int32
     a.n = n; a.n_chunks = L.n_chunks; a.chunk = L.chunk; a.ntx = L.ntx; a.n_tiles = L.n_tiles;
     a.sorted = sorted_ids; a.rect = (const int4*)rect; a.counts = counts; a.ranges = tile_ranges;
     a.pair_ids = pair_ids; a.cap = pair_capacity;
-    size_t lds = (size_t)L.n_tiles * 4;
+    size_t lds_count = (size_t)(L.ntx + 1) * (L.nty + 1) * 4;
+    size_t lds_fill = (size_t)L.n_tiles * 4;
     if (n > 0) {
-        hipLaunchKernelGGL(k_bin_chunk<false>, dim3(L.n_chunks, n_views), dim3(kWave), lds,
-                           stream, a);
+        hipLaunchKernelGGL(k_bin_count, dim3(L.n_chunks, n_views), dim3(kWave), lds_count, stream,
+                           a, L.nty);
     } else {
         hipMemsetAsync(counts, 0, (size_t)n_views * L.n_chunks * L.n_tiles * 4, stream);
     }
     int64_t m = (int64_t)n_views * L.n_tiles;
+    int nsb = (int)((m + kScanBlock - 1) / kScanBlock);
     hipLaunchKernelGGL(k_bin_scan_chunks, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream,
                        counts, n_views, L.n_chunks, L.n_tiles, totals);
-    hipLaunchKernelGGL(k_bin_scan_tiles, dim3(1), dim3(1024), 0, stream, totals, m, pair_capacity,
-                       tile_ranges, n_pairs, status);
+    hipLaunchKernelGGL(k_scan_block_sums, dim3(nsb), dim3(kScanBlock), 0, stream, totals, m,
+                       block_sums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, stream, block_sums, nsb,
+                       pair_capacity, n_pairs, status);
+    hipLaunchKernelGGL(k_scan_ranges, dim3(nsb), dim3(kScanBlock), 0, stream, totals, m,
+                       block_sums, tile_ranges);
     if (n > 0)
-        hipLaunchKernelGGL(k_bin_chunk<true>, dim3(L.n_chunks, n_views), dim3(kWave), lds, stream,
-                           a);
+        hipLaunchKernelGGL(k_bin_fill, dim3(L.n_chunks, n_views), dim3(kWave), lds_fill, stream, a);
     return launch_check("ts_bin_sort(bin)");
 }

@@ -20,7 +20,7 @@ struct BinSortLayout {
     int sort_blocks;      // sort blocks per view
     int n_chunks;         // depth-ordered chunks per view for the tile-list build
     int chunk;            // splats per chunk
-    size_t off_keys_a, off_keys_b, off_vals_a, off_hist, off_counts, off_totals;
+    size_t off_keys_a, off_keys_b, off_vals_a, off_hist, off_counts, off_totals, off_blocksums;
     size_t total;
 };
 
@@ -46,6 +46,7 @@ inline BinSortLayout binsort_layout(int V, int n, int W, int H) {
     L.off_hist = off;   off = align256(off + (size_t)V * kSortBuckets * L.sort_blocks * 4);
     L.off_counts = off; off = align256(off + (size_t)V * L.n_chunks * L.n_tiles * 4);
     L.off_totals = off; off = align256(off + (size_t)V * L.n_tiles * 4);
+    L.off_blocksums = off; off = align256(off + (((size_t)V * L.n_tiles + 1023) / 1024 + 1) * 8);
     L.total = off;
     return L;
 }
