@@ -1,8 +1,18 @@
 """HIP backward (ts_raster_bwd) against the float64 autograd reference (run on an MI355X).
 
-Tolerance per gradient tensor (float32 path vs float64 definition): max |g - g_ref| <=
-1e-3 max |g_ref| + 1e-7 and cosine similarity >= 0.9999. Upstream gradients are zero at pixels
-the oracle marks as near a discrete decision (there both branches are valid renders)."""
+Tolerance per gradient element (float32 path vs float64 definition):
+|g - g_ref| <= 1e-3 max |g_ref| + 1e-7 + 2 spread, and cosine similarity >= 0.9999 per tensor.
+Upstream gradients are zero at pixels the oracle marks as near a discrete decision (there both
+branches are valid renders) and at pixels where a blended splat is seen at grazing incidence
+(|cos| < 1e-3: there (u,v) has a condition number above 1e3).
+
+spread: the render is piecewise smooth. Every bilinear lookup (texels, environment cube,
+split-sum table) has a kink at each cell boundary where the derivative jumps, so at a lookup
+within float32 rounding of a boundary the gradient is set-valued and the side a float32
+evaluation lands on is decided by its rounding. spread is the largest change of the float64
+reference gradient when the splat parameters are moved by +-2^-23 (relative, random
+direction), i.e. by what float32 rounding of the inputs alone does; it is zero except at such
+kinks. Computed from the reference only."""
 import numpy as np
 import pytest
 
@@ -43,23 +53,61 @@ def _np(grads):
     return {k: g.double().cpu().numpy() for k, g in zip(NAMES, grads)}
 
 
-def _compare(g, ref, name):
+def _perturbed(sc, sign, seed):
+    """Scene with means, quats and scales moved by sign * 2^-23 relative in a random direction."""
+    r = np.random.default_rng(seed)
+    out = dict(sc)
+    for k in ("means", "quats", "scales"):
+        x = np.asarray(sc[k], np.float64)
+        out[k] = x * (1.0 + sign * 2.0 ** -23 * r.choice([-1.0, 1.0], size=x.shape))
+    return out
+
+
+def _reference(sc, cams, pix, ds, tabs):
+    """Summed float64 reference gradients over views and their spread under +-2^-23 moves."""
+    def total(scene):
+        acc = {k: 0.0 for k in NAMES}
+        for cam, d in zip(cams, ds):
+            r = og.grads(scene, cam, pix, d, tabs)
+            for k in NAMES:
+                acc[k] = acc[k] + r[k]
+        return acc
+    ref = total(sc)
+    spread = {k: np.zeros_like(ref[k]) for k in NAMES}
+    for seed in (11, 12):
+        for sign in (1.0, -1.0):
+            alt = total(_perturbed(sc, sign, seed))
+            for k in NAMES:
+                spread[k] = np.maximum(spread[k], np.abs(alt[k] - ref[k]))
+    return ref, spread
+
+
+def _compare(g, ref, name, spread=None):
     out = {}
     for k in NAMES:
         a, b = g[k].reshape(-1), ref[k].reshape(-1)
+        sp = np.zeros_like(b) if spread is None else spread[k].reshape(-1)
         scale = np.abs(b).max()
-        err = np.abs(a - b).max()
+        tol = 1e-3 * scale + 1e-7 + 2.0 * sp
+        d = np.abs(a - b)
         cos = float(a @ b / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-300))
-        out[k] = (err / max(scale, 1e-300), cos)
-        assert err <= 1e-3 * scale + 1e-7, (name, k, err, scale)
+        out[k] = (d.max() / max(scale, 1e-300), cos, int((sp > 1e-3 * scale).sum()))
+        if (d > tol).any():
+            i = int(np.argmax(d - tol))
+            print(f"[{name}] worst {k}[{i}] gpu {a[i]:.6g} ref {b[i]:.6g} spread {sp[i]:.3g}",
+                  flush=True)
+        assert (d <= tol).all(), (name, k, float(d.max()), float(scale))
         assert cos >= 0.9999, (name, k, cos)
-    print(f"[{name}] " + " ".join(f"{k}: rel {e:.2e} cos {c:.7f}" for k, (e, c) in out.items()),
-          flush=True)
+    print(f"[{name}] " + " ".join(f"{k}: rel {e:.2e} cos {c:.7f} kinks {n}"
+                                  for k, (e, c, n) in out.items()), flush=True)
 
 
 def _upstream(rng, ref, shape):
     d = rng.normal(size=(ref["rgba"].shape[0], 4))
-    d[ref["stat"][:, 2] > 0] = 0.0
+    skip = (ref["stat"][:, 2] > 0) | (ref["stat"][:, 3] > 0)
+    d[skip] = 0.0
+    print(f"[upstream] {int(skip.sum())} of {len(skip)} pixels excluded "
+          f"({int((ref['stat'][:, 3] > 0).sum())} grazing)", flush=True)
     return d, d.reshape(shape)
 
 
@@ -91,16 +139,15 @@ def test_grads_multi_view_ragged():
     tabs = oracle.tables(sc["env"], 1)
     pix = oracle.all_pixels(45, 37)
     d_all = np.zeros((3, 37, 45, 4))
-    ref = {k: 0.0 for k in NAMES}
+    ds = []
     for v, cam in enumerate(cams):
         ref_f = oracle.render(sc, cam, pixels=pix, tabs=tabs)
         d, d4 = _upstream(rng, ref_f, (37, 45, 4))
         d_all[v] = d4
-        r = og.grads(sc, cam, pix, d, tabs)
-        for k in NAMES:
-            ref[k] = ref[k] + r[k]
+        ds.append(d)
+    ref, spread = _reference(sc, cams, pix, ds, tabs)
     g, _ = _gpu_grads(sc, cams, 45, 37, d_all)
-    _compare(_np(g), ref, "3 views")
+    _compare(_np(g), ref, "3 views", spread)
 
 
 @pytest.mark.parametrize("T", [1, 16])
@@ -111,9 +158,9 @@ def test_grads_texture_resolution(T):
     pix = oracle.all_pixels(40, 40)
     ref_f = oracle.render(sc, cam, pixels=pix, tabs=tabs)
     d, d4 = _upstream(np.random.default_rng(T), ref_f, (1, 40, 40, 4))
-    ref = og.grads(sc, cam, pix, d, tabs)
+    ref, spread = _reference(sc, [cam], pix, [d], tabs)
     g, _ = _gpu_grads(sc, [cam], 40, 40, d4)
-    _compare(_np(g), ref, f"T={T}")
+    _compare(_np(g), ref, f"T={T}", spread)
 
 
 def test_deterministic_beta_and_overflow_retry():
