@@ -1,11 +1,18 @@
-"""Throughput of the textured planar-Gaussian forward render on one MI355X.
+"""Throughput of the textured planar-Gaussian render on one MI355X.
 
-Workload (one step): the 100,000-splat superquadric scene with 8x8 textures per primitive,
-rendered from all 64 orbit cameras at 800x800 (preprocess -> depth sort + tile lists ->
-raster with texture sampling, normal mapping, G-buffer blending and fused split-sum shading),
-inputs and shading tables resident in HBM. Prints one JSON line.
+Headline step (the JSON line's value): the 100,000-splat superquadric scene with 8x8 textures
+per primitive, rendered from all 64 orbit cameras at 800x800 (preprocess -> depth sort + tile
+lists -> raster with texture sampling, normal mapping, G-buffer blending and fused split-sum
+shading), inputs and shading tables resident in HBM.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Further legs, reported in the same JSON object: the step with locality-packed charts;
+forward+backward training steps (300k splats x 8 views at 800x800, and the 1M-splat
+1600x1064 unbounded frame); the 2k-splat 128x128 frame's latency; texture-sampling cost
+against the untextured primitive (the paper's Tab. 3); the serving loop against sequential
+renders; and the FP64 oracle timed on a bounded pixel sample on the host cores.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-fwd-bwd]
+                  [--no-tab3] [--no-serving] [--serving-seconds S] [--profile-run]
 """
 import argparse
 import json
@@ -48,9 +55,18 @@ def cpu_baseline(scene, cam, n_pix=40000, seed=0):
             "evals_per_s": round(float(out["stat"][:, 0].sum()) / dt, 1)}
 
 
-def bench_fwd_bwd(steps, warmup):
-    """One training step of the 300k-splat scene: forward of a batch of 8 orbit views at
-    800x800, L1 loss to a seeded target, hand-written backward to all splat parameters."""
+FWD_BWD_WORKLOADS = {
+    "sq300k_train": "sq300k: 300k splats T=8, 8 orbit views 800x800 per step, L1 to a seeded "
+                    "U(0,1) target, gradients to means/quats/scales/opacity/texels",
+    "field1m": "field1m: 1M splats T=8 (height field + boxes + far shell), one 1600x1064 view "
+               "per step, 256^2 env with 4 levels, L1 to a seeded U(0,1) target, gradients to "
+               "means/quats/scales/opacity/texels",
+}
+
+
+def bench_fwd_bwd(cfg, steps, warmup):
+    """One training step: forward of the config's batch of views, L1 loss to a seeded target,
+    hand-written backward to all splat parameters."""
     import numpy as np
     import torch
 
@@ -58,9 +74,9 @@ def bench_fwd_bwd(steps, warmup):
     from paper_2506_13348_amd import DeviceScene, RenderPlan
     from paper_2506_13348_amd.autograd import BackwardRunner
 
-    sc = synth.make_scene("sq300k_train")
-    cams = synth.config_cameras("sq300k_train")
-    V, W, H = len(cams), 800, 800
+    sc = synth.make_scene(cfg)
+    cams = synth.config_cameras(cfg)
+    V, W, H = len(cams), cams[0]["width"], cams[0]["height"]
     ds = DeviceScene.from_dict(sc, device="cuda")
     del sc
     target = torch.as_tensor(synth.target_image(W, H, seed=1, n_views=V)).cuda()
@@ -100,12 +116,45 @@ def bench_fwd_bwd(steps, warmup):
         raise RuntimeError("backward partial buffer overflow in the timed steps")
     fwd_ms = float(np.mean([ev[k][0].elapsed_time(ev[k][1]) for k in range(steps)]))
     bwd_ms = float(np.mean([ev[k][1].elapsed_time(ev[k][2]) for k in range(steps)]))
-    return {"value": round(V * W * H / dt / 1e6, 2), "unit": "Mpix/s", "ms_per_step": round(dt * 1e3, 3),
-            "steps": steps, "views_per_step": V, "splats": ds.n,
-            "per_phase_ms": {"forward": round(fwd_ms, 3), "loss_and_backward": round(bwd_ms, 3)},
-            "workload": "sq300k: 300k splats T=8, 8 orbit views 800x800 per step, L1 to a "
-                        "seeded U(0,1) target, gradients to means/quats/scales/opacity/texels",
-            "partial_buffer_floats": int(run.partials.numel())}
+    out = {"value": round(V * W * H / dt / 1e6, 2), "unit": "Mpix/s",
+           "ms_per_step": round(dt * 1e3, 3), "steps": steps, "views_per_step": V,
+           "width": W, "height": H, "splats": ds.n,
+           "per_phase_ms": {"forward": round(fwd_ms, 3), "loss_and_backward": round(bwd_ms, 3)},
+           "workload": FWD_BWD_WORKLOADS[cfg],
+           "partial_buffer_floats_used": int(run.used.item())}
+    del plan, run, grads, d_rgba, target, ds
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_small_frame(reps=200):
+    """The 2,000-splat shell, one 128x128 view, T = 4: a launch-latency-bound frame; median
+    of per-frame times over reps renders."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2506_13348_amd import DeviceScene, RenderPlan
+
+    sc = synth.make_scene("shell2k")
+    cams = synth.config_cameras("shell2k")
+    ds = DeviceScene.from_dict(sc, device="cuda")
+    plan = RenderPlan(ds, cams, 128, 128)
+    for _ in range(10):
+        plan.run()
+    plan.check()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record()
+        plan.run()
+        e1.record()
+    torch.cuda.synchronize()
+    ts = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+    med = float(np.median(ts))
+    return {"workload": "shell2k: 2k splats T=4, one 128x128 view, 32^2 env",
+            "median_us": round(med * 1e3, 1), "p90_us": round(float(np.percentile(ts, 90)) * 1e3, 1),
+            "mpix_per_s": round(128 * 128 / (med / 1e3) / 1e6, 2)}
 
 
 def bench_tab3(steps=5):
@@ -326,8 +375,12 @@ def main():
         del plan
         torch.cuda.empty_cache()
         log("forward+backward ...")
-        result["fwd_bwd"] = bench_fwd_bwd(max(3, K // 2), 1)
+        result["fwd_bwd"] = bench_fwd_bwd("sq300k_train", max(3, K // 2), 1)
         log(f"fwd+bwd: {result['fwd_bwd']}")
+        result["fwd_bwd_field1m"] = bench_fwd_bwd("field1m", max(3, K // 2), 1)
+        log(f"fwd+bwd field1m: {result['fwd_bwd_field1m']}")
+    result["small_frame"] = bench_small_frame()
+    log(f"small frame: {result['small_frame']}")
     if not args.no_tab3:
         torch.cuda.empty_cache()
         log("texture sampling cost (Tab. 3 analog) ...")

@@ -209,7 +209,9 @@ int ts_shade(int32_t n_views, int32_t width, int32_t height, const ts_camera* ca
  *   partials scratch for per-(tile entry, 8x8 block) partial sums, partial_capacity floats;
  *            if it is too small, *status is set to 2 and the gradients are incomplete
  *            (re-run with a larger buffer). A frame needs about 24 + 8 * (texels touched)
- *            floats per (entry, 8x8 block) with a blended pixel.
+ *            floats per (entry, 8x8 block) with a blended pixel; each 8x8 block of the frame
+ *            takes the buffer in chunks of 2048 floats, so up to that much more per block.
+ *            At most 2^34 floats (TS_E_ARG above).
  *   status   [1] int32 device word, set to 2 on partial-buffer overflow (never cleared here);
  *            the gradient outputs are written only if it is 0 once the partials are built,
  *            so a run that overflowed can be repeated with a larger buffer for any beta

@@ -147,7 +147,8 @@ struct BinArgs {
 // counts.
 __global__ __launch_bounds__(kWave) void k_bin_count(BinArgs a, int nty) {
     extern __shared__ uint32_t cnt[];
-    int c = blockIdx.x, v = blockIdx.y, lane = threadIdx.x;
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    int v = bid / a.n_chunks, c = bid - v * a.n_chunks, lane = threadIdx.x;
     int gw = a.ntx + 1, gh = nty + 1;
     for (int t = lane; t < gw * gh; t += kWave) cnt[t] = 0u;
     __syncthreads();
@@ -185,7 +186,10 @@ __global__ __launch_bounds__(kWave) void k_bin_count(BinArgs a, int nty) {
 // cover the splat's rectangle in 8x8 tile blocks; LDS cursors per tile give each entry its slot.
 __global__ __launch_bounds__(kWave) void k_bin_fill(BinArgs a) {
     extern __shared__ uint32_t cur[];
-    int c = blockIdx.x, v = blockIdx.y, lane = threadIdx.x;
+    // every chunk of a view on the same XCD: the chunks write interleaved short runs of the
+    // same tile lists, whose cache lines are then completed in one L2
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    int v = bid / a.n_chunks, c = bid - v * a.n_chunks, lane = threadIdx.x;
     const uint32_t* row = a.counts + ((int64_t)v * a.n_chunks + c) * a.n_tiles;
     const int32_t* rg = a.ranges + (int64_t)v * a.n_tiles * 2;
     for (int t = lane; t < a.n_tiles; t += kWave) cur[t] = (uint32_t)rg[2 * t] + row[t];
@@ -216,6 +220,11 @@ __global__ __launch_bounds__(kWave) void k_bin_fill(BinArgs a) {
             }
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int64_t m, uint32_t x) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) p[i] = x;
 }
 
 // Column scan over chunks per (view, tile): counts become exclusive prefixes.
@@ -357,10 +366,13 @@ extern "C" int ts_bin_sort(int32_t n_views, int32_t width, int32_t height, int32
     size_t lds_count = (size_t)(L.ntx + 1) * (L.nty + 1) * 4;
     size_t lds_fill = (size_t)L.n_tiles * 4;
     if (n > 0) {
-        hipLaunchKernelGGL(k_bin_count, dim3(L.n_chunks, n_views), dim3(kWave), lds_count, stream,
-                           a, L.nty);
+        hipLaunchKernelGGL(k_bin_count, dim3(L.n_chunks * n_views), dim3(kWave), lds_count,
+                           stream, a, L.nty);
     } else {
-        hipMemsetAsync(counts, 0, (size_t)n_views * L.n_chunks * L.n_tiles * 4, stream);
+        // a kernel, not a memset: the call may be captured into a graph
+        int64_t mc = (int64_t)n_views * L.n_chunks * L.n_tiles;
+        hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((mc + 255) / 256)), dim3(256), 0, stream,
+                           counts, mc, 0u);
     }
     int64_t m = (int64_t)n_views * L.n_tiles;
     int nsb = (int)((m + kScanBlock - 1) / kScanBlock);
@@ -373,6 +385,7 @@ extern "C" int ts_bin_sort(int32_t n_views, int32_t width, int32_t height, int32
     hipLaunchKernelGGL(k_scan_ranges, dim3(nsb), dim3(kScanBlock), 0, stream, totals, m,
                        block_sums, tile_ranges);
     if (n > 0)
-        hipLaunchKernelGGL(k_bin_fill, dim3(L.n_chunks, n_views), dim3(kWave), lds_fill, stream, a);
+        hipLaunchKernelGGL(k_bin_fill, dim3(L.n_chunks * n_views), dim3(kWave), lds_fill, stream,
+                           a);
     return launch_check("ts_bin_sort(bin)");
 }

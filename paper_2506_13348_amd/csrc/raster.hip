@@ -76,9 +76,14 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
         if (tid < nb) {
             int id = a.pair_ids[b0 + tid];
             const float4* src = recv + ((int64_t)v * a.n + (int64_t)id) * kRec4;
+            float4 r0 = src[0], r1 = src[1], r2 = src[2], r3 = src[3];
+            srec[tid * kRec4 + 0] = r0;
+            srec[tid * kRec4 + 1] = r1;
+            srec[tid * kRec4 + 2] = r2;
+            srec[tid * kRec4 + 3] = r3;
 #pragma unroll
-            for (int q = 0; q < kRec4; q++) srec[tid * kRec4 + q] = src[q];
-            qm = quad_mask(src[0], tx * kTile, ty * kTile);
+            for (int q = 4; q < kRec4; q++) srec[tid * kRec4 + q] = src[q];
+            qm = quad_mask_uv(r0, r1, r2, r3, tx * kTile, ty * kTile, a.S, a.amin);
         }
         smask[tid] = qm;
         __syncthreads();

@@ -13,7 +13,7 @@
 //    the opacity and sigma R. Each wave (8x8 pixels) sums its pixels' contributions for one
 //    splat in a fixed lane order and writes one partial — 19 geometric values and the window
 //    of texels it touched — into a slot of a partial buffer. No value is accumulated with
-//    atomics; a single integer atomic hands out slot space.
+//    atomics; a wave takes buffer space in chunks of kChunk floats with one integer atomic.
 // 3. k_bwd_gather: per splat, the partials of its (view, tile, quadrant) entries summed in a
 //    fixed order -> per-view record gradients and the splat's texel gradients.
 // 4. k_bwd_params: per splat, in double precision, the record gradients of every view chained
@@ -27,7 +27,8 @@ namespace ts {
 constexpr int kGeo = 19;          // px py ux uy vx vy wx wy w0 opacity sR[9]
 constexpr int kHdr = 24;          // floats in a partial's header: 19 geometric + window i0 j0 wi wj + pad
 constexpr int kBwdBatch = 128;
-constexpr int kEnt = 36;          // LDS floats per lane entry: taps (4 ints), fx, fy, q[8], pad 2, geo[19], pad 1
+constexpr int kEnt = 36;
+constexpr int kChunk = 2048;      // floats of the partial buffer a wave takes at a time          // LDS floats per lane entry: taps (4 ints), fx, fy, q[8], pad 2, geo[19], pad 1
 
 struct BwdArgs {
     int V, W, H, ntx, n_tiles, T, n;
@@ -115,6 +116,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
     int tile_max = max(max(smax[0], smax[1]), max(smax[2], smax[3]));
     float Tr = Tf;
     float accum = 0.f;
+    unsigned long long ccur = 0, cend = 0;   // this wave's chunk of the partial buffer
 
     for (int bend = tile_max; bend > 0; bend -= kBwdBatch) {
         int bstart = max(0, bend - kBwdBatch);
@@ -124,9 +126,14 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
         if (tid < nb) {
             int id = a.pair_ids[range.x + bstart + tid];
             const float4* src = a.rec + ((int64_t)v * a.n + id) * kRec4;
+            float4 r0 = src[0], r1 = src[1], r2 = src[2], r3 = src[3];
+            srec[tid * kRec4 + 0] = r0;
+            srec[tid * kRec4 + 1] = r1;
+            srec[tid * kRec4 + 2] = r2;
+            srec[tid * kRec4 + 3] = r3;
 #pragma unroll
-            for (int q = 0; q < kRec4; q++) srec[tid * kRec4 + q] = src[q];
-            qmask = quad_mask(src[0], tx * kTile, ty * kTile);
+            for (int q = 4; q < kRec4; q++) srec[tid * kRec4 + q] = src[q];
+            qmask = quad_mask_uv(r0, r1, r2, r3, tx * kTile, ty * kTile, a.S, a.amin);
         }
         if (tid < kBwdBatch) smask[tid] = qmask;
         __syncthreads();
@@ -263,9 +270,18 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
             int wi1 = wave_max_i(bi1), wj1 = wave_max_i(bj1);
             int wi = wi1 - wi0 + 1, wj = wj1 - wj0 + 1, wt = wi * wj;
             int64_t need = kHdr + (int64_t)wt * 8;
-            unsigned long long off = 0;
-            if (lane == 0) off = atomicAdd(a.part_top, (unsigned long long)need);
-            off = __shfl(off, 0);
+            // space from this wave's current chunk; a new chunk (one integer atomic) when
+            // it is used up
+            if (ccur + (unsigned long long)need > cend) {
+                unsigned long long take = (unsigned long long)max(need, (int64_t)kChunk);
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd(a.part_top, take);
+                base = __shfl(base, 0);
+                ccur = base;
+                cend = base + take;
+            }
+            unsigned long long off = ccur;
+            ccur += (unsigned long long)need;
             bool fits = (int64_t)off + need <= a.part_cap;
             int64_t slot_idx = ((int64_t)range.x + pos) * 4 + w;
             if (!fits) {
@@ -276,17 +292,31 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
                 continue;
             }
             float* dst = a.part + off;
-            // geometric sums, lanes 0..18, blended lanes in ascending order
-            float gsum = 0.f;
-            // texel windows: lane owns texels lane, lane+64, ...
+            // geometric sums: lane k + 19 g (g = 0..2) sums entry k over the blended pixels
+            // p = g, g + 3, ...; the three groups are added in a fixed order
+            {
+                float gs = 0.f;
+                if (lane < 3 * kGeo) {
+                    int k = lane % kGeo, g3 = lane / kGeo;
+                    for (int p = g3; p < kWave; p += 3)
+                        if ((blm >> p) & 1ull) gs += E[p * kEnt + 16 + k];
+                }
+                float g1 = __shfl(gs, (lane + kGeo) & 63), g2 = __shfl(gs, (lane + 2 * kGeo) & 63);
+                if (lane < kGeo) dst[lane] = (gs + g1) + g2;
+            }
+            // texel window: lanes form groups of L = pow2 >= wt lanes (texel = lane mod L);
+            // group g sums the blended pixels p = g, g + 64/L, ... in order, then the groups
+            // are combined by a fixed butterfly
+            int L = 1;
+            while (L < wt && L < kWave) L <<= 1;
+            const int ngrp = kWave / L;
+            const int tl = lane & (L - 1), grp = lane / L;
             for (int t0 = 0; t0 < wt; t0 += kWave) {
-                int tt = t0 + lane;
+                int tt = t0 + tl;
                 int ti = wi0 + (tt % wi), tj = wj0 + (tt / wi);
                 float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-                uint64_t mm = blm;
-                while (mm) {
-                    int p = __builtin_ctzll(mm);
-                    mm &= mm - 1;
+                for (int p = grp; p < kWave; p += ngrp) {
+                    if (!((blm >> p) & 1ull)) continue;
                     const float* pe = E + p * kEnt;
                     int pi0 = __float_as_int(pe[0]), pi1 = __float_as_int(pe[1]);
                     int pj0 = __float_as_int(pe[2]), pj1 = __float_as_int(pe[3]);
@@ -296,15 +326,17 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
                     float wq = wxp * wyp;
 #pragma unroll
                     for (int c = 0; c < 8; c++) acc[c] = fmaf(wq, pe[6 + c], acc[c]);
-                    if (t0 == 0 && lane < kGeo) gsum += pe[16 + lane];
                 }
-                if (tt < wt) {
+                for (int sft = L; sft < kWave; sft <<= 1) {
+#pragma unroll
+                    for (int c = 0; c < 8; c++) acc[c] += __shfl_xor(acc[c], sft);
+                }
+                if (grp == 0 && tt < wt) {
                     float4* d4 = (float4*)(dst + kHdr + (int64_t)tt * 8);
                     d4[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
                     d4[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
                 }
             }
-            if (lane < kGeo) dst[lane] = gsum;
             if (lane == kGeo) {
                 dst[kGeo + 0] = __int_as_float(wi0);
                 dst[kGeo + 1] = __int_as_float(wj0);
@@ -343,32 +375,76 @@ __global__ __launch_bounds__(256) void k_bwd_pairs(int V, int n, int ntx, int n_
     }
 }
 
-// Exclusive scan of rect areas over (view, splat) -> start offsets (int64), single block.
-__global__ __launch_bounds__(1024) void k_area_scan(const int4* __restrict__ rect, int64_t m,
-                                                    int64_t* __restrict__ start) {
-    __shared__ int64_t part[1024];
+// Exclusive scan of rect areas over (view, splat) -> int64 start offsets, in three passes:
+// per-block totals (1024 entries per block, 4 per thread), a scan of the block totals, and the
+// in-block scan plus the block's offset.
+constexpr int kAreaPer = 4;
+constexpr int kAreaBlock = 256 * kAreaPer;
+
+__device__ inline int64_t rect_area(int4 r) {
+    return (int64_t)max(r.z - r.x, 0) * max(r.w - r.y, 0);
+}
+
+__device__ inline int64_t block_excl_scan_256(int64_t x, int64_t* sh, int64_t* total) {
     int tid = threadIdx.x;
-    int64_t per = (m + 1023) / 1024;
-    int64_t a0 = tid * per, a1 = min(m, a0 + per);
-    int64_t sum = 0;
-    for (int64_t i = a0; i < a1; i++) {
-        int4 r = rect[i];
-        sum += (int64_t)max(r.z - r.x, 0) * max(r.w - r.y, 0);
-    }
-    part[tid] = sum;
+    sh[tid] = x;
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        int64_t x = tid >= o ? part[tid - o] : 0;
+    for (int o = 1; o < 256; o <<= 1) {
+        int64_t y = tid >= o ? sh[tid - o] : 0;
         __syncthreads();
-        part[tid] += x;
+        sh[tid] += y;
         __syncthreads();
     }
-    int64_t run = part[tid] - sum;
-    for (int64_t i = a0; i < a1; i++) {
-        start[i] = run;
-        int4 r = rect[i];
-        run += (int64_t)max(r.z - r.x, 0) * max(r.w - r.y, 0);
+    int64_t incl = sh[tid];
+    if (total) *total = sh[255];
+    __syncthreads();
+    return incl - x;
+}
+
+__global__ __launch_bounds__(256) void k_area_sums(const int4* __restrict__ rect, int64_t m,
+                                                   int64_t* __restrict__ bsum) {
+    __shared__ int64_t sh[256];
+    int64_t i0 = (int64_t)blockIdx.x * kAreaBlock + threadIdx.x * kAreaPer;
+    int64_t s = 0;
+    for (int k = 0; k < kAreaPer; k++)
+        if (i0 + k < m) s += rect_area(rect[i0 + k]);
+    int64_t tot;
+    block_excl_scan_256(s, sh, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// Single block: exclusive scan of nb block totals in place.
+__global__ __launch_bounds__(256) void k_area_scan_sums(int64_t* __restrict__ bsum, int nb) {
+    __shared__ int64_t sh[256];
+    int per = (nb + 255) / 256;
+    int a0 = threadIdx.x * per, a1 = min(nb, a0 + per);
+    int64_t s = 0;
+    for (int i = a0; i < a1; i++) s += bsum[i];
+    int64_t run = block_excl_scan_256(s, sh, nullptr);
+    for (int i = a0; i < a1; i++) {
+        int64_t x = bsum[i];
+        bsum[i] = run;
+        run += x;
     }
+}
+
+__global__ __launch_bounds__(256) void k_area_apply(const int4* __restrict__ rect, int64_t m,
+                                                    const int64_t* __restrict__ bsum,
+                                                    int64_t* __restrict__ start) {
+    __shared__ int64_t sh[256];
+    int64_t i0 = (int64_t)blockIdx.x * kAreaBlock + threadIdx.x * kAreaPer;
+    int64_t ar[kAreaPer];
+    int64_t s = 0;
+    for (int k = 0; k < kAreaPer; k++) {
+        ar[k] = i0 + k < m ? rect_area(rect[i0 + k]) : 0;
+        s += ar[k];
+    }
+    int64_t run = block_excl_scan_256(s, sh, nullptr) + bsum[blockIdx.x];
+    for (int k = 0; k < kAreaPer; k++)
+        if (i0 + k < m) {
+            start[i0 + k] = run;
+            run += ar[k];
+        }
 }
 
 __global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
@@ -376,7 +452,9 @@ __global__ void k_copy_u64(const unsigned long long* src, int64_t* dst) { *dst =
 
 // One wave per splat: views in order, tiles of rect(s) in row-major order, quadrants 0..3.
 // Lane l owns texels l, l+64, ... of the splat's chart; one pass over the partials per group
-// of 64 texels.
+// of 64 texels. The entries are taken 64 at a time: lane e looks up entry e's slot and window
+// (so those dependent loads overlap), then the entries are summed one after another in order,
+// their slot and window read from the owning lane.
 __global__ __launch_bounds__(64) void k_bwd_gather(int V, int n, int T, const int4* __restrict__ rect,
                                                    const int64_t* __restrict__ start,
                                                    const int32_t* __restrict__ pair_pos,
@@ -393,23 +471,41 @@ __global__ __launch_bounds__(64) void k_bwd_gather(int V, int n, int T, const in
     for (int t0 = 0; t0 < TT; t0 += kWave) {
         int tt = t0 + lane;
         int ti = tt % T, tj = tt / T;
+        bool own = tt < TT;
         float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         for (int v = 0; v < V; v++) {
             int4 r = rect[(int64_t)v * n + s];
             int cnt = max(r.z - r.x, 0) * max(r.w - r.y, 0);
+            if (cnt == 0) {
+                if (t0 == 0 && lane < kGeo) rec_grad[((int64_t)v * n + s) * kGeo + lane] = 0.f;
+                continue;
+            }
             int64_t st = start[(int64_t)v * n + s];
             float gs = 0.f;
-            for (int k = 0; k < cnt; k++) {
-                int p = pair_pos[st + k];
-                for (int q = 0; q < 4; q++) {
-                    int sl = slots[(int64_t)p * 4 + q];
-                    if (sl < 0) continue;
-                    const float* src = part + (int64_t)sl * 8;
+            int ne = cnt * 4;
+            for (int e0 = 0; e0 < ne; e0 += kWave) {
+                int e = e0 + lane;
+                int sl = -1;
+                int win = 0;   // packed i0 | j0 << 8 | wi << 16 | wj << 24 (all < 256)
+                if (e < ne) {
+                    int p = pair_pos[st + (e >> 2)];
+                    sl = slots[(int64_t)p * 4 + (e & 3)];
+                    if (sl >= 0) {
+                        const float* h = part + (int64_t)sl * 8 + kGeo;
+                        win = __float_as_int(h[0]) | (__float_as_int(h[1]) << 8) |
+                              (__float_as_int(h[2]) << 16) | (__float_as_int(h[3]) << 24);
+                    }
+                }
+                int m = min(kWave, ne - e0);
+                for (int j = 0; j < m; j++) {
+                    int slj = __shfl(sl, j);
+                    if (slj < 0) continue;
+                    int wj = __shfl(win, j);
+                    const float* src = part + (int64_t)slj * 8;
                     if (t0 == 0 && lane < kGeo) gs += src[lane];
-                    int wi0 = __float_as_int(src[kGeo + 0]), wj0 = __float_as_int(src[kGeo + 1]);
-                    int wi = __float_as_int(src[kGeo + 2]), wj = __float_as_int(src[kGeo + 3]);
-                    int li = ti - wi0, lj = tj - wj0;
-                    if (tt < TT && li >= 0 && lj >= 0 && li < wi && lj < wj) {
+                    int li = ti - (wj & 255), lj = tj - ((wj >> 8) & 255);
+                    int wi = (wj >> 16) & 255, wh = (wj >> 24) & 255;
+                    if (own && li >= 0 && lj >= 0 && li < wi && lj < wh) {
                         const float4* s4 = (const float4*)(src + kHdr + (int64_t)(lj * wi + li) * 8);
                         float4 lo = s4[0], hi = s4[1];
                         acc[0] += lo.x; acc[1] += lo.y; acc[2] += lo.z; acc[3] += lo.w;
@@ -419,7 +515,7 @@ __global__ __launch_bounds__(64) void k_bwd_gather(int V, int n, int T, const in
             }
             if (t0 == 0 && lane < kGeo) rec_grad[((int64_t)v * n + s) * kGeo + lane] = gs;
         }
-        if (tt < TT) {
+        if (own) {
             float4 lo = make_float4(acc[0], acc[1], acc[2], acc[3]);
             float4 hi = make_float4(acc[4], acc[5], acc[6], acc[7]);
             if (beta != 0.f) {
@@ -548,7 +644,8 @@ __global__ __launch_bounds__(256) void k_bwd_params(int V, int n, const ts_camer
 }
 
 struct BwdLayout {
-    size_t off_start, off_pairpos, off_slots, off_recgrad, off_top, total;
+    size_t off_start, off_pairpos, off_slots, off_recgrad, off_top, off_bsum, total;
+    int area_blocks;
 };
 
 inline BwdLayout bwd_layout(int V, int n, int64_t cap) {
@@ -562,6 +659,8 @@ inline BwdLayout bwd_layout(int V, int n, int64_t cap) {
     L.off_slots = off; off = al(off + c * 16);
     L.off_recgrad = off; off = al(off + vn * kGeo * 4);
     L.off_top = off; off = al(off + 8);
+    L.area_blocks = (int)((vn + kAreaBlock - 1) / kAreaBlock);
+    L.off_bsum = off; off = al(off + (size_t)L.area_blocks * 8);
     L.total = off;
     return L;
 }
@@ -607,6 +706,11 @@ extern "C" int ts_raster_bwd(int32_t n_views, int32_t width, int32_t height, con
                   "give the untextured primitive)");
         return params->sampler == TS_SAMPLER_HARDWARE ? TS_E_UNSUPPORTED : TS_E_ARG;
     }
+    if (partial_capacity < 0 || partial_capacity > (int64_t)INT32_MAX * 8) {
+        set_error("ts_raster_bwd: partial_capacity %lld outside 0..2^34 floats",
+                  (long long)partial_capacity);
+        return TS_E_ARG;
+    }
     BwdLayout L = bwd_layout(n_views, n, pair_capacity);
     if (!ws || ws_bytes < L.total) {
         set_error("ts_raster_bwd: workspace %zu < %zu bytes", ws_bytes, L.total);
@@ -622,7 +726,12 @@ extern "C" int ts_raster_bwd(int32_t n_views, int32_t width, int32_t height, con
     int ntx = tiles_x(width), n_tiles = ntx * tiles_y(height);
     int64_t vn = (int64_t)n_views * n;
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, stream, top);
-    hipLaunchKernelGGL(k_area_scan, dim3(1), dim3(1024), 0, stream, (const int4*)rect, vn, start);
+    int64_t* bsum = (int64_t*)(wsc + L.off_bsum);
+    hipLaunchKernelGGL(k_area_sums, dim3(L.area_blocks), dim3(256), 0, stream, (const int4*)rect,
+                       vn, bsum);
+    hipLaunchKernelGGL(k_area_scan_sums, dim3(1), dim3(256), 0, stream, bsum, L.area_blocks);
+    hipLaunchKernelGGL(k_area_apply, dim3(L.area_blocks), dim3(256), 0, stream,
+                       (const int4*)rect, vn, (const int64_t*)bsum, start);
     hipLaunchKernelGGL(k_bwd_pairs, dim3(n_views * n_tiles), dim3(256), 0, stream, n_views, n, ntx,
                        n_tiles, (const int2*)tile_ranges, pair_capacity, pair_ids,
                        (const int4*)rect, (const int64_t*)start, pair_pos, slots);

@@ -49,14 +49,21 @@ __device__ inline void cube_sample_bwd(const float4* __restrict__ cube, int r, c
     int m_ax, s_ax, t_ax;
     float m_sign, s_sign, t_sign;
     face_axes(tap.face, m_ax, m_sign, s_ax, s_sign, t_ax, t_sign);
-    float ma = m_sign * d[m_ax];
-    float sc = s_sign * d[s_ax], tc = t_sign * d[t_ax];
+    // axis selects instead of indexing by a run-time axis (keeps d and gd in registers)
+    auto pick = [&](int ax) {
+        return (float)(ax == 0) * d[0] + (float)(ax == 1) * d[1] + (float)(ax == 2) * d[2];
+    };
+    float ma = m_sign * pick(m_ax);
+    float sc = s_sign * pick(s_ax), tc = t_sign * pick(t_ax);
     float hr = 0.5f * (float)r;
     float ima = 1.0f / ma;
     // X = hr (sc/ma + 1) - 1/2
-    gd[s_ax] += dX * hr * ima * s_sign;
-    gd[t_ax] += dY * hr * ima * t_sign;
-    gd[m_ax] += -(dX * sc + dY * tc) * hr * ima * ima * m_sign;
+    float gs = dX * hr * ima * s_sign;
+    float gt = dY * hr * ima * t_sign;
+    float gm = -(dX * sc + dY * tc) * hr * ima * ima * m_sign;
+#pragma unroll
+    for (int k = 0; k < 3; k++)
+        gd[k] += (float)(s_ax == k) * gs + (float)(t_ax == k) * gt + (float)(m_ax == k) * gm;
 }
 
 // LUT sample with derivatives in x and y.

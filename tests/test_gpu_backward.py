@@ -150,6 +150,57 @@ def test_grads_multi_view_ragged():
     _compare(_np(g), ref, "3 views", spread)
 
 
+def _full_size_sampled(cfg, n_views, per_view, seed):
+    """Full-size frame(s) of a config with dL/dC nonzero only at sampled pixels: the GPU runs the
+    whole backward over every tile and view; the float64 reference needs only those pixels."""
+    from parity import sample_pixels
+    sc = synth.make_scene(cfg)
+    cams = synth.config_cameras(cfg)
+    W, H = cams[0]["width"], cams[0]["height"]
+    tabs = oracle.tables(sc["env"], sc["env_levels"])
+    rng = np.random.default_rng(seed)
+    d_all = np.zeros((len(cams), H, W, 4))
+    pix_v, ds, used = [], [], []
+    for v in range(min(n_views, len(cams))):
+        pix = np.unique(sample_pixels(rng, W, H, per_view), axis=0)
+        ref_f = oracle.render(sc, cams[v], pixels=pix, tabs=tabs)
+        d = rng.normal(size=(len(pix), 4))
+        skip = (ref_f["stat"][:, 2] > 0) | (ref_f["stat"][:, 3] > 0)
+        d[skip] = 0.0
+        d_all[v, pix[:, 1], pix[:, 0]] = d
+        pix_v.append(pix)
+        ds.append(d)
+        used.append(cams[v])
+    print(f"[{cfg}] {sum(len(p) for p in pix_v)} pixels with dL/dC over {len(used)} views",
+          flush=True)
+
+    def total(scene):
+        acc = {k: 0.0 for k in NAMES}
+        for cam, pix, d in zip(used, pix_v, ds):
+            r = og.grads(scene, cam, pix, d, tabs)
+            for k in NAMES:
+                acc[k] = acc[k] + r[k]
+        return acc
+    ref = total(sc)
+    spread = {k: np.zeros_like(ref[k]) for k in NAMES}
+    for sign in (1.0, -1.0):
+        alt = total(_perturbed(sc, sign, 11))
+        for k in NAMES:
+            spread[k] = np.maximum(spread[k], np.abs(alt[k] - ref[k]))
+    g, run = _gpu_grads(sc, cams, W, H, d_all)
+    _compare(_np(g), ref, cfg, spread)
+
+
+def test_grads_sq300k_training_batch_sampled():
+    """The 300k-splat, 8-view 800x800 training batch through the whole backward."""
+    _full_size_sampled("sq300k_train", 8, 10, 5)
+
+
+def test_grads_field1m_sampled():
+    """The 1M-splat 1600x1064 unbounded frame through the whole backward."""
+    _full_size_sampled("field1m", 1, 24, 6)
+
+
 @pytest.mark.parametrize("T", [1, 16])
 def test_grads_texture_resolution(T):
     sc = synth.make_scene("shell2k", n=500, tex_res=T)

@@ -175,6 +175,28 @@ def test_sq100k_full_size_sampled():
         _frame_parity(sc, pick[v], out, v=v, pixels=pix, name=f"sq100k v{v}")
 
 
+def test_sq300k_training_batch_sampled():
+    """300,000 splats, T = 8: the 8-view 800x800 training batch rendered in one launch with
+    G-buffers (as the backward needs them), checked at sampled pixels of three views."""
+    sc = synth.make_scene("sq300k_train")
+    cams = synth.config_cameras("sq300k_train")
+    ds, out = _render(sc, cams, 800, 800, gbuf=True, aux=True)
+    rng = np.random.default_rng(3)
+    for v in (0, 3, 7):
+        pix = sample_pixels(rng, 800, 800, 96)
+        _frame_parity(sc, cams[v], out, v=v, pixels=pix, name=f"sq300k v{v}")
+
+
+def test_field1m_full_size_sampled():
+    """1,000,000 splats (height field, boxes, far shell r in [5,50]), 1600x1064, 256^2 env with
+    4 levels: one full frame, checked at sampled pixels."""
+    sc = synth.make_scene("field1m")
+    cam = synth.config_cameras("field1m")[0]
+    ds, out = _render(sc, [cam], 1600, 1064, gbuf=True, aux=True)
+    pix = sample_pixels(np.random.default_rng(4), 1600, 1064, 200)
+    _frame_parity(sc, cam, out, pixels=pix, name="field1m")
+
+
 def test_constant_sampler_is_the_untextured_primitive():
     """Sampler CONSTANT on 1x1 textures equals the oracle's 1x1-texture render."""
     P = _pkg()
