@@ -12,7 +12,7 @@ against the untextured primitive (the paper's Tab. 3); the serving loop against 
 renders; and the FP64 oracle timed on a bounded pixel sample on the host cores.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-fwd-bwd]
-                  [--no-tab3] [--no-serving] [--serving-seconds S] [--profile-run]
+                  [--no-tab3] [--no-serving] [--serving-seconds S] [--profile-run | --profile-train]
 """
 import argparse
 import json
@@ -259,6 +259,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-tab3", action="store_true")
     ap.add_argument("--serving-seconds", type=float, default=5.0)
+    ap.add_argument("--profile-train", action="store_true",
+                    help="only a few forward+backward steps of the 300k-splat training batch "
+                         "(for counter collection)")
     ap.add_argument("--profile-run", action="store_true",
                     help="only the forward workload (few steps) plus a 256 MiB device copy that "
                          "calibrates the FETCH_SIZE / WRITE_SIZE counters")
@@ -276,6 +279,10 @@ def main():
     _ffi.lib()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.profile_train:
+        out = bench_fwd_bwd("sq300k_train", args.steps, args.warmup)
+        print(json.dumps({"profile_train": True, **out}), flush=True)
+        return
     t0 = time.perf_counter()
     sc = synth.make_scene("sq100k")
     cams = synth.config_cameras("sq100k")

@@ -27,8 +27,8 @@ namespace ts {
 constexpr int kGeo = 19;          // px py ux uy vx vy wx wy w0 opacity sR[9]
 constexpr int kHdr = 24;          // floats in a partial's header: 19 geometric + window i0 j0 wi wj + pad
 constexpr int kBwdBatch = 128;
-constexpr int kEnt = 36;
-constexpr int kChunk = 2048;      // floats of the partial buffer a wave takes at a time          // LDS floats per lane entry: taps (4 ints), fx, fy, q[8], pad 2, geo[19], pad 1
+constexpr int kEnt = 16;          // LDS floats per lane entry: taps (4 ints), fx, fy, q[8], pad 2
+constexpr int kChunk = 2048;      // floats of the partial buffer a wave takes at a time
 
 struct BwdArgs {
     int V, W, H, ntx, n_tiles, T, n;
@@ -153,6 +153,9 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
             uint64_t blm = __ballot(bl);
             if (blm == 0) continue;
             float geo[kGeo];
+            int i0 = 0x7fffffff, i1 = -1, j0 = 0x7fffffff, j1 = -1;   // texel taps (blended)
+#pragma unroll
+            for (int k = 0; k < kGeo; k++) geo[k] = 0.f;
             if (bl) {
                 float4 c1 = r[1], c2 = r[2], c3 = r[3], c4 = r[4], c5 = r[5], c6 = r[6];
                 int chart = __builtin_amdgcn_readfirstlane(__float_as_int(c6.y));
@@ -161,8 +164,10 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
                 float sx = fmaf(u, tscale, toff), sy = fmaf(vv, tscale, toff);
                 float fx0 = floorf(sx), fy0 = floorf(sy);
                 float fx = sx - fx0, fy = sy - fy0;
-                int i0 = (int)fx0, j0 = (int)fy0;
-                int i1 = min(max(i0 + 1, 0), T - 1), j1 = min(max(j0 + 1, 0), T - 1);
+                i0 = (int)fx0;
+                j0 = (int)fy0;
+                i1 = min(max(i0 + 1, 0), T - 1);
+                j1 = min(max(j0 + 1, 0), T - 1);
                 i0 = min(max(i0, 0), T - 1);
                 j0 = min(max(j0, 0), T - 1);
                 __amdgpu_buffer_rsrc_t tr = chart_rsrc(a.atlas + (size_t)(unsigned)chart * chart4,
@@ -258,16 +263,10 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
                 me[4] = fx; me[5] = fy;
 #pragma unroll
                 for (int c = 0; c < 8; c++) me[6 + c] = q[c];
-#pragma unroll
-                for (int k = 0; k < kGeo; k++) me[16 + k] = geo[k];
             }
             // window of texels touched by this wave
-            int bi0 = bl ? __float_as_int(E[lane * kEnt + 0]) : 0x7fffffff;
-            int bj0 = bl ? __float_as_int(E[lane * kEnt + 2]) : 0x7fffffff;
-            int bi1 = bl ? __float_as_int(E[lane * kEnt + 1]) : -1;
-            int bj1 = bl ? __float_as_int(E[lane * kEnt + 3]) : -1;
-            int wi0 = wave_min_i(bi0), wj0 = wave_min_i(bj0);
-            int wi1 = wave_max_i(bi1), wj1 = wave_max_i(bj1);
+            int wi0 = wave_min_dpp(i0), wj0 = wave_min_dpp(j0);
+            int wi1 = wave_max_dpp(i1), wj1 = wave_max_dpp(j1);
             int wi = wi1 - wi0 + 1, wj = wj1 - wj0 + 1, wt = wi * wj;
             int64_t need = kHdr + (int64_t)wt * 8;
             // space from this wave's current chunk; a new chunk (one integer atomic) when
@@ -292,17 +291,18 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
                 continue;
             }
             float* dst = a.part + off;
-            // geometric sums: lane k + 19 g (g = 0..2) sums entry k over the blended pixels
-            // p = g, g + 3, ...; the three groups are added in a fixed order
-            {
-                float gs = 0.f;
-                if (lane < 3 * kGeo) {
-                    int k = lane % kGeo, g3 = lane / kGeo;
-                    for (int p = g3; p < kWave; p += 3)
-                        if ((blm >> p) & 1ull) gs += E[p * kEnt + 16 + k];
-                }
-                float g1 = __shfl(gs, (lane + kGeo) & 63), g2 = __shfl(gs, (lane + 2 * kGeo) & 63);
-                if (lane < kGeo) dst[lane] = (gs + g1) + g2;
+            // geometric sums over the wave (zeros from the other lanes), fixed DPP order; lane
+            // 63 writes them with the window as the partial's header
+#pragma unroll
+            for (int k = 0; k < kGeo; k++) geo[k] = dpp_sum_f(geo[k]);
+            if (lane == kWave - 1) {
+                float4* h4 = (float4*)dst;
+                h4[0] = make_float4(geo[0], geo[1], geo[2], geo[3]);
+                h4[1] = make_float4(geo[4], geo[5], geo[6], geo[7]);
+                h4[2] = make_float4(geo[8], geo[9], geo[10], geo[11]);
+                h4[3] = make_float4(geo[12], geo[13], geo[14], geo[15]);
+                h4[4] = make_float4(geo[16], geo[17], geo[18], __int_as_float(wi0));
+                h4[5] = make_float4(__int_as_float(wj0), __int_as_float(wi), __int_as_float(wj), 0.f);
             }
             // texel window: lanes form groups of L = pow2 >= wt lanes (texel = lane mod L);
             // group g sums the blended pixels p = g, g + 64/L, ... in order, then the groups
@@ -336,13 +336,6 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
                     d4[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
                     d4[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
                 }
-            }
-            if (lane == kGeo) {
-                dst[kGeo + 0] = __int_as_float(wi0);
-                dst[kGeo + 1] = __int_as_float(wj0);
-                dst[kGeo + 2] = __int_as_float(wi);
-                dst[kGeo + 3] = __int_as_float(wj);
-                dst[kGeo + 4] = 0.f;
             }
             if (lane == 0) a.slots[slot_idx] = (int32_t)(off / 8);
           }

@@ -39,6 +39,35 @@ __device__ inline int xcd_remap(int i, int g) {
     return x * q + (x < r ? x : r) + k;
 }
 
+// Wave64 reductions with DPP lane moves (quad permutes, row mirrors, row broadcasts 15 and
+// 31). The combination order is the same on every call, so the result is deterministic; the
+// total ends in lanes 48..63 (read it from lane 63). `ident` fills lanes a move leaves unset.
+template <typename Op>
+__device__ inline int dpp_reduce_i(int x, int ident, Op op) {
+    x = op(x, __builtin_amdgcn_update_dpp(ident, x, 0xB1, 0xF, 0xF, false));   // quad [1,0,3,2]
+    x = op(x, __builtin_amdgcn_update_dpp(ident, x, 0x4E, 0xF, 0xF, false));   // quad [2,3,0,1]
+    x = op(x, __builtin_amdgcn_update_dpp(ident, x, 0x141, 0xF, 0xF, false));  // row half-mirror
+    x = op(x, __builtin_amdgcn_update_dpp(ident, x, 0x140, 0xF, 0xF, false));  // row mirror
+    x = op(x, __builtin_amdgcn_update_dpp(ident, x, 0x142, 0xA, 0xF, false));  // row bcast 15
+    x = op(x, __builtin_amdgcn_update_dpp(ident, x, 0x143, 0xC, 0xF, false));  // row bcast 31
+    return x;
+}
+
+__device__ inline float dpp_sum_f(float x) {
+    auto add = [](int a, int b) { return __float_as_int(__int_as_float(a) + __int_as_float(b)); };
+    return __int_as_float(dpp_reduce_i(__float_as_int(x), 0, add));
+}
+
+// Wave-uniform min / max of an int (from lane 63 of the DPP reduction).
+__device__ inline int wave_min_dpp(int x) {
+    int r = dpp_reduce_i(x, 0x7fffffff, [](int a, int b) { return min(a, b); });
+    return __builtin_amdgcn_readlane(r, 63);
+}
+__device__ inline int wave_max_dpp(int x) {
+    int r = dpp_reduce_i(x, (int)0x80000000, [](int a, int b) { return max(a, b); });
+    return __builtin_amdgcn_readlane(r, 63);
+}
+
 // Buffer descriptor over one chart of the atlas (SGPR base, bounded to the chart's bytes: an
 // out-of-range offset reads 0 instead of faulting). Word 3 = raw 32-bit data, gfx9 layout.
 __device__ inline __amdgpu_buffer_rsrc_t chart_rsrc(const float4* chart_base, unsigned bytes) {
