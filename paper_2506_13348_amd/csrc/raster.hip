@@ -141,23 +141,22 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
                             t0 = p0.x; t1 = p0.y; t2 = p0.z; t3 = p0.w;
                             t4 = q0.x; t5 = q0.y; t6 = q0.z; t7 = q0.w;
                         }
+                        // sigma R (t / |t|) = (sigma R t) / |t|: rotate the sampled tangent
+                        // normal, then scale by w / |t|; a zero-length sample is (0,0,1)
                         float nl = t4 * t4 + t5 * t5 + t6 * t6;
-                        float nx, ny, nz;
-                        if (nl > 0.f) {
-                            float il = __builtin_amdgcn_rsqf(nl);
-                            nx = t4 * il; ny = t5 * il; nz = t6 * il;
-                        } else {
-                            nx = 0.f; ny = 0.f; nz = 1.f;
-                        }
+                        bool hasn = nl > 0.f;
+                        float il = hasn ? __builtin_amdgcn_rsqf(nl) : 1.f;
+                        float tz = hasn ? t6 : 1.f;
                         float ww = alpha * Tr;
+                        float wn = ww * il;
                         acc[0] = fmaf(ww, t0, acc[0]);
                         acc[1] = fmaf(ww, t1, acc[1]);
                         acc[2] = fmaf(ww, t2, acc[2]);
                         acc[3] = fmaf(ww, t7, acc[3]);   // metallic
                         acc[4] = fmaf(ww, t3, acc[4]);   // roughness
-                        acc[5] = fmaf(ww, c4.x * nx + c4.y * ny + c4.z * nz, acc[5]);
-                        acc[6] = fmaf(ww, c4.w * nx + c5.x * ny + c5.y * nz, acc[6]);
-                        acc[7] = fmaf(ww, c5.z * nx + c5.w * ny + c6.x * nz, acc[7]);
+                        acc[5] = fmaf(wn, c4.x * t4 + c4.y * t5 + c4.z * tz, acc[5]);
+                        acc[6] = fmaf(wn, c4.w * t4 + c5.x * t5 + c5.y * tz, acc[6]);
+                        acc[7] = fmaf(wn, c5.z * t4 + c5.w * t5 + c6.x * tz, acc[7]);
                         Tr = Tn;
                         last = b0 - range.x + j + 1;
                         nbl++;

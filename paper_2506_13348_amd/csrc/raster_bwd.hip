@@ -52,19 +52,6 @@ struct BwdArgs {
     int32_t* status;
 };
 
-__device__ inline float wave_min_f(float v) {
-    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
-    return v;
-}
-__device__ inline int wave_min_i(int v) {
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
-    return v;
-}
-__device__ inline int wave_max_i(int v) {
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-    return v;
-}
-
 __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
     __shared__ float4 srec[kBwdBatch * kRec4];
     __shared__ float ent[4][kWave * kEnt];
@@ -110,7 +97,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
 #pragma unroll
         for (int c = 0; c < 8; c++) gx[c] = 0.f;
     }
-    int wmax = wave_max_i(my_last);
+    int wmax = wave_max_dpp(my_last);
     if (lane == 0) smax[w] = wmax;
     __syncthreads();
     int tile_max = max(max(smax[0], smax[1]), max(smax[2], smax[3]));
@@ -203,11 +190,12 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
                 float nw[3];
                 for (int i = 0; i < 3; i++) nw[i] = sR[3 * i] * nh[0] + sR[3 * i + 1] * nh[1] + sR[3 * i + 2] * nh[2];
                 // transmittance before this splat and dL/dalpha
-                float Tb = Tr / (1.0f - alpha);
+                float r1m = 1.0f / (1.0f - alpha);
+                float Tb = Tr * r1m;
                 float wgt = alpha * Tb;
                 float cdot = gx[0] * tv[0] + gx[1] * tv[1] + gx[2] * tv[2] + gx[3] * tv[7] +
                              gx[4] * tv[3] + gx[5] * nw[0] + gx[6] * nw[1] + gx[7] * nw[2];
-                float dalpha = Tb * cdot - (accum + dLdTf * Tf) / (1.0f - alpha);
+                float dalpha = Tb * cdot - (accum + dLdTf * Tf) * r1m;
                 accum = fmaf(wgt, cdot, accum);
                 Tr = Tb;
                 // texture-sample gradients q[8] (channel order of the texels)
@@ -291,18 +279,22 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
                 continue;
             }
             float* dst = a.part + off;
-            // geometric sums over the wave (zeros from the other lanes), fixed DPP order; lane
-            // 63 writes them with the window as the partial's header
+            // geometric sums over the wave (zeros from the other lanes) by a transposing
+            // reduction: lane l < 32 ends with the sum of entry bitrev5(l); fixed order
+            {
+                float xs[32];
 #pragma unroll
-            for (int k = 0; k < kGeo; k++) geo[k] = dpp_sum_f(geo[k]);
-            if (lane == kWave - 1) {
-                float4* h4 = (float4*)dst;
-                h4[0] = make_float4(geo[0], geo[1], geo[2], geo[3]);
-                h4[1] = make_float4(geo[4], geo[5], geo[6], geo[7]);
-                h4[2] = make_float4(geo[8], geo[9], geo[10], geo[11]);
-                h4[3] = make_float4(geo[12], geo[13], geo[14], geo[15]);
-                h4[4] = make_float4(geo[16], geo[17], geo[18], __int_as_float(wi0));
-                h4[5] = make_float4(__int_as_float(wj0), __int_as_float(wi), __int_as_float(wj), 0.f);
+                for (int k = 0; k < 32; k++) xs[k] = k < kGeo ? geo[k] : 0.f;
+                float tot = wave_transpose_sum32(xs, lane);
+                int vi = bitrev5(lane & 31);
+                if (lane < 32 && vi < kGeo) dst[vi] = tot;
+                if (lane == kWave - 1) {
+                    dst[kGeo + 0] = __int_as_float(wi0);
+                    dst[kGeo + 1] = __int_as_float(wj0);
+                    dst[kGeo + 2] = __int_as_float(wi);
+                    dst[kGeo + 3] = __int_as_float(wj);
+                    dst[kGeo + 4] = 0.f;
+                }
             }
             // texel window: lanes form groups of L = pow2 >= wt lanes (texel = lane mod L);
             // group g sums the blended pixels p = g, g + 64/L, ... in order, then the groups

@@ -53,9 +53,55 @@ __device__ inline int dpp_reduce_i(int x, int ident, Op op) {
     return x;
 }
 
-__device__ inline float dpp_sum_f(float x) {
-    auto add = [](int a, int b) { return __float_as_int(__int_as_float(a) + __int_as_float(b)); };
-    return __int_as_float(dpp_reduce_i(__float_as_int(x), 0, add));
+// Transposing wave sum of 32 values per lane: at each level a lane keeps half of its values
+// and adds its partner's copy of that half (partners differ in one lane bit: quad permutes for
+// bits 0-1, row shifts for bits 2-3, lane shuffles for bits 4-5), so after five levels each
+// lane holds one value summed over 32 lanes and the last level adds the other half-wave.
+// Returns, in every lane, the total of value index
+// v = 16 b0 + 8 b1 + 4 b2 + 2 b3 + b4 (b_k = bit k of the lane): the bit-reversed low five
+// lane bits. The combination order is fixed, so the result is deterministic.
+template <int kCtrl>
+__device__ inline float dpp_f(float x) {
+    return __builtin_amdgcn_update_dpp(-0.0f, x, kCtrl, 0xF, 0xF, false);
+}
+__device__ inline float wave_transpose_sum32(float (&x)[32], int lane) {
+    const bool b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
+    const bool b4 = (lane >> 4) & 1;
+#pragma unroll
+    for (int j = 0; j < 16; j++) {   // partner lane ^ 1
+        float lo = x[j], hi = x[16 + j];
+        float send = b0 ? lo : hi, keep = b0 ? hi : lo;
+        x[j] = keep + dpp_f<0xB1>(send);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; j++) {    // partner lane ^ 2
+        float lo = x[j], hi = x[8 + j];
+        float send = b1 ? lo : hi, keep = b1 ? hi : lo;
+        x[j] = keep + dpp_f<0x4E>(send);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++) {    // partner lane ^ 4: row shift left / right by 4
+        float lo = x[j], hi = x[4 + j];
+        float send = b2 ? lo : hi, keep = b2 ? hi : lo;
+        float from_up = dpp_f<0x104>(send), from_down = dpp_f<0x114>(send);
+        x[j] = keep + (b2 ? from_down : from_up);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; j++) {    // partner lane ^ 8: row shift left / right by 8
+        float lo = x[j], hi = x[2 + j];
+        float send = b3 ? lo : hi, keep = b3 ? hi : lo;
+        float from_up = dpp_f<0x108>(send), from_down = dpp_f<0x118>(send);
+        x[j] = keep + (b3 ? from_down : from_up);
+    }
+    {                                // partner lane ^ 16
+        float send = b4 ? x[0] : x[1], keep = b4 ? x[1] : x[0];
+        x[0] = keep + __shfl_xor(send, 16);
+    }
+    return x[0] + __shfl_xor(x[0], 32);
+}
+
+__device__ inline int bitrev5(int l) {
+    return ((l & 1) << 4) | ((l & 2) << 2) | (l & 4) | ((l & 8) >> 2) | ((l & 16) >> 4);
 }
 
 // Wave-uniform min / max of an int (from lane 63 of the DPP reduction).
