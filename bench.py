@@ -249,6 +249,17 @@ def bench_serving(duration, rate=200.0, warm=1.0):
             "server_stats": srv.stats}
 
 
+def calibration_copy(dev):
+    """A 256 MiB device-to-device copy: the counter reading per byte moved that scales the
+    FETCH_SIZE / WRITE_SIZE passes."""
+    import torch
+    src = torch.empty(64 << 20, device=dev, dtype=torch.float32).fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    return src.numel() * 4
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -281,6 +292,7 @@ def main():
     torch.cuda.set_device(dev)
     if args.profile_train:
         out = bench_fwd_bwd("sq300k_train", args.steps, args.warmup)
+        calibration_copy(dev)
         print(json.dumps({"profile_train": True, **out}), flush=True)
         return
     t0 = time.perf_counter()
@@ -311,12 +323,9 @@ def main():
     t_total = time.perf_counter() - t_start
     plan.check()
     if args.profile_run:
-        src = torch.empty(64 << 20, device=dev, dtype=torch.float32).fill_(1.0)
-        dst = torch.empty_like(src)
-        dst.copy_(src)   # calibration: 256 MiB read + 256 MiB written
-        torch.cuda.synchronize()
+        nbytes = calibration_copy(dev)
         print(json.dumps({"profile_run": True, "steps": K, "views": V,
-                          "calibration_copy_bytes": src.numel() * 4}), flush=True)
+                          "calibration_copy_bytes": nbytes}), flush=True)
         return
     ms_step = t_total / K * 1e3
     pre_ms = float(np.mean([ev[k][0].elapsed_time(ev[k][1]) for k in range(K)]))
@@ -332,6 +341,11 @@ def main():
     n_blend = int(aux.n_blend.to(torch.int64).sum().item())
     del aux
     achieved = n_blend * FLOPS_PER_BLEND / (ras_ms / 1e3) / 1e12
+    # HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary, only while the
+    # kernel's sources are the ones the counters were taken on
+    from paper_2506_13348_amd.profiling import read_traffic
+    traffic = read_traffic(os.path.join(ROOT, "profiles", "raster_fwd_sq100k_counters.md"),
+                           "k_raster_fwd")
     result = {
         "metric": METRIC,
         "value": round(mpix, 2),
@@ -356,7 +370,7 @@ def main():
         "roofline": {"kernel": "k_raster_fwd", "bound": "alu",
                      "achieved": round(achieved, 3), "peak": round(PEAK_FP32_UNPACKED, 2),
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_UNPACKED, 4),
-                     "traffic": None,
+                     "traffic": traffic,
                      "note": f"{n_blend} blended evaluations x {FLOPS_PER_BLEND} flops per launch"},
     }
     # the same step with charts packed in Morton order of the centres (locality-aware atlas)
