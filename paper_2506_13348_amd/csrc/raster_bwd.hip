@@ -2,8 +2,9 @@
 // rotations (unnormalised quaternions), scales, opacities and atlas texels (the parameters the
 // paper optimises end to end, Sec. 3.6).
 //
-// 1. k_bwd_pairs: per (view, tile) list entry, the entry's index among its splat's tiles
-//    (splat-major map of the tile lists) and an empty slot per (entry, quadrant).
+// 1. k_area_*: exclusive scan of the splats' tile-rectangle areas (the splat-major row of
+//    each (splat, tile) pair: start[v][s] + row-major index of the tile in the rectangle);
+//    k_clear_slots: every (pair, 8x8 block) slot starts empty.
 // 2. k_raster_bwd: per tile, per pixel: the adjoint of the shading (dL/dX for the 8 G-buffer
 //    channels, dL/dT), then the tile list back to front from the pixel's last blended splat,
 //    recovering T_i = T_{i+1} / (1 - alpha_i), with
@@ -12,10 +13,12 @@
 //    normalisation and rotation (Eq. 2-9), down to the 9 coefficients of the closed-form (u,v),
 //    the opacity and sigma R. Each wave (8x8 pixels) sums its pixels' contributions for one
 //    splat in a fixed lane order and writes one partial — 19 geometric values and the window
-//    of texels it touched — into a slot of a partial buffer. No value is accumulated with
+//    of texels it touched — into the partial buffer and records where in the pair's
+//    splat-major slot row. No value is accumulated with
 //    atomics; a wave takes buffer space in chunks of kChunk floats with one integer atomic.
 // 3. k_bwd_gather: per splat, the partials of its (view, tile, quadrant) entries summed in a
-//    fixed order -> per-view record gradients and the splat's texel gradients.
+//    fixed order (its slot rows are contiguous) -> per-view record gradients and the splat's
+//    texel gradients.
 // 4. k_bwd_params: per splat, in double precision, the record gradients of every view chained
 //    through the projection set-up to the splat parameters.
 #include "eval.h"
@@ -45,7 +48,9 @@ struct BwdArgs {
     const float* t_final;
     const int32_t* n_contrib;
     const float4* d_rgba;
-    int32_t* slots;          // [cap][4]
+    int32_t* slots;          // [cap][4], splat-major: entry start[v][s] + k, block 0..3
+    const int4* rect;        // [V][n] tile rectangles
+    const int64_t* start;    // [V][n] exclusive scan of the rectangle areas
     float* part;             // partial buffer
     int64_t part_cap;        // floats
     unsigned long long* part_top;
@@ -57,6 +62,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
     __shared__ float ent[4][kWave * kEnt];
     __shared__ int smax[4];
     __shared__ uint32_t smask[kBwdBatch];
+    __shared__ int32_t sslot[kBwdBatch];
     const int g = gridDim.x;
     const int bid = xcd_remap(blockIdx.x, g);
     const int v = bid / a.n_tiles;
@@ -112,6 +118,12 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
         uint32_t qmask = 0;
         if (tid < nb) {
             int id = a.pair_ids[range.x + bstart + tid];
+            // splat-major slot row of this (splat, tile): k = row-major index of the tile
+            // inside the splat's rectangle (the list holds only splats covering the tile)
+            int4 rr = a.rect[(int64_t)v * a.n + id];
+            int64_t si = a.start[(int64_t)v * a.n + id] + (int64_t)(ty - rr.y) * (rr.z - rr.x) +
+                         (tx - rr.x);
+            sslot[tid] = si < a.cap ? (int32_t)si : -1;
             const float4* src = a.rec + ((int64_t)v * a.n + id) * kRec4;
             float4 r0 = src[0], r1 = src[1], r2 = src[2], r3 = src[3];
             srec[tid * kRec4 + 0] = r0;
@@ -270,11 +282,12 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
             unsigned long long off = ccur;
             ccur += (unsigned long long)need;
             bool fits = (int64_t)off + need <= a.part_cap;
-            int64_t slot_idx = ((int64_t)range.x + pos) * 4 + w;
+            const int srow = sslot[j];
+            const int64_t slot_idx = (int64_t)srow * 4 + w;
             if (!fits) {
                 if (lane == 0) {
                     a.status[0] = 2;
-                    a.slots[slot_idx] = -1;
+                    if (srow >= 0) a.slots[slot_idx] = -1;
                 }
                 continue;
             }
@@ -329,35 +342,22 @@ __global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
                     d4[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
                 }
             }
-            if (lane == 0) a.slots[slot_idx] = (int32_t)(off / 8);
+            if (lane == 0 && srow >= 0) a.slots[slot_idx] = (int32_t)(off / 8);
           }
         }
     }
 }
 
-// Splat-major index of the tile lists: for list entry p of tile (tx,ty) holding splat s,
-// pair_pos[start[v][s] + k] = p with k the tile's row-major index inside rect(s); slots of
-// every entry start empty.
-__global__ __launch_bounds__(256) void k_bwd_pairs(int V, int n, int ntx, int n_tiles,
-                                                   const int2* __restrict__ ranges, int64_t cap,
-                                                   const int32_t* __restrict__ pair_ids,
-                                                   const int4* __restrict__ rect,
-                                                   const int64_t* __restrict__ start,
-                                                   int32_t* __restrict__ pair_pos,
-                                                   int32_t* __restrict__ slots) {
-    int vt = blockIdx.x;
-    int v = vt / n_tiles, t = vt % n_tiles;
-    int tx = t % ntx, ty = t / ntx;
-    int2 rg = ranges[vt];
-    int64_t s0 = min((int64_t)rg.x, cap), s1 = min((int64_t)rg.y, cap);
-    for (int64_t p = s0 + threadIdx.x; p < s1; p += blockDim.x) {
-        int s = pair_ids[p];
-        int4 r = rect[(int64_t)v * n + s];
-        int k = (ty - r.y) * (r.z - r.x) + (tx - r.x);
-        pair_pos[start[(int64_t)v * n + s] + k] = (int32_t)p;
-        int4* sl = (int4*)(slots + p * 4);
-        *sl = make_int4(-1, -1, -1, -1);
-    }
+// Every (entry, 8x8 block) slot starts empty: rows [0, min(pairs, cap)) of the splat-major
+// slot array, pairs = end of the last tile list.
+__global__ __launch_bounds__(256) void k_clear_slots(const int32_t* __restrict__ ranges,
+                                                     int64_t last, int64_t cap,
+                                                     int32_t* __restrict__ slots) {
+    int64_t rows = min((int64_t)ranges[2 * last + 1], cap);
+    int4* s4 = (int4*)slots;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows;
+         i += (int64_t)gridDim.x * blockDim.x)
+        s4[i] = make_int4(-1, -1, -1, -1);
 }
 
 // Exclusive scan of rect areas over (view, splat) -> int64 start offsets, in three passes:
@@ -442,7 +442,7 @@ __global__ void k_copy_u64(const unsigned long long* src, int64_t* dst) { *dst =
 // their slot and window read from the owning lane.
 __global__ __launch_bounds__(64) void k_bwd_gather(int V, int n, int T, const int4* __restrict__ rect,
                                                    const int64_t* __restrict__ start,
-                                                   const int32_t* __restrict__ pair_pos,
+                                                   int64_t cap,
                                                    const int32_t* __restrict__ slots,
                                                    const float* __restrict__ part,
                                                    const int32_t* __restrict__ chart_of,
@@ -472,29 +472,61 @@ __global__ __launch_bounds__(64) void k_bwd_gather(int V, int n, int T, const in
                 int e = e0 + lane;
                 int sl = -1;
                 int win = 0;   // packed i0 | j0 << 8 | wi << 16 | wj << 24 (all < 256)
-                if (e < ne) {
-                    int p = pair_pos[st + (e >> 2)];
-                    sl = slots[(int64_t)p * 4 + (e & 3)];
+                if (e < ne && st + (e >> 2) < cap) {
+                    sl = slots[(st + (e >> 2)) * 4 + (e & 3)];
                     if (sl >= 0) {
                         const float* h = part + (int64_t)sl * 8 + kGeo;
                         win = __float_as_int(h[0]) | (__float_as_int(h[1]) << 8) |
                               (__float_as_int(h[2]) << 16) | (__float_as_int(h[3]) << 24);
                     }
                 }
-                int m = min(kWave, ne - e0);
-                for (int j = 0; j < m; j++) {
-                    int slj = __shfl(sl, j);
-                    if (slj < 0) continue;
-                    int wj = __shfl(win, j);
-                    const float* src = part + (int64_t)slj * 8;
-                    if (t0 == 0 && lane < kGeo) gs += src[lane];
-                    int li = ti - (wj & 255), lj = tj - ((wj >> 8) & 255);
-                    int wi = (wj >> 16) & 255, wh = (wj >> 24) & 255;
-                    if (own && li >= 0 && lj >= 0 && li < wi && lj < wh) {
-                        const float4* s4 = (const float4*)(src + kHdr + (int64_t)(lj * wi + li) * 8);
-                        float4 lo = s4[0], hi = s4[1];
-                        acc[0] += lo.x; acc[1] += lo.y; acc[2] += lo.z; acc[3] += lo.w;
-                        acc[4] += hi.x; acc[5] += hi.y; acc[6] += hi.z; acc[7] += hi.w;
+                // entries with a partial, in order, four at a time: the loads of the four
+                // are issued together, then added in entry order
+                uint64_t vm = __ballot(sl >= 0);
+                while (vm) {
+                    int js[4];
+                    int nj = 0;
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        js[u] = 0;
+                        if (vm) {
+                            js[u] = __builtin_ctzll(vm);
+                            vm &= vm - 1;
+                            nj = u + 1;
+                        }
+                    }
+                    float g[4];
+                    float4 lo[4], hi[4];
+                    bool in[4];
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        g[u] = 0.f;
+                        in[u] = false;
+                        lo[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+                        hi[u] = lo[u];
+                        if (u < nj) {
+                            int slj = __builtin_amdgcn_readlane(sl, js[u]);
+                            int wj = __builtin_amdgcn_readlane(win, js[u]);
+                            const float* src = part + (int64_t)slj * 8;
+                            if (t0 == 0 && lane < kGeo) g[u] = src[lane];
+                            int li = ti - (wj & 255), lj = tj - ((wj >> 8) & 255);
+                            int wi = (wj >> 16) & 255, wh = (wj >> 24) & 255;
+                            in[u] = own && li >= 0 && lj >= 0 && li < wi && lj < wh;
+                            if (in[u]) {
+                                const float4* s4 =
+                                    (const float4*)(src + kHdr + (int64_t)(lj * wi + li) * 8);
+                                lo[u] = s4[0];
+                                hi[u] = s4[1];
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        if (u < nj && t0 == 0 && lane < kGeo) gs += g[u];
+                        if (in[u]) {
+                            acc[0] += lo[u].x; acc[1] += lo[u].y; acc[2] += lo[u].z; acc[3] += lo[u].w;
+                            acc[4] += hi[u].x; acc[5] += hi[u].y; acc[6] += hi[u].z; acc[7] += hi[u].w;
+                        }
                     }
                 }
             }
@@ -629,7 +661,7 @@ __global__ __launch_bounds__(256) void k_bwd_params(int V, int n, const ts_camer
 }
 
 struct BwdLayout {
-    size_t off_start, off_pairpos, off_slots, off_recgrad, off_top, off_bsum, total;
+    size_t off_start, off_slots, off_recgrad, off_top, off_bsum, total;
     int area_blocks;
 };
 
@@ -640,7 +672,6 @@ inline BwdLayout bwd_layout(int V, int n, int64_t cap) {
     size_t off = 0;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     L.off_start = off; off = al(off + vn * 8);
-    L.off_pairpos = off; off = al(off + c * 4);
     L.off_slots = off; off = al(off + c * 16);
     L.off_recgrad = off; off = al(off + vn * kGeo * 4);
     L.off_top = off; off = al(off + 8);
@@ -704,7 +735,6 @@ extern "C" int ts_raster_bwd(int32_t n_views, int32_t width, int32_t height, con
     if (n == 0) return TS_OK;
     char* wsc = (char*)ws;
     int64_t* start = (int64_t*)(wsc + L.off_start);
-    int32_t* pair_pos = (int32_t*)(wsc + L.off_pairpos);
     int32_t* slots = (int32_t*)(wsc + L.off_slots);
     float* rec_grad = (float*)(wsc + L.off_recgrad);
     unsigned long long* top = (unsigned long long*)(wsc + L.off_top);
@@ -717,9 +747,9 @@ extern "C" int ts_raster_bwd(int32_t n_views, int32_t width, int32_t height, con
     hipLaunchKernelGGL(k_area_scan_sums, dim3(1), dim3(256), 0, stream, bsum, L.area_blocks);
     hipLaunchKernelGGL(k_area_apply, dim3(L.area_blocks), dim3(256), 0, stream,
                        (const int4*)rect, vn, (const int64_t*)bsum, start);
-    hipLaunchKernelGGL(k_bwd_pairs, dim3(n_views * n_tiles), dim3(256), 0, stream, n_views, n, ntx,
-                       n_tiles, (const int2*)tile_ranges, pair_capacity, pair_ids,
-                       (const int4*)rect, (const int64_t*)start, pair_pos, slots);
+    if (pair_capacity > 0)
+        hipLaunchKernelGGL(k_clear_slots, dim3(2048), dim3(256), 0, stream, tile_ranges,
+                           (int64_t)n_views * n_tiles - 1, pair_capacity, slots);
     BwdArgs a = {};
     a.V = n_views; a.W = width; a.H = height; a.ntx = ntx; a.n_tiles = n_tiles;
     a.T = params->tex_res; a.n = n; a.cams = cams;
@@ -736,10 +766,11 @@ extern "C" int ts_raster_bwd(int32_t n_views, int32_t width, int32_t height, con
     a.rec = (const float4*)rec; a.ranges = (const int2*)tile_ranges; a.pair_ids = pair_ids;
     a.cap = pair_capacity; a.atlas = (const float4*)atlas; a.gbuf = gbuf; a.t_final = t_final;
     a.n_contrib = n_contrib; a.d_rgba = (const float4*)d_rgba; a.slots = slots;
+    a.rect = (const int4*)rect; a.start = (const int64_t*)start;
     a.part = partials; a.part_cap = partial_capacity; a.part_top = top; a.status = status;
     hipLaunchKernelGGL(k_raster_bwd, dim3(n_views * n_tiles), dim3(256), 0, stream, a);
     hipLaunchKernelGGL(k_bwd_gather, dim3(n), dim3(64), 0, stream, n_views, n, params->tex_res,
-                       (const int4*)rect, (const int64_t*)start, (const int32_t*)pair_pos,
+                       (const int4*)rect, (const int64_t*)start, pair_capacity,
                        (const int32_t*)slots, (const float*)partials, chart_of,
                        (const int32_t*)status, beta, rec_grad, d_atlas);
     hipLaunchKernelGGL(k_bwd_params, dim3((n + 255) / 256), dim3(256), 0, stream, n_views, n, cams,
