@@ -57,7 +57,9 @@ struct BwdArgs {
     int32_t* status;
 };
 
-__global__ __launch_bounds__(256) void k_raster_bwd(BwdArgs a) {
+// 4 waves per SIMD (at most 128 VGPRs): enough resident waves to cover the texel and
+// record loads measured faster than 3 waves with more registers
+__global__ __launch_bounds__(256, 4) void k_raster_bwd(BwdArgs a) {
     __shared__ float4 srec[kBwdBatch * kRec4];
     __shared__ float ent[4][kWave * kEnt];
     __shared__ int smax[4];
