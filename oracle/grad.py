@@ -4,7 +4,9 @@ A dense float64 formulation of the same per-pixel definition as oracle.c (Sec. 3
 Sec. 3.2-3.3 Eq. 4-6, Sec. 3.5 Eq. 7-12), written with plain PyTorch CPU ops so that autograd
 gives the gradient of any scalar of the rendered RGBA with respect to the splat centres, the
 (unnormalised) quaternions, the linear scales, the opacities and the texels — the quantities
-the paper optimises (Sec. 3.6).
+the paper optimises (Sec. 3.6) — and, on request, to the texels of the environment's shading
+tables (irradiance cube and prefiltered levels taken as learnable, as the environment is
+optimised end to end in Sec. 3.5-3.6).
 
 Discrete decisions are taken from values and carry no gradient, exactly as in the forward
 definition: the near-plane drop, the hit in front of the camera, the square support, the alpha
@@ -87,9 +89,9 @@ def _shade(g, A, dirs, tabs, bg):
     ndv = (Nh * wo).sum(1)
     wr = 2 * ndv[:, None] * Nh - wo
     M, R = g[:, 3], g[:, 4]
-    irr = torch.as_tensor(tabs["irr"], dtype=DT)
+    irr = tabs["irr"] if torch.is_tensor(tabs["irr"]) else torch.as_tensor(tabs["irr"], dtype=DT)
     E = _cube_lookup(irr, Nh)
-    levels = [torch.as_tensor(l, dtype=DT) for l in tabs["spec"]]
+    levels = [l if torch.is_tensor(l) else torch.as_tensor(l, dtype=DT) for l in tabs["spec"]]
     L = len(levels)
     rc = R.clamp(0.0, 1.0)
     lev = rc * (L - 1)
@@ -203,15 +205,27 @@ def render_dense(means, quats, scales, opac, textures, chart_of, cam, pixels, ta
     return rgba, gbuf
 
 
-def grads(scene, cam, pixels, d_rgba, tabs=None, params=None):
-    """Gradients of sum(d_rgba * rgba) w.r.t. means, quats, scales, opac and textures."""
+def grads(scene, cam, pixels, d_rgba, tabs=None, params=None, env=False):
+    """Gradients of sum(d_rgba * rgba) w.r.t. means, quats, scales, opac and textures; with
+    env=True also w.r.t. the texels of the irradiance cube ("irr", [6,r,r,3]) and of every
+    prefiltered level ("spec", list of [6,r_l,r_l,3]), the tables taken as parameters."""
     leaves = {k: torch.tensor(np.asarray(scene[k], np.float32), dtype=DT, requires_grad=True)
               for k in ("means", "quats", "scales", "opac", "textures")}
+    t = tabs
+    if env:
+        t = dict(tabs)
+        t["irr"] = torch.tensor(np.asarray(tabs["irr"]), dtype=DT, requires_grad=True)
+        t["spec"] = [torch.tensor(np.asarray(l), dtype=DT, requires_grad=True)
+                     for l in tabs["spec"]]
     rgba, gbuf = render_dense(leaves["means"], leaves["quats"], leaves["scales"], leaves["opac"],
-                              leaves["textures"], scene["chart_of"], cam, pixels, tabs, params)
+                              leaves["textures"], scene["chart_of"], cam, pixels, t, params)
     loss = (rgba * torch.as_tensor(np.asarray(d_rgba), dtype=DT)).sum()
     loss.backward()
     out = {k: leaves[k].grad.detach().numpy() for k in leaves}
     out["rgba"] = rgba.detach().numpy()
     out["gbuf"] = gbuf.detach().numpy()
+    if env:
+        z = lambda x: (x.grad if x.grad is not None else torch.zeros_like(x)).detach().numpy()
+        out["irr"] = z(t["irr"])
+        out["spec"] = [z(l) for l in t["spec"]]
     return out

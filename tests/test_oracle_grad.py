@@ -92,3 +92,67 @@ def test_texel_gradients_sum_to_single_attribute_gradient():
     for k in ("means", "quats", "scales", "opac"):
         np.testing.assert_allclose(g4[k], g1[k], atol=1e-8 * max(1.0, np.abs(g1[k]).max()))
     assert np.abs(g1["textures"]).max() > 0
+
+
+# ---------------------------------------------------------------- environment-table gradients
+
+@pytest.fixture(scope="module")
+def env_case():
+    sc = synth.make_scene("sq300k_train", n=3000, env_res=16)
+    sc["env_levels"] = 3
+    cam = synth.crop_camera(synth.config_cameras("sq300k_train")[0], 360, 360, 24, 24)
+    tabs = oracle.tables(sc["env"], sc["env_levels"])
+    pix = oracle.all_pixels(24, 24)
+    d = np.random.default_rng(3).normal(size=(len(pix), 4))
+    g = og.grads(sc, cam, pix, d, tabs, env=True)
+    return sc, cam, tabs, pix, d, g
+
+
+def _env_loss(sc, cam, pix, d, tabs, which, level, idx, val):
+    t = dict(tabs)
+    if which == "irr":
+        a = np.array(tabs["irr"], np.float64)
+        a.reshape(-1)[idx] = val
+        t["irr"] = a
+    else:
+        levels = [np.array(l, np.float64) for l in tabs["spec"]]
+        levels[level].reshape(-1)[idx] = val
+        t["spec"] = levels
+    leaves = {k: torch.tensor(np.asarray(sc[k], np.float32), dtype=torch.float64)
+              for k in ("means", "quats", "scales", "opac", "textures")}
+    rgba, _ = og.render_dense(leaves["means"], leaves["quats"], leaves["scales"], leaves["opac"],
+                              leaves["textures"], sc["chart_of"], cam, pix, t)
+    return float((rgba * torch.as_tensor(d)).sum())
+
+
+def test_env_gradients_equal_unit_differences(env_case):
+    """The render is linear in every table texel (faces and taps depend on directions only),
+    so a central difference with a step of 1 is the exact derivative."""
+    sc, cam, tabs, pix, d, g = env_case
+    rng = np.random.default_rng(5)
+    checked = 0
+    cases = [("irr", 0, g["irr"], tabs["irr"])]
+    cases += [("spec", l, g["spec"][l], tabs["spec"][l]) for l in range(len(tabs["spec"]))]
+    for which, level, grad, base in cases:
+        flat = grad.reshape(-1)
+        hit = np.nonzero(np.abs(flat) > 0)[0]
+        assert len(hit) > 0, (which, level)
+        for idx in list(rng.choice(hit, min(4, len(hit)), replace=False)) + [int(np.argmax(np.abs(flat)))]:
+            x0 = float(np.asarray(base).reshape(-1)[idx])
+            fd = (_env_loss(sc, cam, pix, d, tabs, which, level, idx, x0 + 1.0) -
+                  _env_loss(sc, cam, pix, d, tabs, which, level, idx, x0 - 1.0)) / 2.0
+            assert abs(fd - flat[idx]) <= 1e-9 * max(1.0, abs(fd)), (which, level, idx, fd, flat[idx])
+            checked += 1
+    assert checked >= 10
+
+
+def test_irradiance_gradients_partition_of_unity(env_case):
+    """Bilinear weights sum to one, so the irradiance-texel gradients of each channel sum to
+    sum_pixels dL/dC_c * albedo_c (1 - M) / pi over the covered pixels (Eq. 11)."""
+    sc, cam, tabs, pix, d, g = env_case
+    ref = oracle.render(sc, cam, pixels=pix, tabs=tabs)
+    gb, A = ref["gbuf"], ref["rgba"][:, 3]
+    cov = A > 0
+    expect = (d[cov, :3] * gb[cov, 0:3] * (1 - gb[cov, 3:4]) / np.pi).sum(0)
+    got = g["irr"].reshape(-1, 3).sum(0)
+    np.testing.assert_allclose(got, expect, rtol=1e-10, atol=1e-12)
