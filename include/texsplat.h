@@ -236,6 +236,36 @@ int ts_raster_bwd(int32_t n_views, int32_t width, int32_t height, const ts_camer
 int ts_raster_bwd_workspace(int32_t n_views, int32_t n, int64_t pair_capacity, size_t* bytes);
 
 /*
+ * ts_env_bwd — gradients of the same loss with respect to the texels of the environment's
+ * shading tables, taken as learnable parameters (the environment is optimised end to end,
+ * Sec. 3.5-3.6): the irradiance cube E of Eq. 11 and every prefiltered level of the split-sum
+ * specular term of Eq. 12. The shaded colour is linear in each texel; per covered pixel the
+ * irradiance lookup at N receives dL/dC * albedo (1-M)/pi and the two specular lookups at the
+ * reflected direction receive dL/dC * (F0 A + B) weighted (1-f) and f between the levels
+ * around R (L-1), each spread over 4 texels by the bilinear weights. Empty pixels (alpha = 0,
+ * background only) contribute nothing. Summed without floating-point atomics (records sorted
+ * by texel, summed in pixel order): run-to-run identical.
+ *
+ *   cams, env    as given to ts_raster_fwd / ts_raster_bwd
+ *   gbuf, t_final  forward outputs of the same frame ([n_views][8][H][W], [n_views][H][W])
+ *   d_rgba       [n_views][H][W][4] dL/d(rgb, alpha) (alpha does not reach the tables)
+ *   ws, ws_bytes scratch, at least ts_env_bwd_workspace(n_views, width, height) bytes
+ *                (about 56 bytes per pixel)
+ *   beta         0: overwrite the outputs; 1: add to them
+ *   d_irr        [6][irr_res][irr_res][4] out, layout of env->irr (the 4th component is 0)
+ *   d_spec       levels back to back as env->spec, [6][r_l][r_l][4] each, out
+ * Errors: TS_E_ARG (null pointers, bad sizes, more than 2^31-1 records), TS_E_WORKSPACE,
+ * TS_E_LAUNCH.
+ */
+int ts_env_bwd(int32_t n_views, int32_t width, int32_t height, const ts_camera* cams,
+               const ts_env* env, const float* gbuf, const float* t_final, const float* d_rgba,
+               void* ws, size_t ws_bytes, float beta, float* d_irr, float* d_spec,
+               hipStream_t stream);
+
+/* Scratch bytes ts_env_bwd needs (host only). */
+int ts_env_bwd_workspace(int32_t n_views, int32_t width, int32_t height, size_t* bytes);
+
+/*
  * ts_brdf_lut — the split-sum BRDF table (Sec. 3.5.4 precomputed 2D lookup; split sum of
  * Karis 2013): texel (i,j) at N.V = (i+1/2)/n, roughness r = (j+1/2)/n holds
  *   A = mean_k (1 - Fc) G_vis,  B = mean_k Fc G_vis,

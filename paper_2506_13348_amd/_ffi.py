@@ -52,6 +52,9 @@ _SIGS = {
                       c_void_p, c_float, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                       c_void_p],
     "ts_raster_bwd_workspace": [c_int32, c_int32, c_int64, ctypes.POINTER(c_size_t)],
+    "ts_env_bwd": [c_int32, c_int32, c_int32, c_void_p, ctypes.POINTER(TsEnv), c_void_p, c_void_p,
+                   c_void_p, c_void_p, c_size_t, ctypes.c_float, c_void_p, c_void_p, c_void_p],
+    "ts_env_bwd_workspace": [c_int32, c_int32, c_int32, ctypes.POINTER(c_size_t)],
     "ts_brdf_lut": [c_int32, c_int32, c_void_p, c_void_p],
     "ts_env_tables": [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p],
     "ts_atlas_pack": [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p],
@@ -161,6 +164,21 @@ def ts_raster_fwd(n_views, width, height, cams, params, n, rec, tile_ranges, pai
                                ptr(gbuf), ptr(t_final), ptr(n_contrib), ptr(n_blend),
                                stream_handle(stream)),
            "ts_raster_fwd")
+
+
+def ts_env_bwd_workspace(n_views, width, height):
+    out = c_size_t(0)
+    _check(lib().ts_env_bwd_workspace(n_views, width, height, ctypes.byref(out)),
+           "ts_env_bwd_workspace")
+    return int(out.value)
+
+
+def ts_env_bwd(n_views, width, height, cams, env, gbuf, t_final, d_rgba, ws, beta, d_irr, d_spec,
+               stream=None):
+    _check(lib().ts_env_bwd(n_views, width, height, ptr(cams), ctypes.byref(env), ptr(gbuf),
+                            ptr(t_final), ptr(d_rgba), ptr(ws), ws.numel() * ws.element_size(),
+                            float(beta), ptr(d_irr), ptr(d_spec), stream_handle(stream)),
+           "ts_env_bwd")
 
 
 def ts_raster_bwd_workspace(n_views, n, pair_capacity):

@@ -60,6 +60,28 @@ class BackwardRunner:
         raise RuntimeError("ts_raster_bwd: partial buffer overflow after resizing")
 
 
+class EnvBackward:
+    """Workspace of ts_env_bwd for one render plan: gradients of the loss with respect to the
+    texels of the plan's shading tables (irradiance cube and prefiltered levels)."""
+
+    def __init__(self, plan: RenderPlan):
+        self.plan = plan
+        dev = plan.scene.device
+        ws = F.ts_env_bwd_workspace(plan.V, plan.W, plan.H)
+        self.ws = torch.empty((ws + 7) // 8, device=dev, dtype=torch.int64)
+        tabs = plan.scene.tables
+        self.d_irr = torch.zeros_like(tabs.irr)
+        self.d_spec = torch.zeros_like(tabs.spec)
+
+    def run(self, d_rgba, beta=0.0):
+        p = self.plan
+        if p.gbuf is None or p.t_final is None:
+            raise RuntimeError("environment gradients need the plan's G-buffers (gbuf=True)")
+        F.ts_env_bwd(p.V, p.W, p.H, p.cams, p.scene.tables.struct, p.gbuf, p.t_final,
+                     d_rgba.contiguous(), self.ws, beta, self.d_irr, self.d_spec, p.stream)
+        return self.d_irr, self.d_spec
+
+
 class TexSplatRender(torch.autograd.Function):
     @staticmethod
     def forward(ctx, means, quats, scales, opac, atlas, chart_of, cams, width, height, tables,

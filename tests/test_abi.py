@@ -47,6 +47,10 @@ def test_host_side_argument_errors():
                            ctypes.c_void_p(16), None, None, None, None, None, None, None) == -1
     assert b"tex_res" in L.ts_last_error()
     assert L.ts_brdf_lut(0, 16, None, None) == -1
+    assert L.ts_env_bwd_workspace(0, 8, 8, ctypes.byref(out)) == -1
+    assert L.ts_env_bwd_workspace(2, 8, 8, ctypes.byref(out)) == 0 and out.value >= 2 * 64 * 12 * 36
+    assert L.ts_env_bwd(1, 8, 8, None, None, None, None, None, None, 0, ctypes.c_float(0.0),
+                        None, None, None) == -1
 
 
 def test_hardware_sampler_reported_unsupported():

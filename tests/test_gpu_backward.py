@@ -252,3 +252,117 @@ def test_autograd_function_matches_runner():
     g, _ = _gpu_grads(sc, [cam], 128, 128, d4.cpu().numpy())
     for leaf, ref in zip(leaves, g):
         torch.testing.assert_close(leaf.grad, ref, rtol=0, atol=0)
+
+
+# ------------------------------------------------------------ environment-table gradients
+
+def _env_ref(sc, cams, pix_list, ds, tabs):
+    """Summed float64 reference of the table gradients over views, and their spread under
+    +-2^-23 moves of the splat parameters (taps at a texel boundary)."""
+    def total(scene):
+        irr, spec = 0.0, None
+        for cam, pix, d in zip(cams, pix_list, ds):
+            r = og.grads(scene, cam, pix, d, tabs, env=True)
+            irr = irr + r["irr"]
+            spec = r["spec"] if spec is None else [a + b for a, b in zip(spec, r["spec"])]
+        return [irr] + spec
+    ref = total(sc)
+    spread = [np.zeros_like(x) for x in ref]
+    for sign in (1.0, -1.0):
+        alt = total(_perturbed(sc, sign, 11))
+        spread = [np.maximum(s, np.abs(a - b)) for s, a, b in zip(spread, alt, ref)]
+    return ref, spread
+
+
+def _gpu_env_grads(sc, cams, W, H, d_rgba, beta_twice=False):
+    P = _pkg()
+    from paper_2506_13348_amd.autograd import EnvBackward
+    ds = P.DeviceScene.from_dict(sc, device="cuda")
+    plan = P.RenderPlan(ds, cams, W, H, gbuf=True, aux=True)
+    plan.run()
+    plan.check()
+    eb = EnvBackward(plan)
+    d = torch.as_tensor(np.asarray(d_rgba, np.float32)).cuda().contiguous()
+    eb.run(d)
+    torch.cuda.synchronize()
+    out = [eb.d_irr.clone()]
+    first = [eb.d_irr.clone(), eb.d_spec.clone()]
+    if beta_twice:
+        eb.run(d, beta=1.0)
+        torch.cuda.synchronize()
+    tabs = ds.tables
+    r_irr = tabs.irr_res
+    irr = eb.d_irr.view(6, r_irr, r_irr, 4)
+    spec, off = [], 0
+    for l in range(tabs.levels):
+        rl = max(tabs.res >> l, 1)
+        m = 6 * rl * rl * 4
+        spec.append(eb.d_spec[off:off + m].view(6, rl, rl, 4))
+        off += m
+    return [irr] + spec, first, eb
+
+
+def _compare_env(g, ref, spread, name):
+    for k, (a, b, sp) in enumerate(zip(g, ref, spread)):
+        a4 = a.double().cpu().numpy()
+        assert np.all(a4[..., 3] == 0.0)
+        a, b, sp = a4[..., :3].reshape(-1), b.reshape(-1), sp.reshape(-1)
+        scale = np.abs(b).max()
+        tol = 1e-3 * scale + 1e-7 + 2.0 * sp
+        d = np.abs(a - b)
+        cos = float(a @ b / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-300))
+        if (d > tol).any():
+            i = int(np.argmax(d - tol))
+            print(f"[{name}] table {k} worst [{i}] gpu {a[i]:.6g} ref {b[i]:.6g} spread {sp[i]:.3g}",
+                  flush=True)
+        print(f"[{name}] table {k}: rel {d.max() / max(scale, 1e-300):.2e} cos {cos:.7f} "
+              f"nonzero {int((b != 0).sum())}", flush=True)
+        assert (d <= tol).all(), (name, k)
+        assert cos >= 0.9999, (name, k, cos)
+
+
+def test_env_grads_multi_view():
+    sc = synth.make_scene("sq300k_train", n=3000, env_res=16)
+    sc["env_levels"] = 3
+    cams = [synth.crop_camera(c, 330, 340, 45, 37) for c in synth.config_cameras("sq300k_train")[:2]]
+    tabs = oracle.tables(sc["env"], sc["env_levels"])
+    pix = oracle.all_pixels(45, 37)
+    rng = np.random.default_rng(8)
+    d_all = np.zeros((2, 37, 45, 4))
+    ds = []
+    for v, cam in enumerate(cams):
+        ref_f = oracle.render(sc, cam, pixels=pix, tabs=tabs)
+        d, d4 = _upstream(rng, ref_f, (37, 45, 4))
+        d_all[v] = d4
+        ds.append(d)
+    ref, spread = _env_ref(sc, cams, [pix, pix], ds, tabs)
+    g, first, _ = _gpu_env_grads(sc, cams, 45, 37, d_all, beta_twice=True)
+    # beta = 1 added the same gradients once more
+    for a, b in zip([first[0]], [g[0]]):
+        assert torch.equal(2 * a, b.reshape(-1))
+    g2, _, _ = _gpu_env_grads(sc, cams, 45, 37, d_all)
+    for a, b in zip(g, g2):
+        assert torch.equal(a, 2 * b)
+    _compare_env(g2, ref, spread, "env 2 views")
+
+
+def test_env_grads_sq300k_training_batch_sampled():
+    """The 8-view 800x800 training batch with dL/dC at sampled pixels only."""
+    from parity import sample_pixels
+    sc = synth.make_scene("sq300k_train")
+    cams = synth.config_cameras("sq300k_train")
+    tabs = oracle.tables(sc["env"], sc["env_levels"])
+    rng = np.random.default_rng(9)
+    d_all = np.zeros((len(cams), 800, 800, 4))
+    pix_v, ds = [], []
+    for v in range(3):
+        pix = np.unique(sample_pixels(rng, 800, 800, 12), axis=0)
+        ref_f = oracle.render(sc, cams[v], pixels=pix, tabs=tabs)
+        d = rng.normal(size=(len(pix), 4))
+        d[(ref_f["stat"][:, 2] > 0) | (ref_f["stat"][:, 3] > 0)] = 0.0
+        d_all[v, pix[:, 1], pix[:, 0]] = d
+        pix_v.append(pix)
+        ds.append(d)
+    ref, spread = _env_ref(sc, cams[:3], pix_v, ds, tabs)
+    g, _, _ = _gpu_env_grads(sc, cams, 800, 800, d_all)
+    _compare_env(g, ref, spread, "env sq300k")
