@@ -116,11 +116,25 @@ def bench_fwd_bwd(cfg, steps, warmup):
         raise RuntimeError("backward partial buffer overflow in the timed steps")
     fwd_ms = float(np.mean([ev[k][0].elapsed_time(ev[k][1]) for k in range(steps)]))
     bwd_ms = float(np.mean([ev[k][1].elapsed_time(ev[k][2]) for k in range(steps)]))
+    # gradients of the same loss w.r.t. the environment-table texels (learnable environment),
+    # timed on their own after the step
+    from paper_2506_13348_amd.autograd import EnvBackward
+    eb = EnvBackward(plan)
+    eb.run(d_rgba)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        eb.run(d_rgba)
+    e1.record()
+    torch.cuda.synchronize()
+    env_ms = e0.elapsed_time(e1) / 3
+    del eb
     out = {"value": round(V * W * H / dt / 1e6, 2), "unit": "Mpix/s",
            "ms_per_step": round(dt * 1e3, 3), "steps": steps, "views_per_step": V,
            "width": W, "height": H, "splats": ds.n,
            "per_phase_ms": {"forward": round(fwd_ms, 3), "loss_and_backward": round(bwd_ms, 3)},
            "workload": FWD_BWD_WORKLOADS[cfg],
+           "env_tables_bwd_ms": round(env_ms, 3),
            "partial_buffer_floats_used": int(run.used.item())}
     del plan, run, grads, d_rgba, target, ds
     torch.cuda.empty_cache()
