@@ -61,6 +61,66 @@ __global__ __launch_bounds__(1024) void k_sort_scan(uint32_t* __restrict__ hist,
     }
 }
 
+// Multi-block form of the same exclusive scan, for histograms too long for one block:
+// per 1024-entry block totals, a one-block scan of those per segment, then each block's own
+// scan plus its offset.
+__device__ inline uint32_t block_excl_scan_u32(uint32_t x, uint32_t* sh, uint32_t* total) {
+    int tid = threadIdx.x;
+    sh[tid] = x;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        uint32_t y = tid >= o ? sh[tid - o] : 0u;
+        __syncthreads();
+        sh[tid] += y;
+        __syncthreads();
+    }
+    uint32_t incl = sh[tid];
+    if (total) *total = sh[1023];
+    __syncthreads();
+    return incl - x;
+}
+
+__global__ __launch_bounds__(1024) void k_sort_scan_sums(const uint32_t* __restrict__ hist,
+                                                         int nblk, int nbs,
+                                                         uint32_t* __restrict__ tmp) {
+    __shared__ uint32_t sh[1024];
+    int b = blockIdx.x, v = blockIdx.y;
+    int64_t m = (int64_t)kSortBuckets * nblk;
+    int64_t i = (int64_t)b * 1024 + threadIdx.x;
+    uint32_t x = i < m ? hist[(int64_t)v * m + i] : 0u;
+    uint32_t tot;
+    block_excl_scan_u32(x, sh, &tot);
+    if (threadIdx.x == 0) tmp[(int64_t)v * nbs + b] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_sort_scan_tmp(uint32_t* __restrict__ tmp, int nbs) {
+    __shared__ uint32_t sh[1024];
+    int v = blockIdx.x;
+    uint32_t* t = tmp + (int64_t)v * nbs;
+    int per = (nbs + 1023) / 1024;
+    int a0 = threadIdx.x * per, a1 = min(nbs, a0 + per);
+    uint32_t s = 0;
+    for (int i = a0; i < a1; i++) s += t[i];
+    uint32_t run = block_excl_scan_u32(s, sh, nullptr);
+    for (int i = a0; i < a1; i++) {
+        uint32_t x = t[i];
+        t[i] = run;
+        run += x;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_sort_scan_apply(uint32_t* __restrict__ hist, int nblk,
+                                                          int nbs,
+                                                          const uint32_t* __restrict__ tmp) {
+    __shared__ uint32_t sh[1024];
+    int b = blockIdx.x, v = blockIdx.y;
+    int64_t m = (int64_t)kSortBuckets * nblk;
+    int64_t i = (int64_t)b * 1024 + threadIdx.x;
+    uint32_t x = i < m ? hist[(int64_t)v * m + i] : 0u;
+    uint32_t ex = block_excl_scan_u32(x, sh, nullptr) + tmp[(int64_t)v * nbs + b];
+    if (i < m) hist[(int64_t)v * m + i] = ex;
+}
+
 // Stable scatter. Wave w of the block owns items [w*1024, (w+1)*1024) of the block's range,
 // taken 64 at a time in order; lanes with equal digits are ranked with ballots, and a
 // per-wave running count per digit (LDS) carries ranks across rounds.

@@ -286,8 +286,8 @@ __global__ __launch_bounds__(256) void k_env_clear(float4* __restrict__ p, int64
 struct EnvBwdLayout {
     int64_t m;               // records
     int nblk_sort, nb_scan;
-    size_t off_keys, off_vals, off_ka, off_kb, off_va, off_order, off_hist, off_run, off_bsum,
-        off_pieces, total;
+    size_t off_keys, off_vals, off_ka, off_kb, off_va, off_order, off_hist, off_stmp, off_run,
+        off_bsum, off_pieces, total;
 };
 
 inline EnvBwdLayout env_bwd_layout(int V, int W, int H) {
@@ -304,6 +304,8 @@ inline EnvBwdLayout env_bwd_layout(int V, int W, int H) {
     L.off_va = off; off = align256(off + m * 4);
     L.off_order = off; off = align256(off + m * 4);
     L.off_hist = off; off = align256(off + (size_t)kSortBuckets * L.nblk_sort * 4);
+    L.off_stmp = off;
+    off = align256(off + (size_t)sort_scan_tmp_entries((int)(m < 0x7FFFFFFF ? m : 0x7FFFFFFF)) * 4);
     L.off_run = off; off = align256(off + m * 4);
     L.off_bsum = off; off = align256(off + (size_t)(L.nb_scan + 1) * 4);
     L.off_pieces = off; off = align256(off + m * 16);
@@ -381,7 +383,8 @@ extern "C" int ts_env_bwd(int32_t n_views, int32_t width, int32_t height, const 
     hipLaunchKernelGGL(k_env_records, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, stream, a);
     int m = (int)L.m;
     // sorted keys land in kb, the record order in `order` (four passes)
-    radix_sort_indices(keys, m, 1, ka, kb, va, hist, order, stream);
+    radix_sort_indices(keys, m, 1, ka, kb, va, hist, order, stream,
+                       (uint32_t*)(w + L.off_stmp));
     static_assert(kSortPasses == 4, "sorted keys are read from the second key buffer");
     unsigned g256 = (unsigned)((L.m + 255) / 256);
     hipLaunchKernelGGL(k_env_run_flags, dim3(g256), dim3(256), 0, stream, kb, L.m, run);
