@@ -57,7 +57,8 @@ def lib():
             build()
             L = ctypes.CDLL(_LIB)
             for name in ["or_irradiance", "or_prefilter", "or_brdf_lut", "or_render", "or_shade",
-                         "or_cube_sample", "or_cube_texels", "or_lut_sample", "or_splat_setup"]:
+                         "or_cube_sample", "or_cube_texels", "or_lut_sample", "or_splat_setup",
+                         "or_sh_basis", "or_indirect_eval"]:
                 getattr(L, name).restype = ctypes.c_int
             _lib = L
     return _lib
@@ -188,13 +189,19 @@ def all_pixels(width, height):
     return np.stack([xs.ravel(), ys.ravel()], axis=1).astype(np.int32)
 
 
-def render(scene, cam, pixels=None, params=None, tabs=None, shade=True):
+GB = 11   # G-buffer channels of the oracle: albedo 3, metallic, roughness, normal 3, L_ind 3
+
+
+def render(scene, cam, pixels=None, params=None, tabs=None, shade=True, lind=None, vis=None):
     """Render the listed pixels ([P,2] x,y; default: the whole frame).
 
+    lind: per-splat indirect radiance [n,3] of this view (indirect_eval), or None;
+    vis: visibility V per listed pixel [P], or None (V = 1).
+
     Returns dict with rgba [P,4], gbuf [P,8] (albedo 3, metallic, roughness, normal 3),
-    stat [P,7] (n_blend, n_support, n_ambiguous, grazing, min cube-face gap, n_alt,
-    shading sensitivity = sum over G-buffer channels of max_rgb |dC/dg_c|),
-    alt_rgba [P,MAX_ALT,4], alt_gbuf [P,MAX_ALT,8]."""
+    gind [P,3] (blended L_ind), stat [P,7] (n_blend, n_support, n_ambiguous, grazing,
+    min cube-face gap, n_alt, shading sensitivity = sum over G-buffer channels of
+    max_rgb |dC/dg_c|), alt_rgba [P,MAX_ALT,4], alt_gbuf [P,MAX_ALT,8], alt_gind [P,MAX_ALT,3]."""
     if pixels is None:
         pixels = all_pixels(cam["width"], cam["height"])
     pixels = np.ascontiguousarray(pixels, dtype=np.int32).reshape(-1, 2)
@@ -203,8 +210,12 @@ def render(scene, cam, pixels=None, params=None, tabs=None, shade=True):
     T = int(scene["textures"].shape[1])
     m, q, s, o, tex = (_f32(scene[k]) for k in ("means", "quats", "scales", "opac", "textures"))
     chart = np.ascontiguousarray(scene["chart_of"], dtype=np.int32)
-    out = {"rgba": np.zeros((P, 4)), "gbuf": np.zeros((P, 8)), "stat": np.zeros((P, 7)),
-           "alt_rgba": np.zeros((P, MAX_ALT, 4)), "alt_gbuf": np.zeros((P, MAX_ALT, 8))}
+    gbuf = np.zeros((P, GB))
+    alt_gbuf = np.zeros((P, MAX_ALT, GB))
+    out = {"rgba": np.zeros((P, 4)), "stat": np.zeros((P, 7)),
+           "alt_rgba": np.zeros((P, MAX_ALT, 4))}
+    li = None if lind is None else _f64(lind).reshape(n, 3)
+    vi = None if vis is None else _f64(vis).reshape(P)
     if shade:
         if tabs is None:
             tabs = tables(scene["env"], scene["env_levels"])
@@ -216,15 +227,25 @@ def render(scene, cam, pixels=None, params=None, tabs=None, shade=True):
         env_args = (None, 0, 0, None, 0, None, 0)
     rc = lib().or_render(n, T, _p(m), _p(q), _p(s), _p(o), _p(tex), _p(chart),
                          _p(cam16(cam)), _p(params_vec(params)), *env_args,
-                         _p(pixels), P, _p(out["rgba"]), _p(out["gbuf"]), _p(out["stat"]),
-                         _p(out["alt_rgba"]), _p(out["alt_gbuf"]))
+                         None if li is None else _p(li), None if vi is None else _p(vi),
+                         _p(pixels), P, _p(out["rgba"]), _p(gbuf), _p(out["stat"]),
+                         _p(out["alt_rgba"]), _p(alt_gbuf))
     assert rc == 0
+    out["gbuf"], out["gind"] = gbuf[:, :8], gbuf[:, 8:]
+    out["alt_gbuf"], out["alt_gind"] = alt_gbuf[:, :, :8], alt_gbuf[:, :, 8:]
     return out
 
 
-def shade_gbuffer(gbuf, alpha, cam, pixels, tabs, params=None):
-    """Shade given G-buffer values: gbuf [P,8], alpha [P] at pixels [P,2] -> rgb [P,3]."""
-    gbuf = _f64(gbuf).reshape(-1, 8)
+def shade_gbuffer(gbuf, alpha, cam, pixels, tabs, params=None, gind=None, vis=None):
+    """Shade given G-buffer values: gbuf [P,8], alpha [P] at pixels [P,2] -> rgb [P,3];
+    gind [P,3] blended indirect radiance (default 0), vis [P] visibility (default 1)."""
+    g8 = _f64(gbuf).reshape(-1, 8)
+    P0 = len(g8)
+    gbuf = np.zeros((P0, GB))
+    gbuf[:, :8] = g8
+    if gind is not None:
+        gbuf[:, 8:] = _f64(gind).reshape(P0, 3)
+    vi = None if vis is None else _f64(vis).reshape(P0)
     alpha = _f64(alpha).reshape(-1)
     pixels = np.ascontiguousarray(pixels, dtype=np.int32).reshape(-1, 2)
     P = len(pixels)
@@ -232,8 +253,34 @@ def shade_gbuffer(gbuf, alpha, cam, pixels, tabs, params=None):
     irr, lut = _f64(tabs["irr"]), _f64(tabs["lut"])
     rgb = np.zeros((P, 3))
     gap = np.zeros(P)
-    assert lib().or_shade(_p(gbuf), _p(alpha), _p(pixels), P, _p(cam16(cam)),
+    assert lib().or_shade(_p(gbuf), _p(alpha), None if vi is None else _p(vi), _p(pixels), P,
+                          _p(cam16(cam)),
                           _p(params_vec(params)), _p(spec), tabs["spec"][0].shape[1],
                           len(tabs["spec"]), _p(irr), irr.shape[1], _p(lut), lut.shape[0],
                           _p(rgb), _p(gap)) == 0
     return rgb, gap
+
+
+# ----------------------------------------------------------------------------------------
+# indirect light (per-splat spherical harmonics)
+# ----------------------------------------------------------------------------------------
+
+def sh_basis(degree, dirs):
+    """Real orthonormal SH basis values at directions [P,3] -> [P,(degree+1)^2]."""
+    dirs = _f64(dirs).reshape(-1, 3)
+    K = (degree + 1) ** 2
+    out = np.zeros((len(dirs), K))
+    assert lib().or_sh_basis(int(degree), _p(dirs), len(dirs), _p(out)) == 0
+    return out
+
+
+def indirect_eval(scene, cam, sh, degree):
+    """Per-splat indirect radiance [n,3] for one camera from sh [n,(degree+1)^2,3]."""
+    n = len(scene["opac"])
+    K = (degree + 1) ** 2
+    sh = _f32(sh).reshape(n, K, 3)
+    m, q = _f32(scene["means"]), _f32(scene["quats"])
+    out = np.zeros((n, 3))
+    assert lib().or_indirect_eval(n, _p(m), _p(q), _p(sh), int(degree), _p(cam16(cam)),
+                                  _p(out)) == 0
+    return out

@@ -14,6 +14,9 @@
  *   - tangent normal rotated to world space, n = R n^t                      (Eq. 7)
  *   - G-buffers X = [albedo, metallic, roughness, normal]                   (Eq. 9)
  *   - split-sum shading L_o = L_d + L_s against an environment cubemap      (Eq. 10-12)
+ *   - the indirect term: per-splat indirect radiance from spherical harmonics, blended as a
+ *     fifth G-buffer map L_ind, and the visibility-weighted specular mix
+ *     BRDF_LUT (V L_dir + (1 - V) L_ind)                                     (Eq. 9, Eq. 12)
  *   - the pre-integrated tables the shading reads: diffuse irradiance, roughness-prefiltered
  *     specular levels and the 2D BRDF lookup table                         (Sec. 3.5.4)
  * Every splat is tested against every pixel (no tiles, no culling grid).
@@ -28,6 +31,11 @@
  *   maps as they are (premultiplied), F0 = 0.04 (1-M) + albedo M, and an empty pixel takes
  *   the background colour; cube lookups use the OpenGL major-axis face rule with ties going
  *   X, then Y, then Z, bilinear at texel centres inside the face with clamp-to-edge.
+ *   Indirect light: splat k carries real spherical-harmonic coefficients (orthonormal basis,
+ *   no Condon-Shortley phase, degree <= 3) per colour channel, evaluated once per view at the
+ *   mirror reflection of the camera-to-centre direction about the splat's plane and clamped
+ *   at zero; the blended L_ind enters the shading premultiplied like the other maps, and V is
+ *   a per-pixel input (V = 1 and no indirect map give the plain split sum).
  *
  * Decisions a tiny rounding difference can flip (support edge, alpha cut-off, termination,
  * grazing rays, cube-face ties) are recorded per pixel; for each flippable one the pixel is
@@ -402,11 +410,14 @@ static void tex_bilinear(const scene_t* sc, int k, double s, double t, double* a
 }
 
 /* ------------------------------------------------------------------------------------- */
-/* shading (Eq. 10-12, split sum with V = 1 and no indirect term)                         */
+/* shading (Eq. 10-12: split sum, specular mix of direct and indirect light by V)         */
 /* ------------------------------------------------------------------------------------- */
-/* g = [albedo r,g,b, metallic, roughness, normal x,y,z] (blended), A = alpha,
-   dir = world ray direction through the pixel centre. Returns the smallest cube-face gap. */
-static double shade(const env_t* env, const par_t* par, const double* g, double A,
+#define OR_GB 11   /* G-buffer channels: albedo 3, metallic, roughness, normal 3, L_ind 3 */
+
+/* g = [albedo r,g,b, metallic, roughness, normal x,y,z, L_ind r,g,b] (blended), A = alpha,
+   V = visibility, dir = world ray direction through the pixel centre. Returns the smallest
+   cube-face gap. */
+static double shade(const env_t* env, const par_t* par, const double* g, double A, double V,
                     const double* dir, double* C) {
     if (A <= 0.0) { C[0] = par->bg[0]; C[1] = par->bg[1]; C[2] = par->bg[2]; return 1.0; }
     double wo[3] = {-dir[0], -dir[1], -dir[2]};
@@ -447,7 +458,8 @@ static double shade(const env_t* env, const par_t* par, const double* g, double 
         double Lp = (1 - fl) * P0[c] + fl * P1[c];
         double F0 = 0.04 * (1 - M) + g[c] * M;
         double Ld = g[c] / M_PI * (1 - M) * E[c];
-        C[c] = Ld + Lp * (F0 * ab[0] + ab[1]) + (1 - A) * par->bg[c];
+        double Lmix = V * Lp + (1 - V) * g[8 + c];
+        C[c] = Ld + Lmix * (F0 * ab[0] + ab[1]) + (1 - A) * par->bg[c];
     }
     return gap;
 }
@@ -468,7 +480,7 @@ static int cand_cmp(const void* a, const void* b) {
 typedef struct { int k, kind; } flip_t;   /* kind 0: inclusion of splat k, 1: stop at splat k */
 
 typedef struct {
-    double rgba[4], gbuf[8];
+    double rgba[4], gbuf[OR_GB];
     int n_blend, n_support, graze;
     double min_gap;
     double sens;       /* sum over G-buffer channels of max_rgb |dC/dg_c| (shading condition) */
@@ -488,10 +500,11 @@ static void note_amb(pix_out_t* po, int k, int kind) {
 }
 
 /* Render pixel (x,y). flip (may be NULL) forces the opposite outcome of one decision;
-   record != 0 records the near-threshold decisions in po. cand is scratch of n entries. */
+   record != 0 records the near-threshold decisions in po. cand is scratch of n entries.
+   lind (may be NULL) = per-splat indirect radiance [n][3] of this view; V = visibility. */
 static void render_pixel(const scene_t* sc, const splat_t* sp, const cam_t* cam, const par_t* par,
-                         const env_t* env, int x, int y, const flip_t* flip, int record,
-                         cand_t* cand, pix_out_t* po) {
+                         const env_t* env, const double* lind, double V, int x, int y,
+                         const flip_t* flip, int record, cand_t* cand, pix_out_t* po) {
     double d[3];
     pixel_ray(cam, x, y, d);
     double dn = sqrt(dot3(d, d));
@@ -530,7 +543,8 @@ static void render_pixel(const scene_t* sc, const splat_t* sp, const cam_t* cam,
     }
     qsort(cand, nc, sizeof(cand_t), cand_cmp);
     double T = 1.0;
-    double g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double g[OR_GB];
+    for (int m = 0; m < OR_GB; m++) g[m] = 0.0;
     int nb = 0;
     for (int c = 0; c < nc; c++) {
         const splat_t* s = sp + cand[c].k;
@@ -554,26 +568,30 @@ static void render_pixel(const scene_t* sc, const splat_t* sp, const cam_t* cam,
         g[3] += w * tx[7];
         g[4] += w * tx[3];
         g[5] += w * nw[0]; g[6] += w * nw[1]; g[7] += w * nw[2];
+        if (lind) {
+            const double* li = lind + 3 * (size_t)cand[c].k;
+            g[8] += w * li[0]; g[9] += w * li[1]; g[10] += w * li[2];
+        }
         T = Tn;
         nb++;
     }
     double A = 1.0 - T;
-    for (int m = 0; m < 8; m++) po->gbuf[m] = g[m];
+    for (int m = 0; m < OR_GB; m++) po->gbuf[m] = g[m];
     po->rgba[3] = A;
     po->n_blend = nb;
     double gap = 1.0;
     po->sens = 0.0;
     if (env) {
-        gap = shade(env, par, g, A, d, po->rgba);
+        gap = shade(env, par, g, A, V, d, po->rgba);
         if (record && A > 0.0) {
             /* central differences of the shading in each G-buffer channel: how much a rounding
                of the blended maps moves the shaded radiance */
-            for (int c = 0; c < 8; c++) {
-                double h = 1e-7, gp[8], gm[8], Cp[4], Cm[4];
-                for (int m = 0; m < 8; m++) { gp[m] = g[m]; gm[m] = g[m]; }
+            for (int c = 0; c < OR_GB; c++) {
+                double h = 1e-7, gp[OR_GB], gm[OR_GB], Cp[4], Cm[4];
+                for (int m = 0; m < OR_GB; m++) { gp[m] = g[m]; gm[m] = g[m]; }
                 gp[c] += h; gm[c] -= h;
-                shade(env, par, gp, A, d, Cp);
-                shade(env, par, gm, A, d, Cm);
+                shade(env, par, gp, A, V, d, Cp);
+                shade(env, par, gm, A, V, d, Cm);
                 double mx = 0;
                 for (int m = 0; m < 3; m++) mx = fmax(mx, fabs(Cp[m] - Cm[m]) / (2 * h));
                 po->sens += mx;
@@ -605,10 +623,12 @@ int or_splat_setup(int n, const float* means, const float* quats, const float* s
 
 /*
  * Render the listed pixels (pix = [P][2] x,y).
- * out_rgba [P][4], out_gbuf [P][8],
+ * lind [n][3] per-splat indirect radiance of this view (or NULL: no indirect map),
+ * vis [P] visibility per listed pixel (or NULL: V = 1).
+ * out_rgba [P][4], out_gbuf [P][11] (albedo 3, metallic, roughness, normal 3, L_ind 3),
  * out_stat [P][7]: n_blend, n_support, n_amb, grazing flag, min cube-face gap, n_alt,
  *                  shading sensitivity (sum over channels of max_rgb |dC/dg_c|),
- * alt_rgba [P][OR_MAX_ALT][4], alt_gbuf [P][OR_MAX_ALT][8] (the first n_alt are valid).
+ * alt_rgba [P][OR_MAX_ALT][4], alt_gbuf [P][OR_MAX_ALT][11] (the first n_alt are valid).
  * env_spec == NULL renders G-buffers only (rgb = 0).
  */
 int or_render(int n, int T, const float* means, const float* quats, const float* scales,
@@ -616,7 +636,7 @@ int or_render(int n, int T, const float* means, const float* quats, const float*
               const double* cam16, const double* params,
               const double* env_spec, int spec_res, int spec_levels,
               const double* env_irr, int irr_res, const double* env_lut, int lut_res,
-              const int32_t* pix, int P,
+              const double* lind, const double* vis, const int32_t* pix, int P,
               double* out_rgba, double* out_gbuf, double* out_stat,
               double* alt_rgba, double* alt_gbuf) {
     scene_t sc = {n, T, means, quats, scales, opac, tex, chart_of};
@@ -639,19 +659,21 @@ int or_render(int n, int T, const float* means, const float* quats, const float*
         for (int p = 0; p < P; p++) {
             if (!cand) continue;
             int x = pix[2 * p], y = pix[2 * p + 1];
+            double V = vis ? vis[p] : 1.0;
             pix_out_t po;
-            render_pixel(&sc, sp, &cam, &par, env, x, y, NULL, 1, cand, &po);
+            render_pixel(&sc, sp, &cam, &par, env, lind, V, x, y, NULL, 1, cand, &po);
             for (int m = 0; m < 4; m++) out_rgba[4 * p + m] = po.rgba[m];
-            for (int m = 0; m < 8; m++) out_gbuf[8 * p + m] = po.gbuf[m];
+            for (int m = 0; m < OR_GB; m++) out_gbuf[OR_GB * p + m] = po.gbuf[m];
             int nalt = po.n_amb < OR_MAX_ALT ? po.n_amb : OR_MAX_ALT;
             double* st = out_stat + 7 * p;
             st[0] = po.n_blend; st[1] = po.n_support; st[2] = po.n_amb; st[3] = po.graze;
             st[4] = po.min_gap; st[5] = nalt; st[6] = po.sens;
             for (int a = 0; a < nalt; a++) {
                 pix_out_t pa;
-                render_pixel(&sc, sp, &cam, &par, env, x, y, &po.amb[a], 0, cand, &pa);
+                render_pixel(&sc, sp, &cam, &par, env, lind, V, x, y, &po.amb[a], 0, cand, &pa);
                 for (int m = 0; m < 4; m++) alt_rgba[(p * OR_MAX_ALT + a) * 4 + m] = pa.rgba[m];
-                for (int m = 0; m < 8; m++) alt_gbuf[(p * OR_MAX_ALT + a) * 8 + m] = pa.gbuf[m];
+                for (int m = 0; m < OR_GB; m++)
+                    alt_gbuf[(p * OR_MAX_ALT + a) * OR_GB + m] = pa.gbuf[m];
             }
         }
         free(cand);
@@ -660,8 +682,9 @@ int or_render(int n, int T, const float* means, const float* quats, const float*
     return err;
 }
 
-/* Shade a given G-buffer: gbuf [P][8], alpha [P], pixels [P][2] -> rgb [P][3]. */
-int or_shade(const double* gbuf, const double* alpha, const int32_t* pix, int P,
+/* Shade a given G-buffer: gbuf [P][11], alpha [P], vis [P] (or NULL: V = 1),
+   pixels [P][2] -> rgb [P][3]. */
+int or_shade(const double* gbuf, const double* alpha, const double* vis, const int32_t* pix, int P,
              const double* cam16, const double* params,
              const double* env_spec, int spec_res, int spec_levels,
              const double* env_irr, int irr_res, const double* env_lut, int lut_res,
@@ -673,7 +696,7 @@ int or_shade(const double* gbuf, const double* alpha, const int32_t* pix, int P,
     for (int p = 0; p < P; p++) {
         double d[3], C[4];
         pixel_ray(&cam, pix[2 * p], pix[2 * p + 1], d);
-        double gap = shade(&env, &par, gbuf + 8 * p, alpha[p], d, C);
+        double gap = shade(&env, &par, gbuf + OR_GB * p, alpha[p], vis ? vis[p] : 1.0, d, C);
         out_rgb[3 * p + 0] = C[0]; out_rgb[3 * p + 1] = C[1]; out_rgb[3 * p + 2] = C[2];
         if (out_gap) out_gap[p] = gap;
     }
@@ -701,5 +724,86 @@ int or_cube_texels(int r, double* dirs, double* solid) {
 /* LUT bilinear lookups (for tests): xy [P][2] -> ab [P][2]. */
 int or_lut_sample(const double* lut, int n, const double* xy, int P, double* ab) {
     for (int p = 0; p < P; p++) lut_lookup(lut, n, xy[2 * p], xy[2 * p + 1], ab + 2 * p);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------- */
+/* indirect light from per-splat spherical harmonics (Sec. 3.5-3.6, Eq. 9 and 12)         */
+/* ------------------------------------------------------------------------------------- */
+/* Associated Legendre function P_l^m(x), m >= 0, without the Condon-Shortley phase:
+   P_m^m = (2m-1)!! (1-x^2)^(m/2), P_{m+1}^m = (2m+1) x P_m^m, then the three-term recurrence
+   (l-m) P_l^m = (2l-1) x P_{l-1}^m - (l+m-1) P_{l-2}^m. */
+static double legendre_p(int l, int m, double x) {
+    double pmm = 1.0, st = sqrt(fmax(0.0, 1.0 - x * x));
+    for (int i = 1; i <= m; i++) pmm *= (2.0 * i - 1.0) * st;
+    if (l == m) return pmm;
+    double p1 = (2.0 * m + 1.0) * x * pmm;
+    if (l == m + 1) return p1;
+    double p0 = pmm, pl = p1;
+    for (int ll = m + 2; ll <= l; ll++) {
+        pl = ((2.0 * ll - 1.0) * x * p1 - (ll + m - 1.0) * p0) / (ll - m);
+        p0 = p1; p1 = pl;
+    }
+    return pl;
+}
+
+static double factorial(int k) { double f = 1.0; for (int i = 2; i <= k; i++) f *= i; return f; }
+
+/* Real orthonormal spherical harmonic Y_{l,m} at unit direction d (index l*l + l + m):
+   K = sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!), Y = K P_l^0(cos th) for m = 0,
+   sqrt(2) K P_l^m(cos th) cos(m phi) for m > 0, sqrt(2) K P_l^|m|(cos th) sin(|m| phi) for m < 0,
+   with cos th = d_z and phi = atan2(d_y, d_x). */
+static double sh_real(int l, int m, const double* d) {
+    double r = sqrt(dot3(d, d));
+    double ct = d[2] / r, ph = atan2(d[1], d[0]);
+    int am = m < 0 ? -m : m;
+    double K = sqrt((2.0 * l + 1.0) / (4.0 * M_PI) * factorial(l - am) / factorial(l + am));
+    double P = legendre_p(l, am, ct);
+    if (m == 0) return K * P;
+    if (m > 0) return sqrt(2.0) * K * P * cos(am * ph);
+    return sqrt(2.0) * K * P * sin(am * ph);
+}
+
+/* Basis values for tests: dirs [P][3] -> out [P][(degree+1)^2]. */
+int or_sh_basis(int degree, const double* dirs, int P, double* out) {
+    if (degree < 0 || degree > 3) return -1;
+    int K = (degree + 1) * (degree + 1);
+    for (int p = 0; p < P; p++)
+        for (int l = 0; l <= degree; l++)
+            for (int m = -l; m <= l; m++) out[(size_t)p * K + l * l + l + m] = sh_real(l, m, dirs + 3 * p);
+    return 0;
+}
+
+/* Per-splat indirect radiance for one camera: sh [n][(degree+1)^2][3] coefficients; the
+   direction is the mirror reflection w_r = d - 2 (d.n) n of the unit camera-to-centre
+   direction d about the splat normal n (the third column of R; the sign of n does not
+   matter); out [n][3] = max(0, sum_j c_j Y_j(w_r)) per channel. */
+int or_indirect_eval(int n, const float* means, const float* quats, const float* sh, int degree,
+                     const double* cam16, double* out) {
+    if (degree < 0 || degree > 3) return -1;
+    int K = (degree + 1) * (degree + 1);
+    cam_t cam;
+    make_cam(cam16, &cam);
+    for (int k = 0; k < n; k++) {
+        double q[4], R[9];
+        for (int m = 0; m < 4; m++) q[m] = quats[4 * k + m];
+        double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        for (int m = 0; m < 4; m++) q[m] /= qn;
+        quat_to_rot(q, R);
+        double nrm[3] = {R[2], R[5], R[8]};
+        double d[3] = {means[3 * k + 0] - cam.o[0], means[3 * k + 1] - cam.o[1],
+                       means[3 * k + 2] - cam.o[2]};
+        normalize3(d);
+        double dn = dot3(d, nrm);
+        double wr[3] = {d[0] - 2 * dn * nrm[0], d[1] - 2 * dn * nrm[1], d[2] - 2 * dn * nrm[2]};
+        double acc[3] = {0, 0, 0};
+        for (int l = 0; l <= degree; l++)
+            for (int m = -l; m <= l; m++) {
+                int j = l * l + l + m;
+                double Y = sh_real(l, m, wr);
+                for (int c = 0; c < 3; c++) acc[c] += sh[((size_t)k * K + j) * 3 + c] * Y;
+            }
+        for (int c = 0; c < 3; c++) out[3 * (size_t)k + c] = acc[c] > 0 ? acc[c] : 0.0;
+    }
     return 0;
 }

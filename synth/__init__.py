@@ -29,7 +29,7 @@ __all__ = [
     "CONFIGS", "SceneConfig", "make_scene", "make_env", "look_at_camera", "orbit_cameras",
     "config_cameras", "crop_camera", "random_gbuffer", "poisson_requests", "target_image",
     "cameras_array", "fd_crop_scene", "serving_camera", "serving_scene", "SERVING_SCENES",
-    "SERVING_RESOLUTIONS",
+    "SERVING_RESOLUTIONS", "indirect_sh", "visibility",
 ]
 
 
@@ -414,6 +414,26 @@ def random_gbuffer(rng, n_views, height, width, empty_frac=0.1):
     g[:, 5:8] = np.moveaxis(nrm, -1, 1) * rng.uniform(0.3, 1.0, size=(n_views, 1, height, width))
     g *= a[:, None]
     return g.astype(np.float32), a.astype(np.float32)
+
+
+def indirect_sh(rng, n, degree=3):
+    """Per-splat spherical-harmonic coefficients of the indirect light, [n,(degree+1)^2,3]
+    float32: the constant band drawn U(0.5, 3.5) (a positive mean radiance), band l >= 1
+    drawn N(0, (0.3/l)^2) (smoother light for the higher bands)."""
+    K = (degree + 1) ** 2
+    c = np.empty((n, K, 3))
+    c[:, 0] = rng.uniform(0.5, 3.5, size=(n, 3))
+    for l in range(1, degree + 1):
+        c[:, l * l:(l + 1) * (l + 1)] = rng.normal(0.0, 0.3 / l, size=(n, 2 * l + 1, 3))
+    return c.astype(np.float32)
+
+
+def visibility(rng, n_views, height, width):
+    """Per-pixel visibility V in [0,1], [V,H,W] float32: 40% of pixels fully visible (1),
+    30% occluded (0), 30% partial U(0,1) (pixels on an occluder's edge)."""
+    u = rng.uniform(size=(n_views, height, width))
+    v = rng.uniform(size=(n_views, height, width))
+    return np.where(u < 0.4, 1.0, np.where(u < 0.7, 0.0, v)).astype(np.float32)
 
 
 def fd_crop_scene(scene, cam, x0, y0, w, h, n_keep=500):
