@@ -145,9 +145,36 @@ int ts_bin_sort(int32_t n_views, int32_t width, int32_t height, int32_t n,
                 int32_t* pair_ids, int64_t* n_pairs, int32_t* status, hipStream_t stream);
 
 /*
+ * ts_indirect_eval — per (view, splat) indirect radiance l_ind from per-splat spherical
+ * harmonics (Sec. 3.5-3.6: indirect light encoded per primitive with SH, blended by Eq. 9
+ * and mixed into the specular term by Eq. 12). With d the unit direction from camera v's
+ * centre to the splat centre and n the splat normal (third column of R(q)), the direction is
+ * the mirror reflection w_r = d - 2 (d.n) n, and per channel
+ *   l_ind = max(0, sum_j sh[k][j][c] Y_j(w_r)),
+ * Y_j the real orthonormal SH basis without the Condon-Shortley phase, index j = l*l + l + m:
+ * Y_00 = 1/(2 sqrt(pi)), (Y_1-1, Y_10, Y_11) = sqrt(3/(4 pi)) (y, z, x), and so on to l = 3.
+ * Evaluated in double precision, stored float32.
+ *
+ *   cams      [n_views] cameras (host or device memory readable by the kernel: device)
+ *   means, quats   as given to ts_preprocess
+ *   sh        [n][(sh_degree+1)^2][3] float32 coefficients, device
+ *   sh_degree 0..3
+ *   lind      [n_views][n][4] out (rgb, 0), device; input of ts_raster_fwd
+ * A splat with a zero quaternion gets l_ind = 0.
+ * Errors: TS_E_ARG (degree outside 0..3, null pointers, n_views * n above 2^31-1),
+ *         TS_E_LAUNCH.
+ */
+int ts_indirect_eval(int32_t n_views, const ts_camera* cams, int32_t n, const float* means,
+                     const float* quats, const float* sh, int32_t sh_degree, float* lind,
+                     hipStream_t stream);
+
+/*
  * ts_raster_fwd — per pixel, front-to-back over its tile's list: (u,v) -> G -> alpha ->
  * bilinear texel fetch from the atlas -> normal mapping -> G-buffer blend (Eq. 2-9), with
  * the split-sum shading of Eq. 10-12 fused into the epilogue when env != NULL.
+ * With lind != NULL the indirect term is on: each blended splat also adds w l_ind to a
+ * blended indirect map L_ind (Eq. 9), and the fused shading takes the specular radiance as
+ * V Lspec + (1 - V) L_ind (Eq. 12).
  *
  *   n       splats per view (rec is [n_views][n][TS_REC_FLOATS])
  *   rec, tile_ranges, pair_ids   from ts_preprocess / ts_bin_sort
@@ -164,21 +191,28 @@ int ts_bin_sort(int32_t n_views, int32_t width, int32_t height, int32_t n,
  *           one past the last blended splat, 0 if none
  *   n_blend [n_views][H][W] int32 out or NULL: number of splats blended into the pixel
  *           (the contributing splat-pixel evaluations)
- * Errors: TS_E_ARG (null required pointer, tex_res outside 1..32, rgba without env),
- *         TS_E_LAUNCH.
+ *   lind    [n_views][n][4] from ts_indirect_eval, or NULL: no indirect term (then vis and
+ *           gbuf_ind must be NULL)
+ *   vis     [n_views][H][W] visibility V in [0,1] (an input: the paper ray-traces an
+ *           extracted mesh for it), or NULL: V = 1; needs rgba and env
+ *   gbuf_ind [n_views][3][H][W] out or NULL: the blended L_ind map, planar
+ * Errors: TS_E_ARG (null required pointer, tex_res outside 1..32, rgba without env,
+ *         vis or gbuf_ind without lind, vis without rgba), TS_E_LAUNCH.
  */
 int ts_raster_fwd(int32_t n_views, int32_t width, int32_t height, const ts_camera* cams,
                   const ts_params* params, int32_t n, const float* rec, const int32_t* tile_ranges,
                   const int32_t* pair_ids, int64_t pair_capacity, const float* atlas,
                   const ts_env* env,
                   float* rgba, float* gbuf, float* t_final, int32_t* n_contrib,
-                  int32_t* n_blend, hipStream_t stream);
+                  int32_t* n_blend, const float* lind, const float* vis, float* gbuf_ind,
+                  hipStream_t stream);
 
 /*
- * ts_shade — deferred split-sum shading of given G-buffers (Eq. 10-12, V = 1, no indirect
- * term): with N^ = N/|N| (the view vector if |N| = 0), w_o the unit vector to the camera,
+ * ts_shade — deferred split-sum shading of given G-buffers (Eq. 10-12): with N^ = N/|N|
+ * (the view vector if |N| = 0), w_o the unit vector to the camera,
  * w_r = 2 (N^.w_o) N^ - w_o, level = clamp(R,0,1) (L-1):
- *   C = albedo/pi (1-M) E(N^) + Lspec(w_r, level) (F0 A + B) + (1 - alpha) bg,
+ *   C = albedo/pi (1-M) E(N^) + (V Lspec(w_r, level) + (1-V) L_ind) (F0 A + B)
+ *       + (1 - alpha) bg,
  *   F0 = 0.04 (1-M) + albedo M, (A,B) = lut(clamp(N^.w_o,0,1), clamp(R,0,1));
  * pixels with alpha = 0 take bg. Cube lookups pick the face by the major axis (ties X, Y,
  * Z) and filter bilinearly inside the face at texel centres with clamp-to-edge.
@@ -186,10 +220,13 @@ int ts_raster_fwd(int32_t n_views, int32_t width, int32_t height, const ts_camer
  *   gbuf    [n_views][8][H][W] (layout of ts_raster_fwd)
  *   t_final [n_views][H][W] transmittance, alpha = 1 - T
  *   rgba    [n_views][H][W][4] out
+ *   gbuf_ind [n_views][3][H][W] blended indirect map L_ind, or NULL: L_ind = 0
+ *   vis     [n_views][H][W] visibility V, or NULL: V = 1
  */
 int ts_shade(int32_t n_views, int32_t width, int32_t height, const ts_camera* cams,
              const ts_params* params, const ts_env* env, const float* gbuf,
-             const float* t_final, float* rgba, hipStream_t stream);
+             const float* t_final, float* rgba, const float* gbuf_ind, const float* vis,
+             hipStream_t stream);
 
 /*
  * ts_raster_bwd — gradients of a scalar loss L of the shaded output with respect to the

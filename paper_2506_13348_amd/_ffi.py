@@ -42,9 +42,13 @@ _SIGS = {
                     c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
     "ts_raster_fwd": [c_int32, c_int32, c_int32, c_void_p, ctypes.POINTER(TsParams), c_int32,
                       c_void_p, c_void_p, c_void_p, c_int64, c_void_p, ctypes.POINTER(TsEnv),
-                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
+                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                      c_void_p, c_void_p],
     "ts_shade": [c_int32, c_int32, c_int32, c_void_p, ctypes.POINTER(TsParams),
-                 ctypes.POINTER(TsEnv), c_void_p, c_void_p, c_void_p, c_void_p],
+                 ctypes.POINTER(TsEnv), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                 c_void_p],
+    "ts_indirect_eval": [c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_int32,
+                         c_void_p, c_void_p],
     "ts_raster_bwd": [c_int32, c_int32, c_int32, c_void_p, ctypes.POINTER(TsParams), c_int32,
                       c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                       c_void_p, c_int64, c_void_p, ctypes.POINTER(TsEnv), c_void_p, c_void_p,
@@ -157,13 +161,19 @@ def ts_bin_sort(n_views, width, height, n, rect, depth_key, ws, pair_capacity, s
 
 def ts_raster_fwd(n_views, width, height, cams, params, n, rec, tile_ranges, pair_ids,
                   pair_capacity, atlas, env, rgba, gbuf, t_final, n_contrib, n_blend=None,
-                  stream=None):
+                  stream=None, lind=None, vis=None, gbuf_ind=None):
     _check(lib().ts_raster_fwd(n_views, width, height, ptr(cams), ctypes.byref(params), n,
                                ptr(rec), ptr(tile_ranges), ptr(pair_ids), pair_capacity, ptr(atlas),
                                ctypes.byref(env) if env is not None else None, ptr(rgba),
-                               ptr(gbuf), ptr(t_final), ptr(n_contrib), ptr(n_blend),
-                               stream_handle(stream)),
+                               ptr(gbuf), ptr(t_final), ptr(n_contrib), ptr(n_blend), ptr(lind),
+                               ptr(vis), ptr(gbuf_ind), stream_handle(stream)),
            "ts_raster_fwd")
+
+
+def ts_indirect_eval(n_views, cams, n, means, quats, sh, sh_degree, lind, stream=None):
+    _check(lib().ts_indirect_eval(n_views, ptr(cams), n, ptr(means), ptr(quats), ptr(sh),
+                                  int(sh_degree), ptr(lind), stream_handle(stream)),
+           "ts_indirect_eval")
 
 
 def ts_env_bwd_workspace(n_views, width, height):
@@ -203,10 +213,11 @@ def ts_raster_bwd(n_views, width, height, cams, params, n, means, quats, scales,
                                ptr(d_atlas), stream_handle(stream)), "ts_raster_bwd")
 
 
-def ts_shade(n_views, width, height, cams, params, env, gbuf, t_final, rgba, stream=None):
+def ts_shade(n_views, width, height, cams, params, env, gbuf, t_final, rgba, stream=None,
+             gbuf_ind=None, vis=None):
     _check(lib().ts_shade(n_views, width, height, ptr(cams), ctypes.byref(params),
-                          ctypes.byref(env), ptr(gbuf), ptr(t_final), ptr(rgba),
-                          stream_handle(stream)), "ts_shade")
+                          ctypes.byref(env), ptr(gbuf), ptr(t_final), ptr(rgba), ptr(gbuf_ind),
+                          ptr(vis), stream_handle(stream)), "ts_shade")
 
 
 def ts_brdf_lut(n, samples, lut, stream=None):

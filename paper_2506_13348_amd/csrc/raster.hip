@@ -12,6 +12,9 @@
 // on the primitive's T x T texels in the atlas at s = (u+S)/(2S), t = (v+S)/(2S), texel
 // centres at (i+1/2)/T, clamp-to-edge within the chart; the tangent normal is normalised and
 // rotated by sigma R (Eq. 7); the eight G-buffer channels accumulate with w = alpha T.
+// With the indirect term (Eq. 9, Eq. 12) each record's l_ind (per view and splat) is staged
+// beside it, a ninth to eleventh channel blends it, and the fused shading mixes the direct
+// and indirect specular light by the pixel's visibility.
 #include "eval.h"
 #include "shade.h"
 #include "ts_internal.h"
@@ -35,17 +38,22 @@ struct RasterArgs {
     float* t_final;
     int32_t* n_contrib;
     int32_t* n_blend;
+    const float4* lind;      // [V][n] indirect radiance per (view, splat), kInd only
+    const float* vis;        // [V][H][W] visibility or null (V = 1)
+    float* gbuf_ind;         // [V][3][H][W] blended L_ind or null
 };
 
 constexpr int kBatch = 192;   // records staged per batch (a multiple of 64)
 static_assert(kBatch % kWave == 0, "the batch is walked in rows of 64");
 
-template <bool kTextured>
+template <bool kTextured, bool kInd>
 // 6 waves per SIMD: at most 80 VGPRs and a 22.5 KB record batch, so six workgroups fit a CU
-// (measured faster than 5 waves with 256-record batches)
-__global__ __launch_bounds__(256, 6) void k_raster_fwd(RasterArgs a) {
+// (measured faster than 5 waves with 256-record batches). The indirect variant carries three
+// more accumulators and needs more than 80 VGPRs: 5 waves per SIMD, no spills.
+__global__ __launch_bounds__(256, kInd ? 5 : 6) void k_raster_fwd(RasterArgs a) {
     __shared__ float4 srec[kBatch * kRec4];
     __shared__ uint32_t smask[kBatch];
+    __shared__ float4 slind[kInd ? kBatch : 1];
     const int g = gridDim.x;
     const int bid = xcd_remap(blockIdx.x, g);
     const int v = bid / a.n_tiles;
@@ -68,6 +76,7 @@ __global__ __launch_bounds__(256, 6) void k_raster_fwd(RasterArgs a) {
 
     float Tr = 1.0f;
     float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float ai[3] = {0.f, 0.f, 0.f};
     bool done = !inside;
     int last = 0;
     int nbl = 0;
@@ -86,6 +95,7 @@ __global__ __launch_bounds__(256, 6) void k_raster_fwd(RasterArgs a) {
             srec[tid * kRec4 + 3] = r3;
 #pragma unroll
             for (int q = 4; q < kRec4; q++) srec[tid * kRec4 + q] = src[q];
+            if (kInd) slind[tid] = a.lind[(int64_t)v * a.n + id];
             qm = quad_mask_uv(r0, r1, r2, r3, tx * kTile, ty * kTile, a.S, a.amin);
         }
         if (tid < kBatch) smask[tid] = qm;
@@ -160,6 +170,12 @@ __global__ __launch_bounds__(256, 6) void k_raster_fwd(RasterArgs a) {
                         acc[5] = fmaf(wn, c4.x * t4 + c4.y * t5 + c4.z * tz, acc[5]);
                         acc[6] = fmaf(wn, c4.w * t4 + c5.x * t5 + c5.y * tz, acc[6]);
                         acc[7] = fmaf(wn, c5.z * t4 + c5.w * t5 + c6.x * tz, acc[7]);
+                        if (kInd) {
+                            float4 l4 = slind[j];
+                            ai[0] = fmaf(ww, l4.x, ai[0]);
+                            ai[1] = fmaf(ww, l4.y, ai[1]);
+                            ai[2] = fmaf(ww, l4.z, ai[2]);
+                        }
                         Tr = Tn;
                         last = b0 - range.x + j + 1;
                         nbl++;
@@ -182,12 +198,18 @@ __global__ __launch_bounds__(256, 6) void k_raster_fwd(RasterArgs a) {
 #pragma unroll
         for (int c = 0; c < 8; c++) gb[c * plane] = acc[c];
     }
+    if (kInd && a.gbuf_ind) {
+        float* gi = a.gbuf_ind + (int64_t)v * 3 * plane + (int64_t)y * a.W + x;
+#pragma unroll
+        for (int c = 0; c < 3; c++) gi[c * plane] = ai[c];
+    }
     if (a.t_final) a.t_final[pix] = Tr;
     if (a.n_contrib) a.n_contrib[pix] = last;
     if (a.n_blend) a.n_blend[pix] = nbl;
     if (a.shade) {
         float3 d = pixel_ray(a.cams[v], X, Y);
-        float3 C = shade_pixel(a.env, a.sc, acc, Tr, d);
+        float vis = (kInd && a.vis) ? a.vis[pix] : 1.0f;
+        float3 C = shade_pixel<kInd>(a.env, a.sc, acc, Tr, d, ai, vis);
         a.rgba[pix] = make_float4(C.x, C.y, C.z, 1.0f - Tr);
     }
 }
@@ -200,8 +222,11 @@ struct ShadeArgs {
     const float* gbuf;
     const float* t_final;
     float4* rgba;
+    const float* gbuf_ind;   // [V][3][H][W] or null (L_ind = 0)
+    const float* vis;        // [V][H][W] or null (V = 1)
 };
 
+template <bool kInd>
 __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t plane = (int64_t)a.H * a.W;
@@ -215,7 +240,17 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
     for (int c = 0; c < 8; c++) g[c] = gb[c * plane];
     float T = a.t_final[i];
     float3 d = pixel_ray(a.cams[v], (float)x + 0.5f, (float)y + 0.5f);
-    float3 C = shade_pixel(a.env, a.sc, g, T, d);
+    float li[3] = {0.f, 0.f, 0.f};
+    float vis = 1.0f;
+    if (kInd) {
+        if (a.gbuf_ind) {
+            const float* gi = a.gbuf_ind + (int64_t)v * 3 * plane + p;
+#pragma unroll
+            for (int c = 0; c < 3; c++) li[c] = gi[c * plane];
+        }
+        if (a.vis) vis = a.vis[i];
+    }
+    float3 C = shade_pixel<kInd>(a.env, a.sc, g, T, d, li, vis);
     a.rgba[i] = make_float4(C.x, C.y, C.z, 1.0f - T);
 }
 
@@ -244,7 +279,8 @@ extern "C" int ts_raster_fwd(int32_t n_views, int32_t width, int32_t height, con
                              const int32_t* tile_ranges, const int32_t* pair_ids,
                              int64_t pair_capacity, const float* atlas, const ts_env* env,
                              float* rgba, float* gbuf, float* t_final, int32_t* n_contrib,
-                             int32_t* n_blend, hipStream_t stream) {
+                             int32_t* n_blend, const float* lind, const float* vis,
+                             float* gbuf_ind, hipStream_t stream) {
     if (n_views < 1 || width < 1 || height < 1 || n < 0 || !params || !cams || !tile_ranges ||
         (n > 0 && (!atlas || !rec || !pair_ids))) {
         set_error("ts_raster_fwd: bad argument");
@@ -271,6 +307,14 @@ extern "C" int ts_raster_fwd(int32_t n_views, int32_t width, int32_t height, con
         set_error("ts_raster_fwd: rgba and env must be given together");
         return TS_E_ARG;
     }
+    if (!lind && (vis || gbuf_ind)) {
+        set_error("ts_raster_fwd: vis and gbuf_ind need lind (the indirect term)");
+        return TS_E_ARG;
+    }
+    if (vis && !rgba) {
+        set_error("ts_raster_fwd: vis is a shading input and needs rgba and env");
+        return TS_E_ARG;
+    }
     RasterArgs a = {};
     a.V = n_views; a.W = width; a.H = height; a.n = n;
     a.ntx = tiles_x(width);
@@ -295,21 +339,30 @@ extern "C" int ts_raster_fwd(int32_t n_views, int32_t width, int32_t height, con
     a.t_final = t_final;
     a.n_contrib = n_contrib;
     a.n_blend = n_blend;
+    a.lind = (const float4*)lind;
+    a.vis = vis;
+    a.gbuf_ind = gbuf_ind;
     int64_t blocks = (int64_t)n_views * a.n_tiles;
     if (blocks > 0x7FFFFFFF) {
         set_error("ts_raster_fwd: too many tiles");
         return TS_E_ARG;
     }
-    if (params->sampler == TS_SAMPLER_CONSTANT)
-        hipLaunchKernelGGL(k_raster_fwd<false>, dim3((unsigned)blocks), dim3(256), 0, stream, a);
-    else
-        hipLaunchKernelGGL(k_raster_fwd<true>, dim3((unsigned)blocks), dim3(256), 0, stream, a);
+    const dim3 grid((unsigned)blocks), block(256);
+    const bool cst = params->sampler == TS_SAMPLER_CONSTANT;
+    if (lind) {
+        if (cst) hipLaunchKernelGGL((k_raster_fwd<false, true>), grid, block, 0, stream, a);
+        else hipLaunchKernelGGL((k_raster_fwd<true, true>), grid, block, 0, stream, a);
+    } else {
+        if (cst) hipLaunchKernelGGL((k_raster_fwd<false, false>), grid, block, 0, stream, a);
+        else hipLaunchKernelGGL((k_raster_fwd<true, false>), grid, block, 0, stream, a);
+    }
     return launch_check("ts_raster_fwd");
 }
 
 extern "C" int ts_shade(int32_t n_views, int32_t width, int32_t height, const ts_camera* cams,
                         const ts_params* params, const ts_env* env, const float* gbuf,
-                        const float* t_final, float* rgba, hipStream_t stream) {
+                        const float* t_final, float* rgba, const float* gbuf_ind,
+                        const float* vis, hipStream_t stream) {
     if (n_views < 1 || width < 1 || height < 1 || !params || !cams || !env || !gbuf || !t_final ||
         !rgba) {
         set_error("ts_shade: bad argument");
@@ -321,7 +374,10 @@ extern "C" int ts_shade(int32_t n_views, int32_t width, int32_t height, const ts
     int rc = env_from(env, a.env, "ts_shade");
     if (rc != TS_OK) return rc;
     a.gbuf = gbuf; a.t_final = t_final; a.rgba = (float4*)rgba;
+    a.gbuf_ind = gbuf_ind; a.vis = vis;
     int64_t total = (int64_t)n_views * width * height;
-    hipLaunchKernelGGL(k_shade, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, a);
+    const dim3 grid((unsigned)((total + 255) / 256)), block(256);
+    if (gbuf_ind || vis) hipLaunchKernelGGL(k_shade<true>, grid, block, 0, stream, a);
+    else hipLaunchKernelGGL(k_shade<false>, grid, block, 0, stream, a);
     return launch_check("ts_shade");
 }

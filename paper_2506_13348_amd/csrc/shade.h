@@ -1,5 +1,6 @@
-// Deferred split-sum shading of one pixel (Eq. 10-12 with V = 1 and no indirect term),
-// used by the fused raster epilogue and by ts_shade.
+// Deferred split-sum shading of one pixel (Eq. 10-12), used by the fused raster epilogue
+// and by ts_shade. With the indirect term the specular radiance is V L_dir + (1 - V) L_ind
+// (Eq. 12), V the pixel's visibility and L_ind the blended indirect map; without it V = 1.
 #pragma once
 #include "ts_internal.h"
 
@@ -85,9 +86,12 @@ __device__ inline float3 pixel_ray(const ts_camera& cam, float X, float Y) {
                        w[2] * cx + w[6] * cy + w[10]);
 }
 
-// g = blended (albedo r,g,b, metallic, roughness, normal x,y,z); T = transmittance.
+// g = blended (albedo r,g,b, metallic, roughness, normal x,y,z); T = transmittance;
+// li = blended indirect radiance and vis = visibility (read only when kInd).
+template <bool kInd = false>
 __device__ inline float3 shade_pixel(const EnvDev& env, const ShadeConst& sc, const float* g,
-                                     float T, float3 d) {
+                                     float T, float3 d, const float* li = nullptr,
+                                     float vis = 1.0f) {
     if (T >= 1.0f) return make_float3(sc.bg[0], sc.bg[1], sc.bg[2]);
     float A = 1.0f - T;
     float il = rsqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
@@ -130,10 +134,13 @@ __device__ inline float3 shade_pixel(const EnvDev& env, const ShadeConst& sc, co
     float3 C;
     float Lp, F0;
     Lp = P0.x + fl * (P1.x - P0.x); F0 = 0.04f * oneM + g[0] * M;
+    if (kInd) Lp = vis * Lp + (1.f - vis) * li[0];
     C.x = g[0] * kd * E.x + Lp * (F0 * ab.x + ab.y) + (1.f - A) * sc.bg[0];
     Lp = P0.y + fl * (P1.y - P0.y); F0 = 0.04f * oneM + g[1] * M;
+    if (kInd) Lp = vis * Lp + (1.f - vis) * li[1];
     C.y = g[1] * kd * E.y + Lp * (F0 * ab.x + ab.y) + (1.f - A) * sc.bg[1];
     Lp = P0.z + fl * (P1.z - P0.z); F0 = 0.04f * oneM + g[2] * M;
+    if (kInd) Lp = vis * Lp + (1.f - vis) * li[2];
     C.z = g[2] * kd * E.z + Lp * (F0 * ab.x + ab.y) + (1.f - A) * sc.bg[2];
     return C;
 }

@@ -4,7 +4,10 @@ A `DeviceScene` holds one scene on the GPU: splat parameters, the packed texture
 its indirection buffer (Supp. Sec. 1) and the shading tables of its environment (Sec. 3.5.4).
 A `RenderPlan` preallocates every buffer of a batch of same-resolution views, so `run()`
 enqueues the whole path (preprocess -> bin/sort -> raster with fused shading) on a stream
-without allocating or synchronising; `check()` reads the pair-list status afterwards."""
+without allocating or synchronising; `check()` reads the pair-list status afterwards.
+A scene with per-splat indirect-light SH coefficients renders with the indirect term of
+Eq. 9 and Eq. 12 (per-view SH evaluation, blended L_ind map, visibility-weighted specular
+mix; the visibility is an input of the plan)."""
 from __future__ import annotations
 
 import numpy as np
@@ -76,8 +79,11 @@ class DeviceScene:
     """Splats + packed atlas + shading tables resident on one device."""
 
     def __init__(self, means, quats, scales, opac, textures, env=None, env_levels=1,
-                 device="cuda", perm=None, tables=None, locality=False):
+                 device="cuda", perm=None, tables=None, locality=False, sh=None, sh_degree=0):
         self.device = torch.device(device)
+        # indirect light: [n, (degree+1)^2, 3] SH coefficients per splat, or None
+        self.sh = None if sh is None else _dev(sh, device, torch.float32)
+        self.sh_degree = int(sh_degree)
         self.means = _dev(means, device, torch.float32)
         self.quats = _dev(quats, device, torch.float32)
         self.scales = _dev(scales, device, torch.float32)
@@ -104,6 +110,8 @@ class DeviceScene:
 
     @classmethod
     def from_dict(cls, sc, device="cuda", **kw):
+        if "sh" in sc and "sh" not in kw:
+            kw = dict(kw, sh=sc["sh"], sh_degree=sc.get("sh_degree", 3))
         return cls(sc["means"], sc["quats"], sc["scales"], sc["opac"], sc["textures"],
                    sc.get("env"), sc.get("env_levels", 1), device=device, **kw)
 
@@ -112,6 +120,8 @@ class DeviceScene:
                 (self.means, self.quats, self.scales, self.opac, self.atlas, self.chart_of))
         if self.tables is not None:
             b += sum(t.numel() * 4 for t in (self.tables.spec, self.tables.irr, self.tables.lut))
+        if self.sh is not None:
+            b += self.sh.numel() * 4
         return b
 
 
@@ -119,7 +129,7 @@ class RenderPlan:
     """All buffers for rendering `cams` (same resolution) of `scene`; run() is alloc-free."""
 
     def __init__(self, scene: DeviceScene, cams, width, height, params=None, shade=True,
-                 gbuf=False, aux=False, pair_capacity=None, stream=None):
+                 gbuf=False, aux=False, pair_capacity=None, stream=None, vis=None):
         p = dict(DEFAULTS)
         if params:
             p.update(params)
@@ -149,6 +159,17 @@ class RenderPlan:
         self.t_final = torch.empty(plane, device=dev, dtype=torch.float32) if (aux or gbuf or not self.shade) else None
         self.n_contrib = torch.empty(plane, **i32) if aux else None
         self.n_blend = torch.empty(plane, **i32) if aux else None
+        # indirect term (on when the scene carries SH coefficients)
+        self.indirect = scene.sh is not None
+        self.lind = (torch.empty(V * max(n, 1) * 4, device=dev, dtype=torch.float32)
+                     if self.indirect else None)
+        self.gbuf_ind = (torch.empty(plane * 3, device=dev, dtype=torch.float32)
+                         if self.indirect and self.gbuf is not None else None)
+        if vis is not None and not (self.indirect and self.shade):
+            raise ValueError("visibility needs a scene with indirect SH and shading")
+        self.vis = None if vis is None else _dev(vis, dev, torch.float32).reshape(-1)
+        if self.vis is not None and self.vis.numel() != plane:
+            raise ValueError(f"visibility has {self.vis.numel()} values for {plane} pixels")
         self.stream = stream
         if pair_capacity is None:
             self.pair_ids = torch.empty(1, **i32)
@@ -171,8 +192,15 @@ class RenderPlan:
                       self.cap, self.sorted_ids, self.tile_ranges, self.pair_ids, self.n_pairs,
                       self.status, self.stream)
 
+    def indirect_eval(self):
+        sc = self.scene
+        F.ts_indirect_eval(self.V, self.cams, sc.n, sc.means, sc.quats, sc.sh, sc.sh_degree,
+                           self.lind, self.stream)
+
     def _front(self):
         self.preprocess()
+        if self.indirect:
+            self.indirect_eval()
         self.bin_sort()
 
     def raster(self):
@@ -180,7 +208,8 @@ class RenderPlan:
         env = sc.tables.struct if self.shade else None
         F.ts_raster_fwd(self.V, self.W, self.H, self.cams, self.params, sc.n, self.rec,
                         self.tile_ranges, self.pair_ids, self.cap, sc.atlas, env, self.rgba, self.gbuf,
-                        self.t_final, self.n_contrib, self.n_blend, self.stream)
+                        self.t_final, self.n_contrib, self.n_blend, self.stream, lind=self.lind,
+                        vis=self.vis, gbuf_ind=self.gbuf_ind)
 
     def run(self):
         """Enqueue preprocess, bin/sort and raster(+shade). No host synchronisation."""
@@ -206,18 +235,23 @@ class RenderPlan:
         if self.n_contrib is not None:
             out["n_contrib"] = self.n_contrib.view(V, H, W)
             out["n_blend"] = self.n_blend.view(V, H, W)
+        if self.gbuf_ind is not None:
+            out["gbuf_ind"] = self.gbuf_ind.view(V, 3, H, W)
+        if self.lind is not None:
+            out["lind"] = self.lind.view(V, -1, 4)[:, :self.scene.n]
         return out
 
 
 def render(scene: DeviceScene, cams, width, height, params=None, shade=True, gbuf=False,
-           aux=False):
+           aux=False, vis=None):
     """Render a batch of views; grows the pair capacity and re-runs if it overflowed."""
-    plan = RenderPlan(scene, cams, width, height, params, shade=shade, gbuf=gbuf, aux=aux)
+    plan = RenderPlan(scene, cams, width, height, params, shade=shade, gbuf=gbuf, aux=aux,
+                      vis=vis)
     plan.run()
     (plan.stream or torch.cuda.current_stream()).synchronize()
     if int(plan.status.item()) != 0:
         plan = RenderPlan(scene, cams, width, height, params, shade=shade, gbuf=gbuf, aux=aux,
-                          pair_capacity=2 * int(plan.n_pairs.item()) + 4096)
+                          pair_capacity=2 * int(plan.n_pairs.item()) + 4096, vis=vis)
         plan.run()
         plan.check()
     out = plan.outputs()

@@ -17,29 +17,32 @@ TOL_G = 1e-5
 
 
 def pixel_match(gpu_rgba, gpu_gbuf, ref, tol_rgb=TOL_RGB, tol_a=TOL_A, tol_g=TOL_G,
-                check_rgb=True):
-    """gpu_rgba [P,4], gpu_gbuf [P,8] or None, ref = oracle.render output for the same pixels.
-    Returns (ok [P] bool, info dict)."""
+                check_rgb=True, gpu_gind=None):
+    """gpu_rgba [P,4], gpu_gbuf [P,8] or None, gpu_gind [P,3] (blended indirect map) or None,
+    ref = oracle.render output for the same pixels. Returns (ok [P] bool, info dict)."""
     P = len(ref["rgba"])
     sens = ref["stat"][:, 6]
     tol_pix = tol_rgb + sens * tol_g
 
-    def ok_against(rr, gg):
+    def ok_against(rr, gg, gi):
         ok = np.abs(gpu_rgba[:, 3] - rr[:, 3]) <= tol_a
         if check_rgb:
             ok &= np.abs(gpu_rgba[:, :3] - rr[:, :3]).max(axis=1) <= tol_pix
         if gpu_gbuf is not None:
             ok &= np.abs(gpu_gbuf - gg).max(axis=1) <= tol_g
+        if gpu_gind is not None:
+            ok &= np.abs(gpu_gind - gi).max(axis=1) <= tol_g
         return ok
 
-    ok_primary = ok_against(ref["rgba"], ref["gbuf"])
+    ok_primary = ok_against(ref["rgba"], ref["gbuf"], ref["gind"])
     ok = ok_primary.copy()
     n_alt = ref["stat"][:, 5].astype(int)
     for a in range(ref["alt_rgba"].shape[1]):
         has = n_alt > a
         if not has.any():
             continue
-        ok |= has & ok_against(ref["alt_rgba"][:, a], ref["alt_gbuf"][:, a])
+        ok |= has & ok_against(ref["alt_rgba"][:, a], ref["alt_gbuf"][:, a],
+                               ref["alt_gind"][:, a])
     err_rgb = np.abs(gpu_rgba[:, :3] - ref["rgba"][:, :3]).max(axis=1)
     err_a = np.abs(gpu_rgba[:, 3] - ref["rgba"][:, 3])
     clear = ref["stat"][:, 2] == 0
@@ -59,6 +62,9 @@ def pixel_match(gpu_rgba, gpu_gbuf, ref, tol_rgb=TOL_RGB, tol_a=TOL_A, tol_g=TOL
         err_g = np.abs(gpu_gbuf - ref["gbuf"]).max(axis=1)
         info["max_err_gbuf_unambiguous"] = float(err_g[clear].max(initial=0.0))
         info["p99_err_gbuf"] = float(np.percentile(err_g[clear], 99)) if clear.any() else 0.0
+    if gpu_gind is not None:
+        err_i = np.abs(gpu_gind - ref["gind"]).max(axis=1)
+        info["max_err_gind_unambiguous"] = float(err_i[clear].max(initial=0.0))
     return ok, info
 
 
@@ -71,6 +77,14 @@ def gather(out, v, pixels):
         g = out["gbuf"][v].double().cpu().numpy()
         gb = g[:, ys, xs].T
     return rgba, gb
+
+
+def gather_ind(out, v, pixels):
+    """The blended indirect map of view v at pixels [P,2] as float64 [P,3] (or None)."""
+    if "gbuf_ind" not in out:
+        return None
+    g = out["gbuf_ind"][v].double().cpu().numpy()
+    return g[:, pixels[:, 1], pixels[:, 0]].T
 
 
 def sample_pixels(rng, width, height, n, tile=16):

@@ -19,7 +19,8 @@ def declared():
 def test_header_declares_the_path():
     names = declared()
     for n in ("ts_preprocess", "ts_bin_sort", "ts_raster_fwd", "ts_shade", "ts_env_tables",
-              "ts_brdf_lut", "ts_atlas_pack", "ts_workspace_size", "ts_last_error"):
+              "ts_brdf_lut", "ts_atlas_pack", "ts_workspace_size", "ts_last_error",
+              "ts_indirect_eval"):
         assert n in names
 
 
@@ -44,8 +45,22 @@ def test_host_side_argument_errors():
     p.tex_res = 64
     assert L.ts_raster_fwd(1, 16, 16, ctypes.c_void_p(16), ctypes.byref(p), 1,
                            ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), 10,
-                           ctypes.c_void_p(16), None, None, None, None, None, None, None) == -1
+                           ctypes.c_void_p(16), None, None, None, None, None, None, None,
+                           None, None, None) == -1
     assert b"tex_res" in L.ts_last_error()
+    p.tex_res = 8
+    one = ctypes.c_void_p(16)
+    assert L.ts_raster_fwd(1, 16, 16, one, ctypes.byref(p), 1, one, one, one, 10, one, None,
+                           None, None, None, None, None, None, one, None, None) == -1
+    assert b"need lind" in L.ts_last_error()
+    assert L.ts_raster_fwd(1, 16, 16, one, ctypes.byref(p), 1, one, one, one, 10, one, None,
+                           None, None, None, None, None, one, one, None, None) == -1
+    assert b"needs rgba" in L.ts_last_error()
+    assert L.ts_indirect_eval(1, one, 10, one, one, one, 4, one, None) == -1
+    assert b"degree" in L.ts_last_error()
+    assert L.ts_indirect_eval(0, one, 10, one, one, one, 3, one, None) == -1
+    assert L.ts_indirect_eval(2, one, 10, None, one, one, 3, one, None) == -1
+    assert L.ts_indirect_eval(2, one, 0, None, None, None, 3, None, None) == 0
     assert L.ts_brdf_lut(0, 16, None, None) == -1
     assert L.ts_env_bwd_workspace(0, 8, 8, ctypes.byref(out)) == -1
     assert L.ts_env_bwd_workspace(2, 8, 8, ctypes.byref(out)) == 0 and out.value >= 2 * 64 * 12 * 36
@@ -60,11 +75,11 @@ def test_hardware_sampler_reported_unsupported():
     p = _ffi.make_params(8, sampler=_ffi.SAMPLER_HARDWARE)
     one = ctypes.c_void_p(16)
     rc = L.ts_raster_fwd(1, 16, 16, one, ctypes.byref(p), 1, one, one, one, 10, one, None, None,
-                         None, None, None, None, None)
+                         None, None, None, None, None, None, None, None)
     assert rc == -4 and b"gfx950" in L.ts_last_error()
     p = _ffi.make_params(4, sampler=_ffi.SAMPLER_CONSTANT)
     rc = L.ts_raster_fwd(1, 16, 16, one, ctypes.byref(p), 1, one, one, one, 10, one, None, None,
-                         None, None, None, None, None)
+                         None, None, None, None, None, None, None, None)
     assert rc == -1 and b"tex_res 1" in L.ts_last_error()
 
 

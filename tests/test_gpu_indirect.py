@@ -1,0 +1,209 @@
+"""The indirect term on the HIP path against the FP64 oracle (run on an MI355X).
+
+Per-(view, splat) SH evaluation (ts_indirect_eval), the blended L_ind map and the
+visibility-weighted specular mix fused into ts_raster_fwd (Eq. 9, Eq. 12), and the same mix
+in the standalone ts_shade; ragged frames, the constant sampler, full-size sampled frames and
+the degenerate splats."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import TOL_RGB, gather, gather_ind, pixel_match, sample_pixels
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _pkg():
+    import paper_2506_13348_amd as P
+    P._ffi.lib()
+    return P
+
+
+def _print(name, info):
+    print(f"[{name}] " + " ".join(f"{k}={v}" for k, v in info.items()), flush=True)
+
+
+def _with_sh(sc, degree, seed=11):
+    sc = dict(sc)
+    sc["sh"] = synth.indirect_sh(np.random.default_rng(seed), len(sc["opac"]), degree)
+    sc["sh_degree"] = degree
+    return sc
+
+
+def _eval_gpu(sc, cams, degree):
+    P = _pkg()
+    n = len(sc["opac"])
+    V = len(cams)
+    lind = torch.empty(V * n * 4, device="cuda")
+    P._ffi.ts_indirect_eval(V, P.cameras_tensor(cams), n, torch.as_tensor(sc["means"]).cuda(),
+                            torch.as_tensor(sc["quats"]).cuda(),
+                            torch.as_tensor(sc["sh"]).cuda().contiguous(), degree, lind)
+    torch.cuda.synchronize()
+    return lind.view(V, n, 4).double().cpu().numpy()
+
+
+def _close_f32(got, ref):
+    """float32 rounding of a double-precision result: within 2^-23 relative."""
+    err = np.abs(got - ref)
+    bound = 2.0 ** -23 * np.abs(ref) + 1e-12
+    assert (err <= bound).all(), float((err / (np.abs(ref) + 1e-30)).max())
+
+
+@pytest.mark.parametrize("degree", [0, 1, 2, 3])
+def test_indirect_eval_matches_oracle(degree):
+    sc = _with_sh(synth.make_scene("shell2k"), degree)
+    cams = synth.orbit_cameras(3, 64, 64, dist=2.5, el_deg=35.0)
+    got = _eval_gpu(sc, cams, degree)
+    for v, cam in enumerate(cams):
+        ref = oracle.indirect_eval(sc, cam, sc["sh"], degree)
+        _close_f32(got[v, :, :3], ref)
+        assert (got[v, :, 3] == 0).all()
+    assert (got[..., :3] == 0).any() or degree == 0   # the clamp at zero is reached
+
+
+def test_indirect_eval_all_orbit_views_sampled_splats():
+    """The 100k-splat superquadric with degree-3 SH over all 64 orbit views (the launch the
+    benchmark times), checked on 4,000 sampled splats per view."""
+    sc = _with_sh(synth.make_scene("sq100k"), 3)
+    cams = synth.config_cameras("sq100k")
+    got = _eval_gpu(sc, cams, 3)
+    idx = np.sort(np.random.default_rng(2).choice(len(sc["opac"]), 4000, replace=False))
+    sub = {k: (v[idx] if isinstance(v, np.ndarray) and v.shape[:1] == (len(sc["opac"]),) else v)
+           for k, v in sc.items()}
+    for v in range(0, 64, 3):
+        ref = oracle.indirect_eval(sub, cams[v], sub["sh"], 3)
+        _close_f32(got[v, idx, :3], ref)
+
+
+def test_indirect_eval_degenerate_splats():
+    """A zero quaternion gives l_ind = 0 (no normal); a centre at the camera (to float32
+    rounding) stays finite."""
+    sc = _with_sh(synth.make_scene("shell2k", n=64), 2)
+    cam = synth.config_cameras("shell2k")[0]
+    w2c = np.asarray(cam["w2c"], np.float64)
+    centre = -w2c[:, :3].T @ w2c[:, 3]
+    sc["quats"] = sc["quats"].copy()
+    sc["quats"][5] = 0.0
+    sc["means"] = sc["means"].copy()
+    sc["means"][9] = centre.astype(np.float32)
+    got = _eval_gpu(sc, [cam], 2)
+    assert (got[0, 5] == 0).all() and np.isfinite(got).all()
+    keep = np.ones(64, bool)
+    keep[[5, 9]] = False
+    ref = oracle.indirect_eval(sc, cam, sc["sh"], 2)
+    _close_f32(got[0, keep, :3], ref[keep])
+
+
+# --------------------------------------------------------------------------- frames
+
+def _render(sc, cams, W, H, vis=None, **kw):
+    P = _pkg()
+    ds = P.DeviceScene.from_dict(sc, device="cuda")
+    out = P.render(ds, cams, W, H, vis=None if vis is None else torch.as_tensor(vis).cuda(),
+                   **kw)
+    torch.cuda.synchronize()
+    return ds, out
+
+
+def _frame_parity(sc, cam, out, vis, v=0, pixels=None, name="frame", max_fail=0):
+    W, H = cam["width"], cam["height"]
+    if pixels is None:
+        pixels = oracle.all_pixels(W, H)
+    li = oracle.indirect_eval(sc, cam, sc["sh"], sc["sh_degree"])
+    pv = None if vis is None else vis[v][pixels[:, 1], pixels[:, 0]]
+    ref = oracle.render(sc, cam, pixels=pixels, lind=li, vis=pv)
+    rgba, gb = gather(out, v, pixels)
+    gi = gather_ind(out, v, pixels)
+    ok, info = pixel_match(rgba, gb, ref, gpu_gind=gi)
+    _print(name, info)
+    for b in np.nonzero(~ok)[0][:5]:
+        print("  fail", pixels[b], "gpu", rgba[b], "ref", ref["rgba"][b], "stat", ref["stat"][b])
+    assert info["fail"] <= max_fail, info
+    assert info["over_strict_rgb_tol"] <= max(2, 0.005 * info["pixels"]), info
+    assert gi is None or np.abs(ref["gind"]).max() > 0.1
+    return info
+
+
+def test_shell2k_indirect_full_frame():
+    """The 2,000-splat shell, 128x128, degree-3 SH, mixed visibility: every pixel."""
+    sc = _with_sh(synth.make_scene("shell2k"), 3)
+    cam = synth.config_cameras("shell2k")[0]
+    vis = synth.visibility(np.random.default_rng(5), 1, 128, 128)
+    ds, out = _render(sc, [cam], 128, 128, vis=vis, gbuf=True, aux=True)
+    _frame_parity(sc, cam, out, vis, name="shell2k indirect")
+
+
+def test_indirect_ragged_multi_view():
+    sc = _with_sh(synth.make_scene("sq100k", n=4000, tex_res=8, env_res=32), 2)
+    sc["env_levels"] = 3
+    cams = synth.orbit_cameras(3, 61, 47, dist=2.4, el_deg=30.0)
+    vis = synth.visibility(np.random.default_rng(6), 3, 47, 61)
+    ds, out = _render(sc, cams, 61, 47, vis=vis, gbuf=True)
+    for v in range(3):
+        _frame_parity(sc, cams[v], out, vis, v=v, name=f"indirect ragged v{v}")
+
+
+def test_indirect_constant_sampler():
+    sc = _with_sh(synth.make_scene("shell2k", n=900, tex_res=1), 1)
+    cam = synth.crop_camera(synth.config_cameras("shell2k")[0], 30, 30, 70, 60)
+    vis = synth.visibility(np.random.default_rng(7), 1, 60, 70)
+    ds, out = _render(sc, [cam], 70, 60, vis=vis, params={"sampler": 1}, gbuf=True)
+    _frame_parity(sc, cam, out, vis, name="indirect constant sampler")
+
+
+def test_indirect_full_size_sampled():
+    """The benchmark's indirect workload: 100k splats, all 64 orbit views at 800x800 in one
+    launch, degree-3 SH and mixed visibility; two views checked at sampled pixels."""
+    sc = _with_sh(synth.make_scene("sq100k"), 3)
+    cams = synth.config_cameras("sq100k")
+    vis = synth.visibility(np.random.default_rng(8), 64, 800, 800)
+    ds, out = _render(sc, cams, 800, 800, vis=vis)
+    rng = np.random.default_rng(9)
+    for v in (0, 37):
+        pix = sample_pixels(rng, 800, 800, 160)
+        _frame_parity(sc, cams[v], out, vis, v=v, pixels=pix, name=f"sq100k indirect v{v}")
+
+
+def test_full_visibility_is_the_plain_render():
+    """V = 1: the indirect variant's image equals the plain render (the mix reduces to the
+    direct light; same blend order), and its G-buffer is the same."""
+    sc = synth.make_scene("sq100k", n=6000, env_res=16)
+    cams = synth.orbit_cameras(2, 96, 80)
+    _, plain = _render(sc, cams, 96, 80, gbuf=True)
+    _, ind = _render(_with_sh(sc, 3), cams, 96, 80, vis=np.ones((2, 80, 96), np.float32),
+                     gbuf=True)
+    dg = float((plain["gbuf"] - ind["gbuf"]).abs().max())
+    dc = float((plain["rgba"] - ind["rgba"]).abs().max())
+    print(f"[full visibility] gbuf diff {dg:.3e} rgba diff {dc:.3e}", flush=True)
+    assert dg <= 1e-6 and dc <= 1e-6
+
+
+def test_shade_with_indirect_on_synthetic_gbuffer():
+    P = _pkg()
+    rng = np.random.default_rng(10)
+    V, H, W = 2, 40, 56
+    g, a = synth.random_gbuffer(rng, V, H, W)
+    gind = (rng.uniform(0, 2, size=(V, 3, H, W)) * a[:, None]).astype(np.float32)
+    vis = synth.visibility(rng, V, H, W)
+    env = synth.make_env(rng, 32)
+    tabs_g = P.EnvTables(env, 3, device="cuda")
+    cams = synth.orbit_cameras(V, W, H)
+    rgba = torch.empty(V * H * W * 4, device="cuda")
+    P._ffi.ts_shade(V, W, H, P.cameras_tensor(cams), P._ffi.make_params(8), tabs_g.struct,
+                    torch.as_tensor(g).cuda(), torch.as_tensor(1.0 - a).cuda(), rgba,
+                    gbuf_ind=torch.as_tensor(gind).cuda(), vis=torch.as_tensor(vis).cuda())
+    torch.cuda.synchronize()
+    rgba = rgba.view(V, H, W, 4).double().cpu().numpy()
+    tabs = oracle.tables(env, 3)
+    pix = oracle.all_pixels(W, H)
+    for v in range(V):
+        gg = g[v].reshape(8, -1).T.astype(np.float64)
+        aa = (1.0 - (1.0 - a[v].astype(np.float32))).reshape(-1).astype(np.float64)
+        ref, gap = oracle.shade_gbuffer(gg, aa, cams[v], pix, tabs,
+                                        gind=gind[v].reshape(3, -1).T, vis=vis[v].reshape(-1))
+        err = np.abs(rgba[v].reshape(-1, 4)[:, :3] - ref).max(axis=1)
+        tie = gap < 1e-5
+        assert (err[~tie] <= TOL_RGB).all(), err.max()
+        print(f"[shade indirect v{v}] max err {err[~tie].max():.3e}", flush=True)
