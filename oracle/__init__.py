@@ -195,6 +195,11 @@ GB = 11   # G-buffer channels of the oracle: albedo 3, metallic, roughness, norm
 def render(scene, cam, pixels=None, params=None, tabs=None, shade=True, lind=None, vis=None):
     """Render the listed pixels ([P,2] x,y; default: the whole frame).
 
+    Texture variants read from the scene dict: "tex_format" 1 = textures with 7 channels
+    (albedo 3, roughness, normal x, y, metallic; n_z rebuilt), "trilinear" = filter over the
+    box-filtered mip chain, "chart_table" [n_charts,2] = (level-0 texel offset, log2 T) of
+    each chart with "textures" then a flat [texels, C] array.
+
     lind: per-splat indirect radiance [n,3] of this view (indirect_eval), or None;
     vis: visibility V per listed pixel [P], or None (V = 1).
 
@@ -207,9 +212,18 @@ def render(scene, cam, pixels=None, params=None, tabs=None, shade=True, lind=Non
     pixels = np.ascontiguousarray(pixels, dtype=np.int32).reshape(-1, 2)
     P = len(pixels)
     n = len(scene["opac"])
-    T = int(scene["textures"].shape[1])
     m, q, s, o, tex = (_f32(scene[k]) for k in ("means", "quats", "scales", "opac", "textures"))
     chart = np.ascontiguousarray(scene["chart_of"], dtype=np.int32)
+    # texture variants: two-component normals, trilinear mips, per-chart resolutions
+    fmt = int(scene.get("tex_format", 0))
+    tri = 1 if scene.get("trilinear", False) else 0
+    ctab = scene.get("chart_table")
+    if ctab is not None:
+        ctab = np.ascontiguousarray(ctab, dtype=np.int32).reshape(-1, 2)
+        T = 1
+    else:
+        T = int(scene["textures"].shape[1])
+    assert tex.shape[-1] == (7 if fmt else 8)
     gbuf = np.zeros((P, GB))
     alt_gbuf = np.zeros((P, MAX_ALT, GB))
     out = {"rgba": np.zeros((P, 4)), "stat": np.zeros((P, 7)),
@@ -225,8 +239,8 @@ def render(scene, cam, pixels=None, params=None, tabs=None, shade=True, lind=Non
         env_args = (_p(spec), spec_res, levels, _p(irr), irr.shape[1], _p(lut), lut.shape[0])
     else:
         env_args = (None, 0, 0, None, 0, None, 0)
-    rc = lib().or_render(n, T, _p(m), _p(q), _p(s), _p(o), _p(tex), _p(chart),
-                         _p(cam16(cam)), _p(params_vec(params)), *env_args,
+    rc = lib().or_render(n, T, _p(m), _p(q), _p(s), _p(o), _p(tex), _p(chart), fmt, tri,
+                         None if ctab is None else _p(ctab), _p(cam16(cam)), _p(params_vec(params)), *env_args,
                          None if li is None else _p(li), None if vi is None else _p(vi),
                          _p(pixels), P, _p(out["rgba"]), _p(gbuf), _p(out["stat"]),
                          _p(out["alt_rgba"]), _p(alt_gbuf))

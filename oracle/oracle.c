@@ -11,6 +11,10 @@
  *   - front-to-back blending in the global depth order                      (Eq. 3, Eq. 8)
  *   - texture coordinates s = (u+S)/(2S), t = (v+S)/(2S), S = 3             (Eq. 5)
  *   - bilinear texture filtering per primitive                              (Eq. 4, Eq. 6)
+ *   - texture variants: tangent normals stored as two components with
+ *     n_z = sqrt(max(0, 1 - n_x^2 - n_y^2)) rebuilt after filtering          (Sec. 3.5.1)
+ *     per-primitive texture resolution and trilinear filtering over a box-filtered mip chain
+ *     (the adaptive allocation and mipmapping the paper names as open)      (Sec. 6)
  *   - tangent normal rotated to world space, n = R n^t                      (Eq. 7)
  *   - G-buffers X = [albedo, metallic, roughness, normal]                   (Eq. 9)
  *   - split-sum shading L_o = L_d + L_s against an environment cubemap      (Eq. 10-12)
@@ -340,6 +344,10 @@ typedef struct {
     int n, T;
     const float *means, *quats, *scales, *opac, *tex;
     const int32_t* chart_of;
+    int fmt;                 /* 0: 8 channels per texel (normal xyz); 1: 7 channels (normal xy) */
+    int tri;                 /* 1: trilinear filtering over the chart's mip chain */
+    const int32_t* ctab;     /* [n_charts][2] level-0 texel offset and log2 T of each chart;
+                                NULL: every chart is T x T, chart c at texel c T^2 */
 } scene_t;
 
 typedef struct {
@@ -390,22 +398,75 @@ static void setup_splat(const scene_t* sc, const cam_t* cam, const par_t* par, i
     s->sigma = dot3(s->n, om) >= 0 ? 1.0 : -1.0;
 }
 
-/* Texture value of primitive k at (s,t): bilinear with texel centres at (i+1/2)/T and
-   clamp-to-edge inside the primitive's own T x T texels (Eq. 6). */
-static void tex_bilinear(const scene_t* sc, int k, double s, double t, double* a) {
-    int T = sc->T;
-    double X = s * T - 0.5, Y = t * T - 0.5;
+/* Texel (i,j) of mip level l of a chart whose level 0 is T x T texels at P (C channels per
+   texel): level l is the mean of the 2^l x 2^l block of level-0 texels it covers (the box
+   filter the chain is defined by; level 0 is the texture itself). */
+static void mip_texel(const float* P, int T, int C, int l, int i, int j, double* v) {
+    int b = 1 << l;
+    for (int c = 0; c < C; c++) v[c] = 0.0;
+    for (int jj = j * b; jj < (j + 1) * b; jj++)
+        for (int ii = i * b; ii < (i + 1) * b; ii++)
+            for (int c = 0; c < C; c++) v[c] += P[((size_t)jj * T + ii) * C + c];
+    for (int c = 0; c < C; c++) v[c] /= (double)b * b;
+}
+
+/* Bilinear at (s,t) on mip level l (T_l = T >> l texels a side): texel centres at
+   (i+1/2)/T_l, clamp-to-edge inside the chart (Eq. 6). */
+static void bilinear_level(const float* P, int T, int C, int l, double s, double t, double* a) {
+    int Tl = T >> l;
+    double X = s * Tl - 0.5, Y = t * Tl - 0.5;
     double fx0 = floor(X), fy0 = floor(Y), fx = X - fx0, fy = Y - fy0;
     int i0 = (int)fx0, j0 = (int)fy0, i1 = i0 + 1, j1 = j0 + 1;
-    if (i0 < 0) i0 = 0; if (i0 > T - 1) i0 = T - 1;
-    if (i1 < 0) i1 = 0; if (i1 > T - 1) i1 = T - 1;
-    if (j0 < 0) j0 = 0; if (j0 > T - 1) j0 = T - 1;
-    if (j1 < 0) j1 = 0; if (j1 > T - 1) j1 = T - 1;
-    const float* P = sc->tex + (size_t)sc->chart_of[k] * T * T * 8;
-    for (int c = 0; c < 8; c++) {
-        double v00 = P[((size_t)j0 * T + i0) * 8 + c], v10 = P[((size_t)j0 * T + i1) * 8 + c];
-        double v01 = P[((size_t)j1 * T + i0) * 8 + c], v11 = P[((size_t)j1 * T + i1) * 8 + c];
-        a[c] = (1 - fy) * ((1 - fx) * v00 + fx * v10) + fy * ((1 - fx) * v01 + fx * v11);
+    if (i0 < 0) i0 = 0; if (i0 > Tl - 1) i0 = Tl - 1;
+    if (i1 < 0) i1 = 0; if (i1 > Tl - 1) i1 = Tl - 1;
+    if (j0 < 0) j0 = 0; if (j0 > Tl - 1) j0 = Tl - 1;
+    if (j1 < 0) j1 = 0; if (j1 > Tl - 1) j1 = Tl - 1;
+    double v00[8], v10[8], v01[8], v11[8];
+    mip_texel(P, T, C, l, i0, j0, v00);
+    mip_texel(P, T, C, l, i1, j0, v10);
+    mip_texel(P, T, C, l, i0, j1, v01);
+    mip_texel(P, T, C, l, i1, j1, v11);
+    for (int c = 0; c < C; c++)
+        a[c] = (1 - fy) * ((1 - fx) * v00[c] + fx * v10[c]) + fy * ((1 - fx) * v01[c] + fx * v11[c]);
+}
+
+/* Texture value of primitive k at (s,t), as 8 channels (albedo 3, roughness, normal xyz,
+   metallic). rho = texture footprint of one pixel in level-0 texels of a unit-resolution
+   chart (scaled by the chart's T below); used only with trilinear filtering, whose level is
+   lambda = log2(T rho): below 0 the level-0 bilinear sample, else the blend of levels
+   floor(lambda) and floor(lambda)+1 by the fraction, the last level alone beyond it. With
+   two-component normals the third is rebuilt after filtering. */
+static void tex_sample(const scene_t* sc, int k, double s, double t, double rho, double* a) {
+    int chart = sc->chart_of[k];
+    int C = sc->fmt ? 7 : 8;
+    int T = sc->T;
+    size_t off = (size_t)chart * T * T;
+    if (sc->ctab) { off = (size_t)sc->ctab[2 * chart]; T = 1 << sc->ctab[2 * chart + 1]; }
+    const float* P = sc->tex + off * C;
+    double v[8];
+    int L = 0;
+    while ((1 << L) < T) L++;              /* levels 0..L, T = 2^L */
+    double lam = sc->tri ? log2(T * rho) : 0.0;
+    if (!sc->tri || !(lam > 0.0)) {
+        bilinear_level(P, T, C, 0, s, t, v);
+    } else {
+        int l0 = (int)floor(lam);
+        if (l0 >= L) {
+            bilinear_level(P, T, C, L, s, t, v);
+        } else {
+            double f = lam - l0, v1[8];
+            bilinear_level(P, T, C, l0, s, t, v);
+            bilinear_level(P, T, C, l0 + 1, s, t, v1);
+            for (int c = 0; c < C; c++) v[c] = (1 - f) * v[c] + f * v1[c];
+        }
+    }
+    if (sc->fmt) {
+        /* stored (albedo 3, roughness, n_x, n_y, metallic) */
+        for (int c = 0; c < 6; c++) a[c] = v[c];
+        a[6] = sqrt(fmax(0.0, 1.0 - v[4] * v[4] - v[5] * v[5]));
+        a[7] = v[6];
+    } else {
+        for (int c = 0; c < 8; c++) a[c] = v[c];
     }
 }
 
@@ -467,7 +528,7 @@ static double shade(const env_t* env, const par_t* par, const double* g, double 
 /* ------------------------------------------------------------------------------------- */
 /* one pixel                                                                              */
 /* ------------------------------------------------------------------------------------- */
-typedef struct { float key; int k; double alpha, u, v; } cand_t;
+typedef struct { float key; int k; double alpha, u, v, rho; } cand_t;
 
 static int cand_cmp(const void* a, const void* b) {
     const cand_t* x = (const cand_t*)a;
@@ -539,6 +600,26 @@ static void render_pixel(const scene_t* sc, const splat_t* sp, const cam_t* cam,
         if (in_support) po->n_support++;
         if (!include) continue;
         cand[nc].key = s->depth32; cand[nc].k = k; cand[nc].alpha = alpha; cand[nc].u = u; cand[nc].v = v;
+        cand[nc].rho = 0.0;
+        if (sc->tri) {
+            /* footprint of the pixel on the texture: derivatives of (s,t) = ((u,v)+S)/(2S)
+               along the image axes, from the ray d(X,Y) = R^T ((X-cx)/fx, (Y-cy)/fy, 1),
+               lambda = ((mu-o).n)/(d.n) and P = o + lambda d - mu */
+            double J[2][2];
+            for (int ax = 0; ax < 2; ax++) {
+                double dd[3];
+                for (int m = 0; m < 3; m++)
+                    dd[m] = cam->Rc2w[m * 3 + ax] / (ax == 0 ? cam->fx : cam->fy);
+                double dlam = -lam * dot3(dd, s->n) / den;
+                double dP[3] = {lam * dd[0] + dlam * d[0], lam * dd[1] + dlam * d[1],
+                                lam * dd[2] + dlam * d[2]};
+                J[ax][0] = dot3(dP, s->tu) / s->su / (2 * par->S);
+                J[ax][1] = dot3(dP, s->tv) / s->sv / (2 * par->S);
+            }
+            double rx = sqrt(J[0][0] * J[0][0] + J[0][1] * J[0][1]);
+            double ry = sqrt(J[1][0] * J[1][0] + J[1][1] * J[1][1]);
+            cand[nc].rho = rx > ry ? rx : ry;
+        }
         nc++;
     }
     qsort(cand, nc, sizeof(cand_t), cand_cmp);
@@ -557,7 +638,7 @@ static void render_pixel(const scene_t* sc, const splat_t* sp, const cam_t* cam,
         double w = a * T;
         double tx[8];
         double ss = (cand[c].u + par->S) / (2 * par->S), tt = (cand[c].v + par->S) / (2 * par->S);
-        tex_bilinear(sc, cand[c].k, ss, tt, tx);
+        tex_sample(sc, cand[c].k, ss, tt, cand[c].rho, tx);
         double nt[3] = {tx[4], tx[5], tx[6]};
         double l = sqrt(dot3(nt, nt));
         if (l > 0) { nt[0] /= l; nt[1] /= l; nt[2] /= l; } else { nt[0] = 0; nt[1] = 0; nt[2] = 1; }
@@ -610,7 +691,7 @@ static void render_pixel(const scene_t* sc, const splat_t* sp, const cam_t* cam,
 int or_splat_setup(int n, const float* means, const float* quats, const float* scales,
                    const float* opac, const double* cam16, const double* params,
                    float* depth32, int32_t* keep, double* sigma) {
-    scene_t sc = {n, 1, means, quats, scales, opac, NULL, NULL};
+    scene_t sc = {n, 1, means, quats, scales, opac, NULL, NULL, 0, 0, NULL};
     cam_t cam; par_t par;
     make_cam(cam16, &cam); make_par(params, &par);
     for (int k = 0; k < n; k++) {
@@ -623,6 +704,9 @@ int or_splat_setup(int n, const float* means, const float* quats, const float* s
 
 /*
  * Render the listed pixels (pix = [P][2] x,y).
+ * tex: level-0 texels, [n_charts][T][T][C] or, with ctab, charts of 2^ctab[2c+1] texels a
+ * side at texel offsets ctab[2c]; C = 8 (fmt 0) or 7 (fmt 1: albedo 3, roughness, n_x, n_y,
+ * metallic); tri = 1 filters trilinearly over the box-filtered mip chain.
  * lind [n][3] per-splat indirect radiance of this view (or NULL: no indirect map),
  * vis [P] visibility per listed pixel (or NULL: V = 1).
  * out_rgba [P][4], out_gbuf [P][11] (albedo 3, metallic, roughness, normal 3, L_ind 3),
@@ -633,13 +717,14 @@ int or_splat_setup(int n, const float* means, const float* quats, const float* s
  */
 int or_render(int n, int T, const float* means, const float* quats, const float* scales,
               const float* opac, const float* tex, const int32_t* chart_of,
+              int fmt, int tri, const int32_t* ctab,
               const double* cam16, const double* params,
               const double* env_spec, int spec_res, int spec_levels,
               const double* env_irr, int irr_res, const double* env_lut, int lut_res,
               const double* lind, const double* vis, const int32_t* pix, int P,
               double* out_rgba, double* out_gbuf, double* out_stat,
               double* alt_rgba, double* alt_gbuf) {
-    scene_t sc = {n, T, means, quats, scales, opac, tex, chart_of};
+    scene_t sc = {n, T, means, quats, scales, opac, tex, chart_of, fmt, tri, ctab};
     cam_t cam; par_t par;
     make_cam(cam16, &cam); make_par(params, &par);
     env_t envs = {env_spec, spec_res, spec_levels, env_irr, irr_res, env_lut, lut_res};
