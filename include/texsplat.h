@@ -67,7 +67,24 @@ typedef struct ts_params {
     float bg[3];      /* background radiance of empty pixels                           [0] */
     int32_t tex_res;  /* T: texels per side of each primitive's texture, 1..32        [8] */
     int32_t sampler;  /* TS_SAMPLER_*                                          [BILINEAR] */
+    int32_t tex_format;          /* TS_TEX_*: texel layout of the atlas           [RGBN3] */
+    const int32_t* chart_table;  /* device [n_charts][2]: texel offset of the chart's level 0
+                                    and log2 of its side (0..5), for atlases of per-chart
+                                    resolutions (Sec. 6, adaptive allocation); NULL: every
+                                    chart is tex_res a side, chart c at texel c * (texels of
+                                    one chart with its mip chain if any)           [NULL] */
+    int64_t atlas_texels;        /* texels in the atlas (bounds every chart-table entry; a
+                                    chart reaching past it samples as 0); read only with
+                                    chart_table                                       [0] */
 } ts_params;
+
+/* Texel layouts (ts_params.tex_format). A chart holds its texels row-major, level 0 first;
+   with TS_SAMPLER_TRILINEAR its box-filtered levels 1..log2(T) follow (level l is
+   (T>>l)^2 texels, level l at texel offset 4 (T^2 - (T>>l)^2) / 3 of the chart). */
+#define TS_TEX_RGBN3 0   /* 8 floats: albedo rgb, roughness, tangent normal xyz, metallic    */
+#define TS_TEX_RGBN2 1   /* 7 floats: albedo rgb, roughness, tangent normal xy, metallic;
+                            n_z = sqrt(max(0, 1 - n_x^2 - n_y^2)) rebuilt after filtering
+                            (the paper's memory encoding, Sec. 3.5.1)                       */
 
 /* Texture sampling of ts_raster_fwd / ts_raster_bwd (ts_params.sampler). */
 #define TS_SAMPLER_BILINEAR 0   /* software bilinear on the packed atlas (Eq. 5-6)             */
@@ -76,6 +93,13 @@ typedef struct ts_params {
 #define TS_SAMPLER_HARDWARE 2   /* texture-unit bilinear on an image atlas (Supp. Sec. 1 Eq.
                                    S1-S2); the gfx950 toolchain offers no image/texture
                                    instructions, so this returns TS_E_UNSUPPORTED              */
+#define TS_SAMPLER_TRILINEAR 3  /* mipmapping (Sec. 6): level lambda = log2(T rho), rho the
+                                   larger of the pixel's two texture-space steps (the
+                                   derivatives of (s,t) along the image axes from the closed-
+                                   form (u,v)); lambda <= 0: level-0 bilinear, else bilinear on
+                                   levels floor(lambda) and floor(lambda)+1 blended by the
+                                   fraction, the last level alone beyond it. The atlas holds
+                                   each chart's mip chain (ts_atlas_pack2 / ts_atlas_mips)     */
 
 /* Shading tables (device pointers, produced by ts_env_tables / ts_brdf_lut). */
 typedef struct ts_env {
@@ -341,6 +365,28 @@ int ts_env_tables(const float* env, int32_t r, int32_t levels, int32_t irr_res, 
  */
 int ts_atlas_pack(const float* textures, int32_t n, int32_t tex_res, const int32_t* perm,
                   float* atlas, int32_t* chart_of, hipStream_t stream);
+
+/*
+ * ts_atlas_pack2 — ts_atlas_pack into a chosen texel layout: chart perm[k] receives primitive
+ * k's level 0 ([n][T][T][8] input, converted to tex_format), charts at a stride of T^2
+ * texels, or of the whole mip chain ((4 T^2 - 1)/3 texels) when mips != 0, in which case the
+ * chain is built as by ts_atlas_mips. atlas holds n such charts (C = 8 or 7 floats a texel).
+ * Errors: TS_E_ARG (null pointers, T not a power of two in 1..32, unknown format), TS_E_LAUNCH.
+ */
+int ts_atlas_pack2(const float* textures, int32_t n, int32_t tex_res, const int32_t* perm,
+                   int32_t tex_format, int32_t mips, float* atlas, int32_t* chart_of,
+                   hipStream_t stream);
+
+/*
+ * ts_atlas_mips — build levels 1..log2(T_c) of every chart in place from its level 0: texel
+ * (i,j) of level l is the mean of texels (2i..2i+1, 2j..2j+1) of level l-1 (the box filter;
+ * so the mean of its 2^l x 2^l level-0 block). chart_table (device [n_charts][2], as in
+ * ts_params) or NULL for uniform charts of tex_res texels a side with their chains at a
+ * stride of (4 T^2 - 1)/3 texels; max_log2 bounds the per-chart log2 sides (0..5);
+ * atlas_texels bounds table entries (a chart past it is skipped).
+ */
+int ts_atlas_mips(float* atlas, int32_t n_charts, int32_t tex_res, const int32_t* chart_table,
+                  int32_t max_log2, int64_t atlas_texels, int32_t tex_format, hipStream_t stream);
 
 /*
  * ts_locality_perm — a chart permutation that stores the textures of nearby primitives next to

@@ -25,7 +25,8 @@ c_int32, c_int64, c_float, c_void_p, c_size_t = (ctypes.c_int32, ctypes.c_int64,
 class TsParams(ctypes.Structure):
     _fields_ = [("s_sigma", c_float), ("alpha_min", c_float), ("alpha_max", c_float),
                 ("t_min", c_float), ("near_z", c_float), ("bg", c_float * 3),
-                ("tex_res", c_int32), ("sampler", c_int32)]
+                ("tex_res", c_int32), ("sampler", c_int32), ("tex_format", c_int32),
+                ("chart_table", c_void_p), ("atlas_texels", c_int64)]
 
 
 class TsEnv(ctypes.Structure):
@@ -63,6 +64,9 @@ _SIGS = {
     "ts_env_tables": [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p],
     "ts_atlas_pack": [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p],
     "ts_locality_perm": [c_void_p, c_int32, c_void_p, c_size_t, c_void_p, c_void_p],
+    "ts_atlas_pack2": [c_void_p, c_int32, c_int32, c_void_p, c_int32, c_int32, c_void_p, c_void_p,
+                       c_void_p],
+    "ts_atlas_mips": [c_void_p, c_int32, c_int32, c_void_p, c_int32, c_int64, c_int32, c_void_p],
     "ts_locality_perm_workspace": [c_int32, ctypes.POINTER(c_size_t)],
 }
 
@@ -110,17 +114,23 @@ def stream_handle(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-SAMPLER_BILINEAR, SAMPLER_CONSTANT, SAMPLER_HARDWARE = 0, 1, 2
+SAMPLER_BILINEAR, SAMPLER_CONSTANT, SAMPLER_HARDWARE, SAMPLER_TRILINEAR = 0, 1, 2, 3
+TEX_RGBN3, TEX_RGBN2 = 0, 1
 
 
 def make_params(tex_res, s_sigma=3.0, alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4,
-                near_z=0.2, bg=(0.0, 0.0, 0.0), sampler=SAMPLER_BILINEAR):
+                near_z=0.2, bg=(0.0, 0.0, 0.0), sampler=SAMPLER_BILINEAR, tex_format=0,
+                chart_table=None, atlas_texels=0):
+    """chart_table: device int32 tensor [n_charts, 2] or None (kept alive by the caller)."""
     p = TsParams()
     p.s_sigma, p.alpha_min, p.alpha_max, p.t_min, p.near_z = s_sigma, alpha_min, alpha_max, t_min, near_z
     for i in range(3):
         p.bg[i] = bg[i]
     p.tex_res = int(tex_res)
     p.sampler = int(sampler)
+    p.tex_format = int(tex_format)
+    p.chart_table = None if chart_table is None else ptr(chart_table)
+    p.atlas_texels = int(atlas_texels)
     return p
 
 
@@ -240,3 +250,16 @@ def ts_locality_perm(means, n, perm, stream=None):
     ws = torch.empty(max(int(nb.value), 1), device=means.device, dtype=torch.uint8)
     _check(lib().ts_locality_perm(ptr(means), n, ptr(ws), ws.numel(), ptr(perm),
                                   stream_handle(stream)), "ts_locality_perm")
+
+
+def ts_atlas_pack2(textures, n, tex_res, perm, tex_format, mips, atlas, chart_of, stream=None):
+    _check(lib().ts_atlas_pack2(ptr(textures), n, tex_res, ptr(perm), int(tex_format), int(mips),
+                                ptr(atlas), ptr(chart_of), stream_handle(stream)),
+           "ts_atlas_pack2")
+
+
+def ts_atlas_mips(atlas, n_charts, tex_res, chart_table, max_log2, atlas_texels, tex_format,
+                  stream=None):
+    _check(lib().ts_atlas_mips(ptr(atlas), n_charts, tex_res, ptr(chart_table), int(max_log2),
+                               int(atlas_texels), int(tex_format), stream_handle(stream)),
+           "ts_atlas_mips")

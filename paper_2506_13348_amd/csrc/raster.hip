@@ -15,8 +15,16 @@
 // With the indirect term (Eq. 9, Eq. 12) each record's l_ind (per view and splat) is staged
 // beside it, a ninth to eleventh channel blends it, and the fused shading mixes the direct
 // and indirect specular light by the pixel's visibility.
+//
+// Texture paths (template kSamp): 0 the default atlas (8-float texels, uniform charts,
+// bilinear on level 0) in straight-line code; 1 one attribute per splat; 2 the atlas variants
+// with bilinear sampling (two-component normals, per-chart resolutions through a chart
+// table); 3 the same with trilinear sampling over each chart's mip chain, the level taken from
+// the pixel's footprint on the splat (derivatives of the closed-form (u,v) along the image
+// axes: du/dX = (u_x - u w_x) / den, and likewise for v and Y).
 #include "eval.h"
 #include "shade.h"
+#include "texture.h"
 #include "ts_internal.h"
 
 namespace ts {
@@ -41,16 +49,19 @@ struct RasterArgs {
     const float4* lind;      // [V][n] indirect radiance per (view, splat), kInd only
     const float* vis;        // [V][H][W] visibility or null (V = 1)
     float* gbuf_ind;         // [V][3][H][W] blended L_ind or null
+    TexArgs tex;             // atlas description of the variant paths (kSamp 2, 3)
 };
 
 constexpr int kBatch = 192;   // records staged per batch (a multiple of 64)
 static_assert(kBatch % kWave == 0, "the batch is walked in rows of 64");
 
-template <bool kTextured, bool kInd>
+template <int kSamp, bool kInd>
 // 6 waves per SIMD: at most 80 VGPRs and a 22.5 KB record batch, so six workgroups fit a CU
 // (measured faster than 5 waves with 256-record batches). The indirect variant carries three
-// more accumulators and needs more than 80 VGPRs: 5 waves per SIMD, no spills.
-__global__ __launch_bounds__(256, kInd ? 5 : 6) void k_raster_fwd(RasterArgs a) {
+// more accumulators and needs more than 80 VGPRs: 5 waves per SIMD, no spills; the atlas
+// variants (two texel levels in flight) 4.
+__global__ __launch_bounds__(256, kSamp >= 2 ? 4 : (kInd ? 5 : 6)) void k_raster_fwd(RasterArgs a) {
+    constexpr bool kTextured = kSamp != 1;
     __shared__ float4 srec[kBatch * kRec4];
     __shared__ uint32_t smask[kBatch];
     __shared__ float4 slind[kInd ? kBatch : 1];
@@ -121,10 +132,25 @@ __global__ __launch_bounds__(256, kInd ? 5 : 6) void k_raster_fwd(RasterArgs a) 
                         float4 c4 = rp[4], c5 = rp[5], c6 = rp[6];
                         // the chart is the same for the whole wave: scalar base address
                         int chart = __builtin_amdgcn_readfirstlane(__float_as_int(c6.y));
-                        __amdgpu_buffer_rsrc_t tr = chart_rsrc(a.atlas + (size_t)(unsigned)chart * chart4,
-                                                               chart4 * 16u);
                         float t0, t1, t2, t3, t4, t5, t6, t7;
-                        if (kTextured) {
+                        if (kSamp >= 2) {
+                            float lr = 0.f;
+                            if (kSamp == 3) {
+                                float4 c1 = rp[1], c2 = rp[2], c3 = rp[3];
+                                float dux = (c1.z - u * c3.x) * e.inv, duy = (c1.w - u * c3.y) * e.inv;
+                                float dvx = (c2.y - vv * c3.x) * e.inv, dvy = (c2.z - vv * c3.y) * e.inv;
+                                float ax = fmaf(dux, dux, dvx * dvx), ay = fmaf(duy, duy, dvy * dvy);
+                                // log2 rho = log2 max(|d(u,v)/dX|, |d(u,v)/dY|) - log2(2 S)
+                                lr = 0.5f * __builtin_amdgcn_logf(fmaxf(ax, ay)) -
+                                     __builtin_amdgcn_logf(2.0f * a.S);
+                            }
+                            float tt[8];
+                            sample_chart<kSamp == 3>(a.tex, chart, u, vv, a.S, lr, tt);
+                            t0 = tt[0]; t1 = tt[1]; t2 = tt[2]; t3 = tt[3];
+                            t4 = tt[4]; t5 = tt[5]; t6 = tt[6]; t7 = tt[7];
+                        } else if (kTextured) {
+                            __amdgpu_buffer_rsrc_t tr = chart_rsrc(a.atlas + (size_t)(unsigned)chart * chart4,
+                                                                   chart4 * 16u);
                             float sx = fmaf(u, tscale, toff), sy = fmaf(vv, tscale, toff);
                             float fx0 = floorf(sx), fy0 = floorf(sy);
                             float fx = sx - fx0, fy = sy - fy0;
@@ -149,6 +175,8 @@ __global__ __launch_bounds__(256, kInd ? 5 : 6) void k_raster_fwd(RasterArgs a) 
                             t7 = w00 * q00.w + w10 * q10.w + w01 * q01.w + w11 * q11.w;
                         } else {
                             // one attribute per splat (the untextured primitive)
+                            __amdgpu_buffer_rsrc_t tr = chart_rsrc(a.atlas + (size_t)(unsigned)chart * chart4,
+                                                                   chart4 * 16u);
                             float4 p0, q0;
                             load_texel8(tr, 0u, p0, q0);
                             t0 = p0.x; t1 = p0.y; t2 = p0.z; t3 = p0.w;
@@ -295,12 +323,30 @@ extern "C" int ts_raster_fwd(int32_t n_views, int32_t width, int32_t height, con
                   "instructions for this target)");
         return TS_E_UNSUPPORTED;
     }
-    if (params->sampler != TS_SAMPLER_BILINEAR && params->sampler != TS_SAMPLER_CONSTANT) {
+    if (params->sampler != TS_SAMPLER_BILINEAR && params->sampler != TS_SAMPLER_CONSTANT &&
+        params->sampler != TS_SAMPLER_TRILINEAR) {
         set_error("ts_raster_fwd: unknown sampler %d", params->sampler);
         return TS_E_ARG;
     }
     if (params->sampler == TS_SAMPLER_CONSTANT && params->tex_res != 1) {
         set_error("ts_raster_fwd: the constant sampler needs tex_res 1 (got %d)", params->tex_res);
+        return TS_E_ARG;
+    }
+    if (params->tex_format != TS_TEX_RGBN3 && params->tex_format != TS_TEX_RGBN2) {
+        set_error("ts_raster_fwd: unknown tex_format %d", params->tex_format);
+        return TS_E_ARG;
+    }
+    // the atlas variants: another texel layout, a chart table or trilinear sampling
+    const bool variant = params->tex_format != TS_TEX_RGBN3 || params->chart_table ||
+                         params->sampler == TS_SAMPLER_TRILINEAR;
+    if (variant && !params->chart_table &&
+        (params->tex_res & (params->tex_res - 1)) != 0) {
+        set_error("ts_raster_fwd: atlas variants need a power-of-two tex_res (got %d)",
+                  params->tex_res);
+        return TS_E_ARG;
+    }
+    if (params->chart_table && params->atlas_texels <= 0) {
+        set_error("ts_raster_fwd: chart_table needs atlas_texels");
         return TS_E_ARG;
     }
     if ((rgba != nullptr) != (env != nullptr)) {
@@ -342,19 +388,36 @@ extern "C" int ts_raster_fwd(int32_t n_views, int32_t width, int32_t height, con
     a.lind = (const float4*)lind;
     a.vis = vis;
     a.gbuf_ind = gbuf_ind;
+    const bool tri = params->sampler == TS_SAMPLER_TRILINEAR;
+    a.tex.atlas = (const char*)atlas;
+    a.tex.table = (const int2*)params->chart_table;
+    a.tex.atlas_texels = params->atlas_texels;
+    a.tex.T = params->tex_res;
+    a.tex.L = ilog2(params->tex_res);
+    a.tex.chart_texels = tri ? chain_texels(params->tex_res)
+                             : (unsigned)(params->tex_res * params->tex_res);
+    a.tex.fmt = params->tex_format;
     int64_t blocks = (int64_t)n_views * a.n_tiles;
     if (blocks > 0x7FFFFFFF) {
         set_error("ts_raster_fwd: too many tiles");
         return TS_E_ARG;
     }
     const dim3 grid((unsigned)blocks), block(256);
-    const bool cst = params->sampler == TS_SAMPLER_CONSTANT;
+    const int samp = tri ? 3 : variant ? 2 : params->sampler == TS_SAMPLER_CONSTANT ? 1 : 0;
     if (lind) {
-        if (cst) hipLaunchKernelGGL((k_raster_fwd<false, true>), grid, block, 0, stream, a);
-        else hipLaunchKernelGGL((k_raster_fwd<true, true>), grid, block, 0, stream, a);
+        switch (samp) {
+            case 0: hipLaunchKernelGGL((k_raster_fwd<0, true>), grid, block, 0, stream, a); break;
+            case 1: hipLaunchKernelGGL((k_raster_fwd<1, true>), grid, block, 0, stream, a); break;
+            case 2: hipLaunchKernelGGL((k_raster_fwd<2, true>), grid, block, 0, stream, a); break;
+            default: hipLaunchKernelGGL((k_raster_fwd<3, true>), grid, block, 0, stream, a); break;
+        }
     } else {
-        if (cst) hipLaunchKernelGGL((k_raster_fwd<false, false>), grid, block, 0, stream, a);
-        else hipLaunchKernelGGL((k_raster_fwd<true, false>), grid, block, 0, stream, a);
+        switch (samp) {
+            case 0: hipLaunchKernelGGL((k_raster_fwd<0, false>), grid, block, 0, stream, a); break;
+            case 1: hipLaunchKernelGGL((k_raster_fwd<1, false>), grid, block, 0, stream, a); break;
+            case 2: hipLaunchKernelGGL((k_raster_fwd<2, false>), grid, block, 0, stream, a); break;
+            default: hipLaunchKernelGGL((k_raster_fwd<3, false>), grid, block, 0, stream, a); break;
+        }
     }
     return launch_check("ts_raster_fwd");
 }

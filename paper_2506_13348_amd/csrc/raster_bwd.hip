@@ -722,7 +722,13 @@ extern "C" int ts_raster_bwd(int32_t n_views, int32_t width, int32_t height, con
     if (params->sampler != TS_SAMPLER_BILINEAR) {
         set_error("ts_raster_bwd: only the bilinear sampler is differentiated (T = 1 textures "
                   "give the untextured primitive)");
-        return params->sampler == TS_SAMPLER_HARDWARE ? TS_E_UNSUPPORTED : TS_E_ARG;
+        return params->sampler == TS_SAMPLER_HARDWARE || params->sampler == TS_SAMPLER_TRILINEAR
+                   ? TS_E_UNSUPPORTED : TS_E_ARG;
+    }
+    if (params->tex_format != TS_TEX_RGBN3 || params->chart_table) {
+        set_error("ts_raster_bwd: the atlas variants (two-component normals, chart tables) are "
+                  "rendered forward only");
+        return TS_E_UNSUPPORTED;
     }
     if (partial_capacity < 0 || partial_capacity > (int64_t)INT32_MAX * 8) {
         set_error("ts_raster_bwd: partial_capacity %lld outside 0..2^34 floats",

@@ -1,0 +1,124 @@
+// Texture sampling of the atlas variants (two-component normals, per-chart resolutions,
+// trilinear over the mip chain), shared by the raster and the atlas builders. The default
+// layout (8-float texels, uniform charts, bilinear on level 0) keeps its own straight-line
+// path in the raster kernel.
+#pragma once
+#include "ts_internal.h"
+
+namespace ts {
+
+constexpr int kMaxTexLog2 = 5;   // charts of at most 32 x 32 texels
+
+__host__ __device__ inline int ilog2(int x) {
+    int l = 0;
+    while ((1 << (l + 1)) <= x) l++;
+    return l;
+}
+// texels of a chart of side T with its full mip chain: T^2 + (T/2)^2 + ... + 1
+__host__ __device__ inline unsigned chain_texels(int T) { return (unsigned)(4 * T * T - 1) / 3u; }
+// first texel of level l inside such a chart
+__host__ __device__ inline unsigned level_offset(int T, int l) {
+    int s = T >> l;
+    return (unsigned)(4 * (T * T - s * s)) / 3u;
+}
+
+struct TexArgs {
+    const char* atlas;       // texel bytes
+    const int2* table;       // per chart (level-0 texel offset, log2 side) or null
+    int64_t atlas_texels;    // bound of table entries
+    int T, L;                // uniform side and its log2
+    unsigned chart_texels;   // uniform chart stride in texels
+    int fmt;                 // TS_TEX_*
+};
+
+// The eight channels of texel t (albedo rgb, roughness | normal xyz, metallic); with the
+// two-component layout n_z comes back as 0 (rebuilt after filtering).
+__device__ inline void fetch_texel(__amdgpu_buffer_rsrc_t r, int fmt, unsigned t, float4& lo,
+                                   float4& hi) {
+    if (fmt) {
+        lo = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, t * 28u, 0, 0));
+        auto q = __builtin_amdgcn_raw_buffer_load_b96(r, t * 28u + 16u, 0, 0);
+        hi = make_float4(__int_as_float(q[0]), __int_as_float(q[1]), 0.f, __int_as_float(q[2]));
+    } else {
+        load_texel8(r, t, lo, hi);
+    }
+}
+
+// Bilinear on level l of a chart of side Tc at local (u,v) (s = (u+S)/(2S)): texel centres at
+// (i+1/2)/T_l, clamp-to-edge inside the chart (Eq. 5-6).
+__device__ inline void bilinear_level(__amdgpu_buffer_rsrc_t r, int fmt, int Tc, int l, float u,
+                                      float v, float S, float* o) {
+    const int Tl = Tc >> l;
+    const float sc = (float)Tl / (2.0f * S), off = 0.5f * (float)Tl - 0.5f;
+    float sx = fmaf(u, sc, off), sy = fmaf(v, sc, off);
+    float fx0 = floorf(sx), fy0 = floorf(sy);
+    float fx = sx - fx0, fy = sy - fy0;
+    int i0 = (int)fx0, j0 = (int)fy0;
+    int i1 = min(max(i0 + 1, 0), Tl - 1), j1 = min(max(j0 + 1, 0), Tl - 1);
+    i0 = min(max(i0, 0), Tl - 1);
+    j0 = min(max(j0, 0), Tl - 1);
+    const unsigned lo = level_offset(Tc, l);
+    float4 p00, q00, p10, q10, p01, q01, p11, q11;
+    fetch_texel(r, fmt, lo + (unsigned)(j0 * Tl + i0), p00, q00);
+    fetch_texel(r, fmt, lo + (unsigned)(j0 * Tl + i1), p10, q10);
+    fetch_texel(r, fmt, lo + (unsigned)(j1 * Tl + i0), p01, q01);
+    fetch_texel(r, fmt, lo + (unsigned)(j1 * Tl + i1), p11, q11);
+    float w00 = (1.f - fx) * (1.f - fy), w10 = fx * (1.f - fy);
+    float w01 = (1.f - fx) * fy, w11 = fx * fy;
+    o[0] = w00 * p00.x + w10 * p10.x + w01 * p01.x + w11 * p11.x;
+    o[1] = w00 * p00.y + w10 * p10.y + w01 * p01.y + w11 * p11.y;
+    o[2] = w00 * p00.z + w10 * p10.z + w01 * p01.z + w11 * p11.z;
+    o[3] = w00 * p00.w + w10 * p10.w + w01 * p01.w + w11 * p11.w;
+    o[4] = w00 * q00.x + w10 * q10.x + w01 * q01.x + w11 * q11.x;
+    o[5] = w00 * q00.y + w10 * q10.y + w01 * q01.y + w11 * q11.y;
+    o[6] = w00 * q00.z + w10 * q10.z + w01 * q01.z + w11 * q11.z;
+    o[7] = w00 * q00.w + w10 * q10.w + w01 * q01.w + w11 * q11.w;
+}
+
+// Texture of chart `chart` (the same for the whole wave) at (u,v). lr = log2 of the pixel's
+// footprint in units of the whole chart (log2 rho); the level is lambda = log2 T_c + lr.
+template <bool kTri>
+__device__ inline void sample_chart(const TexArgs& ta, int chart, float u, float v, float S,
+                                    float lr, float* t) {
+    int64_t base;
+    int L;
+    bool ok = true;
+    if (ta.table) {
+        int2 e = ta.table[chart];
+        base = e.x;
+        L = e.y;
+        ok = L >= 0 && L <= kMaxTexLog2 && base >= 0 &&
+             base + (int64_t)(kTri ? chain_texels(1 << L) : (1u << (2 * L))) <= ta.atlas_texels;
+        if (!ok) { base = 0; L = 0; }
+    } else {
+        base = (int64_t)chart * ta.chart_texels;
+        L = ta.L;
+    }
+    const int Tc = 1 << L;
+    const unsigned tb = ta.fmt ? 28u : 32u;
+    const unsigned n_tex = ok ? (kTri ? chain_texels(Tc) : (unsigned)(Tc * Tc)) : 0u;
+    __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(ta.atlas + base * tb), (short)0, (int)(n_tex * tb), 0x00020000);
+    if (!kTri) {
+        bilinear_level(r, ta.fmt, Tc, 0, u, v, S, t);
+    } else {
+        float lam = (float)L + lr;
+        if (!(lam > 0.f)) {
+            bilinear_level(r, ta.fmt, Tc, 0, u, v, S, t);
+        } else {
+            int l0 = (int)floorf(lam);
+            if (l0 >= L) {
+                bilinear_level(r, ta.fmt, Tc, L, u, v, S, t);
+            } else {
+                float f = lam - (float)l0, t1[8];
+                bilinear_level(r, ta.fmt, Tc, l0, u, v, S, t);
+                bilinear_level(r, ta.fmt, Tc, l0 + 1, u, v, S, t1);
+#pragma unroll
+                for (int q = 0; q < 8; q++) t[q] = fmaf(f, t1[q] - t[q], t[q]);
+            }
+        }
+    }
+    if (ta.fmt) t[6] = sqrtf(fmaxf(0.f, 1.f - t[4] * t[4] - t[5] * t[5]));
+}
+
+}  // namespace ts

@@ -79,8 +79,15 @@ class DeviceScene:
     """Splats + packed atlas + shading tables resident on one device."""
 
     def __init__(self, means, quats, scales, opac, textures, env=None, env_levels=1,
-                 device="cuda", perm=None, tables=None, locality=False, sh=None, sh_degree=0):
+                 device="cuda", perm=None, tables=None, locality=False, sh=None, sh_degree=0,
+                 tex_format=0, mips=False, chart_log2=None):
+        """Atlas variants: tex_format 1 stores 7-float texels (two-component normals); mips
+        builds each chart's box-filtered chain and renders with trilinear sampling;
+        chart_log2 [n] gives per-splat texture sides 2^l, textures then being the level-0
+        texels of all splats back to back ([sum 4^l, 8], splat order)."""
         self.device = torch.device(device)
+        self.tex_format, self.mips = int(tex_format), bool(mips)
+        self.chart_table, self.atlas_texels = None, 0
         # indirect light: [n, (degree+1)^2, 3] SH coefficients per splat, or None
         self.sh = None if sh is None else _dev(sh, device, torch.float32)
         self.sh_degree = int(sh_degree)
@@ -88,25 +95,63 @@ class DeviceScene:
         self.quats = _dev(quats, device, torch.float32)
         self.scales = _dev(scales, device, torch.float32)
         self.opac = _dev(opac, device, torch.float32)
-        tex = _dev(textures, device, torch.float32)
         self.n = int(self.means.shape[0])
-        self.tex_res = int(tex.shape[1])
-        self.atlas = torch.empty_like(tex)
-        self.chart_of = torch.empty(self.n, device=device, dtype=torch.int32)
-        permt = None if perm is None else _dev(np.asarray(perm, np.int32), device, torch.int32)
-        if locality and perm is None and self.n:
-            # charts in Morton order of the centres: neighbouring splats share cache lines
-            permt = torch.empty(self.n, device=device, dtype=torch.int32)
-            F.ts_locality_perm(self.means, self.n, permt)
-        if self.n:
-            F.ts_atlas_pack(tex, self.n, self.tex_res, permt, self.atlas, self.chart_of)
-        del tex
+        if chart_log2 is not None:
+            self._adaptive_atlas(np.asarray(textures, np.float32), np.asarray(chart_log2))
+        else:
+            tex = _dev(textures, device, torch.float32)
+            self.tex_res = int(tex.shape[1])
+            T, C = self.tex_res, (7 if self.tex_format else 8)
+            chart = (4 * T * T - 1) // 3 if self.mips else T * T
+            self.atlas = (torch.empty_like(tex) if not (self.tex_format or self.mips) else
+                          torch.empty(max(self.n, 1) * chart * C, device=device,
+                                      dtype=torch.float32))
+            self.chart_of = torch.empty(self.n, device=device, dtype=torch.int32)
+            permt = None if perm is None else _dev(np.asarray(perm, np.int32), device, torch.int32)
+            if locality and perm is None and self.n:
+                # charts in Morton order of the centres: neighbouring splats share cache lines
+                permt = torch.empty(self.n, device=device, dtype=torch.int32)
+                F.ts_locality_perm(self.means, self.n, permt)
+            if self.n:
+                if self.tex_format or self.mips:
+                    F.ts_atlas_pack2(tex, self.n, T, permt, self.tex_format, self.mips,
+                                     self.atlas, self.chart_of)
+                else:
+                    F.ts_atlas_pack(tex, self.n, T, permt, self.atlas, self.chart_of)
+            del tex
         if tables is not None:
             self.tables = tables
         elif env is not None:
             self.tables = EnvTables(env, env_levels, device)
         else:
             self.tables = None
+
+    def _adaptive_atlas(self, texels, log2):
+        """Charts of per-splat sides 2^log2[k] (with their mip chains when self.mips), packed
+        back to back in splat order; the chart table holds (level-0 texel offset, log2)."""
+        n = self.n
+        sides = 1 << log2.astype(np.int64)
+        chain = (4 * sides * sides - 1) // 3 if self.mips else sides * sides
+        offs = np.concatenate([[0], np.cumsum(chain)])[:-1]
+        total = int(chain.sum()) if n else 1
+        C = 7 if self.tex_format else 8
+        host = np.zeros((max(total, 1), C), np.float32)
+        src = np.concatenate([[0], np.cumsum(sides * sides)])
+        lv0 = texels.reshape(-1, 8)
+        if self.tex_format:
+            lv0 = np.concatenate([lv0[:, 0:6], lv0[:, 7:8]], 1)
+        for k in range(n):
+            m = int(sides[k] * sides[k])
+            host[offs[k]:offs[k] + m] = lv0[src[k]:src[k] + m]
+        self.atlas = torch.as_tensor(host.reshape(-1)).to(self.device)
+        table = np.stack([offs, log2], 1).astype(np.int32)
+        self.chart_table = torch.as_tensor(table).to(self.device).contiguous()
+        self.atlas_texels = total
+        self.chart_of = torch.arange(n, device=self.device, dtype=torch.int32)
+        self.tex_res = int(sides.max()) if n else 1
+        if self.mips and n:
+            F.ts_atlas_mips(self.atlas, n, self.tex_res, self.chart_table,
+                            int(log2.max()), total, self.tex_format)
 
     @classmethod
     def from_dict(cls, sc, device="cuda", **kw):
@@ -137,7 +182,13 @@ class RenderPlan:
         self.W, self.H = int(width), int(height)
         self.cams = cameras_tensor(cams, scene.device)
         self.V = int(self.cams.shape[0])
-        self.params = F.make_params(scene.tex_res, **p)
+        # atlas variants and the indirect term (absent on plain scene views)
+        mips = getattr(scene, "mips", False)
+        if mips and not (params and "sampler" in params):
+            p["sampler"] = F.SAMPLER_TRILINEAR
+        self.params = F.make_params(scene.tex_res, tex_format=getattr(scene, "tex_format", 0),
+                                    chart_table=getattr(scene, "chart_table", None),
+                                    atlas_texels=getattr(scene, "atlas_texels", 0), **p)
         self.ntx = (self.W + F.TILE - 1) // F.TILE
         self.nty = (self.H + F.TILE - 1) // F.TILE
         self.n_tiles = self.ntx * self.nty
@@ -160,7 +211,7 @@ class RenderPlan:
         self.n_contrib = torch.empty(plane, **i32) if aux else None
         self.n_blend = torch.empty(plane, **i32) if aux else None
         # indirect term (on when the scene carries SH coefficients)
-        self.indirect = scene.sh is not None
+        self.indirect = getattr(scene, "sh", None) is not None
         self.lind = (torch.empty(V * max(n, 1) * 4, device=dev, dtype=torch.float32)
                      if self.indirect else None)
         self.gbuf_ind = (torch.empty(plane * 3, device=dev, dtype=torch.float32)

@@ -29,7 +29,7 @@ __all__ = [
     "CONFIGS", "SceneConfig", "make_scene", "make_env", "look_at_camera", "orbit_cameras",
     "config_cameras", "crop_camera", "random_gbuffer", "poisson_requests", "target_image",
     "cameras_array", "fd_crop_scene", "serving_camera", "serving_scene", "SERVING_SCENES",
-    "SERVING_RESOLUTIONS", "indirect_sh", "visibility",
+    "SERVING_RESOLUTIONS", "indirect_sh", "visibility", "texture_sides", "adaptive_textures",
 ]
 
 
@@ -426,6 +426,22 @@ def indirect_sh(rng, n, degree=3):
     for l in range(1, degree + 1):
         c[:, l * l:(l + 1) * (l + 1)] = rng.normal(0.0, 0.3 / l, size=(n, 2 * l + 1, 3))
     return c.astype(np.float32)
+
+
+def texture_sides(scales, base_log2=3, max_log2=4):
+    """Per-splat texture side exponents for an adaptive atlas: larger primitives get more
+    texels, log2 T_k = clip(round(log2(s_k / median s) + base_log2), 0, max_log2) with s_k the
+    larger scale (an allocation by primitive size, the policy the paper suggests)."""
+    s = np.asarray(scales, np.float64).max(axis=1)
+    med = np.median(s) if len(s) else 1.0
+    return np.clip(np.round(np.log2(s / med) + base_log2), 0, max_log2).astype(np.int32)
+
+
+def adaptive_textures(rng, log2):
+    """Level-0 texels of every splat at its own side 2^log2[k], back to back in splat order
+    ([sum 4^log2, 8] float32; channel distributions as the uniform textures)."""
+    parts = [_textures(rng, 1, 1 << int(l)).reshape(-1, 8) for l in log2]
+    return (np.concatenate(parts) if parts else np.zeros((0, 8), np.float32)).astype(np.float32)
 
 
 def visibility(rng, n_views, height, width):

@@ -61,6 +61,24 @@ def test_host_side_argument_errors():
     assert L.ts_indirect_eval(0, one, 10, one, one, one, 3, one, None) == -1
     assert L.ts_indirect_eval(2, one, 10, None, one, one, 3, one, None) == -1
     assert L.ts_indirect_eval(2, one, 0, None, None, None, 3, None, None) == 0
+    # atlas variants
+    assert L.ts_atlas_pack2(one, 4, 6, None, 0, 1, one, one, None) == -1
+    assert L.ts_atlas_pack2(one, 4, 8, None, 3, 0, one, one, None) == -1
+    assert L.ts_atlas_mips(one, 4, 8, None, 0, 0, 2, None) == -1
+    assert L.ts_atlas_mips(one, 4, 0, one, 6, 100, 0, None) == -1
+    assert L.ts_atlas_mips(one, 0, 8, None, 0, 0, 1, None) == 0
+    for kw, msg in ((dict(tex_format=4), b"tex_format"),
+                    (dict(sampler=_ffi.SAMPLER_TRILINEAR), b"power-of-two"),
+                    (dict(tex_format=1), b"power-of-two")):
+        q = _ffi.make_params(6, **kw)
+        assert L.ts_raster_fwd(1, 16, 16, one, ctypes.byref(q), 1, one, one, one, 10, one, None,
+                               None, None, None, None, None, None, None, None, None) == -1
+        assert msg in L.ts_last_error()
+    q = _ffi.make_params(8)
+    q.chart_table = 16
+    assert L.ts_raster_fwd(1, 16, 16, one, ctypes.byref(q), 1, one, one, one, 10, one, None,
+                           None, None, None, None, None, None, None, None, None) == -1
+    assert b"atlas_texels" in L.ts_last_error()
     assert L.ts_brdf_lut(0, 16, None, None) == -1
     assert L.ts_env_bwd_workspace(0, 8, 8, ctypes.byref(out)) == -1
     assert L.ts_env_bwd_workspace(2, 8, 8, ctypes.byref(out)) == 0 and out.value >= 2 * 64 * 12 * 36
