@@ -198,6 +198,51 @@ def bench_indirect(sc, cams, W, H, cap, steps, warmup, degree=3):
                                        "algorithmic_bytes": ind_bytes}}
 
 
+def bench_atlas_variants(sc, cams, W, H, cap, steps, base_ms, base_bytes):
+    """The headline step with the atlas variants: two-component normals (7-float texels),
+    trilinear sampling over mip chains, per-splat resolutions by primitive size (sides 1..16,
+    texture_sides), and the last two combined with two-component normals."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2506_13348_amd import DeviceScene, RenderPlan
+    dev = torch.device("cuda:0")
+    V = len(cams)
+    log2 = synth.texture_sides(sc["scales"])
+    flat = synth.adaptive_textures(np.random.default_rng(3), log2)
+    cases = {
+        "normals_xy": (sc, dict(tex_format=1)),
+        "trilinear": (sc, dict(mips=True)),
+        "normals_xy_trilinear": (sc, dict(tex_format=1, mips=True)),
+        "adaptive_sides": (dict(sc, textures=flat), dict(chart_log2=log2)),
+        "adaptive_sides_xy_trilinear": (dict(sc, textures=flat),
+                                        dict(chart_log2=log2, tex_format=1, mips=True)),
+    }
+    out = {"default": {"ms_per_step": round(base_ms, 3), "atlas_mb": round(base_bytes / 1e6, 1)}}
+    for name, (scn, kw) in cases.items():
+        ds = DeviceScene.from_dict(scn, device=dev, **kw)
+        plan = RenderPlan(ds, cams, W, H, pair_capacity=cap)
+        plan.run()
+        plan.check()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            plan.run()
+        e1.record()
+        torch.cuda.synchronize()
+        plan.check()
+        ms = e0.elapsed_time(e1) / steps
+        out[name] = {"ms_per_step": round(ms, 3),
+                     "mpix_per_s": round(V * W * H / (ms / 1e3) / 1e6, 2),
+                     "atlas_mb": round(ds.atlas.numel() * 4 / 1e6, 1),
+                     "vs_default": round(base_ms / ms, 3)}
+        del plan, ds
+        torch.cuda.empty_cache()
+    out["mean_texels_adaptive"] = round(float(np.mean((1 << log2) ** 2)), 2)
+    return out
+
+
 def bench_small_frame(reps=200):
     """The 2,000-splat shell, one 128x128 view, T = 4: a launch-latency-bound frame; median
     of per-frame times over reps renders."""
@@ -465,6 +510,9 @@ def main():
     del plan_loc, ds_loc
     result["indirect"] = bench_indirect(sc, cams, W, H, plan.cap, K, args.warmup)
     log(f"indirect: {result['indirect']}")
+    result["atlas_variants"] = bench_atlas_variants(sc, cams, W, H, plan.cap, max(3, K // 2),
+                                                    ms_step, ds.atlas.numel() * 4)
+    log(f"atlas variants: {result['atlas_variants']}")
     if not args.no_fwd_bwd:
         del plan
         torch.cuda.empty_cache()

@@ -58,9 +58,9 @@ static_assert(kBatch % kWave == 0, "the batch is walked in rows of 64");
 template <int kSamp, bool kInd>
 // 6 waves per SIMD: at most 80 VGPRs and a 22.5 KB record batch, so six workgroups fit a CU
 // (measured faster than 5 waves with 256-record batches). The indirect variant carries three
-// more accumulators and needs more than 80 VGPRs: 5 waves per SIMD, no spills; the atlas
-// variants (two texel levels in flight) 4.
-__global__ __launch_bounds__(256, kSamp >= 2 ? 4 : (kInd ? 5 : 6)) void k_raster_fwd(RasterArgs a) {
+// more accumulators and needs more than 80 VGPRs: 5 waves per SIMD, no spills; trilinear
+// sampling (two texel levels in flight) 4.
+__global__ __launch_bounds__(256, kSamp == 3 ? 4 : (kInd ? 5 : 6)) void k_raster_fwd(RasterArgs a) {
     constexpr bool kTextured = kSamp != 1;
     __shared__ float4 srec[kBatch * kRec4];
     __shared__ uint32_t smask[kBatch];
