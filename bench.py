@@ -200,8 +200,9 @@ def bench_indirect(sc, cams, W, H, cap, steps, warmup, degree=3):
 
 def bench_atlas_variants(sc, cams, W, H, cap, steps, base_ms, base_bytes):
     """The headline step with the atlas variants: two-component normals (7-float texels),
-    trilinear sampling over mip chains, per-splat resolutions by primitive size (sides 1..16,
-    texture_sides), and the last two combined with two-component normals."""
+    trilinear sampling over mip chains, per-splat resolutions by primitive size (sides 1..8:
+    the median splat keeps 8 x 8, smaller ones get fewer texels; texture_sides), and the last
+    two combined with two-component normals."""
     import numpy as np
     import torch
 
@@ -209,7 +210,7 @@ def bench_atlas_variants(sc, cams, W, H, cap, steps, base_ms, base_bytes):
     from paper_2506_13348_amd import DeviceScene, RenderPlan
     dev = torch.device("cuda:0")
     V = len(cams)
-    log2 = synth.texture_sides(sc["scales"])
+    log2 = synth.texture_sides(sc["scales"], base_log2=3, max_log2=3)
     flat = synth.adaptive_textures(np.random.default_rng(3), log2)
     cases = {
         "normals_xy": (sc, dict(tex_format=1)),

@@ -37,10 +37,27 @@ __device__ inline double dot3(const double* a, const double* b) {
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
+__device__ void preprocess_one(const PreArgs& a, int64_t gid, float4* r4);
+
+// Records leave through LDS: each thread builds its 7 float4 there, then the workgroup
+// writes its 256 consecutive records (28 KB) with consecutive lanes on consecutive float4s
+// (a thread writing its own 112-byte record would touch 7 lines per lane and store).
+// Records of dropped splats are written too (zeros); no list refers to them.
 __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
-    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t total = (int64_t)a.V * a.n;
-    if (gid >= total) return;
+    __shared__ float4 srec[256 * kRec4];
+    const int64_t block0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t total = (int64_t)a.V * a.n;
+    const int nrec = (int)min((int64_t)blockDim.x, total - block0);
+#pragma unroll
+    for (int q = 0; q < kRec4; q++) srec[threadIdx.x * kRec4 + q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (threadIdx.x < nrec) preprocess_one(a, block0 + threadIdx.x, srec + threadIdx.x * kRec4);
+    __syncthreads();
+    float4* dst = (float4*)a.rec + block0 * kRec4;
+    for (int i = threadIdx.x; i < nrec * kRec4; i += blockDim.x) dst[i] = srec[i];
+}
+
+// One (view, splat): rect, depth key, and the record into r4 (left untouched when dropped).
+__device__ void preprocess_one(const PreArgs& a, int64_t gid, float4* r4) {
     int v = (int)(gid / a.n);
     int k = (int)(gid - (int64_t)v * a.n);
     const ts_camera& cam = a.cams[v];
@@ -156,7 +173,6 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a) {
         int iy0 = (int)fmax(fy0, 0.0), iy1 = (int)fmin(fy1, (double)(a.H - 1));
         if (ix0 <= ix1 && iy0 <= iy1 && bx0 <= bx1 && by0 <= by1) {
             rect_out = make_int4(ix0 / kTile, iy0 / kTile, ix1 / kTile + 1, iy1 / kTile + 1);
-            float4* r4 = (float4*)(a.rec + ((int64_t)v * a.n + k) * kRec);
             r4[0] = make_float4((float)ix0, (float)iy0, (float)ix1, (float)iy1);
             r4[1] = make_float4(px_hi, py_hi, (float)ux, (float)uy);
             r4[2] = make_float4((float)u0, (float)vx, (float)vy, (float)v0);

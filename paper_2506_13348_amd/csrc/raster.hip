@@ -65,6 +65,7 @@ __global__ __launch_bounds__(256, kSamp == 3 ? 4 : (kInd ? 5 : 6)) void k_raster
     __shared__ float4 srec[kBatch * kRec4];
     __shared__ uint32_t smask[kBatch];
     __shared__ float4 slind[kInd ? kBatch : 1];
+    __shared__ int2 schart[kSamp >= 2 ? kBatch : 1];   // chart entries of the variant paths
     const int g = gridDim.x;
     const int bid = xcd_remap(blockIdx.x, g);
     const int v = bid / a.n_tiles;
@@ -107,6 +108,8 @@ __global__ __launch_bounds__(256, kSamp == 3 ? 4 : (kInd ? 5 : 6)) void k_raster
 #pragma unroll
             for (int q = 4; q < kRec4; q++) srec[tid * kRec4 + q] = src[q];
             if (kInd) slind[tid] = a.lind[(int64_t)v * a.n + id];
+            if (kSamp >= 2)
+                schart[tid] = chart_entry<kSamp == 3>(a.tex, __float_as_int(srec[tid * kRec4 + 6].y));
             qm = quad_mask_uv(r0, r1, r2, r3, tx * kTile, ty * kTile, a.S, a.amin);
         }
         if (tid < kBatch) smask[tid] = qm;
@@ -145,7 +148,10 @@ __global__ __launch_bounds__(256, kSamp == 3 ? 4 : (kInd ? 5 : 6)) void k_raster
                                      __builtin_amdgcn_logf(2.0f * a.S);
                             }
                             float tt[8];
-                            sample_chart<kSamp == 3>(a.tex, chart, u, vv, a.S, lr, tt);
+                            int2 ce = schart[j];
+                            ce.x = __builtin_amdgcn_readfirstlane(ce.x);
+                            ce.y = __builtin_amdgcn_readfirstlane(ce.y);
+                            sample_chart<kSamp == 3>(a.tex, ce, u, vv, a.S, lr, tt);
                             t0 = tt[0]; t1 = tt[1]; t2 = tt[2]; t3 = tt[3];
                             t4 = tt[4]; t5 = tt[5]; t6 = tt[6]; t7 = tt[7];
                         } else if (kTextured) {

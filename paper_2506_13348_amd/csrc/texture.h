@@ -75,25 +75,26 @@ __device__ inline void bilinear_level(__amdgpu_buffer_rsrc_t r, int fmt, int Tc,
     o[7] = w00 * q00.w + w10 * q10.w + w01 * q01.w + w11 * q11.w;
 }
 
-// Texture of chart `chart` (the same for the whole wave) at (u,v). lr = log2 of the pixel's
-// footprint in units of the whole chart (log2 rho); the level is lambda = log2 T_c + lr.
+// Where chart `chart` lives: (level-0 texel offset, log2 side); log2 side -1 marks a table
+// entry outside the atlas (sampled as 0).
 template <bool kTri>
-__device__ inline void sample_chart(const TexArgs& ta, int chart, float u, float v, float S,
+__device__ inline int2 chart_entry(const TexArgs& ta, int chart) {
+    if (!ta.table) return make_int2((int)((unsigned)chart * ta.chart_texels), ta.L);
+    int2 e = ta.table[chart];
+    bool ok = e.y >= 0 && e.y <= kMaxTexLog2 && e.x >= 0 &&
+              (int64_t)e.x + (int64_t)(kTri ? chain_texels(1 << e.y) : (1u << (2 * e.y))) <=
+                  ta.atlas_texels;
+    return ok ? e : make_int2(0, -1);
+}
+
+// Texture of the chart at entry `ce` (the same for the whole wave) at (u,v). lr = log2 of the
+// pixel's footprint in units of the whole chart (log2 rho); the level is lambda = log2 T_c + lr.
+template <bool kTri>
+__device__ inline void sample_chart(const TexArgs& ta, int2 ce, float u, float v, float S,
                                     float lr, float* t) {
-    int64_t base;
-    int L;
-    bool ok = true;
-    if (ta.table) {
-        int2 e = ta.table[chart];
-        base = e.x;
-        L = e.y;
-        ok = L >= 0 && L <= kMaxTexLog2 && base >= 0 &&
-             base + (int64_t)(kTri ? chain_texels(1 << L) : (1u << (2 * L))) <= ta.atlas_texels;
-        if (!ok) { base = 0; L = 0; }
-    } else {
-        base = (int64_t)chart * ta.chart_texels;
-        L = ta.L;
-    }
+    const bool ok = ce.y >= 0;
+    const int64_t base = (unsigned)ce.x;
+    const int L = ok ? ce.y : 0;
     const int Tc = 1 << L;
     const unsigned tb = ta.fmt ? 28u : 32u;
     const unsigned n_tex = ok ? (kTri ? chain_texels(Tc) : (unsigned)(Tc * Tc)) : 0u;
