@@ -25,7 +25,10 @@ ROOT = os.path.dirname(HERE)
 
 # the source files each profiled kernel is built from
 KERNEL_SOURCES = {
-    "k_raster_fwd": ["csrc/raster.hip", "csrc/eval.h", "csrc/shade.h", "csrc/ts_internal.h"],
+    "k_raster_fwd": ["csrc/raster.hip", "csrc/eval.h", "csrc/shade.h", "csrc/texture.h",
+                     "csrc/ts_internal.h"],
+    "k_preprocess": ["csrc/preprocess.hip", "csrc/ts_internal.h"],
+    "k_bin_fill": ["csrc/binsort.hip", "csrc/binsort_layout.h", "csrc/ts_internal.h"],
     "k_raster_bwd": ["csrc/raster_bwd.hip", "csrc/eval.h", "csrc/shade.h", "csrc/shade_bwd.h",
                      "csrc/ts_internal.h"],
 }
