@@ -287,21 +287,42 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int6
     if (i < m) p[i] = x;
 }
 
-// Column scan over chunks per (view, tile): counts become exclusive prefixes.
-__global__ __launch_bounds__(256) void k_bin_scan_chunks(uint32_t* __restrict__ counts, int V,
-                                                         int n_chunks, int n_tiles,
-                                                         uint32_t* __restrict__ totals) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)V * n_tiles) return;
-    int v = (int)(i / n_tiles), t = (int)(i % n_tiles);
+// Column scan over chunks per (view, tile): counts become exclusive prefixes. A workgroup
+// takes 64 (view, tile) columns (lane = column, coalesced rows) and cuts the chunks into 16
+// segments, one per wave: segment sums, their prefix across the waves in LDS, then each wave
+// rewrites its segment. One column per thread walking every chunk would serialise thousands
+// of dependent steps when one view is cut into many chunks.
+constexpr int kScanSegs = 16;
+
+__global__ __launch_bounds__(kScanSegs * kWave) void k_bin_scan_chunks(
+    uint32_t* __restrict__ counts, int V, int n_chunks, int n_tiles, uint32_t* __restrict__ totals) {
+    __shared__ uint32_t seg[kScanSegs][kWave];
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int64_t i = (int64_t)blockIdx.x * kWave + lane;
+    const bool valid = i < (int64_t)V * n_tiles;
+    const int v = valid ? (int)(i / n_tiles) : 0, t = valid ? (int)(i % n_tiles) : 0;
     uint32_t* col = counts + (int64_t)v * n_chunks * n_tiles + t;
-    uint32_t run = 0;
-    for (int c = 0; c < n_chunks; c++) {
-        uint32_t x = col[(int64_t)c * n_tiles];
-        col[(int64_t)c * n_tiles] = run;
-        run += x;
+    const int per = (n_chunks + kScanSegs - 1) / kScanSegs;
+    const int c0 = min(n_chunks, wv * per), c1 = min(n_chunks, c0 + per);
+    uint32_t s = 0;
+    if (valid) {
+#pragma unroll 8
+        for (int c = c0; c < c1; c++) s += col[(int64_t)c * n_tiles];
     }
-    totals[i] = run;
+    seg[wv][lane] = s;
+    __syncthreads();
+    uint32_t run = 0;
+    for (int k = 0; k < wv; k++) run += seg[k][lane];
+    if (valid) {
+#pragma unroll 8
+        for (int c = c0; c < c1; c++) {
+            uint32_t x = col[(int64_t)c * n_tiles];
+            col[(int64_t)c * n_tiles] = run;
+            run += x;
+        }
+        // the last segment ends at n_chunks: its running sum is the column total
+        if (wv == kScanSegs - 1) totals[i] = run;
+    }
 }
 
 // Exclusive scan of all (view, tile) totals in three steps: block sums, a scan of the block
@@ -436,8 +457,9 @@ extern "C" int ts_bin_sort(int32_t n_views, int32_t width, int32_t height, int32
     }
     int64_t m = (int64_t)n_views * L.n_tiles;
     int nsb = (int)((m + kScanBlock - 1) / kScanBlock);
-    hipLaunchKernelGGL(k_bin_scan_chunks, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream,
-                       counts, n_views, L.n_chunks, L.n_tiles, totals);
+    hipLaunchKernelGGL(k_bin_scan_chunks, dim3((unsigned)((m + kWave - 1) / kWave)),
+                       dim3(kScanSegs * kWave), 0, stream, counts, n_views, L.n_chunks, L.n_tiles,
+                       totals);
     hipLaunchKernelGGL(k_scan_block_sums, dim3(nsb), dim3(kScanBlock), 0, stream, totals, m,
                        block_sums);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, stream, block_sums, nsb,
