@@ -292,3 +292,47 @@ def test_locality_packing_is_a_relabelling():
     ra = P.render(a, cams, 160, 120)["rgba"]
     rb = P.render(b, cams, 160, 120)["rgba"]
     assert torch.equal(ra, rb)
+
+
+# ------------------------------------------------------------------------------ maximum sizes
+
+def test_max_texture_resolution():
+    """T = 32, the largest chart side the library takes: every pixel of a crop."""
+    sc = synth.make_scene("shell2k", n=400, tex_res=32)
+    cam = synth.crop_camera(synth.config_cameras("shell2k")[0], 20, 28, 72, 64)
+    ds, out = _render(sc, [cam], 72, 64, gbuf=True)
+    _frame_parity(sc, cam, out, name="T=32")
+
+
+def test_largest_tile_grid_and_beyond():
+    """2032 x 2032 pixels (127 x 127 tiles) is the largest grid whose per-chunk count grid
+    (128 x 128 words) fits the 64 KB LDS of the count kernel: rendered and checked at sampled
+    pixels. One more tile a side is refused on the host before anything is enqueued."""
+    sc = synth.make_scene("shell2k", n=3000)
+    cam = synth.look_at_camera((0.0, 0.4, 2.2), (0.0, 0.0, 0.0), 2032, 2032, 50.0)
+    ds, out = _render(sc, [cam], 2032, 2032)
+    pix = sample_pixels(np.random.default_rng(12), 2032, 2032, 120)
+    _frame_parity(sc, cam, out, pixels=pix, name="2032x2032")
+    P = _pkg()
+    big = synth.look_at_camera((0.0, 0.4, 2.2), (0.0, 0.0, 0.0), 2048, 2048, 50.0)
+    with pytest.raises(RuntimeError, match="per-view limit"):
+        P.render(ds, [big], 2048, 2048)
+
+
+def test_pair_capacity_overflow_is_reported_and_safe():
+    """A plan whose list capacity is far too small: the status word reports the overflow with
+    the count the frame needed, and the raster reads no entry past the capacity."""
+    P = _pkg()
+    sc = synth.make_scene("sq100k", n=5000, env_res=16)
+    cams = synth.orbit_cameras(2, 96, 80)
+    ds = P.DeviceScene.from_dict(sc, device="cuda")
+    full = P.RenderPlan(ds, cams, 96, 80)
+    full.run()
+    need = full.check()
+    small = P.RenderPlan(ds, cams, 96, 80, pair_capacity=need // 10)
+    small.run()
+    torch.cuda.synchronize()
+    assert int(small.status.item()) == 1 and int(small.n_pairs.item()) == need
+    with pytest.raises(RuntimeError, match="pair capacity"):
+        small.check()
+    assert torch.isfinite(small.rgba).all()
