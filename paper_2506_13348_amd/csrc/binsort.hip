@@ -201,50 +201,63 @@ struct BinArgs {
     int64_t cap;
 };
 
+// LDS words the count and fill kernels may use (64 KB); grids taller than that are done in
+// bands of tile rows, each a pass over the chunk's splats.
+constexpr int kBinLdsWords = 16384;
+
+__host__ __device__ inline int count_band_rows(int ntx) { return max(1, kBinLdsWords / (ntx + 1) - 1); }
+__host__ __device__ inline int fill_band_rows(int ntx) { return max(1, kBinLdsWords / ntx); }
+
 // Counts per (view, chunk, tile): one wavefront per chunk adds each splat's rectangle into an
-// LDS difference grid ((ntx+1) x (nty+1): +1 at (x0,y0) and (x1,y1), -1 at (x1,y0) and (x0,y1);
-// integer adds, so the order does not matter), then a 2D prefix sum turns it into coverage
-// counts.
+// LDS difference grid ((ntx+1) x (rows+1): +1 at (x0,y0) and (x1,y1), -1 at (x1,y0) and
+// (x0,y1); integer adds, so the order does not matter), then a 2D prefix sum turns it into
+// coverage counts. Rectangles are clipped to the band of tile rows in LDS.
 __global__ __launch_bounds__(kWave) void k_bin_count(BinArgs a, int nty) {
     extern __shared__ uint32_t cnt[];
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     int v = bid / a.n_chunks, c = bid - v * a.n_chunks, lane = threadIdx.x;
-    int gw = a.ntx + 1, gh = nty + 1;
-    for (int t = lane; t < gw * gh; t += kWave) cnt[t] = 0u;
-    __syncthreads();
+    const int gw = a.ntx + 1, band = count_band_rows(a.ntx);
     int i0 = c * a.chunk, i1 = min(a.n, i0 + a.chunk);
     const int32_t* sv = a.sorted + (int64_t)v * a.n;
     const int4* rv = a.rect + (int64_t)v * a.n;
-    for (int b = i0 + lane; b < i1; b += kWave) {
-        int4 r = rv[sv[b]];
-        if (r.z <= r.x || r.w <= r.y) continue;
-        atomicAdd(&cnt[r.y * gw + r.x], 1u);
-        atomicAdd(&cnt[r.w * gw + r.z], 1u);
-        atomicSub(&cnt[r.y * gw + r.z], 1u);
-        atomicSub(&cnt[r.w * gw + r.x], 1u);
-    }
-    __syncthreads();
-    // prefix along rows, then along columns (wrap-around arithmetic is exact)
-    for (int y = lane; y < gh; y += kWave) {
-        uint32_t run = 0;
-        for (int x = 0; x < gw; x++) { run += cnt[y * gw + x]; cnt[y * gw + x] = run; }
-    }
-    __syncthreads();
-    for (int x = lane; x < gw; x += kWave) {
-        uint32_t run = 0;
-        for (int y = 0; y < gh; y++) { run += cnt[y * gw + x]; cnt[y * gw + x] = run; }
-    }
-    __syncthreads();
     uint32_t* row = a.counts + ((int64_t)v * a.n_chunks + c) * a.n_tiles;
-    for (int t = lane; t < a.n_tiles; t += kWave) {
-        int ty = t / a.ntx, tx = t - ty * a.ntx;
-        row[t] = cnt[ty * gw + tx];
+    for (int y0 = 0; y0 < nty; y0 += band) {
+        const int y1 = min(nty, y0 + band), gh = y1 - y0 + 1;
+        for (int t = lane; t < gw * gh; t += kWave) cnt[t] = 0u;
+        __syncthreads();
+        for (int b = i0 + lane; b < i1; b += kWave) {
+            int4 r = rv[sv[b]];
+            int ya = max(r.y, y0) - y0, yb = min(r.w, y1) - y0;
+            if (r.z <= r.x || yb <= ya) continue;
+            atomicAdd(&cnt[ya * gw + r.x], 1u);
+            atomicAdd(&cnt[yb * gw + r.z], 1u);
+            atomicSub(&cnt[ya * gw + r.z], 1u);
+            atomicSub(&cnt[yb * gw + r.x], 1u);
+        }
+        __syncthreads();
+        // prefix along rows, then along columns (wrap-around arithmetic is exact)
+        for (int y = lane; y < gh; y += kWave) {
+            uint32_t run = 0;
+            for (int x = 0; x < gw; x++) { run += cnt[y * gw + x]; cnt[y * gw + x] = run; }
+        }
+        __syncthreads();
+        for (int x = lane; x < gw; x += kWave) {
+            uint32_t run = 0;
+            for (int y = 0; y < gh; y++) { run += cnt[y * gw + x]; cnt[y * gw + x] = run; }
+        }
+        __syncthreads();
+        for (int t = y0 * a.ntx + lane; t < y1 * a.ntx; t += kWave) {
+            int ty = t / a.ntx, tx = t - ty * a.ntx;
+            row[t] = cnt[(ty - y0) * gw + tx];
+        }
+        __syncthreads();
     }
 }
 
 // Ordered fill: one wavefront per (view, chunk) walks its splats in depth order; the lanes
 // cover the splat's rectangle in 8x8 tile blocks; LDS cursors per tile give each entry its slot.
-__global__ __launch_bounds__(kWave) void k_bin_fill(BinArgs a) {
+// Grids with more tiles than LDS words are filled in bands of tile rows (a pass each).
+__global__ __launch_bounds__(kWave) void k_bin_fill(BinArgs a, int nty) {
     extern __shared__ uint32_t cur[];
     // every chunk of a view on the same XCD: the chunks write interleaved short runs of the
     // same tile lists, whose cache lines are then completed in one L2
@@ -252,33 +265,41 @@ __global__ __launch_bounds__(kWave) void k_bin_fill(BinArgs a) {
     int v = bid / a.n_chunks, c = bid - v * a.n_chunks, lane = threadIdx.x;
     const uint32_t* row = a.counts + ((int64_t)v * a.n_chunks + c) * a.n_tiles;
     const int32_t* rg = a.ranges + (int64_t)v * a.n_tiles * 2;
-    for (int t = lane; t < a.n_tiles; t += kWave) cur[t] = (uint32_t)rg[2 * t] + row[t];
-    __syncthreads();
     int i0 = c * a.chunk, i1 = min(a.n, i0 + a.chunk);
     const int32_t* sv = a.sorted + (int64_t)v * a.n;
     const int4* rv = a.rect + (int64_t)v * a.n;
     const int lx = lane & 7, ly = lane >> 3;
-    for (int b = i0; b < i1; b += kWave) {
-        int m = min(kWave, i1 - b);
-        int id = lane < m ? sv[b + lane] : 0;
-        int4 r = lane < m ? rv[id] : make_int4(0, 0, 0, 0);
-        for (int j = 0; j < m; j++) {
-            int x0 = __builtin_amdgcn_readlane(r.x, j), y0 = __builtin_amdgcn_readlane(r.y, j);
-            int x1 = __builtin_amdgcn_readlane(r.z, j), y1 = __builtin_amdgcn_readlane(r.w, j);
-            if (x1 <= x0 || y1 <= y0) continue;
-            int sid = __builtin_amdgcn_readlane(id, j);
-            for (int by = y0; by < y1; by += 8) {
-                for (int bx = x0; bx < x1; bx += 8) {
-                    int tx = bx + lx, ty = by + ly;
-                    if (tx < x1 && ty < y1) {
-                        int t = ty * a.ntx + tx;
-                        uint32_t p = cur[t];
-                        cur[t] = p + 1;
-                        if ((int64_t)p < a.cap) a.pair_ids[p] = sid;
+    const int band = fill_band_rows(a.ntx);
+    for (int ya = 0; ya < nty; ya += band) {
+        const int yb = min(nty, ya + band);
+        const int t0 = ya * a.ntx;
+        for (int t = t0 + lane; t < yb * a.ntx; t += kWave) cur[t - t0] = (uint32_t)rg[2 * t] + row[t];
+        __syncthreads();
+        for (int b = i0; b < i1; b += kWave) {
+            int m = min(kWave, i1 - b);
+            int id = lane < m ? sv[b + lane] : 0;
+            int4 r = lane < m ? rv[id] : make_int4(0, 0, 0, 0);
+            for (int j = 0; j < m; j++) {
+                int x0 = __builtin_amdgcn_readlane(r.x, j), y0 = __builtin_amdgcn_readlane(r.y, j);
+                int x1 = __builtin_amdgcn_readlane(r.z, j), y1 = __builtin_amdgcn_readlane(r.w, j);
+                y0 = max(y0, ya);
+                y1 = min(y1, yb);
+                if (x1 <= x0 || y1 <= y0) continue;
+                int sid = __builtin_amdgcn_readlane(id, j);
+                for (int by = y0; by < y1; by += 8) {
+                    for (int bx = x0; bx < x1; bx += 8) {
+                        int tx = bx + lx, ty = by + ly;
+                        if (tx < x1 && ty < y1) {
+                            int t = ty * a.ntx + tx - t0;
+                            uint32_t p = cur[t];
+                            cur[t] = p + 1;
+                            if ((int64_t)p < a.cap) a.pair_ids[p] = sid;
+                        }
                     }
                 }
             }
         }
+        __syncthreads();
     }
 }
 
@@ -419,8 +440,8 @@ extern "C" int ts_bin_sort(int32_t n_views, int32_t width, int32_t height, int32
         set_error("ts_bin_sort: workspace %zu < %zu bytes", ws_bytes, L.total);
         return TS_E_WORKSPACE;
     }
-    if ((size_t)(L.ntx + 1) * (L.nty + 1) * 4 > 64 * 1024) {
-        set_error("ts_bin_sort: %d x %d tiles exceed the per-view limit", L.ntx, L.nty);
+    if (L.ntx + 1 > kBinLdsWords / 2) {
+        set_error("ts_bin_sort: %d tiles per row exceed the per-view limit", L.ntx);
         return TS_E_ARG;
     }
     char* w = (char*)ws;
@@ -444,8 +465,8 @@ extern "C" int ts_bin_sort(int32_t n_views, int32_t width, int32_t height, int32
     a.n = n; a.n_chunks = L.n_chunks; a.chunk = L.chunk; a.ntx = L.ntx; a.n_tiles = L.n_tiles;
     a.sorted = sorted_ids; a.rect = (const int4*)rect; a.counts = counts; a.ranges = tile_ranges;
     a.pair_ids = pair_ids; a.cap = pair_capacity;
-    size_t lds_count = (size_t)(L.ntx + 1) * (L.nty + 1) * 4;
-    size_t lds_fill = (size_t)L.n_tiles * 4;
+    size_t lds_count = (size_t)(L.ntx + 1) * (min(L.nty, count_band_rows(L.ntx)) + 1) * 4;
+    size_t lds_fill = (size_t)L.ntx * min(L.nty, fill_band_rows(L.ntx)) * 4;
     if (n > 0) {
         hipLaunchKernelGGL(k_bin_count, dim3(L.n_chunks * n_views), dim3(kWave), lds_count,
                            stream, a, L.nty);
@@ -468,6 +489,6 @@ extern "C" int ts_bin_sort(int32_t n_views, int32_t width, int32_t height, int32
                        block_sums, tile_ranges);
     if (n > 0)
         hipLaunchKernelGGL(k_bin_fill, dim3(L.n_chunks * n_views), dim3(kWave), lds_fill, stream,
-                           a);
+                           a, L.nty);
     return launch_check("ts_bin_sort(bin)");
 }

@@ -304,19 +304,27 @@ def test_max_texture_resolution():
     _frame_parity(sc, cam, out, name="T=32")
 
 
-def test_largest_tile_grid_and_beyond():
-    """2032 x 2032 pixels (127 x 127 tiles) is the largest grid whose per-chunk count grid
-    (128 x 128 words) fits the 64 KB LDS of the count kernel: rendered and checked at sampled
-    pixels. One more tile a side is refused on the host before anything is enqueued."""
+@pytest.mark.parametrize("W,H", [(2032, 2032), (3840, 2160)])
+def test_large_tile_grids(W, H):
+    """127 x 127 tiles (the count grid fills the 64 KB of LDS in one band) and a 3840 x 2160
+    frame (240 x 135 tiles: counted and filled in bands of tile rows): sampled pixels and
+    tile lists checked."""
     sc = synth.make_scene("shell2k", n=3000)
-    cam = synth.look_at_camera((0.0, 0.4, 2.2), (0.0, 0.0, 0.0), 2032, 2032, 50.0)
-    ds, out = _render(sc, [cam], 2032, 2032)
-    pix = sample_pixels(np.random.default_rng(12), 2032, 2032, 120)
-    _frame_parity(sc, cam, out, pixels=pix, name="2032x2032")
+    cam = synth.look_at_camera((0.0, 0.4, 2.2), (0.0, 0.0, 0.0), W, H, 50.0)
+    ds, out = _render(sc, [cam], W, H)
+    pix = sample_pixels(np.random.default_rng(12), W, H, 120)
+    _frame_parity(sc, cam, out, pixels=pix, name=f"{W}x{H}")
+    _check_lists(out["plan"], 3000)
+
+
+def test_tile_row_limit_is_refused():
+    """A row of more than 8191 tiles is refused on the host before anything is enqueued."""
     P = _pkg()
-    big = synth.look_at_camera((0.0, 0.4, 2.2), (0.0, 0.0, 0.0), 2048, 2048, 50.0)
+    sc = synth.make_scene("shell2k", n=50)
+    ds = P.DeviceScene.from_dict(sc, device="cuda")
+    wide = synth.look_at_camera((0.0, 0.4, 2.2), (0.0, 0.0, 0.0), 131072, 16, 50.0)
     with pytest.raises(RuntimeError, match="per-view limit"):
-        P.render(ds, [big], 2048, 2048)
+        P.render(ds, [wide], 131072, 16)
 
 
 def test_pair_capacity_overflow_is_reported_and_safe():
