@@ -204,6 +204,11 @@ struct BinArgs {
 // LDS words the count and fill kernels may use (64 KB); grids taller than that are done in
 // bands of tile rows, each a pass over the chunk's splats.
 constexpr int kBinLdsWords = 16384;
+// The fill asks for at least 16 KB of LDS, so at most 10 chunk waves share a CU (160 KB):
+// fewer tile lists are written at once and more of the partially written 128-byte lines are
+// completed in the L2 before they leave it (measured on the 64-view sq100k step: 2.36 ms for
+// ts_bin_sort at 16 waves per CU, 2.27 at 6, 2.14 at 8, 2.09 at 10, 2.16 at 12).
+constexpr size_t kFillMinLds = 16 * 1024;
 
 __host__ __device__ inline int count_band_rows(int ntx) { return max(1, kBinLdsWords / (ntx + 1) - 1); }
 __host__ __device__ inline int fill_band_rows(int ntx) { return max(1, kBinLdsWords / ntx); }
@@ -467,6 +472,7 @@ extern "C" int ts_bin_sort(int32_t n_views, int32_t width, int32_t height, int32
     a.pair_ids = pair_ids; a.cap = pair_capacity;
     size_t lds_count = (size_t)(L.ntx + 1) * (min(L.nty, count_band_rows(L.ntx)) + 1) * 4;
     size_t lds_fill = (size_t)L.ntx * min(L.nty, fill_band_rows(L.ntx)) * 4;
+    if (lds_fill < kFillMinLds) lds_fill = kFillMinLds;
     if (n > 0) {
         hipLaunchKernelGGL(k_bin_count, dim3(L.n_chunks * n_views), dim3(kWave), lds_count,
                            stream, a, L.nty);
