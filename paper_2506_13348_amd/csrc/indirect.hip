@@ -94,14 +94,16 @@ __global__ __launch_bounds__(256) void k_indirect_eval(IndArgs a) {
         double oy = -((double)w[1] * w[3] + (double)w[5] * w[7] + (double)w[9] * w[11]);
         double oz = -((double)w[2] * w[3] + (double)w[6] * w[7] + (double)w[10] * w[11]);
         double dx = mx - ox, dy = my - oy, dz = mz - oz;
-        double dl = sqrt(dx * dx + dy * dy + dz * dz);
+        double dd = dx * dx + dy * dy + dz * dz;
         float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (qq > 0.0 && dl > 0.0) {
-            dx /= dl; dy /= dl; dz /= dl;
+        if (qq > 0.0 && dd > 0.0) {
+            // one divide per normalisation: multiply by the reciprocal length
+            double idl = 1.0 / sqrt(dd);
+            dx *= idl; dy *= idl; dz *= idl;
             double dn = dx * nx + dy * ny + dz * nz;
             double rx = dx - 2.0 * dn * nx, ry = dy - 2.0 * dn * ny, rz = dz - 2.0 * dn * nz;
-            double rl = sqrt(rx * rx + ry * ry + rz * rz);
-            rx /= rl; ry /= rl; rz /= rl;
+            double irl = 1.0 / sqrt(rx * rx + ry * ry + rz * rz);
+            rx *= irl; ry *= irl; rz *= irl;
             double Y[K];
             sh_basis<D>(rx, ry, rz, Y);
             double r = 0.0, g = 0.0, b = 0.0;
