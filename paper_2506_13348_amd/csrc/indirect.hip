@@ -10,8 +10,9 @@
 // written out as polynomials of the unit vector. A workgroup takes 64 splats (one per lane)
 // and 16 views (4 per wave): the 64 splats' coefficients are staged in LDS with coalesced
 // loads, each lane keeps its splat's coefficients in registers and evaluates its views; the
-// output rows [view][splat] are written 64 splats at a time. The arithmetic is double
-// precision (per-splat set-up, like the projection), the output float32.
+// output rows [view][splat] are written 64 splats at a time. The arithmetic is float32 (unit
+// vectors and O(1) coefficients: the result is within a few ulp of the sum of |c_j Y_j|;
+// double precision took 1.7x as long).
 #include <math.h>
 
 #include "ts_internal.h"
@@ -29,28 +30,26 @@ struct IndArgs {
 
 // Real SH basis up to degree D at the unit vector (x, y, z).
 template <int D>
-__device__ inline void sh_basis(double x, double y, double z, double* Y) {
-    Y[0] = 0.28209479177387814;                       // 1 / (2 sqrt(pi))
+__device__ inline void sh_basis_f(float x, float y, float z, float* Y) {
+    Y[0] = 0.28209479177387814f;                      // 1 / (2 sqrt(pi))
     if (D < 1) return;
-    const double c1 = 0.48860251190291992;            // sqrt(3 / (4 pi))
-    Y[1] = c1 * y;
-    Y[2] = c1 * z;
-    Y[3] = c1 * x;
+    const float c1 = 0.48860251190291992f;            // sqrt(3 / (4 pi))
+    Y[1] = c1 * y; Y[2] = c1 * z; Y[3] = c1 * x;
     if (D < 2) return;
-    const double xx = x * x, yy = y * y, zz = z * z;
-    Y[4] = 1.0925484305920792 * x * y;                // sqrt(15/pi) / 2
-    Y[5] = 1.0925484305920792 * y * z;
-    Y[6] = 0.31539156525252005 * (3.0 * zz - 1.0);    // sqrt(5/pi) / 4
-    Y[7] = 1.0925484305920792 * x * z;
-    Y[8] = 0.54627421529603959 * (xx - yy);           // sqrt(15/pi) / 4
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = 1.0925484305920792f * x * y;               // sqrt(15/pi) / 2
+    Y[5] = 1.0925484305920792f * y * z;
+    Y[6] = 0.31539156525252005f * (3.0f * zz - 1.0f);  // sqrt(5/pi) / 4
+    Y[7] = 1.0925484305920792f * x * z;
+    Y[8] = 0.54627421529603959f * (xx - yy);          // sqrt(15/pi) / 4
     if (D < 3) return;
-    Y[9] = 0.59004358992664352 * y * (3.0 * xx - yy); // sqrt(35/(2 pi)) / 4
-    Y[10] = 2.8906114426405538 * x * y * z;           // sqrt(105/pi) / 2
-    Y[11] = 0.45704579946446572 * y * (5.0 * zz - 1.0);   // sqrt(21/(2 pi)) / 4
-    Y[12] = 0.37317633259011540 * z * (5.0 * zz - 3.0);   // sqrt(7/pi) / 4
-    Y[13] = 0.45704579946446572 * x * (5.0 * zz - 1.0);
-    Y[14] = 1.4453057213202769 * z * (xx - yy);       // sqrt(105/pi) / 4
-    Y[15] = 0.59004358992664352 * x * (xx - 3.0 * yy);
+    Y[9] = 0.59004358992664352f * y * (3.0f * xx - yy);   // sqrt(35/(2 pi)) / 4
+    Y[10] = 2.8906114426405538f * x * y * z;              // sqrt(105/pi) / 2
+    Y[11] = 0.45704579946446572f * y * (5.0f * zz - 1.0f);  // sqrt(21/(2 pi)) / 4
+    Y[12] = 0.37317633259011540f * z * (5.0f * zz - 3.0f);  // sqrt(7/pi) / 4
+    Y[13] = 0.45704579946446572f * x * (5.0f * zz - 1.0f);
+    Y[14] = 1.4453057213202769f * z * (xx - yy);          // sqrt(105/pi) / 4
+    Y[15] = 0.59004358992664352f * x * (xx - 3.0f * yy);
 }
 
 constexpr int kIndSplats = 64;          // splats per workgroup (one per lane)
@@ -60,7 +59,7 @@ constexpr int kIndViews = 4 * kIndViewsPerWave;   // views per workgroup (4 wave
 template <int D>
 __global__ __launch_bounds__(256) void k_indirect_eval(IndArgs a) {
     constexpr int K = (D + 1) * (D + 1);
-    constexpr int kStride = 3 * K + 1;   // odd LDS stride: lanes hit distinct banks
+    constexpr int kStride = 3 * K + 1;
     __shared__ float sc[kIndSplats * kStride];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int k0 = blockIdx.x * kIndSplats;
@@ -77,43 +76,38 @@ __global__ __launch_bounds__(256) void k_indirect_eval(IndArgs a) {
     float c[K * 3];
 #pragma unroll
     for (int j = 0; j < K * 3; j++) c[j] = sc[lane * kStride + j];
-    double q0 = a.quats[4 * k + 0], q1 = a.quats[4 * k + 1], q2 = a.quats[4 * k + 2],
-           q3 = a.quats[4 * k + 3];
-    double qq = q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3;
-    // third column of the rotation of the normalised quaternion (w, x, y, z)
-    double s = qq > 0.0 ? 2.0 / qq : 0.0;
-    double nx = s * (q1 * q3 + q0 * q2), ny = s * (q2 * q3 - q0 * q1),
-           nz = 1.0 - s * (q1 * q1 + q2 * q2);
-    const double mx = a.means[3 * k + 0], my = a.means[3 * k + 1], mz = a.means[3 * k + 2];
+    float q0 = a.quats[4 * k + 0], q1 = a.quats[4 * k + 1], q2 = a.quats[4 * k + 2], q3 = a.quats[4 * k + 3];
+    float qq = q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3;
+    float s = qq > 0.f ? 2.f / qq : 0.f;
+    float nx = s * (q1 * q3 + q0 * q2), ny = s * (q2 * q3 - q0 * q1), nz = 1.f - s * (q1 * q1 + q2 * q2);
+    const float mx = a.means[3 * k + 0], my = a.means[3 * k + 1], mz = a.means[3 * k + 2];
     for (int i = 0; i < kIndViewsPerWave; i++) {
         const int v = v0 + 4 * i;
         if (v >= a.V) break;
         const float* w = a.cams[v].w2c;
-        // camera centre o = -R^T t
-        double ox = -((double)w[0] * w[3] + (double)w[4] * w[7] + (double)w[8] * w[11]);
-        double oy = -((double)w[1] * w[3] + (double)w[5] * w[7] + (double)w[9] * w[11]);
-        double oz = -((double)w[2] * w[3] + (double)w[6] * w[7] + (double)w[10] * w[11]);
-        double dx = mx - ox, dy = my - oy, dz = mz - oz;
-        double dd = dx * dx + dy * dy + dz * dz;
+        float ox = -(w[0] * w[3] + w[4] * w[7] + w[8] * w[11]);
+        float oy = -(w[1] * w[3] + w[5] * w[7] + w[9] * w[11]);
+        float oz = -(w[2] * w[3] + w[6] * w[7] + w[10] * w[11]);
+        float dx = mx - ox, dy = my - oy, dz = mz - oz;
+        float dd = dx * dx + dy * dy + dz * dz;
         float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (qq > 0.0 && dd > 0.0) {
-            // one divide per normalisation: multiply by the reciprocal length
-            double idl = 1.0 / sqrt(dd);
+        if (qq > 0.f && dd > 0.f) {
+            float idl = rsqrtf(dd);
             dx *= idl; dy *= idl; dz *= idl;
-            double dn = dx * nx + dy * ny + dz * nz;
-            double rx = dx - 2.0 * dn * nx, ry = dy - 2.0 * dn * ny, rz = dz - 2.0 * dn * nz;
-            double irl = 1.0 / sqrt(rx * rx + ry * ry + rz * rz);
+            float dn = dx * nx + dy * ny + dz * nz;
+            float rx = dx - 2.f * dn * nx, ry = dy - 2.f * dn * ny, rz = dz - 2.f * dn * nz;
+            float irl = rsqrtf(rx * rx + ry * ry + rz * rz);
             rx *= irl; ry *= irl; rz *= irl;
-            double Y[K];
-            sh_basis<D>(rx, ry, rz, Y);
-            double r = 0.0, g = 0.0, b = 0.0;
+            float Y[K];
+            sh_basis_f<D>(rx, ry, rz, Y);
+            float r = 0.f, g = 0.f, b = 0.f;
 #pragma unroll
             for (int j = 0; j < K; j++) {
-                r += (double)c[3 * j + 0] * Y[j];
-                g += (double)c[3 * j + 1] * Y[j];
-                b += (double)c[3 * j + 2] * Y[j];
+                r = fmaf(c[3 * j + 0], Y[j], r);
+                g = fmaf(c[3 * j + 1], Y[j], g);
+                b = fmaf(c[3 * j + 2], Y[j], b);
             }
-            out = make_float4((float)fmax(r, 0.0), (float)fmax(g, 0.0), (float)fmax(b, 0.0), 0.f);
+            out = make_float4(fmaxf(r, 0.f), fmaxf(g, 0.f), fmaxf(b, 0.f), 0.f);
         }
         a.lind[(int64_t)v * a.n + k] = out;
     }

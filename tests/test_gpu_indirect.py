@@ -44,11 +44,15 @@ def _eval_gpu(sc, cams, degree):
     return lind.view(V, n, 4).double().cpu().numpy()
 
 
-def _close_f32(got, ref):
-    """float32 rounding of a double-precision result: within 2^-23 relative."""
+def _close_f32(got, ref, sh):
+    """float32 evaluation: the direction to a few ulp, each basis value to about 1e-6, the sum
+    of 16 products rounded at each step, so |got - ref| <= 2e-6 sum_j |c_j| + 1e-7 per
+    channel (sh: the splats' coefficients [n, K, 3])."""
     err = np.abs(got - ref)
-    bound = 2.0 ** -23 * np.abs(ref) + 1e-12
-    assert (err <= bound).all(), float((err / (np.abs(ref) + 1e-30)).max())
+    bound = 2e-6 * np.abs(sh.astype(np.float64)).sum(axis=1) + 1e-7
+    assert (err <= bound).all(), float((err / bound).max())
+    print(f"[indirect eval] max err {err.max():.3e}, max err / bound {(err / bound).max():.3f}",
+          flush=True)
 
 
 @pytest.mark.parametrize("degree", [0, 1, 2, 3])
@@ -58,7 +62,7 @@ def test_indirect_eval_matches_oracle(degree):
     got = _eval_gpu(sc, cams, degree)
     for v, cam in enumerate(cams):
         ref = oracle.indirect_eval(sc, cam, sc["sh"], degree)
-        _close_f32(got[v, :, :3], ref)
+        _close_f32(got[v, :, :3], ref, sc["sh"])
         assert (got[v, :, 3] == 0).all()
     assert (got[..., :3] == 0).any() or degree == 0   # the clamp at zero is reached
 
@@ -74,7 +78,7 @@ def test_indirect_eval_all_orbit_views_sampled_splats():
            for k, v in sc.items()}
     for v in range(0, 64, 3):
         ref = oracle.indirect_eval(sub, cams[v], sub["sh"], 3)
-        _close_f32(got[v, idx, :3], ref)
+        _close_f32(got[v, idx, :3], ref, sub["sh"])
 
 
 def test_indirect_eval_degenerate_splats():
@@ -93,7 +97,7 @@ def test_indirect_eval_degenerate_splats():
     keep = np.ones(64, bool)
     keep[[5, 9]] = False
     ref = oracle.indirect_eval(sc, cam, sc["sh"], 2)
-    _close_f32(got[0, keep, :3], ref[keep])
+    _close_f32(got[0, keep, :3], ref[keep], sc["sh"][keep])
 
 
 # --------------------------------------------------------------------------- frames
