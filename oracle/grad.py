@@ -6,7 +6,8 @@ gives the gradient of any scalar of the rendered RGBA with respect to the splat 
 (unnormalised) quaternions, the linear scales, the opacities and the texels — the quantities
 the paper optimises (Sec. 3.6) — and, on request, to the texels of the environment's shading
 tables (irradiance cube and prefiltered levels taken as learnable, as the environment is
-optimised end to end in Sec. 3.5-3.6).
+optimised end to end in Sec. 3.5-3.6) and to the per-splat spherical-harmonic coefficients of
+the indirect light (Eq. 9, Eq. 12, also learned end to end in Sec. 3.6).
 
 Discrete decisions are taken from values and carry no gradient, exactly as in the forward
 definition: the near-plane drop, the hit in front of the camera, the square support, the alpha
@@ -78,8 +79,51 @@ def _cube_lookup(cube, d):
     return _bilinear(cube.reshape(-1, 3), face * r * r, r, r, X, Y)
 
 
-def _shade(g, A, dirs, tabs, bg):
-    """Split-sum shading (Eq. 10-12) of blended maps g [P,8] with alpha A [P]."""
+def _sh_basis(w, degree):
+    """Real orthonormal spherical harmonics (no Condon-Shortley phase, index l*l + l + m) at
+    unit directions w [M,3] -> [M,(degree+1)^2], differentiable: with z = cos(theta),
+    P_l^m(z) = (1 - z^2)^(m/2) d^m P_l / dz^m (Legendre polynomial derivatives from numpy) and
+    (1 - z^2)^(m/2) (cos, sin)(m phi) = (Re, Im) (x + i y)^m on the unit sphere."""
+    x, y, z = w.unbind(1)
+    K = (degree + 1) ** 2
+    cols = [None] * K
+    re, im = torch.ones_like(x), torch.zeros_like(x)     # (x + i y)^0
+    pw = [(re, im)]
+    for m in range(1, degree + 1):
+        re, im = re * x - im * y, re * y + im * x
+        pw.append((re, im))
+    for l in range(degree + 1):
+        Pl = np.polynomial.legendre.Legendre.basis(l)
+        for m in range(0, l + 1):
+            coef = Pl.deriv(m).convert(kind=np.polynomial.Polynomial).coef
+            pz = torch.zeros_like(z)
+            for i in range(len(coef) - 1, -1, -1):          # Horner in z
+                pz = pz * z + float(coef[i])
+            Klm = math.sqrt((2 * l + 1) / (4 * math.pi) * math.factorial(l - m) /
+                            math.factorial(l + m))
+            if m == 0:
+                cols[l * l + l] = Klm * pz
+            else:
+                cols[l * l + l + m] = math.sqrt(2) * Klm * pz * pw[m][0]
+                cols[l * l + l - m] = math.sqrt(2) * Klm * pz * pw[m][1]
+    return torch.stack(cols, 1)
+
+
+def _indirect(means, quats, sh, degree, o):
+    """Per-splat indirect radiance [N,3]: max(0, sum_j c_j Y_j(w_r)), w_r the mirror reflection
+    of the unit camera-to-centre direction about the splat plane."""
+    n = _quat_rot(quats)[:, :, 2]
+    d = means - o[None]
+    d = d / d.norm(dim=1, keepdim=True)
+    wr = d - 2 * (d * n).sum(1, keepdim=True) * n
+    wr = wr / wr.norm(dim=1, keepdim=True)
+    Y = _sh_basis(wr, degree)
+    return torch.clamp((Y[:, :, None] * sh).sum(1), min=0.0)
+
+
+def _shade(g, A, dirs, tabs, bg, gind=None, vis=None):
+    """Split-sum shading (Eq. 10-12) of blended maps g [P,8] with alpha A [P]; with the
+    indirect term the specular radiance is V L_dir + (1 - V) L_ind (gind [P,3], vis [P])."""
     P = g.shape[0]
     wo = -dirs / dirs.norm(dim=1, keepdim=True)
     N = g[:, 5:8]
@@ -108,6 +152,9 @@ def _shade(g, A, dirs, tabs, bg):
         if m1.any():
             P1 = P1.index_put((m1.nonzero()[:, 0],), _cube_lookup(levels[l], wr[m1]))
     Lp = (1 - fl)[:, None] * P0 + fl[:, None] * P1
+    if gind is not None:
+        V = vis[:, None]
+        Lp = V * Lp + (1 - V) * gind
     lut = torch.as_tensor(tabs["lut"], dtype=DT)
     n = lut.shape[0]
     x = ndv.clamp(0.0, 1.0) * n - 0.5
@@ -122,9 +169,11 @@ def _shade(g, A, dirs, tabs, bg):
 
 
 def render_dense(means, quats, scales, opac, textures, chart_of, cam, pixels, tabs=None,
-                 params=None):
+                 params=None, sh=None, degree=0, vis=None):
     """Differentiable render of pixels [P,2]. Tensors are float64 (leaves may require grad).
-    Returns rgba [P,4] and gbuf [P,8] (albedo 3, metallic, roughness, normal 3)."""
+    Returns rgba [P,4] and gbuf [P,8] (albedo 3, metallic, roughness, normal 3); with sh
+    ([N,(degree+1)^2,3]) the indirect term is on (vis [P] visibility, default 1) and gbuf has
+    the blended L_ind as channels 8..10."""
     p = dict(DEFAULT_PARAMS)
     if params:
         p.update(params)
@@ -194,23 +243,34 @@ def render_dense(means, quats, scales, opac, textures, chart_of, cam, pixels, ta
                       torch.tensor([0.0, 0.0, 1.0], dtype=DT)[None])
     nw = sigma[k][:, None] * torch.einsum("bij,bj->bi", R[k], nth)
     x8 = torch.cat([tx[:, 0:3], tx[:, 7:8], tx[:, 3:4], nw], 1)
+    if sh is not None:
+        x8 = torch.cat([x8, _indirect(means, quats, sh, degree, o)[k]], 1)
     wb = w_o[pi, ki]
-    gbuf = torch.zeros(len(pix), 8, dtype=DT).index_add(0, pi, wb[:, None] * x8)
+    gbuf = torch.zeros(len(pix), x8.shape[1], dtype=DT).index_add(0, pi, wb[:, None] * x8)
     A = 1 - T_final
     if tabs is None:
         rgb = torch.zeros(len(pix), 3, dtype=DT)
-    else:
+    elif sh is None:
         rgb = _shade(gbuf, A, dirs, tabs, bg)
+    else:
+        V = (torch.ones(len(pix), dtype=DT) if vis is None
+             else torch.as_tensor(np.asarray(vis, np.float64)))
+        rgb = _shade(gbuf[:, :8], A, dirs, tabs, bg, gind=gbuf[:, 8:11], vis=V)
     rgba = torch.cat([rgb, A[:, None]], 1)
     return rgba, gbuf
 
 
-def grads(scene, cam, pixels, d_rgba, tabs=None, params=None, env=False):
+def grads(scene, cam, pixels, d_rgba, tabs=None, params=None, env=False, vis=None):
     """Gradients of sum(d_rgba * rgba) w.r.t. means, quats, scales, opac and textures; with
     env=True also w.r.t. the texels of the irradiance cube ("irr", [6,r,r,3]) and of every
-    prefiltered level ("spec", list of [6,r_l,r_l,3]), the tables taken as parameters."""
+    prefiltered level ("spec", list of [6,r_l,r_l,3]), the tables taken as parameters; with
+    scene["sh"] (degree scene["sh_degree"]) the indirect term is on (vis [P] per pixel) and
+    the coefficients get their gradient ("sh")."""
+    names = ["means", "quats", "scales", "opac", "textures"]
+    if scene.get("sh") is not None:
+        names.append("sh")
     leaves = {k: torch.tensor(np.asarray(scene[k], np.float32), dtype=DT, requires_grad=True)
-              for k in ("means", "quats", "scales", "opac", "textures")}
+              for k in names}
     t = tabs
     if env:
         t = dict(tabs)
@@ -218,12 +278,16 @@ def grads(scene, cam, pixels, d_rgba, tabs=None, params=None, env=False):
         t["spec"] = [torch.tensor(np.asarray(l), dtype=DT, requires_grad=True)
                      for l in tabs["spec"]]
     rgba, gbuf = render_dense(leaves["means"], leaves["quats"], leaves["scales"], leaves["opac"],
-                              leaves["textures"], scene["chart_of"], cam, pixels, t, params)
+                              leaves["textures"], scene["chart_of"], cam, pixels, t, params,
+                              sh=leaves.get("sh"), degree=int(scene.get("sh_degree", 0)),
+                              vis=vis)
     loss = (rgba * torch.as_tensor(np.asarray(d_rgba), dtype=DT)).sum()
     loss.backward()
     out = {k: leaves[k].grad.detach().numpy() for k in leaves}
     out["rgba"] = rgba.detach().numpy()
-    out["gbuf"] = gbuf.detach().numpy()
+    out["gbuf"] = gbuf[:, :8].detach().numpy()
+    if gbuf.shape[1] > 8:
+        out["gind"] = gbuf[:, 8:].detach().numpy()
     if env:
         z = lambda x: (x.grad if x.grad is not None else torch.zeros_like(x)).detach().numpy()
         out["irr"] = z(t["irr"])

@@ -156,3 +156,90 @@ def test_irradiance_gradients_partition_of_unity(env_case):
     expect = (d[cov, :3] * gb[cov, 0:3] * (1 - gb[cov, 3:4]) / np.pi).sum(0)
     got = g["irr"].reshape(-1, 3).sum(0)
     np.testing.assert_allclose(got, expect, rtol=1e-10, atol=1e-12)
+
+
+# ------------------------------------------------------------------ indirect term (Eq. 9, 12)
+
+@pytest.fixture(scope="module")
+def ind_case(fd_case):
+    sub, crop, tabs, pix, d = fd_case
+    rng = np.random.default_rng(21)
+    sc = dict(sub)
+    sc["sh"] = synth.indirect_sh(rng, len(sub["opac"]), 3)
+    sc["sh_degree"] = 3
+    vis = synth.visibility(rng, 1, 64, 64)[0].reshape(-1)
+    return sc, crop, tabs, pix, d, vis
+
+
+def test_sh_basis_two_codes():
+    """The differentiable basis of the gradient reference (Legendre-polynomial derivatives
+    and powers of x + iy) equals the C oracle's (associated-Legendre recurrence, atan2)."""
+    rng = np.random.default_rng(0)
+    w = rng.normal(size=(100, 3))
+    w /= np.linalg.norm(w, axis=1, keepdims=True)
+    np.testing.assert_allclose(og._sh_basis(torch.as_tensor(w), 3).numpy(),
+                               oracle.sh_basis(3, w), atol=1e-14)
+
+
+def test_indirect_forward_matches_c_oracle(ind_case):
+    sc, crop, tabs, pix, d, vis = ind_case
+    li = oracle.indirect_eval(sc, crop, sc["sh"], 3)
+    ref = oracle.render(sc, crop, pixels=pix, tabs=tabs, lind=li, vis=vis)
+    g = og.grads(sc, crop, pix, d, tabs, vis=vis)
+    np.testing.assert_allclose(g["rgba"], ref["rgba"], atol=1e-10)
+    np.testing.assert_allclose(g["gind"], ref["gind"], atol=1e-12)
+    assert np.abs(ref["gind"]).max() > 0.1
+
+
+def _loss_ind(sc, crop, pix, d, tabs, vis, name, idx, val):
+    leaves = {k: torch.tensor(np.asarray(sc[k], np.float32), dtype=torch.float64)
+              for k in ("means", "quats", "scales", "opac", "textures", "sh")}
+    leaves[name].view(-1)[idx] = val
+    rgba, _ = og.render_dense(leaves["means"], leaves["quats"], leaves["scales"], leaves["opac"],
+                              leaves["textures"], sc["chart_of"], crop, pix, tabs,
+                              sh=leaves["sh"], degree=3, vis=vis)
+    return float((rgba * torch.as_tensor(d)).sum())
+
+
+def test_sh_gradients_equal_unit_differences(ind_case):
+    """The shaded colour is linear in L_ind, L_ind in each l_ind, and l_ind in each coefficient
+    while the clamp at zero does not switch: a finite step gives the gradient exactly."""
+    sc, crop, tabs, pix, d, vis = ind_case
+    g = og.grads(sc, crop, pix, d, tabs, vis=vis)["sh"].reshape(-1)
+    arr = np.asarray(sc["sh"], np.float64).reshape(-1)
+    rng = np.random.default_rng(3)
+    picks = list(np.argsort(-np.abs(g))[:6]) + list(rng.integers(0, len(arr), 4))
+    base = _loss_ind(sc, crop, pix, d, tabs, vis, "sh", 0, arr[0])
+    for idx in picks:
+        h = 1e-3
+        fd = (_loss_ind(sc, crop, pix, d, tabs, vis, "sh", idx, arr[idx] + h) - base) / h
+        assert abs(fd - g[idx]) <= 1e-7 * max(1.0, abs(g[idx])), (idx, fd, g[idx])
+    assert np.abs(g).max() > 1e-3
+
+
+def test_indirect_gradients_match_central_differences(ind_case):
+    """Centres and rotations move the reflected direction the SH is read at: their gradients
+    (and those of the other parameters) with the indirect term on against central
+    differences, as for the plain render."""
+    sc, crop, tabs, pix, d, vis = ind_case
+    g = og.grads(sc, crop, pix, d, tabs, vis=vis)
+    rng = np.random.default_rng(8)
+    checked, skipped = 0, 0
+    for name in ("means", "quats", "opac", "sh"):
+        arr = np.asarray(sc[name], np.float64).reshape(-1)
+        gg = g[name].reshape(-1)
+        cand = np.argsort(-np.abs(gg))[:40]
+        for idx in list(rng.choice(cand, 5, replace=False)):
+            x0 = arr[idx]
+            h = 1e-6 * max(1.0, abs(x0))
+            f = lambda dx: _loss_ind(sc, crop, pix, d, tabs, vis, name, idx, x0 + dx)
+            d1 = (f(h) - f(-h)) / (2 * h)
+            d2 = (f(h / 2) - f(-h / 2)) / h
+            scale = max(abs(gg[idx]), 1e-3 * np.abs(gg).max(), 1e-8)
+            if abs(d1 - d2) > 1e-4 * scale:
+                skipped += 1
+                continue
+            assert abs(d1 - gg[idx]) <= 2e-5 * scale + 1e-7, (name, idx, d1, gg[idx])
+            checked += 1
+    print(f"checked {checked}, skipped {skipped}")
+    assert checked >= 15 and skipped <= 5, (checked, skipped)
