@@ -279,7 +279,13 @@ int ts_shade(int32_t n_views, int32_t width, int32_t height, const ts_camera* ca
  *   partial_used [1] int64 device word or NULL: floats the frame asked for (also on overflow)
  *   beta     0: overwrite the gradient outputs; 1: add to them
  *   d_means [n,3], d_quats [n,4], d_scales [n,2], d_opac [n], d_atlas [n_charts][T][T][8] out
- * Errors: TS_E_ARG, TS_E_WORKSPACE, TS_E_LAUNCH.
+ *   lind, vis, gbuf_ind   the indirect term of the forward (as given to / written by
+ *            ts_raster_fwd), or NULL for the plain shading; with lind the shading adjoint
+ *            takes the specular radiance V Lspec + (1 - V) L_ind and
+ *   d_lind   [n_views][n][4] out: dL/dl_ind per (view, splat) (rgb, 0), the input of
+ *            ts_indirect_bwd (written, not accumulated)
+ * Errors: TS_E_ARG (also gbuf_ind or d_lind missing with lind, or given without it),
+ *         TS_E_WORKSPACE, TS_E_LAUNCH, TS_E_UNSUPPORTED (atlas variants).
  */
 int ts_raster_bwd(int32_t n_views, int32_t width, int32_t height, const ts_camera* cams,
                   const ts_params* params, int32_t n, const float* means, const float* quats,
@@ -291,7 +297,29 @@ int ts_raster_bwd(int32_t n_views, int32_t width, int32_t height, const ts_camer
                   int64_t partial_capacity, int32_t* status, int64_t* partial_used, float beta,
                   float* d_means,
                   float* d_quats, float* d_scales, float* d_opac, float* d_atlas,
+                  const float* lind, const float* vis, const float* gbuf_ind, float* d_lind,
                   hipStream_t stream);
+
+/*
+ * ts_indirect_bwd — the indirect term's share of the gradients (the SH coefficients are learned
+ * end to end, Sec. 3.6): from dL/dl_ind per (view, splat) (ts_raster_bwd's d_lind) and the
+ * forward's l_ind (a channel clamped at zero passes no gradient), per splat over the views in
+ * order: dL/dc_j = sum_v Y_j(w_r) dL/dl_ind, and through the reflected direction
+ * w_r = normalize(d - 2 (d.n) n), d = normalize(mu - o), n = R(q/|q|) e_z, to the centre and
+ * the (unnormalised) quaternion. float32, one thread per splat, no atomics.
+ *
+ *   cams, means, quats, sh, sh_degree   as given to ts_indirect_eval
+ *   lind     [n_views][n][4] the forward's ts_indirect_eval output
+ *   d_lind   [n_views][n][4] from ts_raster_bwd
+ *   beta     0: overwrite d_sh; 1: add to it
+ *   d_sh     [n][(sh_degree+1)^2][3] out
+ *   d_means [n,3], d_quats [n,4]  ADDED to (call after ts_raster_bwd, which writes them)
+ * Errors: TS_E_ARG, TS_E_LAUNCH.
+ */
+int ts_indirect_bwd(int32_t n_views, const ts_camera* cams, int32_t n, const float* means,
+                    const float* quats, const float* sh, int32_t sh_degree, const float* lind,
+                    const float* d_lind, float beta, float* d_sh, float* d_means, float* d_quats,
+                    hipStream_t stream);
 
 /* Scratch bytes ts_raster_bwd needs (host only). */
 int ts_raster_bwd_workspace(int32_t n_views, int32_t n, int64_t pair_capacity, size_t* bytes);

@@ -55,7 +55,9 @@ _SIGS = {
                       c_void_p, c_int64, c_void_p, ctypes.POINTER(TsEnv), c_void_p, c_void_p,
                       c_void_p, c_void_p, c_void_p, c_size_t, c_void_p, c_int64, c_void_p,
                       c_void_p, c_float, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
-                      c_void_p],
+                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
+    "ts_indirect_bwd": [c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_int32,
+                        c_void_p, c_void_p, c_float, c_void_p, c_void_p, c_void_p, c_void_p],
     "ts_raster_bwd_workspace": [c_int32, c_int32, c_int64, ctypes.POINTER(c_size_t)],
     "ts_env_bwd": [c_int32, c_int32, c_int32, c_void_p, ctypes.POINTER(TsEnv), c_void_p, c_void_p,
                    c_void_p, c_void_p, c_size_t, ctypes.c_float, c_void_p, c_void_p, c_void_p],
@@ -211,7 +213,8 @@ def ts_raster_bwd_workspace(n_views, n, pair_capacity):
 def ts_raster_bwd(n_views, width, height, cams, params, n, means, quats, scales, chart_of, rec,
                   rect, tile_ranges, pair_ids, pair_capacity, atlas, env, gbuf, t_final,
                   n_contrib, d_rgba, ws, partials, status, partial_used, beta, d_means, d_quats,
-                  d_scales, d_opac, d_atlas, stream=None):
+                  d_scales, d_opac, d_atlas, stream=None, lind=None, vis=None, gbuf_ind=None,
+                  d_lind=None):
     _check(lib().ts_raster_bwd(n_views, width, height, ptr(cams), ctypes.byref(params), n,
                                ptr(means), ptr(quats), ptr(scales), ptr(chart_of), ptr(rec),
                                ptr(rect), ptr(tile_ranges), ptr(pair_ids), pair_capacity,
@@ -220,7 +223,16 @@ def ts_raster_bwd(n_views, width, height, cams, params, n, means, quats, scales,
                                ptr(partials), partials.numel(), ptr(status), ptr(partial_used),
                                float(beta),
                                ptr(d_means), ptr(d_quats), ptr(d_scales), ptr(d_opac),
-                               ptr(d_atlas), stream_handle(stream)), "ts_raster_bwd")
+                               ptr(d_atlas), ptr(lind), ptr(vis), ptr(gbuf_ind), ptr(d_lind),
+                               stream_handle(stream)), "ts_raster_bwd")
+
+
+def ts_indirect_bwd(n_views, cams, n, means, quats, sh, sh_degree, lind, d_lind, beta, d_sh,
+                    d_means, d_quats, stream=None):
+    _check(lib().ts_indirect_bwd(n_views, ptr(cams), n, ptr(means), ptr(quats), ptr(sh),
+                                 int(sh_degree), ptr(lind), ptr(d_lind), float(beta), ptr(d_sh),
+                                 ptr(d_means), ptr(d_quats), stream_handle(stream)),
+           "ts_indirect_bwd")
 
 
 def ts_shade(n_views, width, height, cams, params, env, gbuf, t_final, rgba, stream=None,

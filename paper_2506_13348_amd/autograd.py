@@ -1,9 +1,11 @@
-"""torch.autograd.Function over ts_raster_fwd / ts_raster_bwd.
+"""torch.autograd.Function over ts_raster_fwd / ts_raster_bwd (and, with the indirect term,
+ts_indirect_eval / ts_indirect_bwd).
 
 `render_rgba(means, quats, scales, opac, atlas, chart_of, cams, width, height, tables)` renders
-a batch of views and, under autograd, returns gradients for the five splat tensors from the
-hand-written HIP backward (deterministic, no floating-point atomics). Python here allocates
-buffers and enqueues the C entry points; it performs none of the rendering arithmetic."""
+a batch of views and, under autograd, returns gradients for the five splat tensors (and the
+per-splat SH coefficients of the indirect term) from the hand-written HIP backward
+(deterministic, no floating-point atomics). Python here allocates buffers and enqueues the C
+entry points; it performs none of the rendering arithmetic."""
 from __future__ import annotations
 
 from types import SimpleNamespace
@@ -18,11 +20,12 @@ class _SceneView(SimpleNamespace):
     pass
 
 
-def _scene_view(means, quats, scales, opac, atlas, chart_of, tables):
+def _scene_view(means, quats, scales, opac, atlas, chart_of, tables, sh=None, sh_degree=0):
     return _SceneView(device=means.device, n=int(means.shape[0]), tex_res=int(atlas.shape[1]),
                       means=means.contiguous(), quats=quats.contiguous(),
                       scales=scales.contiguous(), opac=opac.contiguous(),
-                      atlas=atlas.contiguous(), chart_of=chart_of.contiguous(), tables=tables)
+                      atlas=atlas.contiguous(), chart_of=chart_of.contiguous(), tables=tables,
+                      sh=None if sh is None else sh.contiguous(), sh_degree=int(sh_degree))
 
 
 class BackwardRunner:
@@ -38,26 +41,41 @@ class BackwardRunner:
         self.partials = torch.empty(int(partial_floats), device=dev, dtype=torch.float32)
         self.status = torch.zeros(1, device=dev, dtype=torch.int32)
         self.used = torch.zeros(1, device=dev, dtype=torch.int64)
+        # the indirect term: dL/dl_ind per (view, splat), then the SH coefficients
+        self.indirect = getattr(plan, "indirect", False)
+        if self.indirect and plan.gbuf_ind is None:
+            raise ValueError("the indirect backward needs the plan's L_ind map (gbuf=True)")
+        self.d_lind = (torch.empty(plan.V * max(plan.scene.n, 1) * 4, device=dev,
+                                   dtype=torch.float32) if self.indirect else None)
 
     def run(self, d_rgba, grads, beta=0.0, retry=True):
+        """grads = (d_means, d_quats, d_scales, d_opac, d_atlas[, d_sh]); d_sh (the SH
+        coefficients' gradient) only for a plan with the indirect term."""
         p, sc = self.plan, self.plan.scene
-        d_means, d_quats, d_scales, d_opac, d_atlas = grads
+        d_means, d_quats, d_scales, d_opac, d_atlas = grads[:5]
+        d_sh = grads[5] if len(grads) > 5 else None
+        ind = dict(lind=p.lind, vis=p.vis, gbuf_ind=p.gbuf_ind, d_lind=self.d_lind) \
+            if self.indirect else {}
         for attempt in range(2):
             self.status.zero_()
             F.ts_raster_bwd(p.V, p.W, p.H, p.cams, p.params, sc.n, sc.means, sc.quats, sc.scales,
                             sc.chart_of, p.rec, p.rect, p.tile_ranges, p.pair_ids, p.cap,
                             sc.atlas, sc.tables.struct, p.gbuf, p.t_final, p.n_contrib,
                             d_rgba.contiguous(), self.ws, self.partials, self.status, self.used,
-                            beta, d_means, d_quats, d_scales, d_opac, d_atlas, p.stream)
+                            beta, d_means, d_quats, d_scales, d_opac, d_atlas, p.stream, **ind)
             if not retry:
-                return
+                break
             if int(self.status.item()) == 0:
-                return
+                break
             # the counter reports what the frame needed: size to it and run again
             need = int(self.used.item())
             self.partials = torch.empty(need + need // 16 + 4096, device=self.partials.device,
                                         dtype=torch.float32)
-        raise RuntimeError("ts_raster_bwd: partial buffer overflow after resizing")
+        else:
+            raise RuntimeError("ts_raster_bwd: partial buffer overflow after resizing")
+        if self.indirect and d_sh is not None:
+            F.ts_indirect_bwd(p.V, p.cams, sc.n, sc.means, sc.quats, sc.sh, sc.sh_degree, p.lind,
+                              self.d_lind, beta, d_sh, d_means, d_quats, p.stream)
 
 
 class EnvBackward:
@@ -85,10 +103,12 @@ class EnvBackward:
 class TexSplatRender(torch.autograd.Function):
     @staticmethod
     def forward(ctx, means, quats, scales, opac, atlas, chart_of, cams, width, height, tables,
-                params):
+                params, sh, sh_degree, vis):
         sv = _scene_view(means.detach(), quats.detach(), scales.detach(), opac.detach(),
-                         atlas.detach(), chart_of, tables)
-        plan = RenderPlan(sv, cams, width, height, params, shade=True, gbuf=True, aux=True)
+                         atlas.detach(), chart_of, tables,
+                         None if sh is None else sh.detach(), sh_degree)
+        plan = RenderPlan(sv, cams, width, height, params, shade=True, gbuf=True, aux=True,
+                          vis=vis)
         plan.run()
         plan.check()
         ctx.plan = plan
@@ -101,12 +121,17 @@ class TexSplatRender(torch.autograd.Function):
         grads = (torch.empty_like(sc.means), torch.empty_like(sc.quats),
                  torch.empty_like(sc.scales), torch.empty_like(sc.opac),
                  torch.empty_like(sc.atlas))
+        if plan.indirect:
+            grads = grads + (torch.empty_like(sc.sh),)
         BackwardRunner(plan).run(d_rgba.contiguous(), grads)
-        return (*grads, None, None, None, None, None, None)
+        d_sh = grads[5] if plan.indirect else None
+        return (*grads[:5], None, None, None, None, None, None, d_sh, None, None)
 
 
 def render_rgba(means, quats, scales, opac, atlas, chart_of, cams, width, height, tables,
-                params=None):
-    """[V,H,W,4] shaded RGBA + alpha, differentiable w.r.t. the first five tensors."""
+                params=None, sh=None, sh_degree=0, vis=None):
+    """[V,H,W,4] shaded RGBA + alpha, differentiable w.r.t. the first five tensors and, with
+    the indirect term (sh [n,(sh_degree+1)^2,3] per-splat SH coefficients, vis [V,H,W] optional
+    visibility), w.r.t. sh as well."""
     return TexSplatRender.apply(means, quats, scales, opac, atlas, chart_of, cams, width, height,
-                                tables, params)
+                                tables, params, sh, sh_degree, vis)

@@ -113,9 +113,169 @@ __global__ __launch_bounds__(256) void k_indirect_eval(IndArgs a) {
     }
 }
 
+// dL/dw at the unit vector w = (x, y, z) of L = sum_j dY[j] Y_j(w), from the Cartesian
+// gradients of the basis polynomials (the normalisation of w projects out the radial part).
+template <int D>
+__device__ inline void sh_basis_grad_f(float x, float y, float z, const float* dY, float* dw) {
+    dw[0] = 0.f; dw[1] = 0.f; dw[2] = 0.f;
+    if (D < 1) return;
+    const float c1 = 0.48860251190291992f;
+    dw[1] += c1 * dY[1];
+    dw[2] += c1 * dY[2];
+    dw[0] += c1 * dY[3];
+    if (D < 2) return;
+    const float a2 = 1.0925484305920792f, b2 = 0.31539156525252005f, e2 = 0.54627421529603959f;
+    dw[0] += a2 * (y * dY[4] + z * dY[7]) + 2.f * e2 * x * dY[8];
+    dw[1] += a2 * (x * dY[4] + z * dY[5]) - 2.f * e2 * y * dY[8];
+    dw[2] += a2 * (y * dY[5] + x * dY[7]) + 6.f * b2 * z * dY[6];
+    if (D < 3) return;
+    const float e3 = 0.59004358992664352f, f3 = 2.8906114426405538f;
+    const float g3 = 0.45704579946446572f, h3 = 0.37317633259011540f, k3 = 1.4453057213202769f;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    dw[0] += 6.f * e3 * x * y * dY[9] + f3 * y * z * dY[10] + g3 * (5.f * zz - 1.f) * dY[13] +
+             2.f * k3 * x * z * dY[14] + e3 * (3.f * xx - 3.f * yy) * dY[15];
+    dw[1] += e3 * (3.f * xx - 3.f * yy) * dY[9] + f3 * x * z * dY[10] +
+             g3 * (5.f * zz - 1.f) * dY[11] - 2.f * k3 * y * z * dY[14] - 6.f * e3 * x * y * dY[15];
+    dw[2] += f3 * x * y * dY[10] + 10.f * g3 * y * z * dY[11] + h3 * (15.f * zz - 3.f) * dY[12] +
+             10.f * g3 * x * z * dY[13] + k3 * (xx - yy) * dY[14];
+}
+
+struct IndBwdArgs {
+    int V, n;
+    const ts_camera* cams;
+    const float* means;
+    const float* quats;
+    const float* sh;
+    const float4* lind;
+    const float4* d_lind;
+    float beta;
+    float* d_sh;
+    float* d_means;
+    float* d_quats;
+};
+
+// One thread per splat, views in order: coefficient gradients Y_j(w_r) dL/dl_ind, and the
+// chain through w_r = normalize(d - 2 (d.n) n), d = normalize(mu - o), n = R(q/|q|) e_z.
+template <int D>
+__global__ __launch_bounds__(256) void k_indirect_bwd(IndBwdArgs a) {
+    constexpr int K = (D + 1) * (D + 1);
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n) return;
+    float c[K * 3], ds[K * 3];
+#pragma unroll
+    for (int j = 0; j < K * 3; j++) {
+        c[j] = a.sh[(int64_t)k * K * 3 + j];
+        ds[j] = 0.f;
+    }
+    float q0 = a.quats[4 * k + 0], q1 = a.quats[4 * k + 1], q2 = a.quats[4 * k + 2],
+          q3 = a.quats[4 * k + 3];
+    float qq = q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3;
+    float qn = sqrtf(qq), iq = qq > 0.f ? 1.f / qn : 0.f;
+    float w_ = q0 * iq, x_ = q1 * iq, y_ = q2 * iq, z_ = q3 * iq;    // unit quaternion
+    float nx = 2.f * (x_ * z_ + w_ * y_), ny = 2.f * (y_ * z_ - w_ * x_),
+          nz = 1.f - 2.f * (x_ * x_ + y_ * y_);
+    const float mx = a.means[3 * k + 0], my = a.means[3 * k + 1], mz = a.means[3 * k + 2];
+    float dmu[3] = {0.f, 0.f, 0.f}, dnv[3] = {0.f, 0.f, 0.f};
+    for (int v = 0; v < a.V && qq > 0.f; v++) {
+        const float4 lv = a.lind[(int64_t)v * a.n + k];
+        const float4 gv = a.d_lind[(int64_t)v * a.n + k];
+        // a channel clamped at zero passes no gradient
+        const float g[3] = {lv.x > 0.f ? gv.x : 0.f, lv.y > 0.f ? gv.y : 0.f,
+                            lv.z > 0.f ? gv.z : 0.f};
+        if (g[0] == 0.f && g[1] == 0.f && g[2] == 0.f) continue;
+        const float* cw = a.cams[v].w2c;
+        float ox = -(cw[0] * cw[3] + cw[4] * cw[7] + cw[8] * cw[11]);
+        float oy = -(cw[1] * cw[3] + cw[5] * cw[7] + cw[9] * cw[11]);
+        float oz = -(cw[2] * cw[3] + cw[6] * cw[7] + cw[10] * cw[11]);
+        float dx = mx - ox, dy = my - oy, dz = mz - oz;
+        float dd = dx * dx + dy * dy + dz * dz;
+        if (!(dd > 0.f)) continue;
+        float idl = rsqrtf(dd);
+        dx *= idl; dy *= idl; dz *= idl;
+        float dn = dx * nx + dy * ny + dz * nz;
+        float ux = dx - 2.f * dn * nx, uy = dy - 2.f * dn * ny, uz = dz - 2.f * dn * nz;
+        float irl = rsqrtf(ux * ux + uy * uy + uz * uz);
+        float rx = ux * irl, ry = uy * irl, rz = uz * irl;
+        float Y[K], dY[K];
+        sh_basis_f<D>(rx, ry, rz, Y);
+#pragma unroll
+        for (int j = 0; j < K; j++) {
+            ds[3 * j + 0] = fmaf(Y[j], g[0], ds[3 * j + 0]);
+            ds[3 * j + 1] = fmaf(Y[j], g[1], ds[3 * j + 1]);
+            ds[3 * j + 2] = fmaf(Y[j], g[2], ds[3 * j + 2]);
+            dY[j] = c[3 * j] * g[0] + c[3 * j + 1] * g[1] + c[3 * j + 2] * g[2];
+        }
+        float dw[3];
+        sh_basis_grad_f<D>(rx, ry, rz, dY, dw);
+        // w = u / |u|
+        float wd = rx * dw[0] + ry * dw[1] + rz * dw[2];
+        float du[3] = {(dw[0] - rx * wd) * irl, (dw[1] - ry * wd) * irl, (dw[2] - rz * wd) * irl};
+        // u = d - 2 (d.n) n
+        float ndu = nx * du[0] + ny * du[1] + nz * du[2];
+        float ddv[3] = {du[0] - 2.f * ndu * nx, du[1] - 2.f * ndu * ny, du[2] - 2.f * ndu * nz};
+        dnv[0] -= 2.f * (dn * du[0] + dx * ndu);
+        dnv[1] -= 2.f * (dn * du[1] + dy * ndu);
+        dnv[2] -= 2.f * (dn * du[2] + dz * ndu);
+        // d = (mu - o) / |mu - o|
+        float dpd = dx * ddv[0] + dy * ddv[1] + dz * ddv[2];
+        dmu[0] += (ddv[0] - dx * dpd) * idl;
+        dmu[1] += (ddv[1] - dy * dpd) * idl;
+        dmu[2] += (ddv[2] - dz * dpd) * idl;
+    }
+    float* out = a.d_sh + (int64_t)k * K * 3;
+#pragma unroll
+    for (int j = 0; j < K * 3; j++) out[j] = a.beta != 0.f ? ds[j] + a.beta * out[j] : ds[j];
+    a.d_means[3 * k + 0] += dmu[0];
+    a.d_means[3 * k + 1] += dmu[1];
+    a.d_means[3 * k + 2] += dmu[2];
+    // n = (2(xz + wy), 2(yz - wx), 1 - 2(x^2 + y^2)) of the unit quaternion, then q / |q|
+    float gw = 2.f * (y_ * dnv[0] - x_ * dnv[1]);
+    float gx = 2.f * (z_ * dnv[0] - w_ * dnv[1]) - 4.f * x_ * dnv[2];
+    float gy = 2.f * (w_ * dnv[0] + z_ * dnv[1]) - 4.f * y_ * dnv[2];
+    float gz = 2.f * (x_ * dnv[0] + y_ * dnv[1]);
+    float pq = w_ * gw + x_ * gx + y_ * gy + z_ * gz;
+    a.d_quats[4 * k + 0] += (gw - w_ * pq) * iq;
+    a.d_quats[4 * k + 1] += (gx - x_ * pq) * iq;
+    a.d_quats[4 * k + 2] += (gy - y_ * pq) * iq;
+    a.d_quats[4 * k + 3] += (gz - z_ * pq) * iq;
+}
+
 }  // namespace ts
 
 using namespace ts;
+
+extern "C" int ts_indirect_bwd(int32_t n_views, const ts_camera* cams, int32_t n,
+                               const float* means, const float* quats, const float* sh,
+                               int32_t sh_degree, const float* lind, const float* d_lind,
+                               float beta, float* d_sh, float* d_means, float* d_quats,
+                               hipStream_t stream) {
+    if (n_views < 1 || n < 0 || !cams || sh_degree < 0 || sh_degree > 3) {
+        set_error("ts_indirect_bwd: bad argument (views=%d n=%d degree=%d)", n_views, n,
+                  sh_degree);
+        return TS_E_ARG;
+    }
+    if (n == 0) return TS_OK;
+    if (!means || !quats || !sh || !lind || !d_lind || !d_sh || !d_means || !d_quats) {
+        set_error("ts_indirect_bwd: null array");
+        return TS_E_ARG;
+    }
+    if ((int64_t)n_views * n > 0x7FFFFFFFLL) {
+        set_error("ts_indirect_bwd: n_views * n above 2^31-1");
+        return TS_E_ARG;
+    }
+    IndBwdArgs a;
+    a.V = n_views; a.n = n; a.cams = cams; a.means = means; a.quats = quats; a.sh = sh;
+    a.lind = (const float4*)lind; a.d_lind = (const float4*)d_lind; a.beta = beta;
+    a.d_sh = d_sh; a.d_means = d_means; a.d_quats = d_quats;
+    dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    switch (sh_degree) {
+        case 0: hipLaunchKernelGGL(k_indirect_bwd<0>, grid, block, 0, stream, a); break;
+        case 1: hipLaunchKernelGGL(k_indirect_bwd<1>, grid, block, 0, stream, a); break;
+        case 2: hipLaunchKernelGGL(k_indirect_bwd<2>, grid, block, 0, stream, a); break;
+        default: hipLaunchKernelGGL(k_indirect_bwd<3>, grid, block, 0, stream, a); break;
+    }
+    return launch_check("ts_indirect_bwd");
+}
 
 extern "C" int ts_indirect_eval(int32_t n_views, const ts_camera* cams, int32_t n,
                                 const float* means, const float* quats, const float* sh,

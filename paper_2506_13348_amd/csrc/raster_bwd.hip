@@ -16,9 +16,11 @@
 //    of texels it touched — into the partial buffer and records where in the pair's
 //    splat-major slot row. No value is accumulated with
 //    atomics; a wave takes buffer space in chunks of kChunk floats with one integer atomic.
+//    With the indirect term (Eq. 9, Eq. 12) the shading adjoint also gives dL/dL_ind, each
+//    blended splat's l_ind joins g . x_i, and its partial carries 3 more sums, w dL/dL_ind.
 // 3. k_bwd_gather: per splat, the partials of its (view, tile, quadrant) entries summed in a
 //    fixed order (its slot rows are contiguous) -> per-view record gradients and the splat's
-//    texel gradients.
+//    texel gradients (and, with the indirect term, dL/dl_ind per view and splat).
 // 4. k_bwd_params: per splat, in double precision, the record gradients of every view chained
 //    through the projection set-up to the splat parameters.
 #include "eval.h"
@@ -29,6 +31,10 @@ namespace ts {
 
 constexpr int kGeo = 19;          // px py ux uy vx vy wx wy w0 opacity sR[9]
 constexpr int kHdr = 24;          // floats in a partial's header: 19 geometric + window i0 j0 wi wj + pad
+// with the indirect term: 19 geometric + 3 of dL/dl_ind, window, pad to a multiple of 8 floats
+// (partials start at multiples of 8 floats)
+template <bool kInd> constexpr int geo_n() { return kInd ? kGeo + 3 : kGeo; }
+template <bool kInd> constexpr int hdr_n() { return kInd ? 32 : kHdr; }
 constexpr int kBwdBatch = 128;
 constexpr int kEnt = 16;          // LDS floats per lane entry: taps (4 ints), fx, fy, q[8], pad 2
 constexpr int kChunk = 2048;      // floats of the partial buffer a wave takes at a time
@@ -55,12 +61,20 @@ struct BwdArgs {
     int64_t part_cap;        // floats
     unsigned long long* part_top;
     int32_t* status;
+    const float4* lind;      // [V][n] per (view, splat) l_ind (indirect term) or null
+    const float* gind;       // [V][3][H][W] the forward's blended L_ind
+    const float* vis;        // [V][H][W] visibility or null (V = 1)
 };
 
 // 4 waves per SIMD (at most 128 VGPRs): enough resident waves to cover the texel and
-// record loads measured faster than 3 waves with more registers
-__global__ __launch_bounds__(256, 4) void k_raster_bwd(BwdArgs a) {
+// record loads measured faster than 3 waves with more registers; the indirect variant (three
+// more sums and the L_ind channel) at 3 waves, without spills
+template <bool kInd>
+__global__ __launch_bounds__(256, kInd ? 3 : 4) void k_raster_bwd(BwdArgs a) {
+    constexpr int kGeoN = geo_n<kInd>();
+    constexpr int kHdrN = hdr_n<kInd>();
     __shared__ float4 srec[kBwdBatch * kRec4];
+    __shared__ float4 slind[kInd ? kBwdBatch : 1];
     __shared__ float ent[4][kWave * kEnt];
     __shared__ int smax[4];
     __shared__ uint32_t smask[kBwdBatch];
@@ -88,6 +102,7 @@ __global__ __launch_bounds__(256, 4) void k_raster_bwd(BwdArgs a) {
     int64_t pix = ((int64_t)v * a.H + (inside ? y : 0)) * a.W + (inside ? x : 0);
     int64_t plane = (int64_t)a.H * a.W;
     float gx[8];
+    float gli[3] = {0.f, 0.f, 0.f};   // dL/dL_ind (indirect term)
     float Tf = 1.f, dLdTf = 0.f;
     int my_last = 0;
     if (inside) {
@@ -99,7 +114,17 @@ __global__ __launch_bounds__(256, 4) void k_raster_bwd(BwdArgs a) {
         my_last = a.n_contrib[pix];
         float4 dC = a.d_rgba[pix];
         float3 dray = pixel_ray(a.cams[v], X, Y);
-        float dT = shade_pixel_bwd(a.env, a.sc, gb, Tf, dray, make_float3(dC.x, dC.y, dC.z), gx);
+        float dT;
+        if (kInd) {
+            float li[3];
+            const float* gi = a.gind + (int64_t)v * 3 * plane + (int64_t)y * a.W + x;
+            li[0] = gi[0]; li[1] = gi[plane]; li[2] = gi[2 * plane];
+            float vis = a.vis ? a.vis[pix] : 1.0f;
+            dT = shade_pixel_bwd<true>(a.env, a.sc, gb, Tf, dray, make_float3(dC.x, dC.y, dC.z),
+                                       gx, li, vis, gli);
+        } else {
+            dT = shade_pixel_bwd(a.env, a.sc, gb, Tf, dray, make_float3(dC.x, dC.y, dC.z), gx);
+        }
         dLdTf = dT - dC.w;   // A = 1 - T_final
     } else {
 #pragma unroll
@@ -134,6 +159,7 @@ __global__ __launch_bounds__(256, 4) void k_raster_bwd(BwdArgs a) {
             srec[tid * kRec4 + 3] = r3;
 #pragma unroll
             for (int q = 4; q < kRec4; q++) srec[tid * kRec4 + q] = src[q];
+            if (kInd) slind[tid] = a.lind[(int64_t)v * a.n + id];
             qmask = quad_mask_uv(r0, r1, r2, r3, tx * kTile, ty * kTile, a.S, a.amin);
         }
         if (tid < kBwdBatch) smask[tid] = qmask;
@@ -153,10 +179,10 @@ __global__ __launch_bounds__(256, 4) void k_raster_bwd(BwdArgs a) {
             bool bl = inside && pos < my_last && ev.hit;
             uint64_t blm = __ballot(bl);
             if (blm == 0) continue;
-            float geo[kGeo];
+            float geo[kGeoN];
             int i0 = 0x7fffffff, i1 = -1, j0 = 0x7fffffff, j1 = -1;   // texel taps (blended)
 #pragma unroll
-            for (int k = 0; k < kGeo; k++) geo[k] = 0.f;
+            for (int k = 0; k < kGeoN; k++) geo[k] = 0.f;
             if (bl) {
                 float4 c1 = r[1], c2 = r[2], c3 = r[3], c4 = r[4], c5 = r[5], c6 = r[6];
                 int chart = __builtin_amdgcn_readfirstlane(__float_as_int(c6.y));
@@ -209,6 +235,10 @@ __global__ __launch_bounds__(256, 4) void k_raster_bwd(BwdArgs a) {
                 float wgt = alpha * Tb;
                 float cdot = gx[0] * tv[0] + gx[1] * tv[1] + gx[2] * tv[2] + gx[3] * tv[7] +
                              gx[4] * tv[3] + gx[5] * nw[0] + gx[6] * nw[1] + gx[7] * nw[2];
+                if (kInd) {
+                    float4 l4 = slind[j];
+                    cdot += gli[0] * l4.x + gli[1] * l4.y + gli[2] * l4.z;
+                }
                 float dalpha = Tb * cdot - (accum + dLdTf * Tf) * r1m;
                 accum = fmaf(wgt, cdot, accum);
                 Tr = Tb;
@@ -258,6 +288,11 @@ __global__ __launch_bounds__(256, 4) void k_raster_bwd(BwdArgs a) {
                 geo[0] = -(gu * c1.z + gv * c2.y) * inv - e * c3.x;   // px
                 geo[1] = -(gu * c1.w + gv * c2.z) * inv - e * c3.y;   // py
                 geo[9] = go;                            // opacity
+                if (kInd) {                             // dL/dl_ind of this splat
+                    geo[kGeo + 0] = wgt * gli[0];
+                    geo[kGeo + 1] = wgt * gli[1];
+                    geo[kGeo + 2] = wgt * gli[2];
+                }
                 // lane entry
                 float* me = E + lane * kEnt;
                 me[0] = __int_as_float(i0); me[1] = __int_as_float(i1);
@@ -270,7 +305,7 @@ __global__ __launch_bounds__(256, 4) void k_raster_bwd(BwdArgs a) {
             int wi0 = wave_min_dpp(i0), wj0 = wave_min_dpp(j0);
             int wi1 = wave_max_dpp(i1), wj1 = wave_max_dpp(j1);
             int wi = wi1 - wi0 + 1, wj = wj1 - wj0 + 1, wt = wi * wj;
-            int64_t need = kHdr + (int64_t)wt * 8;
+            int64_t need = kHdrN + (int64_t)wt * 8;
             // space from this wave's current chunk; a new chunk (one integer atomic) when
             // it is used up
             if (ccur + (unsigned long long)need > cend) {
@@ -299,16 +334,16 @@ __global__ __launch_bounds__(256, 4) void k_raster_bwd(BwdArgs a) {
             {
                 float xs[32];
 #pragma unroll
-                for (int k = 0; k < 32; k++) xs[k] = k < kGeo ? geo[k] : 0.f;
+                for (int k = 0; k < 32; k++) xs[k] = k < kGeoN ? geo[k] : 0.f;
                 float tot = wave_transpose_sum32(xs, lane);
                 int vi = bitrev5(lane & 31);
-                if (lane < 32 && vi < kGeo) dst[vi] = tot;
+                if (lane < 32 && vi < kGeoN) dst[vi] = tot;
                 if (lane == kWave - 1) {
-                    dst[kGeo + 0] = __int_as_float(wi0);
-                    dst[kGeo + 1] = __int_as_float(wj0);
-                    dst[kGeo + 2] = __int_as_float(wi);
-                    dst[kGeo + 3] = __int_as_float(wj);
-                    dst[kGeo + 4] = 0.f;
+                    dst[kGeoN + 0] = __int_as_float(wi0);
+                    dst[kGeoN + 1] = __int_as_float(wj0);
+                    dst[kGeoN + 2] = __int_as_float(wi);
+                    dst[kGeoN + 3] = __int_as_float(wj);
+                    dst[kGeoN + 4] = 0.f;
                 }
             }
             // texel window: lanes form groups of L = pow2 >= wt lanes (texel = lane mod L);
@@ -339,7 +374,7 @@ __global__ __launch_bounds__(256, 4) void k_raster_bwd(BwdArgs a) {
                     for (int c = 0; c < 8; c++) acc[c] += __shfl_xor(acc[c], sft);
                 }
                 if (grp == 0 && tt < wt) {
-                    float4* d4 = (float4*)(dst + kHdr + (int64_t)tt * 8);
+                    float4* d4 = (float4*)(dst + kHdrN + (int64_t)tt * 8);
                     d4[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
                     d4[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
                 }
@@ -442,6 +477,7 @@ __global__ void k_copy_u64(const unsigned long long* src, int64_t* dst) { *dst =
 // of 64 texels. The entries are taken 64 at a time: lane e looks up entry e's slot and window
 // (so those dependent loads overlap), then the entries are summed one after another in order,
 // their slot and window read from the owning lane.
+template <bool kInd>
 __global__ __launch_bounds__(64) void k_bwd_gather(int V, int n, int T, const int4* __restrict__ rect,
                                                    const int64_t* __restrict__ start,
                                                    int64_t cap,
@@ -450,7 +486,10 @@ __global__ __launch_bounds__(64) void k_bwd_gather(int V, int n, int T, const in
                                                    const int32_t* __restrict__ chart_of,
                                                    const int32_t* __restrict__ status,
                                                    float beta, float* __restrict__ rec_grad,
-                                                   float* __restrict__ d_atlas) {
+                                                   float* __restrict__ d_atlas,
+                                                   float* __restrict__ d_lind) {
+    constexpr int kGeoN = geo_n<kInd>();
+    constexpr int kHdrN = hdr_n<kInd>();
     if (status[0] != 0) return;   // incomplete partials: leave the outputs untouched
     int s = blockIdx.x, lane = threadIdx.x;
     int TT = T * T;
@@ -465,6 +504,8 @@ __global__ __launch_bounds__(64) void k_bwd_gather(int V, int n, int T, const in
             int cnt = max(r.z - r.x, 0) * max(r.w - r.y, 0);
             if (cnt == 0) {
                 if (t0 == 0 && lane < kGeo) rec_grad[((int64_t)v * n + s) * kGeo + lane] = 0.f;
+                if (kInd && t0 == 0 && lane >= kGeo && lane < kGeo + 4)
+                    d_lind[((int64_t)v * n + s) * 4 + lane - kGeo] = 0.f;
                 continue;
             }
             int64_t st = start[(int64_t)v * n + s];
@@ -477,7 +518,7 @@ __global__ __launch_bounds__(64) void k_bwd_gather(int V, int n, int T, const in
                 if (e < ne && st + (e >> 2) < cap) {
                     sl = slots[(st + (e >> 2)) * 4 + (e & 3)];
                     if (sl >= 0) {
-                        const float* h = part + (int64_t)sl * 8 + kGeo;
+                        const float* h = part + (int64_t)sl * 8 + kGeoN;
                         win = __float_as_int(h[0]) | (__float_as_int(h[1]) << 8) |
                               (__float_as_int(h[2]) << 16) | (__float_as_int(h[3]) << 24);
                     }
@@ -510,13 +551,13 @@ __global__ __launch_bounds__(64) void k_bwd_gather(int V, int n, int T, const in
                             int slj = __builtin_amdgcn_readlane(sl, js[u]);
                             int wj = __builtin_amdgcn_readlane(win, js[u]);
                             const float* src = part + (int64_t)slj * 8;
-                            if (t0 == 0 && lane < kGeo) g[u] = src[lane];
+                            if (t0 == 0 && lane < kGeoN) g[u] = src[lane];
                             int li = ti - (wj & 255), lj = tj - ((wj >> 8) & 255);
                             int wi = (wj >> 16) & 255, wh = (wj >> 24) & 255;
                             in[u] = own && li >= 0 && lj >= 0 && li < wi && lj < wh;
                             if (in[u]) {
                                 const float4* s4 =
-                                    (const float4*)(src + kHdr + (int64_t)(lj * wi + li) * 8);
+                                    (const float4*)(src + kHdrN + (int64_t)(lj * wi + li) * 8);
                                 lo[u] = s4[0];
                                 hi[u] = s4[1];
                             }
@@ -524,7 +565,7 @@ __global__ __launch_bounds__(64) void k_bwd_gather(int V, int n, int T, const in
                     }
 #pragma unroll
                     for (int u = 0; u < 4; u++) {
-                        if (u < nj && t0 == 0 && lane < kGeo) gs += g[u];
+                        if (u < nj && t0 == 0 && lane < kGeoN) gs += g[u];
                         if (in[u]) {
                             acc[0] += lo[u].x; acc[1] += lo[u].y; acc[2] += lo[u].z; acc[3] += lo[u].w;
                             acc[4] += hi[u].x; acc[5] += hi[u].y; acc[6] += hi[u].z; acc[7] += hi[u].w;
@@ -533,6 +574,8 @@ __global__ __launch_bounds__(64) void k_bwd_gather(int V, int n, int T, const in
                 }
             }
             if (t0 == 0 && lane < kGeo) rec_grad[((int64_t)v * n + s) * kGeo + lane] = gs;
+            if (kInd && t0 == 0 && lane >= kGeo && lane < kGeo + 4)
+                d_lind[((int64_t)v * n + s) * 4 + lane - kGeo] = gs;   // lane kGeo + 3: 0
         }
         if (own) {
             float4 lo = make_float4(acc[0], acc[1], acc[2], acc[3]);
@@ -706,7 +749,9 @@ extern "C" int ts_raster_bwd(int32_t n_views, int32_t width, int32_t height, con
                              const int32_t* n_contrib, const float* d_rgba, void* ws,
                              size_t ws_bytes, float* partials, int64_t partial_capacity,
                              int32_t* status, int64_t* partial_used, float beta, float* d_means, float* d_quats,
-                             float* d_scales, float* d_opac, float* d_atlas, hipStream_t stream) {
+                             float* d_scales, float* d_opac, float* d_atlas, const float* lind,
+                             const float* vis, const float* gbuf_ind, float* d_lind,
+                             hipStream_t stream) {
     if (n_views < 1 || width < 1 || height < 1 || n < 0 || !params || !cams || !env ||
         !tile_ranges || !gbuf || !t_final || !n_contrib || !d_rgba || !status ||
         (n > 0 && (!means || !quats || !scales || !chart_of || !rec || !rect || !pair_ids ||
@@ -729,6 +774,14 @@ extern "C" int ts_raster_bwd(int32_t n_views, int32_t width, int32_t height, con
         set_error("ts_raster_bwd: the atlas variants (two-component normals, chart tables) are "
                   "rendered forward only");
         return TS_E_UNSUPPORTED;
+    }
+    if (lind && (!gbuf_ind || !d_lind)) {
+        set_error("ts_raster_bwd: the indirect term needs gbuf_ind and d_lind");
+        return TS_E_ARG;
+    }
+    if (!lind && (vis || gbuf_ind || d_lind)) {
+        set_error("ts_raster_bwd: vis, gbuf_ind and d_lind need lind (the indirect term)");
+        return TS_E_ARG;
     }
     if (partial_capacity < 0 || partial_capacity > (int64_t)INT32_MAX * 8) {
         set_error("ts_raster_bwd: partial_capacity %lld outside 0..2^34 floats",
@@ -776,11 +829,20 @@ extern "C" int ts_raster_bwd(int32_t n_views, int32_t width, int32_t height, con
     a.n_contrib = n_contrib; a.d_rgba = (const float4*)d_rgba; a.slots = slots;
     a.rect = (const int4*)rect; a.start = (const int64_t*)start;
     a.part = partials; a.part_cap = partial_capacity; a.part_top = top; a.status = status;
-    hipLaunchKernelGGL(k_raster_bwd, dim3(n_views * n_tiles), dim3(256), 0, stream, a);
-    hipLaunchKernelGGL(k_bwd_gather, dim3(n), dim3(64), 0, stream, n_views, n, params->tex_res,
-                       (const int4*)rect, (const int64_t*)start, pair_capacity,
-                       (const int32_t*)slots, (const float*)partials, chart_of,
-                       (const int32_t*)status, beta, rec_grad, d_atlas);
+    a.lind = (const float4*)lind; a.gind = gbuf_ind; a.vis = vis;
+    if (lind) {
+        hipLaunchKernelGGL(k_raster_bwd<true>, dim3(n_views * n_tiles), dim3(256), 0, stream, a);
+        hipLaunchKernelGGL(k_bwd_gather<true>, dim3(n), dim3(64), 0, stream, n_views, n,
+                           params->tex_res, (const int4*)rect, (const int64_t*)start,
+                           pair_capacity, (const int32_t*)slots, (const float*)partials, chart_of,
+                           (const int32_t*)status, beta, rec_grad, d_atlas, d_lind);
+    } else {
+        hipLaunchKernelGGL(k_raster_bwd<false>, dim3(n_views * n_tiles), dim3(256), 0, stream, a);
+        hipLaunchKernelGGL(k_bwd_gather<false>, dim3(n), dim3(64), 0, stream, n_views, n,
+                           params->tex_res, (const int4*)rect, (const int64_t*)start,
+                           pair_capacity, (const int32_t*)slots, (const float*)partials, chart_of,
+                           (const int32_t*)status, beta, rec_grad, d_atlas, (float*)nullptr);
+    }
     hipLaunchKernelGGL(k_bwd_params, dim3((n + 255) / 256), dim3(256), 0, stream, n_views, n, cams,
                        means, quats, scales, (const int4*)rect, (const float*)rec_grad,
                        (const int32_t*)status, beta, d_means, d_quats, d_scales, d_opac);

@@ -87,11 +87,19 @@ __device__ inline float2 lut_sample_d(const float2* __restrict__ lut, int n, flo
                        w00 * a.y + w10 * b.y + w01 * c.y + w11 * d.y);
 }
 
-// dC = dL/d(rgb). Writes dg[8] = dL/dg and returns dL/dT (through the (1-A) bg term).
+// dC = dL/d(rgb). Writes dg[8] = dL/dg and returns dL/dT (through the (1-A) bg term). With
+// the indirect term (kInd) the specular radiance is V L_dir + (1 - V) L_ind: li = the blended
+// L_ind, vis = V, and dli[3] = dL/dL_ind is written too.
+template <bool kInd = false>
 __device__ inline float shade_pixel_bwd(const EnvDev& env, const ShadeConst& sc, const float* g,
-                                        float T, float3 dray, float3 dC, float* dg) {
+                                        float T, float3 dray, float3 dC, float* dg,
+                                        const float* li = nullptr, float vis = 1.0f,
+                                        float* dli = nullptr) {
 #pragma unroll
     for (int c = 0; c < 8; c++) dg[c] = 0.f;
+    if (kInd) {
+        dli[0] = 0.f; dli[1] = 0.f; dli[2] = 0.f;
+    }
     if (T >= 1.0f) return 0.f;
     float il = rsqrtf(dray.x * dray.x + dray.y * dray.y + dray.z * dray.z);
     float wo[3] = {-dray.x * il, -dray.y * il, -dray.z * il};
@@ -141,10 +149,15 @@ __device__ inline float shade_pixel_bwd(const EnvDev& env, const ShadeConst& sc,
     float dE[3], dP0[3], dP1[3];
     for (int c = 0; c < 3; c++) {
         float Lp = P0v[c] + fl * (P1v[c] - P0v[c]);
+        if (kInd) Lp = vis * Lp + (1.f - vis) * li[c];   // the mixed specular radiance
         float F0 = 0.04f * oneM + g[c] * M;
         dg[c] = dCv[c] * (kd * Ev[c] + Lp * ab.x * M);
         dM += dCv[c] * (-g[c] * Ev[c] * ipi + Lp * ab.x * (g[c] - 0.04f));
         float dLp = dCv[c] * (F0 * ab.x + ab.y);
+        if (kInd) {
+            dli[c] = dLp * (1.f - vis);
+            dLp *= vis;
+        }
         dE[c] = dCv[c] * g[c] * kd;
         da += dCv[c] * Lp * F0;
         db += dCv[c] * Lp;

@@ -61,6 +61,22 @@ def test_host_side_argument_errors():
     assert L.ts_indirect_eval(0, one, 10, one, one, one, 3, one, None) == -1
     assert L.ts_indirect_eval(2, one, 10, None, one, one, 3, one, None) == -1
     assert L.ts_indirect_eval(2, one, 0, None, None, None, 3, None, None) == 0
+    # indirect backward: ts_indirect_bwd, and ts_raster_bwd's indirect arguments
+    bwd = lambda *a: L.ts_indirect_bwd(*a, None)
+    assert bwd(1, one, 10, one, one, one, 4, one, one, ctypes.c_float(0), one, one, one) == -1
+    assert b"degree" in L.ts_last_error()
+    assert bwd(1, one, 10, one, one, one, 3, one, None, ctypes.c_float(0), one, one, one) == -1
+    assert b"null" in L.ts_last_error()
+    assert bwd(1, one, 0, None, None, None, 3, None, None, ctypes.c_float(0), None, None,
+               None) == 0
+    for ind, msg in (((None, one, None, None), b"need lind"),
+                     ((one, None, None, one), b"needs gbuf_ind and d_lind"),
+                     ((one, None, one, None), b"needs gbuf_ind and d_lind")):
+        args = [1, 16, 16, one, ctypes.byref(p), 10] + [one] * 8 + [100] + \
+            [one, ctypes.pointer(_ffi.TsEnv()), one, one, one, one, one, 1 << 30, one, 1 << 20,
+             one, one, 0.0, one, one, one, one, one] + list(ind) + [None]
+        assert L.ts_raster_bwd(*args) == -1
+        assert msg in L.ts_last_error(), L.ts_last_error()
     # atlas variants
     assert L.ts_atlas_pack2(one, 4, 6, None, 0, 1, one, one, None) == -1
     assert L.ts_atlas_pack2(one, 4, 8, None, 3, 0, one, one, None) == -1

@@ -369,3 +369,154 @@ def test_env_grads_sq300k_training_batch_sampled():
     ref, spread = _env_ref(sc, cams[:3], pix_v, ds, tabs)
     g, _, _ = _gpu_env_grads(sc, cams, 800, 800, d_all)
     _compare_env(g, ref, spread, "env sq300k")
+
+
+# ------------------------------------------------------------ indirect-term gradients
+
+NAMES_IND = NAMES + ("sh",)
+
+
+def _with_sh(sc, degree, seed):
+    out = dict(sc)
+    out["sh"] = synth.indirect_sh(np.random.default_rng(seed), sc["means"].shape[0], degree)
+    out["sh_degree"] = degree
+    return out
+
+
+def _gpu_grads_ind(sc, cams, W, H, d_rgba, vis, beta=0.0, grads=None):
+    """ts_raster_bwd with the indirect arguments, then ts_indirect_bwd (d_sh; d_means and
+    d_quats gain the reflected-direction terms)."""
+    P = _pkg()
+    from paper_2506_13348_amd.autograd import BackwardRunner
+    ds = P.DeviceScene.from_dict(sc, device="cuda")
+    plan = P.RenderPlan(ds, cams, W, H, gbuf=True, aux=True, vis=torch.as_tensor(vis).cuda())
+    plan.run()
+    plan.check()
+    if grads is None:
+        grads = tuple(torch.zeros_like(t) for t in (ds.means, ds.quats, ds.scales, ds.opac,
+                                                    ds.atlas, ds.sh))
+    BackwardRunner(plan).run(torch.as_tensor(np.asarray(d_rgba, np.float32)).cuda().contiguous(),
+                             grads, beta)
+    torch.cuda.synchronize()
+    return grads
+
+
+def _compare_ind(grads, ref, name, spread=None):
+    """The bar of the plain backward, over the five splat tensors and the SH coefficients."""
+    g = {k: t.double().cpu().numpy() for k, t in zip(NAMES_IND, grads)}
+    for k in NAMES_IND:
+        a, b = g[k].reshape(-1), ref[k].reshape(-1)
+        sp = np.zeros_like(b) if spread is None else spread[k].reshape(-1)
+        scale = np.abs(b).max()
+        tol = 1e-3 * scale + 1e-7 + 2.0 * sp
+        d = np.abs(a - b)
+        cos = float(a @ b / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-300))
+        if (d > tol).any():
+            i = int(np.argmax(d - tol))
+            print(f"[{name}] worst {k}[{i}] gpu {a[i]:.6g} ref {b[i]:.6g} spread {sp[i]:.3g}",
+                  flush=True)
+        print(f"[{name}] {k}: rel {d.max() / max(scale, 1e-300):.2e} cos {cos:.7f}", flush=True)
+        assert (d <= tol).all(), (name, k, float(d.max()), float(scale))
+        assert cos >= 0.9999, (name, k, cos)
+
+
+def _ind_upstream(sc, cams, pix, vis, tabs, rng, H, W):
+    """Per view: the upstream gradient (zero at the oracle's decision and grazing pixels) and
+    the pixels' visibility."""
+    d_all = np.zeros((len(cams), H, W, 4))
+    ds, vs = [], []
+    for v, cam in enumerate(cams):
+        li = oracle.indirect_eval(sc, cam, sc["sh"], sc["sh_degree"])
+        pv = vis[v][pix[:, 1], pix[:, 0]].astype(np.float64)
+        ref_f = oracle.render(sc, cam, pixels=pix, tabs=tabs, lind=li, vis=pv)
+        d, d4 = _upstream(rng, ref_f, (H, W, 4))
+        d_all[v] = d4
+        ds.append(d)
+        vs.append(pv)
+    return d_all, ds, vs
+
+
+def _ind_reference(sc, cams, pix, ds, vs, tabs, spread=True):
+    def total(scene):
+        acc = {k: 0.0 for k in NAMES_IND}
+        for cam, d, pv in zip(cams, ds, vs):
+            r = og.grads(scene, cam, pix, d, tabs, vis=pv)
+            for k in NAMES_IND:
+                acc[k] = acc[k] + r[k]
+        return acc
+    ref = total(sc)
+    if not spread:
+        return ref, None
+    sp = {k: np.zeros_like(ref[k]) for k in NAMES_IND}
+    for sign in (1.0, -1.0):
+        alt = total(_perturbed(sc, sign, 11))
+        for k in NAMES_IND:
+            sp[k] = np.maximum(sp[k], np.abs(alt[k] - ref[k]))
+    return ref, sp
+
+
+def test_indirect_grads_fd_crop(fd_case):
+    """The 64x64 crop of the 300k-splat scene with degree-3 SH and mixed visibility: every
+    gradient, the SH coefficients' included, against the float64 reference."""
+    sub, crop = fd_case
+    sc = _with_sh(sub, 3, 21)
+    tabs = oracle.tables(sc["env"], sc["env_levels"])
+    pix = oracle.all_pixels(64, 64)
+    vis = synth.visibility(np.random.default_rng(22), 1, 64, 64)
+    d_all, ds, vs = _ind_upstream(sc, [crop], pix, vis, tabs, np.random.default_rng(23), 64, 64)
+    ref, sp = _ind_reference(sc, [crop], pix, ds, vs, tabs)
+    g = _gpu_grads_ind(sc, [crop], 64, 64, d_all, vis)
+    _compare_ind(g, ref, "indirect fd crop", sp)
+
+
+@pytest.mark.parametrize("degree", [0, 2])
+def test_indirect_grads_multi_view_ragged(degree):
+    sc = _with_sh(synth.make_scene("shell2k", n=700, tex_res=4), degree, 30 + degree)
+    cams = synth.orbit_cameras(3, 45, 37, dist=2.8, el_deg=10.0)
+    tabs = oracle.tables(sc["env"], 1)
+    pix = oracle.all_pixels(45, 37)
+    vis = synth.visibility(np.random.default_rng(40 + degree), 3, 37, 45)
+    d_all, ds, vs = _ind_upstream(sc, cams, pix, vis, tabs, np.random.default_rng(4), 37, 45)
+    ref, sp = _ind_reference(sc, cams, pix, ds, vs, tabs)
+    g = _gpu_grads_ind(sc, cams, 45, 37, d_all, vis)
+    _compare_ind(g, ref, f"indirect 3 views degree {degree}", sp)
+
+
+def test_indirect_grads_deterministic_and_beta():
+    sc = _with_sh(synth.make_scene("sq100k", n=6000, env_res=16), 3, 50)
+    cams = synth.orbit_cameras(2, 80, 64)
+    vis = synth.visibility(np.random.default_rng(51), 2, 64, 80)
+    d = np.random.default_rng(52).normal(size=(2, 64, 80, 4))
+    g1 = _gpu_grads_ind(sc, cams, 80, 64, d, vis)
+    g2 = _gpu_grads_ind(sc, cams, 80, 64, d, vis)
+    for a, b in zip(g1, g2):
+        assert torch.equal(a, b)
+    assert float(g1[5].abs().max()) > 0
+    acc = tuple(t.clone() for t in g1)
+    _gpu_grads_ind(sc, cams, 80, 64, d, vis, beta=1.0, grads=acc)
+    # the raster terms double exactly; d_means and d_quats gain the indirect terms after the
+    # raster pass's beta, so they are compared to the rounding of one more sum
+    for k, (a, b) in enumerate(zip(g1, acc)):
+        if k in (0, 1):
+            torch.testing.assert_close(b, 2 * a, rtol=1e-6, atol=1e-6 * float(a.abs().max()))
+        else:
+            assert torch.equal(2 * a, b), NAMES_IND[k]
+
+
+def test_indirect_autograd_function_matches_runner():
+    P = _pkg()
+    from paper_2506_13348_amd.autograd import render_rgba
+    sc = _with_sh(synth.make_scene("shell2k", n=800), 3, 60)
+    cam = synth.config_cameras("shell2k")[0]
+    vis = synth.visibility(np.random.default_rng(61), 1, 96, 96)
+    ds = P.DeviceScene.from_dict(sc, device="cuda")
+    leaves = [t.clone().requires_grad_(True) for t in (ds.means, ds.quats, ds.scales, ds.opac,
+                                                       ds.atlas, ds.sh)]
+    cams = P.cameras_tensor([cam])
+    rgba = render_rgba(*leaves[:5], ds.chart_of, cams, 96, 96, ds.tables, sh=leaves[5],
+                       sh_degree=3, vis=torch.as_tensor(vis).cuda())
+    d4 = torch.randn(1, 96, 96, 4, device="cuda", generator=torch.Generator("cuda").manual_seed(2))
+    (rgba * d4).sum().backward()
+    g = _gpu_grads_ind(sc, [cam], 96, 96, d4.cpu().numpy(), vis)
+    for leaf, ref in zip(leaves, g):
+        torch.testing.assert_close(leaf.grad, ref, rtol=0, atol=0)
