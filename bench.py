@@ -65,9 +65,10 @@ FWD_BWD_WORKLOADS = {
 }
 
 
-def bench_fwd_bwd(cfg, steps, warmup):
+def bench_fwd_bwd(cfg, steps, warmup, sh_degree=None):
     """One training step: forward of the config's batch of views, L1 loss to a seeded target,
-    hand-written backward to all splat parameters."""
+    hand-written backward to all splat parameters. With sh_degree, the indirect term is on
+    (per-splat SH of that degree, mixed visibility) and the SH coefficients get gradients."""
     import numpy as np
     import torch
 
@@ -78,13 +79,20 @@ def bench_fwd_bwd(cfg, steps, warmup):
     sc = synth.make_scene(cfg)
     cams = synth.config_cameras(cfg)
     V, W, H = len(cams), cams[0]["width"], cams[0]["height"]
+    vis = None
+    if sh_degree is not None:
+        sc["sh"] = synth.indirect_sh(np.random.default_rng(11), len(sc["opac"]), sh_degree)
+        sc["sh_degree"] = sh_degree
+        vis = torch.as_tensor(synth.visibility(np.random.default_rng(12), V, H, W)).cuda()
     ds = DeviceScene.from_dict(sc, device="cuda")
     del sc
     target = torch.as_tensor(synth.target_image(W, H, seed=1, n_views=V)).cuda()
-    plan = RenderPlan(ds, cams, W, H, gbuf=True, aux=True)
+    plan = RenderPlan(ds, cams, W, H, gbuf=True, aux=True, vis=vis)
     run = BackwardRunner(plan)
     grads = (torch.empty_like(ds.means), torch.empty_like(ds.quats), torch.empty_like(ds.scales),
              torch.empty_like(ds.opac), torch.empty_like(ds.atlas))
+    if sh_degree is not None:
+        grads = grads + (torch.empty_like(ds.sh),)
     d_rgba = torch.zeros(V, H, W, 4, device="cuda")
     inv_n = 1.0 / (V * H * W * 3)
 
@@ -130,13 +138,29 @@ def bench_fwd_bwd(cfg, steps, warmup):
     torch.cuda.synchronize()
     env_ms = e0.elapsed_time(e1) / 3
     del eb
+    ind_ms = None
+    if sh_degree is not None:
+        # ts_indirect_bwd alone (the last kernel of the step's backward)
+        from paper_2506_13348_amd import _ffi as F
+        e0.record()
+        for _ in range(3):
+            F.ts_indirect_bwd(V, plan.cams, ds.n, ds.means, ds.quats, ds.sh, sh_degree, plan.lind,
+                              run.d_lind, 0.0, grads[5], grads[0], grads[1], plan.stream)
+        e1.record()
+        torch.cuda.synchronize()
+        ind_ms = e0.elapsed_time(e1) / 3
     out = {"value": round(V * W * H / dt / 1e6, 2), "unit": "Mpix/s",
            "ms_per_step": round(dt * 1e3, 3), "steps": steps, "views_per_step": V,
            "width": W, "height": H, "splats": ds.n,
            "per_phase_ms": {"forward": round(fwd_ms, 3), "loss_and_backward": round(bwd_ms, 3)},
-           "workload": FWD_BWD_WORKLOADS[cfg],
+           "workload": FWD_BWD_WORKLOADS[cfg] + (
+               "" if sh_degree is None else
+               f"; indirect term: degree-{sh_degree} SH per splat, mixed visibility, gradients "
+               "to the SH coefficients too"),
            "env_tables_bwd_ms": round(env_ms, 3),
            "partial_buffer_floats_used": int(run.used.item())}
+    if ind_ms is not None:
+        out["indirect_bwd_ms"] = round(ind_ms, 4)
     del plan, run, grads, d_rgba, target, ds
     torch.cuda.empty_cache()
     return out
@@ -522,6 +546,9 @@ def main():
         log(f"fwd+bwd: {result['fwd_bwd']}")
         result["fwd_bwd_field1m"] = bench_fwd_bwd("field1m", max(3, K // 2), 1)
         log(f"fwd+bwd field1m: {result['fwd_bwd_field1m']}")
+        result["fwd_bwd_indirect"] = bench_fwd_bwd("sq300k_train", max(3, K // 2), 1,
+                                                   sh_degree=3)
+        log(f"fwd+bwd indirect: {result['fwd_bwd_indirect']}")
     result["small_frame"] = bench_small_frame()
     log(f"small frame: {result['small_frame']}")
     if not args.no_tab3:
