@@ -37,7 +37,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(scene, cam, n_pix=40000, seed=0):
+def cpu_baseline(scene, cam, n_pix=200000, seed=0):
     """The FP64 oracle on a bounded random sample of pixels of one view (tables precomputed)."""
     import numpy as np
     import oracle

@@ -211,3 +211,77 @@ def test_shade_with_indirect_on_synthetic_gbuffer():
         tie = gap < 1e-5
         assert (err[~tie] <= TOL_RGB).all(), err.max()
         print(f"[shade indirect v{v}] max err {err[~tie].max():.3e}", flush=True)
+
+
+@pytest.mark.parametrize("degree", [1, 3])
+def test_indirect_bwd_matches_float64_autograd(degree):
+    """ts_indirect_bwd alone: with dL/dl_ind given per (view, splat), the coefficient, centre
+    and rotation gradients against float64 autograd of the indirect term (the reference's own
+    differentiable SH), summed over 3 views; 100 splats with a negative band 0 so that some
+    channels are clamped at zero (no gradient through them). Upstream values of channels
+    within 1e-5 of the clamp are zeroed (either side of the kink is valid)."""
+    from oracle import grad as og
+    P = _pkg()
+    sc = _with_sh(synth.make_scene("shell2k", n=1500), degree, seed=40 + degree)
+    sc["sh"][:100, 0, :] = -2.0
+    cams = synth.orbit_cameras(3, 64, 64, dist=2.6, el_deg=15.0)
+    n, V = len(sc["opac"]), len(cams)
+    rng = np.random.default_rng(7)
+    d_lind = rng.normal(size=(V, n, 4))
+    DT = torch.float64
+    ref_l = []
+    for v, cam in enumerate(cams):
+        w2c = torch.as_tensor(np.asarray(cam["w2c"], np.float64))
+        o = -(w2c[:, :3].T @ w2c[:, 3])
+        with torch.no_grad():
+            l = og._indirect(torch.as_tensor(sc["means"], dtype=DT),
+                             torch.as_tensor(sc["quats"], dtype=DT),
+                             torch.as_tensor(sc["sh"], dtype=DT), degree, o).numpy()
+        ref_l.append(l)
+        d_lind[v, :, :3][np.abs(l) < 1e-5] = 0.0
+    assert sum(int((l == 0).sum()) for l in ref_l) > 100     # clamped channels present
+    leaves = {k: torch.tensor(np.asarray(sc[k], np.float32), dtype=DT, requires_grad=True)
+              for k in ("means", "quats", "sh")}
+    loss = 0.0
+    for v, cam in enumerate(cams):
+        w2c = torch.as_tensor(np.asarray(cam["w2c"], np.float64))
+        o = -(w2c[:, :3].T @ w2c[:, 3])
+        l = og._indirect(leaves["means"], leaves["quats"], leaves["sh"], degree, o)
+        loss = loss + (l * torch.as_tensor(d_lind[v, :, :3])).sum()
+    loss.backward()
+    ref = {k: t.grad.numpy() for k, t in leaves.items()}
+
+    dev = dict(device="cuda")
+    means = torch.as_tensor(sc["means"]).cuda()
+    quats = torch.as_tensor(sc["quats"]).cuda()
+    sh = torch.as_tensor(sc["sh"]).cuda().contiguous()
+    camt = P.cameras_tensor(cams)
+    lind = torch.empty(V * n * 4, **dev)
+    P._ffi.ts_indirect_eval(V, camt, n, means, quats, sh, degree, lind)
+    d_sh = torch.full_like(sh, 7.0)          # overwritten (beta 0)
+    d_means = torch.zeros(n * 3, **dev)
+    d_quats = torch.zeros(n * 4, **dev)
+    dl = torch.as_tensor(d_lind.astype(np.float32)).cuda().contiguous()
+    P._ffi.ts_indirect_bwd(V, camt, n, means, quats, sh, degree, lind, dl, 0.0, d_sh, d_means,
+                           d_quats)
+    torch.cuda.synchronize()
+    got = {"sh": d_sh.double().cpu().numpy(), "means": d_means.view(n, 3).double().cpu().numpy(),
+           "quats": d_quats.view(n, 4).double().cpu().numpy()}
+    # the clamped channels pass nothing: the coefficient gradients of those channels are 0
+    clamped = np.stack([l <= 0 for l in ref_l]).all(axis=0)          # [n, 3] in every view
+    assert (got["sh"].transpose(0, 2, 1)[clamped] == 0).all()
+    for k in ("sh", "means", "quats"):
+        a, b = got[k].reshape(-1), ref[k].reshape(-1)
+        scale = np.abs(b).max()
+        err = np.abs(a - b).max() / scale
+        cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+        print(f"[indirect bwd degree {degree}] {k}: rel {err:.2e} cos {cos:.8f}", flush=True)
+        assert err <= 1e-4, (k, err)
+        assert cos >= 0.99999, (k, cos)
+    # beta = 1 adds the coefficient gradient onto d_sh; centres and rotations always add
+    P._ffi.ts_indirect_bwd(V, camt, n, means, quats, sh, degree, lind, dl, 1.0, d_sh, d_means,
+                           d_quats)
+    torch.cuda.synchronize()
+    assert torch.equal(d_sh.double().cpu(), torch.as_tensor(2 * got["sh"]))
+    torch.testing.assert_close(d_means.view(n, 3).double().cpu(),
+                               torch.as_tensor(2 * got["means"]), rtol=1e-6, atol=1e-9)
