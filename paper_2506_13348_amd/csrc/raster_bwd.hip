@@ -293,8 +293,8 @@ __global__ __launch_bounds__(256, kInd ? 3 : 4) void k_raster_bwd(BwdArgs a) {
                     geo[kGeo + 1] = wgt * gli[1];
                     geo[kGeo + 2] = wgt * gli[2];
                 }
-                // lane entry
-                float* me = E + lane * kEnt;
+                // lane entry, at the lane's rank among the blended lanes
+                float* me = E + (int)lanes_below(blm) * kEnt;
                 me[0] = __int_as_float(i0); me[1] = __int_as_float(i1);
                 me[2] = __int_as_float(j0); me[3] = __int_as_float(j1);
                 me[4] = fx; me[5] = fy;
@@ -347,8 +347,10 @@ __global__ __launch_bounds__(256, kInd ? 3 : 4) void k_raster_bwd(BwdArgs a) {
                 }
             }
             // texel window: lanes form groups of L = pow2 >= wt lanes (texel = lane mod L);
-            // group g sums the blended pixels p = g, g + 64/L, ... in order, then the groups
-            // are combined by a fixed butterfly
+            // the blended pixels' entries sit at their ranks 0..nbw-1 among the blended lanes;
+            // group g sums entries g, g + 64/L, ... in order, then the groups are combined by
+            // a fixed butterfly
+            const int nbw = __builtin_popcountll(blm);
             int L = 1;
             while (L < wt && L < kWave) L <<= 1;
             const int ngrp = kWave / L;
@@ -357,8 +359,7 @@ __global__ __launch_bounds__(256, kInd ? 3 : 4) void k_raster_bwd(BwdArgs a) {
                 int tt = t0 + tl;
                 int ti = wi0 + (tt % wi), tj = wj0 + (tt / wi);
                 float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-                for (int p = grp; p < kWave; p += ngrp) {
-                    if (!((blm >> p) & 1ull)) continue;
+                for (int p = grp; p < nbw; p += ngrp) {
                     const float* pe = E + p * kEnt;
                     int pi0 = __float_as_int(pe[0]), pi1 = __float_as_int(pe[1]);
                     int pj0 = __float_as_int(pe[2]), pj1 = __float_as_int(pe[3]);
