@@ -210,13 +210,10 @@ __global__ __launch_bounds__(256, kInd ? 3 : 4) void k_raster_bwd(BwdArgs a) {
                 float v11[8] = {p11.x, p11.y, p11.z, p11.w, q11.x, q11.y, q11.z, q11.w};
                 float w00 = (1.f - fx) * (1.f - fy), w10 = fx * (1.f - fy);
                 float w01 = (1.f - fx) * fy, w11 = fx * fy;
-                float tv[8], dtX[8], dtY[8];
+                float tv[8];
 #pragma unroll
-                for (int c = 0; c < 8; c++) {
+                for (int c = 0; c < 8; c++)
                     tv[c] = w00 * v00[c] + w10 * v10[c] + w01 * v01[c] + w11 * v11[c];
-                    dtX[c] = (1.f - fy) * (v10[c] - v00[c]) + fy * (v11[c] - v01[c]);
-                    dtY[c] = (1.f - fx) * (v01[c] - v00[c]) + fx * (v11[c] - v10[c]);
-                }
                 float nl = tv[4] * tv[4] + tv[5] * tv[5] + tv[6] * tv[6];
                 float nh[3], il = 0.f;
                 bool hasn = nl > 0.f;
@@ -268,12 +265,18 @@ __global__ __launch_bounds__(256, kInd ? 3 : 4) void k_raster_bwd(BwdArgs a) {
                     gu = -dalpha * oG * u;
                     gv = -dalpha * oG * vv;
                 }
-                float gX = 0.f, gY = 0.f;
+                // through the bilinear weights: with D_ab = q . v_ab (the four taps),
+                // dL/dfx = (1-fy)(D10 - D00) + fy (D11 - D01), dL/dfy likewise
+                float D00 = 0.f, D10 = 0.f, D01 = 0.f, D11 = 0.f;
 #pragma unroll
                 for (int c = 0; c < 8; c++) {
-                    gX = fmaf(q[c], dtX[c], gX);
-                    gY = fmaf(q[c], dtY[c], gY);
+                    D00 = fmaf(q[c], v00[c], D00);
+                    D10 = fmaf(q[c], v10[c], D10);
+                    D01 = fmaf(q[c], v01[c], D01);
+                    D11 = fmaf(q[c], v11[c], D11);
                 }
+                float gX = (1.f - fy) * (D10 - D00) + fy * (D11 - D01);
+                float gY = (1.f - fx) * (D01 - D00) + fx * (D11 - D10);
                 gu = fmaf(gX, tscale, gu);
                 gv = fmaf(gY, tscale, gv);
                 // (u,v) = (ux dx + uy dy, vx dx + vy dy) / (wx dx + wy dy + w0), dx = X - px
@@ -301,9 +304,24 @@ __global__ __launch_bounds__(256, kInd ? 3 : 4) void k_raster_bwd(BwdArgs a) {
 #pragma unroll
                 for (int c = 0; c < 8; c++) me[6 + c] = q[c];
             }
-            // window of texels touched by this wave
-            int wi0 = wave_min_dpp(i0), wj0 = wave_min_dpp(j0);
-            int wi1 = wave_max_dpp(i1), wj1 = wave_max_dpp(j1);
+            // window of texels touched by this wave: OR over the blended lanes of bit masks of
+            // their tap columns and rows (at least one lane is blended here; i1 >= i0, j1 >= j0)
+            int wi0, wj0, wi1, wj1;
+            if (T <= 16) {
+                unsigned mk = bl ? (1u << i0) | (1u << i1) | (0x10000u << j0) | (0x10000u << j1) : 0u;
+                unsigned m = wave_or_dpp(mk);
+                wi0 = __builtin_ctz(m & 0xFFFFu);
+                wi1 = 31 - __builtin_clz(m & 0xFFFFu);
+                wj0 = __builtin_ctz(m >> 16);
+                wj1 = 31 - __builtin_clz(m >> 16);
+            } else {
+                unsigned mx = wave_or_dpp(bl ? (1u << i0) | (1u << i1) : 0u);
+                unsigned my = wave_or_dpp(bl ? (1u << j0) | (1u << j1) : 0u);
+                wi0 = __builtin_ctz(mx);
+                wi1 = 31 - __builtin_clz(mx);
+                wj0 = __builtin_ctz(my);
+                wj1 = 31 - __builtin_clz(my);
+            }
             int wi = wi1 - wi0 + 1, wj = wj1 - wj0 + 1, wt = wi * wj;
             int64_t need = kHdrN + (int64_t)wt * 8;
             // space from this wave's current chunk; a new chunk (one integer atomic) when
@@ -329,15 +347,27 @@ __global__ __launch_bounds__(256, kInd ? 3 : 4) void k_raster_bwd(BwdArgs a) {
                 continue;
             }
             float* dst = a.part + off;
-            // geometric sums over the wave (zeros from the other lanes) by a transposing
-            // reduction: lane l < 32 ends with the sum of entry bitrev5(l); fixed order
+            // geometric sums over the wave (zeros from the other lanes) by transposing
+            // reductions in a fixed order
             {
-                float xs[32];
+                // the first 16 sums in lanes 0-15 (value bitrev4(lane)), the other 3 (6 with
+                // the indirect term) in lanes 16-19 (16-23)
+                constexpr int kRest = kGeoN - 16 <= 4 ? 4 : 8;
+                static_assert(kGeoN > 16 && kGeoN - 16 <= 8, "16 + at most 8 sums");
+                float xa[16], xb[kRest];
 #pragma unroll
-                for (int k = 0; k < 32; k++) xs[k] = k < kGeoN ? geo[k] : 0.f;
-                float tot = wave_transpose_sum32(xs, lane);
-                int vi = bitrev5(lane & 31);
-                if (lane < 32 && vi < kGeoN) dst[vi] = tot;
+                for (int k = 0; k < 16; k++) xa[k] = geo[k];
+#pragma unroll
+                for (int k = 0; k < kRest; k++) xb[k] = 16 + k < kGeoN ? geo[16 + k] : 0.f;
+                float ta = wave_transpose_sum<16>(xa, lane);
+                float tb = wave_transpose_sum<kRest>(xb, lane);
+                const int l4 = lane & 15;
+                const int va = ((l4 & 1) << 3) | ((l4 & 2) << 1) | ((l4 & 4) >> 1) | ((l4 & 8) >> 3);
+                const int lr = lane & (kRest - 1);
+                const int vb = 16 + (kRest == 4 ? (((lr & 1) << 1) | ((lr & 2) >> 1))
+                                                : (((lr & 1) << 2) | (lr & 2) | ((lr & 4) >> 2)));
+                if (lane < 16) dst[va] = ta;
+                else if (lane < 16 + kRest && vb < kGeoN) dst[vb] = tb;
                 if (lane == kWave - 1) {
                     dst[kGeoN + 0] = __int_as_float(wi0);
                     dst[kGeoN + 1] = __int_as_float(wj0);

@@ -53,55 +53,68 @@ __device__ inline int dpp_reduce_i(int x, int ident, Op op) {
     return x;
 }
 
-// Transposing wave sum of 32 values per lane: at each level a lane keeps half of its values
-// and adds its partner's copy of that half (partners differ in one lane bit: quad permutes for
-// bits 0-1, row shifts for bits 2-3, lane shuffles for bits 4-5), so after five levels each
-// lane holds one value summed over 32 lanes and the last level adds the other half-wave.
-// Returns, in every lane, the total of value index
-// v = 16 b0 + 8 b1 + 4 b2 + 2 b3 + b4 (b_k = bit k of the lane): the bit-reversed low five
-// lane bits. The combination order is fixed, so the result is deterministic.
 template <int kCtrl>
 __device__ inline float dpp_f(float x) {
     return __builtin_amdgcn_update_dpp(-0.0f, x, kCtrl, 0xF, 0xF, false);
 }
-__device__ inline float wave_transpose_sum32(float (&x)[32], int lane) {
+// Transposing wave sum of M = 4, 8, 16 or 32 values per lane: at each of log2 M levels a lane
+// keeps half of its values and adds its partner's copy of that half (partners differ in one
+// lane bit: quad permutes for bits 0-1, row shifts for bits 2-3, lane shuffles for bit 4), so
+// each lane ends with one value summed over M lanes; plain butterfly sums over the remaining
+// lane bits (up to bit 5) complete the totals. Lane l returns the total of value index
+// bitrev_{log2 M}(l mod M) (M = 32: 16 b0 + 8 b1 + 4 b2 + 2 b3 + b4, b_k = bit k of the lane).
+// The combination order is fixed, so the result is deterministic.
+template <int M>
+__device__ inline float wave_transpose_sum(float (&x)[M], int lane) {
+    static_assert(M == 4 || M == 8 || M == 16 || M == 32, "4, 8, 16 or 32 values");
     const bool b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
     const bool b4 = (lane >> 4) & 1;
+    constexpr int H1 = M / 2, H2 = M / 4, H3 = M / 8, H4 = M / 16;
 #pragma unroll
-    for (int j = 0; j < 16; j++) {   // partner lane ^ 1
-        float lo = x[j], hi = x[16 + j];
+    for (int j = 0; j < H1; j++) {   // partner lane ^ 1
+        float lo = x[j], hi = x[H1 + j];
         float send = b0 ? lo : hi, keep = b0 ? hi : lo;
         x[j] = keep + dpp_f<0xB1>(send);
     }
 #pragma unroll
-    for (int j = 0; j < 8; j++) {    // partner lane ^ 2
-        float lo = x[j], hi = x[8 + j];
+    for (int j = 0; j < H2; j++) {   // partner lane ^ 2
+        float lo = x[j], hi = x[H2 + j];
         float send = b1 ? lo : hi, keep = b1 ? hi : lo;
         x[j] = keep + dpp_f<0x4E>(send);
     }
+    if constexpr (M >= 8) {
 #pragma unroll
-    for (int j = 0; j < 4; j++) {    // partner lane ^ 4: row shift left / right by 4
-        float lo = x[j], hi = x[4 + j];
-        float send = b2 ? lo : hi, keep = b2 ? hi : lo;
-        float from_up = dpp_f<0x104>(send), from_down = dpp_f<0x114>(send);
-        x[j] = keep + (b2 ? from_down : from_up);
+        for (int j = 0; j < H3; j++) {   // partner lane ^ 4
+            float lo = x[j], hi = x[H3 + j];
+            float send = b2 ? lo : hi, keep = b2 ? hi : lo;
+            float from_up = dpp_f<0x104>(send), from_down = dpp_f<0x114>(send);
+            x[j] = keep + (b2 ? from_down : from_up);
+        }
+    } else {
+        float from_up = dpp_f<0x104>(x[0]), from_down = dpp_f<0x114>(x[0]);
+        x[0] = b2 ? from_down + x[0] : x[0] + from_up;
     }
+    if constexpr (M >= 16) {
 #pragma unroll
-    for (int j = 0; j < 2; j++) {    // partner lane ^ 8: row shift left / right by 8
-        float lo = x[j], hi = x[2 + j];
-        float send = b3 ? lo : hi, keep = b3 ? hi : lo;
-        float from_up = dpp_f<0x108>(send), from_down = dpp_f<0x118>(send);
-        x[j] = keep + (b3 ? from_down : from_up);
+        for (int j = 0; j < H4; j++) {   // partner lane ^ 8
+            float lo = x[j], hi = x[H4 + j];
+            float send = b3 ? lo : hi, keep = b3 ? hi : lo;
+            float from_up = dpp_f<0x108>(send), from_down = dpp_f<0x118>(send);
+            x[j] = keep + (b3 ? from_down : from_up);
+        }
+    } else {
+        float from_up = dpp_f<0x108>(x[0]), from_down = dpp_f<0x118>(x[0]);
+        x[0] = b3 ? from_down + x[0] : x[0] + from_up;
     }
-    {                                // partner lane ^ 16
+    if constexpr (M == 32) {         // partner lane ^ 16
         float send = b4 ? x[0] : x[1], keep = b4 ? x[1] : x[0];
         x[0] = keep + __shfl_xor(send, 16);
+    } else {
+        float o = __shfl_xor(x[0], 16);
+        x[0] = b4 ? o + x[0] : x[0] + o;
     }
-    return x[0] + __shfl_xor(x[0], 32);
-}
-
-__device__ inline int bitrev5(int l) {
-    return ((l & 1) << 4) | ((l & 2) << 2) | (l & 4) | ((l & 8) >> 2) | ((l & 16) >> 4);
+    float o = __shfl_xor(x[0], 32);
+    return lane & 32 ? o + x[0] : x[0] + o;
 }
 
 // Wave-uniform min / max of an int (from lane 63 of the DPP reduction).
@@ -112,6 +125,10 @@ __device__ inline int wave_min_dpp(int x) {
 __device__ inline int wave_max_dpp(int x) {
     int r = dpp_reduce_i(x, (int)0x80000000, [](int a, int b) { return max(a, b); });
     return __builtin_amdgcn_readlane(r, 63);
+}
+__device__ inline unsigned wave_or_dpp(unsigned x) {
+    int r = dpp_reduce_i((int)x, 0, [](int a, int b) { return a | b; });
+    return (unsigned)__builtin_amdgcn_readlane(r, 63);
 }
 
 // Buffer descriptor over one chart of the atlas (SGPR base, bounded to the chart's bytes: an
