@@ -520,3 +520,18 @@ def test_indirect_autograd_function_matches_runner():
     g = _gpu_grads_ind(sc, [cam], 96, 96, d4.cpu().numpy(), vis)
     for leaf, ref in zip(leaves, g):
         torch.testing.assert_close(leaf.grad, ref, rtol=0, atol=0)
+
+
+def test_indirect_full_visibility_gradients_are_the_plain_ones():
+    """With V = 1 everywhere the indirect light has no weight: the coefficients get exactly zero
+    gradient, and the splat gradients equal those of the plain backward (the indirect kernel
+    variant evaluates the same terms plus exact zeros)."""
+    sc = synth.make_scene("sq100k", n=5000, env_res=16)
+    cams = synth.orbit_cameras(2, 72, 56)
+    d = np.random.default_rng(70).normal(size=(2, 56, 72, 4))
+    plain, _ = _gpu_grads(sc, cams, 72, 56, d)
+    ind = _gpu_grads_ind(_with_sh(sc, 2, 71), cams, 72, 56, d, np.ones((2, 56, 72), np.float32))
+    assert float(ind[5].abs().max()) == 0.0
+    for k, (a, b) in enumerate(zip(plain, ind[:5])):
+        torch.testing.assert_close(b, a, rtol=1e-5, atol=1e-6 * max(float(a.abs().max()), 1e-30),
+                                   msg=NAMES[k])
