@@ -535,3 +535,36 @@ def test_indirect_full_visibility_gradients_are_the_plain_ones():
     for k, (a, b) in enumerate(zip(plain, ind[:5])):
         torch.testing.assert_close(b, a, rtol=1e-5, atol=1e-6 * max(float(a.abs().max()), 1e-30),
                                    msg=NAMES[k])
+
+
+def test_backward_degenerate_frames():
+    """No pairs (every splat behind the camera): every gradient is written as zero (beta 0,
+    over a buffer holding 3.0); a scene without splats is a no-op; a 1x1 frame matches the
+    float64 reference."""
+    sc = synth.make_scene("shell2k", n=50)
+    cam = synth.config_cameras("shell2k")[0]
+    behind = dict(sc)
+    behind["means"] = sc["means"] + np.float32([0, 0, 10])
+    d = np.random.default_rng(80).normal(size=(1, 32, 32, 4))
+    P = _pkg()
+    ds = P.DeviceScene.from_dict(behind, device="cuda")
+    full = tuple(torch.full_like(t, 3.0) for t in (ds.means, ds.quats, ds.scales, ds.opac,
+                                                   ds.atlas))
+    g, _ = _gpu_grads(behind, [cam], 32, 32, d, grads=full)
+    for k, t in zip(NAMES, g):
+        assert torch.all(t == 0), k
+    empty = {k: (v[:0] if isinstance(v, np.ndarray) and v.shape[:1] == (50,) else v)
+             for k, v in sc.items()}
+    g0, _ = _gpu_grads(empty, [cam], 32, 32, d)
+    assert all(t.numel() == 0 for t in g0)
+    big = synth.make_scene("shell2k", n=500)
+    one = synth.crop_camera(synth.config_cameras("shell2k")[0], 48, 44, 1, 1)   # 7 blends
+    tabs = oracle.tables(big["env"], big["env_levels"])
+    pix = oracle.all_pixels(1, 1)
+    ref_f = oracle.render(big, one, pixels=pix, tabs=tabs)
+    assert ref_f["rgba"][0, 3] > 0.5                      # the pixel is covered
+    clean = (ref_f["stat"][:, 2] == 0) & (ref_f["stat"][:, 3] == 0)
+    d1 = np.array([[0.3, -0.7, 0.5, 0.2]]) * clean[:, None]
+    ref = og.grads(big, one, pix, d1, tabs)
+    g1, _ = _gpu_grads(big, [one], 1, 1, d1.reshape(1, 1, 1, 4))
+    _compare(_np(g1), ref, "1x1")
