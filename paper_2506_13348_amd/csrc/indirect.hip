@@ -61,6 +61,7 @@ __global__ __launch_bounds__(256) void k_indirect_eval(IndArgs a) {
     constexpr int K = (D + 1) * (D + 1);
     constexpr int kStride = 3 * K + 1;
     __shared__ float sc[kIndSplats * kStride];
+    __shared__ float so[kIndViews * 3];   // camera centres of the workgroup's views
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int k0 = blockIdx.x * kIndSplats;
     const int nk = min(kIndSplats, a.n - k0);
@@ -68,6 +69,13 @@ __global__ __launch_bounds__(256) void k_indirect_eval(IndArgs a) {
     for (int i = threadIdx.x; i < nk * 3 * K; i += blockDim.x) {
         int s = i / (3 * K), j = i - s * (3 * K);
         sc[s * kStride + j] = src[i];
+    }
+    if (threadIdx.x < kIndViews && (int)(blockIdx.y * kIndViews + threadIdx.x) < a.V) {
+        // o = -R^T t of the world-to-camera transform [R | t]
+        const float* w = a.cams[blockIdx.y * kIndViews + threadIdx.x].w2c;
+        so[3 * threadIdx.x + 0] = -(w[0] * w[3] + w[4] * w[7] + w[8] * w[11]);
+        so[3 * threadIdx.x + 1] = -(w[1] * w[3] + w[5] * w[7] + w[9] * w[11]);
+        so[3 * threadIdx.x + 2] = -(w[2] * w[3] + w[6] * w[7] + w[10] * w[11]);
     }
     __syncthreads();
     const int k = k0 + lane;
@@ -84,11 +92,8 @@ __global__ __launch_bounds__(256) void k_indirect_eval(IndArgs a) {
     for (int i = 0; i < kIndViewsPerWave; i++) {
         const int v = v0 + 4 * i;
         if (v >= a.V) break;
-        const float* w = a.cams[v].w2c;
-        float ox = -(w[0] * w[3] + w[4] * w[7] + w[8] * w[11]);
-        float oy = -(w[1] * w[3] + w[5] * w[7] + w[9] * w[11]);
-        float oz = -(w[2] * w[3] + w[6] * w[7] + w[10] * w[11]);
-        float dx = mx - ox, dy = my - oy, dz = mz - oz;
+        const float* o = so + 3 * (wv + 4 * i);
+        float dx = mx - o[0], dy = my - o[1], dz = mz - o[2];
         float dd = dx * dx + dy * dy + dz * dz;
         float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
         if (qq > 0.f && dd > 0.f) {
