@@ -59,8 +59,11 @@ constexpr int kIndViews = 4 * kIndViewsPerWave;   // views per workgroup (4 wave
 template <int D>
 __global__ __launch_bounds__(256) void k_indirect_eval(IndArgs a) {
     constexpr int K = (D + 1) * (D + 1);
-    constexpr int kStride = 3 * K + 1;
-    __shared__ float sc[kIndSplats * kStride];
+    // a splat's 3K coefficients as whole float4 rows; an odd number of float4 per splat keeps
+    // the lanes' 16-byte reads on distinct banks
+    constexpr int kC4 = (3 * K + 3) / 4;
+    constexpr int kStride = 4 * (kC4 % 2 ? kC4 : kC4 + 1);
+    __shared__ __align__(16) float sc[kIndSplats * kStride];
     __shared__ float so[kIndViews * 3];   // camera centres of the workgroup's views
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int k0 = blockIdx.x * kIndSplats;
@@ -81,9 +84,12 @@ __global__ __launch_bounds__(256) void k_indirect_eval(IndArgs a) {
     const int k = k0 + lane;
     const int v0 = blockIdx.y * kIndViews + wv;
     if (lane >= nk || v0 >= a.V) return;
-    float c[K * 3];
+    float c[kC4 * 4];
 #pragma unroll
-    for (int j = 0; j < K * 3; j++) c[j] = sc[lane * kStride + j];
+    for (int j = 0; j < kC4; j++) {
+        float4 q = *(const float4*)(sc + lane * kStride + 4 * j);
+        c[4 * j] = q.x; c[4 * j + 1] = q.y; c[4 * j + 2] = q.z; c[4 * j + 3] = q.w;
+    }
     float q0 = a.quats[4 * k + 0], q1 = a.quats[4 * k + 1], q2 = a.quats[4 * k + 2], q3 = a.quats[4 * k + 3];
     float qq = q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3;
     float s = qq > 0.f ? 2.f / qq : 0.f;
