@@ -169,11 +169,12 @@ def _shade(g, A, dirs, tabs, bg, gind=None, vis=None):
 
 
 def render_dense(means, quats, scales, opac, textures, chart_of, cam, pixels, tabs=None,
-                 params=None, sh=None, degree=0, vis=None):
+                 params=None, sh=None, degree=0, vis=None, tex_format=0):
     """Differentiable render of pixels [P,2]. Tensors are float64 (leaves may require grad).
     Returns rgba [P,4] and gbuf [P,8] (albedo 3, metallic, roughness, normal 3); with sh
     ([N,(degree+1)^2,3]) the indirect term is on (vis [P] visibility, default 1) and gbuf has
-    the blended L_ind as channels 8..10."""
+    the blended L_ind as channels 8..10. tex_format 1: two-component tangent normals, n_z
+    rebuilt as sqrt(max(0, 1 - n_x^2 - n_y^2)) after filtering (texel channel 6 unused)."""
     p = dict(DEFAULT_PARAMS)
     if params:
         p.update(params)
@@ -238,6 +239,12 @@ def render_dense(means, quats, scales, opac, textures, chart_of, cam, pixels, ta
     chart = torch.as_tensor(np.asarray(chart_of)).long()[k]
     tx = _bilinear(textures.reshape(-1, 8), chart * T * T, T, T, X, Y)        # [B, 8]
     nt = tx[:, 4:7]
+    if tex_format == 1:
+        r2 = 1 - tx[:, 4] * tx[:, 4] - tx[:, 5] * tx[:, 5]
+        pos = (r2 > 0).detach()
+        nz = torch.where(pos, torch.sqrt(torch.where(pos, r2, torch.ones_like(r2))),
+                         torch.zeros_like(r2))
+        nt = torch.stack([tx[:, 4], tx[:, 5], nz], 1)
     ntl = nt.norm(dim=1, keepdim=True)
     nth = torch.where(ntl > 0, nt / torch.where(ntl > 0, ntl, torch.ones_like(ntl)),
                       torch.tensor([0.0, 0.0, 1.0], dtype=DT)[None])
@@ -265,7 +272,8 @@ def grads(scene, cam, pixels, d_rgba, tabs=None, params=None, env=False, vis=Non
     env=True also w.r.t. the texels of the irradiance cube ("irr", [6,r,r,3]) and of every
     prefiltered level ("spec", list of [6,r_l,r_l,3]), the tables taken as parameters; with
     scene["sh"] (degree scene["sh_degree"]) the indirect term is on (vis [P] per pixel) and
-    the coefficients get their gradient ("sh")."""
+    the coefficients get their gradient ("sh"); scene["tex_format"] = 1 renders with
+    two-component tangent normals (textures stay [N,T,T,8]; channel 6 gets no gradient)."""
     names = ["means", "quats", "scales", "opac", "textures"]
     if scene.get("sh") is not None:
         names.append("sh")
@@ -280,7 +288,7 @@ def grads(scene, cam, pixels, d_rgba, tabs=None, params=None, env=False, vis=Non
     rgba, gbuf = render_dense(leaves["means"], leaves["quats"], leaves["scales"], leaves["opac"],
                               leaves["textures"], scene["chart_of"], cam, pixels, t, params,
                               sh=leaves.get("sh"), degree=int(scene.get("sh_degree", 0)),
-                              vis=vis)
+                              vis=vis, tex_format=int(scene.get("tex_format", 0)))
     loss = (rgba * torch.as_tensor(np.asarray(d_rgba), dtype=DT)).sum()
     loss.backward()
     out = {k: leaves[k].grad.detach().numpy() for k in leaves}

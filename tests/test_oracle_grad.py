@@ -243,3 +243,69 @@ def test_indirect_gradients_match_central_differences(ind_case):
             checked += 1
     print(f"checked {checked}, skipped {skipped}")
     assert checked >= 15 and skipped <= 5, (checked, skipped)
+
+
+# ------------------------------------------------------------- two-component tangent normals
+
+def _n2(tex):
+    return np.ascontiguousarray(np.concatenate([tex[..., 0:6], tex[..., 7:8]], -1))
+
+
+def test_two_component_forward_matches_c_oracle(fd_case):
+    """The reference with tex_format 1 (n_z rebuilt after filtering) equals the C oracle
+    rendering the 7-channel atlas of the same scene."""
+    sub, crop, tabs, pix, d = fd_case
+    sc2 = dict(sub, tex_format=1)
+    ref = oracle.render(dict(sc2, textures=_n2(sub["textures"])), crop, pixels=pix, tabs=tabs)
+    g = og.grads(sc2, crop, pix, d, tabs)
+    np.testing.assert_allclose(g["rgba"], ref["rgba"], atol=1e-10)
+    np.testing.assert_allclose(g["gbuf"], ref["gbuf"], atol=1e-12)
+    assert np.all(g["textures"][..., 6] == 0)          # the stored n_z is not read
+    # and it differs from the three-component render (the rebuilt n_z is not the stored one)
+    g3 = og.grads(sub, crop, pix, d, tabs)
+    assert np.abs(g["gbuf"] - g3["gbuf"]).max() > 1e-6
+
+
+def _loss2(sub, crop, pix, d, tabs, name, idx, val):
+    leaves = {k: torch.tensor(np.asarray(sub[k], np.float32), dtype=torch.float64)
+              for k in ("means", "quats", "scales", "opac", "textures")}
+    leaves[name].view(-1)[idx] = val
+    rgba, _ = og.render_dense(leaves["means"], leaves["quats"], leaves["scales"], leaves["opac"],
+                              leaves["textures"], sub["chart_of"], crop, pix, tabs, tex_format=1)
+    return float((rgba * torch.as_tensor(d)).sum())
+
+
+def test_two_component_gradients_match_central_differences(fd_case):
+    """Texel gradients of the two encoded normal channels (and centres, through the
+    rebuilt n_z of the filtered sample) against central differences."""
+    sub, crop, tabs, pix, d = fd_case
+    g = og.grads(dict(sub, tex_format=1), crop, pix, d, tabs)
+    rng = np.random.default_rng(9)
+    checked, skipped = 0, 0
+    tex = np.asarray(sub["textures"], np.float64)
+    gt = g["textures"]
+    for name, pool in (("textures", [4, 5]), ("means", None)):
+        arr = np.asarray(sub[name], np.float64).reshape(-1)
+        gg = g[name].reshape(-1)
+        if pool is None:
+            cand = np.argsort(-np.abs(gg))[:30]
+        else:
+            mask = np.zeros(tex.shape, bool)
+            mask[..., pool] = True
+            flat = np.nonzero(mask.reshape(-1))[0]
+            cand = flat[np.argsort(-np.abs(gt.reshape(-1)[flat]))[:30]]
+        for idx in rng.choice(cand, 6, replace=False):
+            x0 = arr[idx]
+            # a smaller step than the plain pin's: some centres sit where the render is
+            # smooth but steeply curved, and 1e-6 leaves a third-order error near 3e-5
+            h = 1e-7 * max(1.0, abs(x0))
+            f = lambda dx: _loss2(sub, crop, pix, d, tabs, name, idx, x0 + dx)
+            d1 = (f(h) - f(-h)) / (2 * h)
+            d2 = (f(h / 2) - f(-h / 2)) / h
+            scale = max(abs(gg[idx]), 1e-3 * np.abs(gg).max(), 1e-8)
+            if abs(d1 - d2) > 1e-4 * scale:
+                skipped += 1
+                continue
+            assert abs(d1 - gg[idx]) <= 2e-5 * scale + 1e-7, (name, idx, d1, gg[idx])
+            checked += 1
+    assert checked >= 9 and skipped <= 3, (checked, skipped)
