@@ -278,14 +278,18 @@ int ts_shade(int32_t n_views, int32_t width, int32_t height, const ts_camera* ca
  *            so a run that overflowed can be repeated with a larger buffer for any beta
  *   partial_used [1] int64 device word or NULL: floats the frame asked for (also on overflow)
  *   beta     0: overwrite the gradient outputs; 1: add to them
- *   d_means [n,3], d_quats [n,4], d_scales [n,2], d_opac [n], d_atlas [n_charts][T][T][8] out
+ *   d_means [n,3], d_quats [n,4], d_scales [n,2], d_opac [n] out
+ *   d_atlas  out, in the atlas layout of params->tex_format: [n_charts][T][T][8], or
+ *            [n_charts][T][T][7] for TS_TEX_RGBN2 (two-component normals, Sec. 3.5.1: the
+ *            rebuilt n_z's gradient goes to n_x and n_y through n_z = sqrt(1 - n_x^2 - n_y^2))
  *   lind, vis, gbuf_ind   the indirect term of the forward (as given to / written by
  *            ts_raster_fwd), or NULL for the plain shading; with lind the shading adjoint
  *            takes the specular radiance V Lspec + (1 - V) L_ind and
  *   d_lind   [n_views][n][4] out: dL/dl_ind per (view, splat) (rgb, 0), the input of
  *            ts_indirect_bwd (written, not accumulated)
  * Errors: TS_E_ARG (also gbuf_ind or d_lind missing with lind, or given without it),
- *         TS_E_WORKSPACE, TS_E_LAUNCH, TS_E_UNSUPPORTED (atlas variants).
+ *         TS_E_WORKSPACE, TS_E_LAUNCH, TS_E_UNSUPPORTED (chart tables, trilinear sampling:
+ *         rendered forward only).
  */
 int ts_raster_bwd(int32_t n_views, int32_t width, int32_t height, const ts_camera* cams,
                   const ts_params* params, int32_t n, const float* means, const float* quats,

@@ -25,6 +25,7 @@
 //    through the projection set-up to the splat parameters.
 #include "eval.h"
 #include "shade_bwd.h"
+#include "texture.h"
 #include "ts_internal.h"
 
 namespace ts {
@@ -66,10 +67,13 @@ struct BwdArgs {
     const float* vis;        // [V][H][W] visibility or null (V = 1)
 };
 
+// Texel formats: kFmt 0 = 8 floats (normal xyz), 1 = 7 floats (normal xy, n_z rebuilt as
+// sqrt(max(0, 1 - n_x^2 - n_y^2)) after filtering: its gradient folds into n_x and n_y).
+
 // 4 waves per SIMD (at most 128 VGPRs): enough resident waves to cover the texel and
 // record loads measured faster than 3 waves with more registers; the indirect variant (three
 // more sums and the L_ind channel) at 3 waves, without spills
-template <bool kInd>
+template <bool kInd, int kFmt>
 __global__ __launch_bounds__(256, kInd ? 3 : 4) void k_raster_bwd(BwdArgs a) {
     constexpr int kGeoN = geo_n<kInd>();
     constexpr int kHdrN = hdr_n<kInd>();
@@ -197,13 +201,25 @@ __global__ __launch_bounds__(256, kInd ? 3 : 4) void k_raster_bwd(BwdArgs a) {
                 j1 = min(max(j0 + 1, 0), T - 1);
                 i0 = min(max(i0, 0), T - 1);
                 j0 = min(max(j0, 0), T - 1);
-                __amdgpu_buffer_rsrc_t tr = chart_rsrc(a.atlas + (size_t)(unsigned)chart * chart4,
-                                                       (unsigned)chart4 * 16u);
                 float4 p00, q00, p10, q10, p01, q01, p11, q11;
-                load_texel8(tr, (unsigned)(j0 * T + i0), p00, q00);
-                load_texel8(tr, (unsigned)(j0 * T + i1), p10, q10);
-                load_texel8(tr, (unsigned)(j1 * T + i0), p01, q01);
-                load_texel8(tr, (unsigned)(j1 * T + i1), p11, q11);
+                if (kFmt == 0) {
+                    __amdgpu_buffer_rsrc_t tr = chart_rsrc(
+                        a.atlas + (size_t)(unsigned)chart * chart4, (unsigned)chart4 * 16u);
+                    load_texel8(tr, (unsigned)(j0 * T + i0), p00, q00);
+                    load_texel8(tr, (unsigned)(j0 * T + i1), p10, q10);
+                    load_texel8(tr, (unsigned)(j1 * T + i0), p01, q01);
+                    load_texel8(tr, (unsigned)(j1 * T + i1), p11, q11);
+                } else {
+                    // 28-byte texels, channel 6 (n_z) read as 0
+                    const unsigned cb = (unsigned)(T * T) * 28u;
+                    __amdgpu_buffer_rsrc_t tr = __builtin_amdgcn_make_buffer_rsrc(
+                        (void*)((const char*)a.atlas + (size_t)(unsigned)chart * cb), (short)0,
+                        (int)cb, 0x00020000);
+                    fetch_texel(tr, 1, (unsigned)(j0 * T + i0), p00, q00);
+                    fetch_texel(tr, 1, (unsigned)(j0 * T + i1), p10, q10);
+                    fetch_texel(tr, 1, (unsigned)(j1 * T + i0), p01, q01);
+                    fetch_texel(tr, 1, (unsigned)(j1 * T + i1), p11, q11);
+                }
                 float v00[8] = {p00.x, p00.y, p00.z, p00.w, q00.x, q00.y, q00.z, q00.w};
                 float v10[8] = {p10.x, p10.y, p10.z, p10.w, q10.x, q10.y, q10.z, q10.w};
                 float v01[8] = {p01.x, p01.y, p01.z, p01.w, q01.x, q01.y, q01.z, q01.w};
@@ -214,6 +230,7 @@ __global__ __launch_bounds__(256, kInd ? 3 : 4) void k_raster_bwd(BwdArgs a) {
 #pragma unroll
                 for (int c = 0; c < 8; c++)
                     tv[c] = w00 * v00[c] + w10 * v10[c] + w01 * v01[c] + w11 * v11[c];
+                if (kFmt == 1) tv[6] = sqrtf(fmaxf(0.f, 1.f - tv[4] * tv[4] - tv[5] * tv[5]));
                 float nl = tv[4] * tv[4] + tv[5] * tv[5] + tv[6] * tv[6];
                 float nh[3], il = 0.f;
                 bool hasn = nl > 0.f;
@@ -254,6 +271,14 @@ __global__ __launch_bounds__(256, kInd ? 3 : 4) void k_raster_bwd(BwdArgs a) {
                     q[6] = (dnh[2] - nh[2] * pp) * il;
                 } else {
                     q[4] = q[5] = q[6] = 0.f;
+                }
+                if (kFmt == 1) {   // n_z = sqrt(1 - n_x^2 - n_y^2) of the filtered sample
+                    if (tv[6] > 0.f) {
+                        float r6 = q[6] / tv[6];
+                        q[4] -= r6 * tv[4];
+                        q[5] -= r6 * tv[5];
+                    }
+                    q[6] = 0.f;
                 }
                 // d(sigma R): outer(dnw, nh)
                 for (int i = 0; i < 3; i++)
@@ -508,7 +533,7 @@ __global__ void k_copy_u64(const unsigned long long* src, int64_t* dst) { *dst =
 // of 64 texels. The entries are taken 64 at a time: lane e looks up entry e's slot and window
 // (so those dependent loads overlap), then the entries are summed one after another in order,
 // their slot and window read from the owning lane.
-template <bool kInd>
+template <bool kInd, int kFmt>
 __global__ __launch_bounds__(64) void k_bwd_gather(int V, int n, int T, const int4* __restrict__ rect,
                                                    const int64_t* __restrict__ start,
                                                    int64_t cap,
@@ -524,7 +549,7 @@ __global__ __launch_bounds__(64) void k_bwd_gather(int V, int n, int T, const in
     if (status[0] != 0) return;   // incomplete partials: leave the outputs untouched
     int s = blockIdx.x, lane = threadIdx.x;
     int TT = T * T;
-    float4* dst = (float4*)(d_atlas + (int64_t)chart_of[s] * TT * 8);
+    float* dch = d_atlas + (int64_t)chart_of[s] * TT * (kFmt ? 7 : 8);
     for (int t0 = 0; t0 < TT; t0 += kWave) {
         int tt = t0 + lane;
         int ti = tt % T, tj = tt / T;
@@ -611,13 +636,22 @@ __global__ __launch_bounds__(64) void k_bwd_gather(int V, int n, int T, const in
         if (own) {
             float4 lo = make_float4(acc[0], acc[1], acc[2], acc[3]);
             float4 hi = make_float4(acc[4], acc[5], acc[6], acc[7]);
-            if (beta != 0.f) {
-                float4 o0 = dst[tt * 2], o1 = dst[tt * 2 + 1];
-                lo.x += beta * o0.x; lo.y += beta * o0.y; lo.z += beta * o0.z; lo.w += beta * o0.w;
-                hi.x += beta * o1.x; hi.y += beta * o1.y; hi.z += beta * o1.z; hi.w += beta * o1.w;
+            if (kFmt == 0) {
+                float4* dst = (float4*)dch;
+                if (beta != 0.f) {
+                    float4 o0 = dst[tt * 2], o1 = dst[tt * 2 + 1];
+                    lo.x += beta * o0.x; lo.y += beta * o0.y; lo.z += beta * o0.z; lo.w += beta * o0.w;
+                    hi.x += beta * o1.x; hi.y += beta * o1.y; hi.z += beta * o1.z; hi.w += beta * o1.w;
+                }
+                dst[tt * 2] = lo;
+                dst[tt * 2 + 1] = hi;
+            } else {
+                // 7-float texels: albedo rgb, roughness, n_x, n_y, metallic
+                float* d7 = dch + (int64_t)tt * 7;
+                float v7[7] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.w};
+#pragma unroll
+                for (int c = 0; c < 7; c++) d7[c] = beta != 0.f ? v7[c] + beta * d7[c] : v7[c];
             }
-            dst[tt * 2] = lo;
-            dst[tt * 2 + 1] = hi;
         }
     }
 }
@@ -771,6 +805,19 @@ extern "C" int ts_raster_bwd_workspace(int32_t n_views, int32_t n, int64_t pair_
     return TS_OK;
 }
 
+template <bool kInd, int kFmt>
+static void launch_bwd(const BwdArgs& a, int n_views, int n_tiles, int n, int T, const int32_t* rect,
+                       const int64_t* start, int64_t pair_capacity, const int32_t* slots,
+                       const float* partials, const int32_t* chart_of, const int32_t* status,
+                       float beta, float* rec_grad, float* d_atlas, float* d_lind,
+                       hipStream_t stream) {
+    hipLaunchKernelGGL((k_raster_bwd<kInd, kFmt>), dim3(n_views * n_tiles), dim3(256), 0, stream,
+                       a);
+    hipLaunchKernelGGL((k_bwd_gather<kInd, kFmt>), dim3(n), dim3(64), 0, stream, n_views, n, T,
+                       (const int4*)rect, start, pair_capacity, slots, partials, chart_of, status,
+                       beta, rec_grad, d_atlas, d_lind);
+}
+
 extern "C" int ts_raster_bwd(int32_t n_views, int32_t width, int32_t height, const ts_camera* cams,
                              const ts_params* params, int32_t n, const float* means,
                              const float* quats, const float* scales, const int32_t* chart_of,
@@ -801,10 +848,11 @@ extern "C" int ts_raster_bwd(int32_t n_views, int32_t width, int32_t height, con
         return params->sampler == TS_SAMPLER_HARDWARE || params->sampler == TS_SAMPLER_TRILINEAR
                    ? TS_E_UNSUPPORTED : TS_E_ARG;
     }
-    if (params->tex_format != TS_TEX_RGBN3 || params->chart_table) {
-        set_error("ts_raster_bwd: the atlas variants (two-component normals, chart tables) are "
-                  "rendered forward only");
-        return TS_E_UNSUPPORTED;
+    if ((params->tex_format != TS_TEX_RGBN3 && params->tex_format != TS_TEX_RGBN2) ||
+        params->chart_table) {
+        set_error("ts_raster_bwd: per-chart resolutions (chart tables) are rendered forward "
+                  "only");
+        return params->chart_table ? TS_E_UNSUPPORTED : TS_E_ARG;
     }
     if (lind && (!gbuf_ind || !d_lind)) {
         set_error("ts_raster_bwd: the indirect term needs gbuf_ind and d_lind");
@@ -861,19 +909,23 @@ extern "C" int ts_raster_bwd(int32_t n_views, int32_t width, int32_t height, con
     a.rect = (const int4*)rect; a.start = (const int64_t*)start;
     a.part = partials; a.part_cap = partial_capacity; a.part_top = top; a.status = status;
     a.lind = (const float4*)lind; a.gind = gbuf_ind; a.vis = vis;
-    if (lind) {
-        hipLaunchKernelGGL(k_raster_bwd<true>, dim3(n_views * n_tiles), dim3(256), 0, stream, a);
-        hipLaunchKernelGGL(k_bwd_gather<true>, dim3(n), dim3(64), 0, stream, n_views, n,
-                           params->tex_res, (const int4*)rect, (const int64_t*)start,
-                           pair_capacity, (const int32_t*)slots, (const float*)partials, chart_of,
-                           (const int32_t*)status, beta, rec_grad, d_atlas, d_lind);
-    } else {
-        hipLaunchKernelGGL(k_raster_bwd<false>, dim3(n_views * n_tiles), dim3(256), 0, stream, a);
-        hipLaunchKernelGGL(k_bwd_gather<false>, dim3(n), dim3(64), 0, stream, n_views, n,
-                           params->tex_res, (const int4*)rect, (const int64_t*)start,
-                           pair_capacity, (const int32_t*)slots, (const float*)partials, chart_of,
-                           (const int32_t*)status, beta, rec_grad, d_atlas, (float*)nullptr);
-    }
+    const bool xy = params->tex_format == TS_TEX_RGBN2;
+    if (lind && xy)
+        launch_bwd<true, 1>(a, n_views, n_tiles, n, params->tex_res, rect, start, pair_capacity,
+                            slots, partials, chart_of, status, beta, rec_grad, d_atlas, d_lind,
+                            stream);
+    else if (lind)
+        launch_bwd<true, 0>(a, n_views, n_tiles, n, params->tex_res, rect, start, pair_capacity,
+                            slots, partials, chart_of, status, beta, rec_grad, d_atlas, d_lind,
+                            stream);
+    else if (xy)
+        launch_bwd<false, 1>(a, n_views, n_tiles, n, params->tex_res, rect, start, pair_capacity,
+                             slots, partials, chart_of, status, beta, rec_grad, d_atlas, nullptr,
+                             stream);
+    else
+        launch_bwd<false, 0>(a, n_views, n_tiles, n, params->tex_res, rect, start, pair_capacity,
+                             slots, partials, chart_of, status, beta, rec_grad, d_atlas, nullptr,
+                             stream);
     hipLaunchKernelGGL(k_bwd_params, dim3((n + 255) / 256), dim3(256), 0, stream, n_views, n, cams,
                        means, quats, scales, (const int4*)rect, (const float*)rec_grad,
                        (const int32_t*)status, beta, d_means, d_quats, d_scales, d_opac);

@@ -30,7 +30,7 @@ KERNEL_SOURCES = {
     "k_preprocess": ["csrc/preprocess.hip", "csrc/ts_internal.h"],
     "k_bin_fill": ["csrc/binsort.hip", "csrc/binsort_layout.h", "csrc/ts_internal.h"],
     "k_raster_bwd": ["csrc/raster_bwd.hip", "csrc/eval.h", "csrc/shade.h", "csrc/shade_bwd.h",
-                     "csrc/ts_internal.h"],
+                     "csrc/texture.h", "csrc/ts_internal.h"],
 }
 
 

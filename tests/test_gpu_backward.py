@@ -568,3 +568,68 @@ def test_backward_degenerate_frames():
     ref = og.grads(big, one, pix, d1, tabs)
     g1, _ = _gpu_grads(big, [one], 1, 1, d1.reshape(1, 1, 1, 4))
     _compare(_np(g1), ref, "1x1")
+
+
+# ------------------------------------------------ two-component tangent normals (7-float texels)
+
+def _n2(tex):
+    return np.ascontiguousarray(np.concatenate([tex[..., 0:6], tex[..., 7:8]], -1))
+
+
+def _gpu_grads_xy(sc, cams, W, H, d_rgba):
+    P = _pkg()
+    from paper_2506_13348_amd.autograd import BackwardRunner
+    ds = P.DeviceScene.from_dict(sc, device="cuda", tex_format=1)
+    plan = P.RenderPlan(ds, cams, W, H, gbuf=True, aux=True)
+    plan.run()
+    plan.check()
+    grads = tuple(torch.zeros_like(t) for t in (ds.means, ds.quats, ds.scales, ds.opac,
+                                                ds.atlas))
+    BackwardRunner(plan).run(torch.as_tensor(np.asarray(d_rgba, np.float32)).cuda().contiguous(),
+                             grads)
+    torch.cuda.synchronize()
+    T = int(sc["textures"].shape[1])
+    out = {k: g.double().cpu().numpy() for k, g in zip(NAMES[:4], grads[:4])}
+    out["textures"] = grads[4].double().cpu().numpy().reshape(ds.n, T, T, 7)
+    return out
+
+
+def _seven(ref):
+    """Reference texture gradients in the 7-float layout (the stored n_z is not read)."""
+    r = dict(ref)
+    assert np.all(ref["textures"][..., 6] == 0)
+    r["textures"] = ref["textures"][..., [0, 1, 2, 3, 4, 5, 7]]
+    return r
+
+
+def test_xy_normal_grads_fd_crop(fd_case):
+    """Two-component normals (n_z rebuilt after filtering): every gradient on the 64x64 crop
+    against the float64 reference, texel gradients in the 7-float layout."""
+    sub, crop = fd_case
+    sc = dict(sub, tex_format=1)
+    tabs = oracle.tables(sub["env"], sub["env_levels"])
+    pix = oracle.all_pixels(64, 64)
+    ref_f = oracle.render(dict(sc, textures=_n2(sub["textures"])), crop, pixels=pix, tabs=tabs)
+    d, d4 = _upstream(np.random.default_rng(81), ref_f, (1, 64, 64, 4))
+    ref = og.grads(sc, crop, pix, d, tabs)
+    g = _gpu_grads_xy(sub, [crop], 64, 64, d4)
+    _compare(g, _seven(ref), "xy normals fd crop")
+
+
+def test_xy_normal_grads_multi_view_ragged():
+    sc = synth.make_scene("shell2k", n=700, tex_res=4)
+    cams = synth.orbit_cameras(3, 45, 37, dist=2.8, el_deg=10.0)
+    rng = np.random.default_rng(82)
+    tabs = oracle.tables(sc["env"], 1)
+    pix = oracle.all_pixels(45, 37)
+    sc1 = dict(sc, tex_format=1)
+    d_all = np.zeros((3, 37, 45, 4))
+    ds = []
+    for v, cam in enumerate(cams):
+        ref_f = oracle.render(dict(sc1, textures=_n2(sc["textures"])), cam, pixels=pix, tabs=tabs)
+        d, d4 = _upstream(rng, ref_f, (37, 45, 4))
+        d_all[v] = d4
+        ds.append(d)
+    ref, spread = _reference(sc1, cams, pix, ds, tabs)
+    g = _gpu_grads_xy(sc, cams, 45, 37, d_all)
+    _compare(g, _seven(ref), "xy normals 3 views", _seven(spread))
