@@ -25,6 +25,8 @@ def _scene_view(means, quats, scales, opac, atlas, chart_of, tables, sh=None, sh
                       means=means.contiguous(), quats=quats.contiguous(),
                       scales=scales.contiguous(), opac=opac.contiguous(),
                       atlas=atlas.contiguous(), chart_of=chart_of.contiguous(), tables=tables,
+                      # [n_charts, T, T, 7]: two-component tangent normals
+                      tex_format=1 if atlas.dim() == 4 and atlas.shape[-1] == 7 else 0,
                       sh=None if sh is None else sh.contiguous(), sh_degree=int(sh_degree))
 
 
@@ -130,7 +132,8 @@ class TexSplatRender(torch.autograd.Function):
 
 def render_rgba(means, quats, scales, opac, atlas, chart_of, cams, width, height, tables,
                 params=None, sh=None, sh_degree=0, vis=None):
-    """[V,H,W,4] shaded RGBA + alpha, differentiable w.r.t. the first five tensors and, with
+    """[V,H,W,4] shaded RGBA + alpha, differentiable w.r.t. the first five tensors (atlas
+    [n_charts,T,T,8], or [n_charts,T,T,7] with two-component tangent normals) and, with
     the indirect term (sh [n,(sh_degree+1)^2,3] per-splat SH coefficients, vis [V,H,W] optional
     visibility), w.r.t. sh as well."""
     return TexSplatRender.apply(means, quats, scales, opac, atlas, chart_of, cams, width, height,

@@ -633,3 +633,21 @@ def test_xy_normal_grads_multi_view_ragged():
     ref, spread = _reference(sc1, cams, pix, ds, tabs)
     g = _gpu_grads_xy(sc, cams, 45, 37, d_all)
     _compare(g, _seven(ref), "xy normals 3 views", _seven(spread))
+
+
+def test_xy_normal_autograd_function_matches_runner():
+    P = _pkg()
+    from paper_2506_13348_amd.autograd import render_rgba
+    sc = synth.make_scene("shell2k", n=600)
+    cam = synth.config_cameras("shell2k")[0]
+    ds = P.DeviceScene.from_dict(sc, device="cuda", tex_format=1)
+    T = ds.tex_res
+    leaves = [t.clone().requires_grad_(True) for t in (ds.means, ds.quats, ds.scales, ds.opac,
+                                                       ds.atlas.view(ds.n, T, T, 7))]
+    rgba = render_rgba(*leaves, ds.chart_of, P.cameras_tensor([cam]), 96, 96, ds.tables)
+    d4 = torch.randn(1, 96, 96, 4, device="cuda", generator=torch.Generator("cuda").manual_seed(3))
+    (rgba * d4).sum().backward()
+    g = _gpu_grads_xy(sc, [cam], 96, 96, d4.cpu().numpy())
+    for k, leaf in zip(NAMES, leaves):
+        torch.testing.assert_close(leaf.grad.double().cpu().reshape(g[k].shape),
+                                   torch.as_tensor(g[k]), rtol=0, atol=0, msg=k)
