@@ -71,10 +71,11 @@ struct BwdArgs {
 // sqrt(max(0, 1 - n_x^2 - n_y^2)) after filtering: its gradient folds into n_x and n_y).
 
 // 4 waves per SIMD (at most 128 VGPRs): enough resident waves to cover the texel and
-// record loads measured faster than 3 waves with more registers; the indirect variant (three
-// more sums and the L_ind channel) at 3 waves, without spills
+// record loads measured faster than 3 waves with more registers; also for the indirect
+// variant (three more sums and the L_ind channel), whose few register spills at 4 waves cost
+// less than the fourth wave gains (training step with the indirect term 37.4 -> 33.0 ms)
 template <bool kInd, int kFmt>
-__global__ __launch_bounds__(256, kInd ? 3 : 4) void k_raster_bwd(BwdArgs a) {
+__global__ __launch_bounds__(256, 4) void k_raster_bwd(BwdArgs a) {
     constexpr int kGeoN = geo_n<kInd>();
     constexpr int kHdrN = hdr_n<kInd>();
     __shared__ float4 srec[kBwdBatch * kRec4];
