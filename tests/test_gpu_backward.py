@@ -651,3 +651,30 @@ def test_xy_normal_autograd_function_matches_runner():
     for k, leaf in zip(NAMES, leaves):
         torch.testing.assert_close(leaf.grad.double().cpu().reshape(g[k].shape),
                                    torch.as_tensor(g[k]), rtol=0, atol=0, msg=k)
+
+
+def test_xy_normals_with_indirect_term_grads_fd_crop(fd_case):
+    """Both at once: two-component normals and degree-2 SH with mixed visibility on the crop
+    (the backward kernel's <indirect, 7-float texel> variant)."""
+    sub, crop = fd_case
+    sc = dict(_with_sh(sub, 2, 90), tex_format=1)
+    tabs = oracle.tables(sc["env"], sc["env_levels"])
+    pix = oracle.all_pixels(64, 64)
+    vis = synth.visibility(np.random.default_rng(91), 1, 64, 64)
+    osc = dict(sc, textures=_n2(sub["textures"]))
+    d_all, ds, vs = _ind_upstream(osc, [crop], pix, vis, tabs, np.random.default_rng(92), 64, 64)
+    ref, sp = _ind_reference(sc, [crop], pix, ds, vs, tabs, spread=False)
+    P = _pkg()
+    from paper_2506_13348_amd.autograd import BackwardRunner
+    dsc = P.DeviceScene.from_dict(sc, device="cuda", tex_format=1)
+    plan = P.RenderPlan(dsc, [crop], 64, 64, gbuf=True, aux=True, vis=torch.as_tensor(vis).cuda())
+    plan.run()
+    plan.check()
+    grads = tuple(torch.zeros_like(t) for t in (dsc.means, dsc.quats, dsc.scales, dsc.opac,
+                                                dsc.atlas, dsc.sh))
+    BackwardRunner(plan).run(torch.as_tensor(d_all.astype(np.float32)).cuda().contiguous(), grads)
+    torch.cuda.synchronize()
+    T = int(sub["textures"].shape[1])
+    g = list(grads)
+    g[4] = g[4].view(dsc.n, T, T, 7)
+    _compare_ind(g, _seven(ref), "xy normals + indirect fd crop")
