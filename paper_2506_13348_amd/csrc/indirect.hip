@@ -8,7 +8,7 @@
 //   l_ind = max(0, sum_j c_kj Y_j(w_r)),
 // Y_j the real orthonormal SH basis (no Condon-Shortley phase, index l*l + l + m, degree <= 3)
 // written out as polynomials of the unit vector. A workgroup takes 64 splats (one per lane)
-// and 16 views (4 per wave): the 64 splats' coefficients are staged in LDS with coalesced
+// and 64 views (16 per wave): the 64 splats' coefficients are staged in LDS with coalesced
 // loads, each lane keeps its splat's coefficients in registers and evaluates its views; the
 // output rows [view][splat] are written 64 splats at a time. The arithmetic is float32 (unit
 // vectors and O(1) coefficients: the result is within a few ulp of the sum of |c_j Y_j|;
@@ -53,7 +53,10 @@ __device__ inline void sh_basis_f(float x, float y, float z, float* Y) {
 }
 
 constexpr int kIndSplats = 64;          // splats per workgroup (one per lane)
-constexpr int kIndViewsPerWave = 4;
+// 16 views per wave: the staged coefficients and the per-splat set-up serve 64 views (measured
+// back to back on 64 views x 100k splats at degree 3: 29 us, against 37 us with 4 views per
+// wave and 82 us with 1)
+constexpr int kIndViewsPerWave = 16;
 constexpr int kIndViews = 4 * kIndViewsPerWave;   // views per workgroup (4 waves)
 
 template <int D>
