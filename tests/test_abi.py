@@ -77,6 +77,18 @@ def test_host_side_argument_errors():
              one, one, 0.0, one, one, one, one, one] + list(ind) + [None]
         assert L.ts_raster_bwd(*args) == -1
         assert msg in L.ts_last_error(), L.ts_last_error()
+    # backward of the atlas variants: chart tables are refused (forward only), an unknown
+    # texel format is an argument error
+    for kw, code, msg in ((dict(chart_table=16), -4, b"forward only"),
+                          (dict(tex_format=3), -1, b"forward only")):
+        q = _ffi.make_params(8)
+        for k, v in kw.items():
+            setattr(q, k, v)
+        args = [1, 16, 16, one, ctypes.byref(q), 10] + [one] * 8 + [100] + \
+            [one, ctypes.pointer(_ffi.TsEnv()), one, one, one, one, one, 1 << 30, one, 1 << 20,
+             one, one, 0.0, one, one, one, one, one, None, None, None, None, None]
+        assert L.ts_raster_bwd(*args) == code, L.ts_last_error()
+        assert msg in L.ts_last_error(), L.ts_last_error()
     # atlas variants
     assert L.ts_atlas_pack2(one, 4, 6, None, 0, 1, one, one, None) == -1
     assert L.ts_atlas_pack2(one, 4, 8, None, 3, 0, one, one, None) == -1
