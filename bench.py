@@ -305,9 +305,34 @@ def bench_small_frame(reps=200):
     torch.cuda.synchronize()
     ts = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
     med = float(np.median(ts))
+    # the same frame replayed from a HIP graph (as the serving loop does): one launch per frame
+    eager = plan.rgba.clone()
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        plan.run()
+    stream.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        plan.run()
+    stream.synchronize()
+    gev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    with torch.cuda.stream(stream):
+        for e0, e1 in gev:
+            e0.record()
+            graph.replay()
+            e1.record()
+    torch.cuda.synchronize()
+    gts = np.array([e0.elapsed_time(e1) for e0, e1 in gev])
+    gmed = float(np.median(gts))
+    if not torch.equal(plan.rgba, eager):
+        raise RuntimeError("graph replay of the small frame differs from the eager render")
     return {"workload": "shell2k: 2k splats T=4, one 128x128 view, 32^2 env",
             "median_us": round(med * 1e3, 1), "p90_us": round(float(np.percentile(ts, 90)) * 1e3, 1),
-            "mpix_per_s": round(128 * 128 / (med / 1e3) / 1e6, 2)}
+            "mpix_per_s": round(128 * 128 / (med / 1e3) / 1e6, 2),
+            "graph_replay_median_us": round(gmed * 1e3, 1),
+            "graph_replay_mpix_per_s": round(128 * 128 / (gmed / 1e3) / 1e6, 2)}
 
 
 def bench_tab3(steps=5):
