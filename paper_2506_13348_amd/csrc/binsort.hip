@@ -187,6 +187,92 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     }
 }
 
+// Views of at most kSortItems splats: all four passes in one workgroup per view. The items
+// stay in LDS between passes; each pass ranks them exactly as k_sort_scatter does (per-wave
+// ballot ranking in item order, wave prefixes per digit), with the block's own exclusive scan
+// of the 256 digit totals as the offsets, so the order is the same stable LSD sort.
+static_assert(kSortThreads == kSortBuckets, "one thread per digit in the digit scans");
+__global__ __launch_bounds__(kSortThreads) void k_sort_small(const uint32_t* __restrict__ keys,
+                                                             int n,
+                                                             int32_t* __restrict__ vals_out) {
+    __shared__ uint32_t sk[kSortItems];
+    __shared__ int32_t sv[kSortItems];
+    __shared__ uint32_t cnt[kSortThreads / kWave][kSortBuckets];
+    __shared__ uint32_t tot[kSortBuckets];
+    const int v = blockIdx.x, tid = threadIdx.x;
+    const int w = tid / kWave, lane = tid % kWave;
+    const int base = w * (kSortItemsPerThread * kWave);
+    const uint32_t* kv = keys + (int64_t)v * n;
+    for (int i = tid; i < n; i += kSortThreads) {
+        sk[i] = kv[i];
+        sv[i] = i;
+    }
+    __syncthreads();
+    for (int p = 0; p < kSortPasses; p++) {
+        const int shift = p * kSortRadixBits;
+        for (int i = tid; i < (kSortThreads / kWave) * kSortBuckets; i += kSortThreads)
+            (&cnt[0][0])[i] = 0;
+        __syncthreads();
+        uint32_t key[kSortItemsPerThread];
+        int32_t val[kSortItemsPerThread];
+        uint32_t loc[kSortItemsPerThread];
+#pragma unroll
+        for (int r = 0; r < kSortItemsPerThread; r++) {
+            int i = base + r * kWave + lane;
+            bool ok = i < n;
+            uint32_t k = ok ? sk[i] : 0u;
+            key[r] = k;
+            val[r] = ok ? sv[i] : 0;
+            uint32_t d = (k >> shift) & (kSortBuckets - 1);
+            uint64_t peers = __ballot(ok);
+#pragma unroll
+            for (int bit = 0; bit < kSortRadixBits; bit++) {
+                uint64_t m = __ballot((d >> bit) & 1u);
+                peers &= ((d >> bit) & 1u) ? m : ~m;
+            }
+            uint32_t old = ok ? cnt[w][d] : 0u;
+            loc[r] = old + lanes_below(peers);
+            bool leader = ok && ((peers >> lane) == 1ull);
+            if (leader) cnt[w][d] = old + (uint32_t)__popcll(peers);
+        }
+        __syncthreads();
+        {
+            // digit d = tid: its count over the waves, then the exclusive scan over digits
+            int d = tid;   // kSortThreads == kSortBuckets
+            uint32_t t = 0;
+            for (int ww = 0; ww < kSortThreads / kWave; ww++) t += cnt[ww][d];
+            tot[d] = t;
+            __syncthreads();
+            for (int o = 1; o < kSortBuckets; o <<= 1) {
+                uint32_t y = d >= o ? tot[d - o] : 0u;
+                __syncthreads();
+                tot[d] += y;
+                __syncthreads();
+            }
+            uint32_t run = tot[d] - t;   // exclusive prefix of digit d
+            for (int ww = 0; ww < kSortThreads / kWave; ww++) {
+                uint32_t c = cnt[ww][d];
+                cnt[ww][d] = run;
+                run += c;
+            }
+        }
+        __syncthreads();   // every item is in registers: the LDS rows can be overwritten
+#pragma unroll
+        for (int r = 0; r < kSortItemsPerThread; r++) {
+            int i = base + r * kWave + lane;
+            if (i < n) {
+                uint32_t d = (key[r] >> shift) & (kSortBuckets - 1);
+                uint32_t pos = cnt[w][d] + loc[r];
+                sk[pos] = key[r];
+                sv[pos] = val[r];
+            }
+        }
+        __syncthreads();
+    }
+    int32_t* vo = vals_out + (int64_t)v * n;
+    for (int i = tid; i < n; i += kSortThreads) vo[i] = sv[i];
+}
+
 // ---------------------------------------------------------------------------------------
 // tile lists
 // ---------------------------------------------------------------------------------------
@@ -461,8 +547,12 @@ extern "C" int ts_bin_sort(int32_t n_views, int32_t width, int32_t height, int32
     if (n > 0) {
         // pass p reads (keys_in, vals_in) and writes (keys_out, vals_out); the final pass
         // writes the splat ids to sorted_ids (also used as the ping-pong value buffer)
-        radix_sort_indices(depth_key, n, n_views, keys_a, keys_b, vals_a, hist, sorted_ids,
-                           stream);
+        if (n <= kSortItems)
+            hipLaunchKernelGGL(k_sort_small, dim3(n_views), dim3(kSortThreads), 0, stream,
+                               depth_key, n, sorted_ids);
+        else
+            radix_sort_indices(depth_key, n, n_views, keys_a, keys_b, vals_a, hist, sorted_ids,
+                               stream);
         static_assert(kSortPasses % 2 == 0, "the last pass must land in sorted_ids");
         if ((rc = launch_check("ts_bin_sort(sort)")) != TS_OK) return rc;
     }
