@@ -105,6 +105,20 @@ def test_depth_keys_bit_exact_and_lists():
     _check_lists(plan, len(sc["opac"]))
 
 
+@pytest.mark.parametrize("n", [4096, 4097])
+def test_sort_paths_at_the_small_view_limit(n):
+    """Views of at most 4096 splats are sorted by one workgroup, larger ones by the multi-block
+    radix sort: both give the stable order of the depth keys, with equal keys present."""
+    sc = synth.make_scene("sq100k", n=n, tex_res=2, env_res=16)
+    sc["means"][: n // 8] = sc["means"][n // 8: 2 * (n // 8)]    # duplicated centres: equal keys
+    cams = synth.orbit_cameras(2, 64, 48, dist=2.8)
+    ds, out = _render(sc, cams, 64, 48)
+    plan = out["plan"]
+    keys = plan.depth_key.view(2, -1)[:, :n].cpu().numpy().view(np.uint32)
+    assert len(np.unique(keys[0])) < n                              # ties present
+    _check_lists(plan, n)
+
+
 def test_lists_ragged_and_many_views():
     sc = synth.make_scene("sq100k", n=3000, tex_res=4, env_res=16)
     cams = synth.orbit_cameras(5, 75, 53, dist=2.6)
