@@ -77,3 +77,33 @@ def test_pair_overflow_is_rerendered():
     assert srv.stats["overflow_retries"] == 1 and reqs[0].retried
     alone = P.render(scenes[0], [cam], 128, 128)["rgba"][0]
     assert torch.equal(alone, reqs[0].output)
+
+
+def test_serving_scenes_with_the_indirect_term_and_xy_normals():
+    """Resident scenes of the other kinds in the same server: one with per-splat SH (the
+    indirect evaluation captured in the graph), one with the two-component normal atlas;
+    every request equals the same request rendered alone, bit for bit."""
+    import paper_2506_13348_amd as P
+    from paper_2506_13348_amd.serve import Request, Server
+    P._ffi.lib()
+    a = synth.make_scene("shell2k", seed=23, n=1200)
+    a["sh"] = synth.indirect_sh(np.random.default_rng(1), 1200, 2)
+    a["sh_degree"] = 2
+    b = synth.make_scene("shell2k", seed=24, n=900)
+    scenes = [P.DeviceScene.from_dict(a, device="cuda"),
+              P.DeviceScene.from_dict(b, device="cuda", tex_format=1)]
+    rng = np.random.default_rng(6)
+    trace = _trace(rng, 20, [(64, 64), (96, 80)])
+    samples = {}
+    for t, s, (W, H), cam in trace:
+        samples.setdefault((s, W, H), []).append(cam)
+    srv = Server(scenes, slots=3, capacity_samples=samples, keep_outputs=True)
+    srv.prepare([((s, W, H), c[0]) for (s, W, H), c in samples.items()], per_key=2)
+    reqs = [Request(i, t, s, wh[0], wh[1], cam) for i, (t, s, wh, cam) in enumerate(trace)]
+    srv.serve(reqs, realtime=False)
+    torch.cuda.synchronize()
+    assert srv.stats["graph_replays"] >= len(reqs) - srv.stats["overflow_retries"]
+    for r in reqs:
+        alone = P.render(scenes[r.scene], [r.cam], r.width, r.height)["rgba"][0]
+        assert torch.equal(alone, r.output), (r.scene, r.width, r.height)
+    print(f"[serve variants] {len(reqs)} requests bit-identical alone vs mix, stats {srv.stats}")
