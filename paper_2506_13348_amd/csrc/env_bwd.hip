@@ -382,10 +382,13 @@ extern "C" int ts_env_bwd(int32_t n_views, int32_t width, int32_t height, const 
     int64_t P = (int64_t)n_views * width * height;
     hipLaunchKernelGGL(k_env_records, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, stream, a);
     int m = (int)L.m;
-    // sorted keys land in kb, the record order in `order` (four passes)
+    // Texel keys are below n_irr + n_spec, so only the digits that span that range are sorted;
+    // the unused records' key (all ones) is above every texel key in those low bits too, so
+    // they still sort last. Sorted keys land in kb, the record order in `order`.
+    int passes = 1;
+    while (passes < kSortPasses && (n_irr + n_spec) >= (1LL << (kSortRadixBits * passes))) passes++;
     radix_sort_indices(keys, m, 1, ka, kb, va, hist, order, stream,
-                       (uint32_t*)(w + L.off_stmp));
-    static_assert(kSortPasses == 4, "sorted keys are read from the second key buffer");
+                       (uint32_t*)(w + L.off_stmp), passes);
     unsigned g256 = (unsigned)((L.m + 255) / 256);
     hipLaunchKernelGGL(k_env_run_flags, dim3(g256), dim3(256), 0, stream, kb, L.m, run);
     hipLaunchKernelGGL(k_env_scan_sums, dim3(L.nb_scan), dim3(256), 0, stream, run, L.m, bsum);

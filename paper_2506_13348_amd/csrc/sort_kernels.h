@@ -23,21 +23,25 @@ __global__ void k_sort_scatter(const uint32_t* __restrict__ keys_in,
                                int32_t* __restrict__ vals_out);
 
 // Stable LSD sort of n 32-bit keys per segment (grid.y segments of n keys each):
-// vals_out[s][i] = index of the i-th smallest key of segment s. Scratch: keys_a, keys_b,
+// vals_out[s][i] = index of the i-th smallest key of segment s, the keys themselves in that
+// order in keys_b. `passes` digits of 8 bits from the lowest: with fewer than four the order
+// is that of the low 8 * passes bits of each key. Scratch: keys_a, keys_b,
 // vals_a of n * segs each and hist of segs * 256 * nblk words; scan_tmp (segs *
 // sort_scan_tmp_entries(n) words) or null: the digit histograms are then scanned by one block
 // per segment, which suits short histograms only.
 inline void radix_sort_indices(const uint32_t* keys, int n, int segs, uint32_t* keys_a,
                                uint32_t* keys_b, int32_t* vals_a, uint32_t* hist,
                                int32_t* vals_out, hipStream_t stream,
-                               uint32_t* scan_tmp = nullptr) {
+                               uint32_t* scan_tmp = nullptr, int passes = kSortPasses) {
     int nblk = n > 0 ? (n + kSortItems - 1) / kSortItems : 1;
     int nbs = sort_scan_tmp_entries(n);
     const uint32_t* kin = keys;
     const int32_t* vin = nullptr;
-    for (int p = 0; p < kSortPasses; p++) {
-        uint32_t* kout = (p & 1) ? keys_b : keys_a;
-        int32_t* vout = (p & 1) ? vals_out : vals_a;
+    for (int p = 0; p < passes; p++) {
+        // the last pass writes keys_b / vals_out, earlier ones alternate back from there
+        bool last_parity = ((passes - 1 - p) & 1) == 0;
+        uint32_t* kout = last_parity ? keys_b : keys_a;
+        int32_t* vout = last_parity ? vals_out : vals_a;
         int shift = p * kSortRadixBits;
         hipLaunchKernelGGL(k_sort_hist, dim3(nblk, segs), dim3(kSortThreads), 0, stream, kin, n,
                            nblk, shift, hist);
