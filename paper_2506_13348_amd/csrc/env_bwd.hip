@@ -214,17 +214,31 @@ __global__ __launch_bounds__(256) void k_env_scan_sums(const int32_t* __restrict
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
+// Exclusive scan of the nb block totals in place by one block, in tiles of kEnvScanBlock
+// (4 consecutive totals per thread, so each tile's loads coalesce) with a running carry; the
+// next tile is loaded before the current one is scanned.
 __global__ __launch_bounds__(256) void k_env_scan_bsums(int32_t* __restrict__ bsum, int nb) {
     __shared__ int sh[256];
-    int per = (nb + 255) / 256;
-    int a0 = threadIdx.x * per, a1 = min(nb, a0 + per);
-    int s = 0;
-    for (int i = a0; i < a1; i++) s += bsum[i];
-    int run = block_excl_scan_i32(s, sh, nullptr);
-    for (int i = a0; i < a1; i++) {
-        int x = bsum[i];
-        bsum[i] = run;
-        run += x;
+    int carry = 0;
+    int i0 = threadIdx.x * kEnvScanPer;
+    int x[kEnvScanPer];
+    for (int k = 0; k < kEnvScanPer; k++) x[k] = i0 + k < nb ? bsum[i0 + k] : 0;
+    for (int base = 0; base < nb; base += kEnvScanBlock) {
+        int j0 = i0 + kEnvScanBlock, nx[kEnvScanPer], s = 0;
+        for (int k = 0; k < kEnvScanPer; k++) {
+            nx[k] = j0 + k < nb ? bsum[j0 + k] : 0;
+            s += x[k];
+        }
+        int tot;
+        int run = carry + block_excl_scan_i32(s, sh, &tot);
+        for (int k = 0; k < kEnvScanPer; k++)
+            if (i0 + k < nb) {
+                bsum[i0 + k] = run;
+                run += x[k];
+            }
+        carry += tot;
+        i0 = j0;
+        for (int k = 0; k < kEnvScanPer; k++) x[k] = nx[k];
     }
 }
 
