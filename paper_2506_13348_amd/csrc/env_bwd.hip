@@ -174,15 +174,15 @@ __global__ __launch_bounds__(kEnvBlock) void k_env_block_sums(const uint32_t* __
     if (last) pieces[first + (run_id[i] - run_id[first])] = x;
 }
 
-// Run starts -> flags; an inclusive scan of them minus one is the run id of every record.
-__global__ __launch_bounds__(256) void k_env_run_flags(const uint32_t* __restrict__ keys,
-                                                       int64_t m, int32_t* __restrict__ flags) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < m) flags[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+// A sorted record starts a run when its key differs from the one before it; an inclusive scan
+// of these flags minus one is the run id of every record.
+__device__ inline int run_start(const uint32_t* __restrict__ keys, int64_t i) {
+    return (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
 }
 
-// Inclusive scan of int32 flags (1024 per block: block totals, a one-block scan of those,
-// then each block's scan plus its offset), minus one: run ids.
+// Inclusive scan of the run-start flags, taken from the sorted keys (1024 per block: block
+// totals, a one-block scan of those, then each block's scan plus its offset), minus one: run
+// ids.
 constexpr int kEnvScanPer = 4;
 constexpr int kEnvScanBlock = 256 * kEnvScanPer;
 
@@ -202,13 +202,13 @@ __device__ inline int block_excl_scan_i32(int x, int* sh, int* total) {
     return incl - x;
 }
 
-__global__ __launch_bounds__(256) void k_env_scan_sums(const int32_t* __restrict__ f, int64_t m,
-                                                       int32_t* __restrict__ bsum) {
+__global__ __launch_bounds__(256) void k_env_scan_sums(const uint32_t* __restrict__ keys,
+                                                       int64_t m, int32_t* __restrict__ bsum) {
     __shared__ int sh[256];
     int64_t i0 = (int64_t)blockIdx.x * kEnvScanBlock + threadIdx.x * kEnvScanPer;
     int s = 0;
     for (int k = 0; k < kEnvScanPer; k++)
-        if (i0 + k < m) s += f[i0 + k];
+        if (i0 + k < m) s += run_start(keys, i0 + k);
     int tot;
     block_excl_scan_i32(s, sh, &tot);
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
@@ -242,14 +242,15 @@ __global__ __launch_bounds__(256) void k_env_scan_bsums(int32_t* __restrict__ bs
     }
 }
 
-__global__ __launch_bounds__(256) void k_env_scan_apply(int32_t* __restrict__ f, int64_t m,
+__global__ __launch_bounds__(256) void k_env_scan_apply(const uint32_t* __restrict__ keys,
+                                                        int32_t* __restrict__ f, int64_t m,
                                                         const int32_t* __restrict__ bsum) {
     __shared__ int sh[256];
     int64_t i0 = (int64_t)blockIdx.x * kEnvScanBlock + threadIdx.x * kEnvScanPer;
     int x[kEnvScanPer];
     int s = 0;
     for (int k = 0; k < kEnvScanPer; k++) {
-        x[k] = i0 + k < m ? f[i0 + k] : 0;
+        x[k] = i0 + k < m ? run_start(keys, i0 + k) : 0;
         s += x[k];
     }
     int run = block_excl_scan_i32(s, sh, nullptr) + bsum[blockIdx.x];
@@ -404,10 +405,10 @@ extern "C" int ts_env_bwd(int32_t n_views, int32_t width, int32_t height, const 
     radix_sort_indices(keys, m, 1, ka, kb, va, hist, order, stream,
                        (uint32_t*)(w + L.off_stmp), passes);
     unsigned g256 = (unsigned)((L.m + 255) / 256);
-    hipLaunchKernelGGL(k_env_run_flags, dim3(g256), dim3(256), 0, stream, kb, L.m, run);
-    hipLaunchKernelGGL(k_env_scan_sums, dim3(L.nb_scan), dim3(256), 0, stream, run, L.m, bsum);
+    hipLaunchKernelGGL(k_env_scan_sums, dim3(L.nb_scan), dim3(256), 0, stream, kb, L.m, bsum);
     hipLaunchKernelGGL(k_env_scan_bsums, dim3(1), dim3(256), 0, stream, bsum, L.nb_scan);
-    hipLaunchKernelGGL(k_env_scan_apply, dim3(L.nb_scan), dim3(256), 0, stream, run, L.m, bsum);
+    hipLaunchKernelGGL(k_env_scan_apply, dim3(L.nb_scan), dim3(256), 0, stream, kb, run, L.m,
+                       bsum);
     hipLaunchKernelGGL(k_env_block_sums, dim3((unsigned)((L.m + kEnvBlock - 1) / kEnvBlock)),
                        dim3(kEnvBlock), 0, stream, kb, order, vals, run, L.m, pieces);
     hipLaunchKernelGGL(k_env_texel_sums, dim3(g256), dim3(256), 0, stream, kb, run, pieces, L.m,
