@@ -344,11 +344,11 @@ int ts_raster_bwd_workspace(int32_t n_views, int32_t n, int64_t pair_capacity, s
  *   d_rgba       [n_views][H][W][4] dL/d(rgb, alpha) (alpha does not reach the tables)
  *   ws, ws_bytes scratch, at least ts_env_bwd_workspace(n_views, width, height) bytes
  *                (about 56 bytes per pixel)
- *   beta         0: overwrite the outputs; 1: add to them
+ *   beta         0: overwrite the outputs; 1: add to them (any other value is TS_E_ARG)
  *   d_irr        [6][irr_res][irr_res][4] out, layout of env->irr (the 4th component is 0)
  *   d_spec       levels back to back as env->spec, [6][r_l][r_l][4] each, out
- * Errors: TS_E_ARG (null pointers, bad sizes, more than 2^31-1 records), TS_E_WORKSPACE,
- * TS_E_LAUNCH.
+ * Errors: TS_E_ARG (null pointers, bad sizes, beta not 0 or 1, more than 2^31-1 records),
+ * TS_E_WORKSPACE, TS_E_LAUNCH.
  */
 int ts_env_bwd(int32_t n_views, int32_t width, int32_t height, const ts_camera* cams,
                const ts_env* env, const float* gbuf, const float* t_final, const float* d_rgba,

@@ -346,6 +346,11 @@ extern "C" int ts_env_bwd(int32_t n_views, int32_t width, int32_t height, const 
                           const ts_env* env, const float* gbuf, const float* t_final,
                           const float* d_rgba, void* ws, size_t ws_bytes, float beta,
                           float* d_irr, float* d_spec, hipStream_t stream) {
+    // texels no record reaches are left as they are, so only these two modes are exact
+    if (beta != 0.f && beta != 1.f) {
+        set_error("ts_env_bwd: beta must be 0 (overwrite) or 1 (accumulate), got %g", (double)beta);
+        return TS_E_ARG;
+    }
     if (n_views < 1 || width < 1 || height < 1 || !cams || !env || !gbuf || !t_final ||
         !d_rgba || !d_irr || !d_spec || !env->spec || !env->irr || !env->lut ||
         env->spec_levels < 1 || env->spec_res < 1 || env->irr_res < 1 || env->lut_res < 1) {
