@@ -244,3 +244,184 @@ def test_shading_mirror_returns_environment_radiance(lut):
         faces.append(2 * ax + (0 if wo[ax] >= 0 else 1))
     rgb, _ = oracle.shade_gbuffer(g, np.ones(3), cam, pix, tabs)
     np.testing.assert_allclose(rgb[:, 0], face_val[faces], rtol=2e-4)
+
+
+# ----------------------------------------------------------------------------------------
+# pins of the cube-face orientation and of the roughness-selected level blend
+# ----------------------------------------------------------------------------------------
+
+def _opengl_face_st(d):
+    """Face and (s,t) of direction d from the public OpenGL cube-map table (major axis ma,
+    in-face coordinates sc, tc; s = (sc/|ma| + 1)/2, t = (tc/|ma| + 1)/2), written out here
+    independently of the oracle."""
+    x, y, z = d
+    ax, ay, az = abs(x), abs(y), abs(z)
+    if ax >= ay and ax >= az:
+        face, sc, tc, ma = (0, -z, -y, ax) if x >= 0 else (1, z, -y, ax)
+    elif ay >= az:
+        face, sc, tc, ma = (2, x, z, ay) if y >= 0 else (3, x, -z, ay)
+    else:
+        face, sc, tc, ma = (4, x, -y, az) if z >= 0 else (5, -x, -y, az)
+    return face, 0.5 * (sc / ma + 1.0), 0.5 * (tc / ma + 1.0)
+
+
+def _coordinate_cube(r):
+    """Cube whose texel [f][row j][col i] holds (f, (i+1/2)/r, (j+1/2)/r): bilinear filtering
+    of these affine fields returns the face and the exact (s,t) of any lookup that lands
+    between texel centres."""
+    cube = np.zeros((6, r, r, 3))
+    c = (np.arange(r) + 0.5) / r
+    cube[..., 0] = np.arange(6)[:, None, None]
+    cube[..., 1] = c[None, None, :]
+    cube[..., 2] = c[None, :, None]
+    return cube
+
+
+def test_cube_orientation_matches_opengl_table():
+    """For several directions on every face, the oracle's lookup lands on the face and the
+    in-face (s,t) of the OpenGL table (column s, row t), so no face is mirrored, rotated or
+    transposed."""
+    r = 16
+    cube = _coordinate_cube(r)
+    rng = np.random.default_rng(3)
+    dirs = []
+    for axis in range(3):
+        for sign in (1.0, -1.0):
+            for _ in range(6):
+                d = rng.uniform(-0.7, 0.7, 3)
+                d[axis] = sign
+                dirs.append(d * rng.uniform(0.5, 2.0))
+    dirs = np.array(dirs)
+    got = oracle.cube_sample(cube, dirs)
+    for d, g in zip(dirs, got):
+        face, s, t = _opengl_face_st(d)
+        assert int(round(g[0])) == face, (d, g)
+        assert g[1] == pytest.approx(s, abs=1e-12), (d, g, s, t)
+        assert g[2] == pytest.approx(t, abs=1e-12), (d, g, s, t)
+
+
+def test_cube_orientation_hand_picked():
+    """A few directions whose table values are written by hand: e.g. +X with y, z < 0 lands in
+    the lower half of neither axis (sc = -z > 0, tc = -y > 0)."""
+    cube = _coordinate_cube(8)
+    cases = [  # direction, face, s, t
+        ((1.0, -0.2, -0.4), 0, 0.7, 0.6),
+        ((-1.0, -0.2, -0.4), 1, 0.3, 0.6),
+        ((0.4, 1.0, 0.2), 2, 0.7, 0.6),
+        ((0.4, -1.0, 0.2), 3, 0.7, 0.4),
+        ((0.4, 0.2, 1.0), 4, 0.7, 0.4),
+        ((0.4, 0.2, -1.0), 5, 0.3, 0.4),
+    ]
+    got = oracle.cube_sample(cube, np.array([c[0] for c in cases]))
+    for (d, f, s, t), g in zip(cases, got):
+        np.testing.assert_allclose(g, [f, s, t], atol=1e-12, err_msg=str(d))
+
+
+def _level_tables(levels, r, lut_ab, irr_val):
+    """Hand-built shading tables: specular level l constant with channel values
+    (1 + l, 10 + 3 l, 0.5 l) at resolution r >> l; irradiance constant; split-sum table lut_ab
+    [n][n][2]."""
+    spec = []
+    for l in range(levels):
+        rl = max(r >> l, 1)
+        lv = np.empty((6, rl, rl, 3))
+        lv[...] = [1.0 + l, 10.0 + 3.0 * l, 0.5 * l]
+        spec.append(lv)
+    irr = np.full((6, 4, 4, 3), irr_val)
+    return {"spec": spec, "irr": irr, "lut": lut_ab}
+
+
+def _pixel_dirs(cam, pix):
+    w2c = np.asarray(cam["w2c"], np.float64)
+    out = []
+    for x, y in pix:
+        d = w2c[:, :3].T @ np.array([(x + 0.5 - cam["cx"]) / cam["fx"],
+                                     (y + 0.5 - cam["cy"]) / cam["fy"], 1.0])
+        out.append(d / np.linalg.norm(d))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("levels", [2, 3, 4, 5])
+def test_shading_level_blend_closed_form(levels):
+    """Eq. 12 with roughness selecting the prefiltered level (reading: level = clamp(R,0,1)
+    (L-1), linear between the two levels around it). With constant levels c_l, a constant
+    split-sum table (A, B) and constant irradiance E the shaded colour is exactly
+    albedo/pi (1-M) E + lerp(c_floor, c_ceil, frac) (F0 A + B), F0 = 0.04 (1-M) + albedo M.
+    Roughness values sit on every level boundary, between them, and outside [0,1] (clamped).
+    A wrong mapping (R^2, R L, reversed levels) or a wrong level offset picks other
+    constants."""
+    n = 8
+    A, B = 0.63, 0.21
+    lut_ab = np.empty((n, n, 2))
+    lut_ab[..., 0], lut_ab[..., 1] = A, B
+    E = np.array([0.9, 1.3, 2.1])
+    tabs = _level_tables(levels, 32, lut_ab, 1.0)
+    tabs["irr"][...] = E
+    cam = camera(16, 16)
+    rough = sorted(set([l / (levels - 1) for l in range(levels)] +
+                       [(l + f) / (levels - 1) for l in range(levels - 1)
+                        for f in (0.25, 0.5, 0.9)] + [-0.3, 1.4]))
+    P = len(rough)
+    rng = np.random.default_rng(levels)
+    pix = rng.integers(2, 14, size=(P, 2)).astype(np.int32)
+    g = np.zeros((P, 8))
+    g[:, 0:3] = rng.uniform(0.1, 0.9, (P, 3))
+    g[:, 3] = rng.uniform(0, 1, P)
+    g[:, 4] = rough
+    g[:, 5:8] = -_pixel_dirs(cam, pix) + 0.2 * rng.normal(size=(P, 3))
+    rgb, _ = oracle.shade_gbuffer(g, np.ones(P), cam, pix, tabs)
+    for p in range(P):
+        lev = min(max(rough[p], 0.0), 1.0) * (levels - 1)
+        l0 = min(int(np.floor(lev)), levels - 1)
+        l1 = min(l0 + 1, levels - 1)
+        f = lev - l0
+        c0 = np.array([1.0 + l0, 10.0 + 3.0 * l0, 0.5 * l0])
+        c1 = np.array([1.0 + l1, 10.0 + 3.0 * l1, 0.5 * l1])
+        Lp = (1 - f) * c0 + f * c1
+        M = g[p, 3]
+        F0 = 0.04 * (1 - M) + g[p, 0:3] * M
+        want = g[p, 0:3] / math.pi * (1 - M) * E + Lp * (F0 * A + B)
+        np.testing.assert_allclose(rgb[p], want, rtol=1e-12, atol=1e-12,
+                                   err_msg=f"R={rough[p]} L={levels}")
+
+
+def test_shading_lut_axes_closed_form():
+    """The split-sum table is read at (column = clamp(N.V,0,1), row = clamp(R,0,1)), bilinear at
+    texel centres: with A affine in the column and B affine in the row, interior lookups return
+    the affine values exactly, so transposed or flipped axes fail. One level (L = 1), constant
+    radiance c: colour = albedo/pi (1-M) E + c (F0 A + B)."""
+    n = 16
+    xc = (np.arange(n) + 0.5) / n
+    lut_ab = np.empty((n, n, 2))
+    lut_ab[..., 0] = (0.2 + 0.5 * xc)[None, :]     # A(N.V): varies along columns
+    lut_ab[..., 1] = (0.05 + 0.3 * xc)[:, None]    # B(R): varies along rows
+    c = 1.6
+    tabs = _level_tables(1, 8, lut_ab, 0.0)
+    tabs["spec"][0][...] = c
+    cam = camera(16, 16)
+    rng = np.random.default_rng(5)
+    P = 24
+    pix = rng.integers(0, 16, size=(P, 2)).astype(np.int32)
+    d = _pixel_dirs(cam, pix)
+    wo = -d
+    g = np.zeros((P, 8))
+    g[:, 0:3] = rng.uniform(0.1, 0.9, (P, 3))
+    g[:, 3] = rng.uniform(0, 1, P)
+    g[:, 4] = rng.uniform(0.1, 0.9, P)
+    # normals tilted away from the view vector so that N.V spans the table's interior
+    for p in range(P):
+        axis = np.cross(wo[p], [0.0, 1.0, 0.0])
+        axis /= np.linalg.norm(axis)
+        ang = rng.uniform(0.3, 1.3)
+        nrm = math.cos(ang) * wo[p] + math.sin(ang) * axis
+        g[p, 5:8] = nrm * rng.uniform(0.3, 1.0)
+    rgb, _ = oracle.shade_gbuffer(g, np.ones(P), cam, pix, tabs)
+    for p in range(P):
+        N = g[p, 5:8] / np.linalg.norm(g[p, 5:8])
+        ndv = float(N @ wo[p])
+        assert 0.5 / n < ndv < 1 - 0.5 / n
+        A = 0.2 + 0.5 * ndv
+        B = 0.05 + 0.3 * g[p, 4]
+        M = g[p, 3]
+        F0 = 0.04 * (1 - M) + g[p, 0:3] * M
+        np.testing.assert_allclose(rgb[p], c * (F0 * A + B), rtol=1e-12, atol=1e-12)
