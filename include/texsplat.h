@@ -70,7 +70,7 @@ typedef struct ts_params {
     int32_t tex_format;          /* TS_TEX_*: texel layout of the atlas           [RGBN3] */
     const int32_t* chart_table;  /* device [n_charts][2]: texel offset of the chart's level 0
                                     and log2 of its side (0..5), for atlases of per-chart
-                                    resolutions (Sec. 6, adaptive allocation); NULL: every
+                                    resolutions (Sec. 5, adaptive allocation); NULL: every
                                     chart is tex_res a side, chart c at texel c * (texels of
                                     one chart with its mip chain if any)           [NULL] */
     int64_t atlas_texels;        /* texels in the atlas (bounds every chart-table entry; a
@@ -93,7 +93,7 @@ typedef struct ts_params {
 #define TS_SAMPLER_HARDWARE 2   /* texture-unit bilinear on an image atlas (Supp. Sec. 1 Eq.
                                    S1-S2); the gfx950 toolchain offers no image/texture
                                    instructions, so this returns TS_E_UNSUPPORTED              */
-#define TS_SAMPLER_TRILINEAR 3  /* mipmapping (Sec. 6): level lambda = log2(T rho), rho the
+#define TS_SAMPLER_TRILINEAR 3  /* mipmapping (Sec. 5): level lambda = log2(T rho), rho the
                                    larger of the pixel's two texture-space steps (the
                                    derivatives of (s,t) along the image axes from the closed-
                                    form (u,v)); lambda <= 0: level-0 bilinear, else bilinear on
@@ -334,14 +334,17 @@ int ts_raster_bwd_workspace(int32_t n_views, int32_t n, int64_t pair_capacity, s
  * Sec. 3.5-3.6): the irradiance cube E of Eq. 11 and every prefiltered level of the split-sum
  * specular term of Eq. 12. The shaded colour is linear in each texel; per covered pixel the
  * irradiance lookup at N receives dL/dC * albedo (1-M)/pi and the two specular lookups at the
- * reflected direction receive dL/dC * (F0 A + B) weighted (1-f) and f between the levels
- * around R (L-1), each spread over 4 texels by the bilinear weights. Empty pixels (alpha = 0,
- * background only) contribute nothing. Summed without floating-point atomics (records sorted
- * by texel, summed in pixel order): run-to-run identical.
+ * reflected direction receive dL/dC * V (F0 A + B) weighted (1-f) and f between the levels
+ * around R (L-1), each spread over 4 texels by the bilinear weights (V the pixel's
+ * visibility: with the indirect term the specular radiance is V L_pref + (1 - V) L_ind).
+ * Empty pixels (alpha = 0, background only) contribute nothing. Summed without
+ * floating-point atomics (records sorted by texel, summed in pixel order): run-to-run
+ * identical.
  *
  *   cams, env    as given to ts_raster_fwd / ts_raster_bwd
  *   gbuf, t_final  forward outputs of the same frame ([n_views][8][H][W], [n_views][H][W])
  *   d_rgba       [n_views][H][W][4] dL/d(rgb, alpha) (alpha does not reach the tables)
+ *   vis          [n_views][H][W] the visibility the frame was shaded with, or NULL: V = 1
  *   ws, ws_bytes scratch, at least ts_env_bwd_workspace(n_views, width, height) bytes
  *                (about 56 bytes per pixel)
  *   beta         0: overwrite the outputs; 1: add to them (any other value is TS_E_ARG)
@@ -352,8 +355,8 @@ int ts_raster_bwd_workspace(int32_t n_views, int32_t n, int64_t pair_capacity, s
  */
 int ts_env_bwd(int32_t n_views, int32_t width, int32_t height, const ts_camera* cams,
                const ts_env* env, const float* gbuf, const float* t_final, const float* d_rgba,
-               void* ws, size_t ws_bytes, float beta, float* d_irr, float* d_spec,
-               hipStream_t stream);
+               const float* vis, void* ws, size_t ws_bytes, float beta, float* d_irr,
+               float* d_spec, hipStream_t stream);
 
 /* Scratch bytes ts_env_bwd needs (host only). */
 int ts_env_bwd_workspace(int32_t n_views, int32_t width, int32_t height, size_t* bytes);

@@ -14,7 +14,7 @@
  *   - texture variants: tangent normals stored as two components with
  *     n_z = sqrt(max(0, 1 - n_x^2 - n_y^2)) rebuilt after filtering          (Sec. 3.5.1)
  *     per-primitive texture resolution and trilinear filtering over a box-filtered mip chain
- *     (the adaptive allocation and mipmapping the paper names as open)      (Sec. 6)
+ *     (the adaptive allocation and mipmapping the paper names as open)      (Sec. 5)
  *   - tangent normal rotated to world space, n = R n^t                      (Eq. 7)
  *   - G-buffers X = [albedo, metallic, roughness, normal]                   (Eq. 9)
  *   - split-sum shading L_o = L_d + L_s against an environment cubemap      (Eq. 10-12)

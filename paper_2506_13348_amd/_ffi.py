@@ -60,7 +60,8 @@ _SIGS = {
                         c_void_p, c_void_p, c_float, c_void_p, c_void_p, c_void_p, c_void_p],
     "ts_raster_bwd_workspace": [c_int32, c_int32, c_int64, ctypes.POINTER(c_size_t)],
     "ts_env_bwd": [c_int32, c_int32, c_int32, c_void_p, ctypes.POINTER(TsEnv), c_void_p, c_void_p,
-                   c_void_p, c_void_p, c_size_t, ctypes.c_float, c_void_p, c_void_p, c_void_p],
+                   c_void_p, c_void_p, c_void_p, c_size_t, ctypes.c_float, c_void_p, c_void_p,
+                   c_void_p],
     "ts_env_bwd_workspace": [c_int32, c_int32, c_int32, ctypes.POINTER(c_size_t)],
     "ts_brdf_lut": [c_int32, c_int32, c_void_p, c_void_p],
     "ts_env_tables": [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p],
@@ -196,9 +197,10 @@ def ts_env_bwd_workspace(n_views, width, height):
 
 
 def ts_env_bwd(n_views, width, height, cams, env, gbuf, t_final, d_rgba, ws, beta, d_irr, d_spec,
-               stream=None):
+               stream=None, vis=None):
     _check(lib().ts_env_bwd(n_views, width, height, ptr(cams), ctypes.byref(env), ptr(gbuf),
-                            ptr(t_final), ptr(d_rgba), ptr(ws), ws.numel() * ws.element_size(),
+                            ptr(t_final), ptr(d_rgba), ptr(vis), ptr(ws),
+                            ws.numel() * ws.element_size(),
                             float(beta), ptr(d_irr), ptr(d_spec), stream_handle(stream)),
            "ts_env_bwd")
 

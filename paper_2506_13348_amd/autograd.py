@@ -82,7 +82,8 @@ class BackwardRunner:
 
 class EnvBackward:
     """Workspace of ts_env_bwd for one render plan: gradients of the loss with respect to the
-    texels of the plan's shading tables (irradiance cube and prefiltered levels)."""
+    texels of the plan's shading tables (irradiance cube and prefiltered levels); a plan with
+    the indirect term passes its visibility, which weights the specular tables' share."""
 
     def __init__(self, plan: RenderPlan):
         self.plan = plan
@@ -98,7 +99,8 @@ class EnvBackward:
         if p.gbuf is None or p.t_final is None:
             raise RuntimeError("environment gradients need the plan's G-buffers (gbuf=True)")
         F.ts_env_bwd(p.V, p.W, p.H, p.cams, p.scene.tables.struct, p.gbuf, p.t_final,
-                     d_rgba.contiguous(), self.ws, beta, self.d_irr, self.d_spec, p.stream)
+                     d_rgba.contiguous(), self.ws, beta, self.d_irr, self.d_spec, p.stream,
+                     vis=p.vis)
         return self.d_irr, self.d_spec
 
 

@@ -1,5 +1,5 @@
 // Atlas variants (once per scene): texel layout conversion, chart strides with room for the
-// mip chain, and the box-filtered chain itself (Sec. 3.5.1 two-component normals; Sec. 6
+// mip chain, and the box-filtered chain itself (Sec. 3.5.1 two-component normals; Sec. 5
 // adaptive resolution and mipmapping).
 //
 // A chart holds level 0 (T x T texels, row-major) and, for trilinear sampling, levels

@@ -4,8 +4,9 @@
 // splats, Sec. 3.5-3.6; Eq. 11-12 read the tables through bilinear cube lookups).
 //
 // The shaded colour is linear in each table texel: per pixel, dL/dE = dL/dC * albedo (1-M)/pi
-// at the irradiance lookup of N, and dL/dL_pref = dL/dC * (F0 A + B) split between the two
-// levels around R (L-1) at the lookup of the reflected direction. Each lookup spreads its
+// at the irradiance lookup of N, and dL/dL_pref = dL/dC * V (F0 A + B) split between the two
+// levels around R (L-1) at the lookup of the reflected direction (V the pixel's visibility:
+// with the indirect term the specular radiance is V L_pref + (1 - V) L_ind, Eq. 12). Each lookup spreads its
 // gradient over 4 texels with the bilinear weights.
 //
 // Deterministic without floating-point atomics:
@@ -34,6 +35,7 @@ struct EnvBwdArgs {
     const float* gbuf;       // [V][8][H][W]
     const float* t_final;    // [V][H][W]
     const float4* d_rgba;    // [V][H][W]
+    const float* vis;        // [V][H][W] visibility or null (V = 1)
     uint32_t* keys;          // [P * 12]
     float4* vals;            // [P * 12]
     int n_irr;               // texels of the irradiance cube (6 r^2)
@@ -112,9 +114,10 @@ __global__ __launch_bounds__(256) void k_env_records(EnvBwdArgs a) {
     float kd = (1.f - M) * ipi;
     float dE[3], dP0[3], dP1[3];
     float dCv[3] = {dC.x, dC.y, dC.z};
+    const float vis = a.vis ? a.vis[gid] : 1.0f;
     for (int c = 0; c < 3; c++) {
         float F0 = 0.04f * (1.f - M) + g[c] * M;
-        float dLp = dCv[c] * (F0 * ab.x + ab.y);
+        float dLp = dCv[c] * vis * (F0 * ab.x + ab.y);
         dE[c] = dCv[c] * g[c] * kd;
         dP0[c] = dLp * (1.f - fl);
         dP1[c] = dLp * fl;
@@ -344,8 +347,8 @@ extern "C" int ts_env_bwd_workspace(int32_t n_views, int32_t width, int32_t heig
 
 extern "C" int ts_env_bwd(int32_t n_views, int32_t width, int32_t height, const ts_camera* cams,
                           const ts_env* env, const float* gbuf, const float* t_final,
-                          const float* d_rgba, void* ws, size_t ws_bytes, float beta,
-                          float* d_irr, float* d_spec, hipStream_t stream) {
+                          const float* d_rgba, const float* vis, void* ws, size_t ws_bytes,
+                          float beta, float* d_irr, float* d_spec, hipStream_t stream) {
     // texels no record reaches are left as they are, so only these two modes are exact
     if (beta != 0.f && beta != 1.f) {
         set_error("ts_env_bwd: beta must be 0 (overwrite) or 1 (accumulate), got %g", (double)beta);
@@ -397,7 +400,7 @@ extern "C" int ts_env_bwd(int32_t n_views, int32_t width, int32_t height, const 
     a.env.spec = (const float4*)env->spec; a.env.irr = (const float4*)env->irr;
     a.env.lut = (const float2*)env->lut; a.env.spec_res = env->spec_res;
     a.env.levels = env->spec_levels; a.env.irr_res = env->irr_res; a.env.lut_res = env->lut_res;
-    a.gbuf = gbuf; a.t_final = t_final; a.d_rgba = (const float4*)d_rgba;
+    a.gbuf = gbuf; a.t_final = t_final; a.d_rgba = (const float4*)d_rgba; a.vis = vis;
     a.keys = keys; a.vals = vals; a.n_irr = (int)n_irr;
     int64_t P = (int64_t)n_views * width * height;
     hipLaunchKernelGGL(k_env_records, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, stream, a);

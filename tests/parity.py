@@ -1,82 +1,106 @@
-"""Comparison of HIP outputs with the FP64 oracle, pixel by pixel.
+"""Comparison of HIP outputs with the FP64 oracle, pixel by pixel, in two stages.
 
-Tolerances (float32 path against the float64 definition): alpha max-abs 1e-5, G-buffer
-channels max-abs 1e-5, linear RGB max-abs 1e-4 plus the first-order effect of the G-buffer
-tolerance, sens * 1e-5, where sens = sum_c max_rgb |dC/dg_c| is the oracle's own
-finite-difference sensitivity of the shading to the blended maps. Where sens * 1e-5 exceeds
-1e-4 the pixel is counted as ill-conditioned (typically a low-coverage pixel, whose normal is
-normalised from a short blended vector, in front of a high-contrast environment texel).
+Stage 1 (blending): alpha within 1e-5 and every G-buffer channel (albedo, metallic,
+roughness, normal; the blended L_ind map when present) within 1e-5 of the oracle.
+Stage 2 (shading): the HIP shaded linear RGB within a strict 1e-4 of the oracle's shading of
+the HIP path's own G-buffer (the same blended maps and alpha, shaded in float64). Only
+cube-face ties (the two largest direction components within 1e-5 relative, where either face
+is a correct lookup) are exempt, and they are counted.
+End to end: HIP RGB against the oracle's own RGB at 1e-4 is reported as a count of misses.
+A glossy lookup into a log-normal environment turns the 1e-5 that stage 1 allows into more
+than 1e-4 of radiance on a few pixels (a short blended normal normalised on a low-coverage
+pixel, a high-contrast texel), so the end-to-end bar is a bound on the number of such pixels,
+not a per-pixel bar.
+
 A pixel whose oracle result has near-threshold decisions (support edge, alpha cut-off,
-termination) passes if the HIP value matches the primary oracle result or one of the
-alternates with that decision flipped."""
+termination) passes stage 1 if the HIP values match the primary oracle result or one of the
+alternates rendered with that decision flipped."""
 import numpy as np
+
+import oracle
 
 TOL_RGB = 1e-4
 TOL_A = 1e-5
 TOL_G = 1e-5
+TIE_GAP = 1e-5
+E2E_FRAC = 0.005
 
 
-def pixel_match(gpu_rgba, gpu_gbuf, ref, tol_rgb=TOL_RGB, tol_a=TOL_A, tol_g=TOL_G,
-                check_rgb=True, gpu_gind=None, skip_graze=False):
-    """gpu_rgba [P,4], gpu_gbuf [P,8] or None, gpu_gind [P,3] (blended indirect map) or None,
-    ref = oracle.render output for the same pixels. Returns (ok [P] bool, info dict).
+def pixel_match(gpu_rgba, gpu_gbuf, ref, cam, pixels, tabs, gpu_gind=None, vis=None,
+                params=None, check_rgb=True, skip_graze=False):
+    """gpu_rgba [P,4] and gpu_gbuf [P,8] (albedo 3, metallic, roughness, normal 3) of the HIP
+    path at pixels [P,2] (x,y) of camera cam; gpu_gind [P,3] the blended indirect map or
+    None; vis [P] the visibility or None (V = 1); ref = oracle.render of the same pixels;
+    tabs = the oracle's shading tables of the scene. Returns (ok [P] bool, info dict).
 
     skip_graze: pixels that blend a splat seen nearly edge-on (the oracle's grazing flag,
-    |cos(ray, normal)| below its `graze` parameter) are not held to the G-buffer bar: the
-    float32 closed-form (u,v) loses about 1/|cos| of its precision there, and a
-    high-resolution chart turns that into texture error. They are counted in the info."""
+    |cos(ray, normal)| below its `graze` parameter) are not held to the G-buffer bar of stage
+    1 (the float32 closed-form (u,v) loses about 1/|cos| of its precision there and a
+    high-resolution chart turns that into texture error); alpha, the L_ind map and stage 2
+    still apply to them. They are counted."""
     P = len(ref["rgba"])
-    sens = ref["stat"][:, 6]
-    tol_pix = tol_rgb + sens * tol_g
+    graze = ref["stat"][:, 3] > 0
+    gb_mask = ~graze if skip_graze else np.ones(P, bool)
 
-    def ok_against(rr, gg, gi):
-        ok = np.abs(gpu_rgba[:, 3] - rr[:, 3]) <= tol_a
-        if check_rgb:
-            ok &= np.abs(gpu_rgba[:, :3] - rr[:, :3]).max(axis=1) <= tol_pix
-        if gpu_gbuf is not None:
-            ok &= np.abs(gpu_gbuf - gg).max(axis=1) <= tol_g
+    def stage1(rr, gg, gi):
+        ok = np.abs(gpu_rgba[:, 3] - rr[:, 3]) <= TOL_A
+        ok &= ~gb_mask | (np.abs(gpu_gbuf - gg).max(axis=1) <= TOL_G)
         if gpu_gind is not None:
-            ok &= np.abs(gpu_gind - gi).max(axis=1) <= tol_g
+            ok &= np.abs(gpu_gind - gi).max(axis=1) <= TOL_G
         return ok
 
-    ok_primary = ok_against(ref["rgba"], ref["gbuf"], ref["gind"])
-    ok = ok_primary.copy()
+    ok1 = stage1(ref["rgba"], ref["gbuf"], ref["gind"])
+    ok1_primary = ok1.copy()
+    e2e = np.abs(gpu_rgba[:, :3] - ref["rgba"][:, :3]).max(axis=1)
     n_alt = ref["stat"][:, 5].astype(int)
     for a in range(ref["alt_rgba"].shape[1]):
         has = n_alt > a
         if not has.any():
             continue
-        ok |= has & ok_against(ref["alt_rgba"][:, a], ref["alt_gbuf"][:, a],
-                               ref["alt_gind"][:, a])
-    graze = ref["stat"][:, 3] > 0
-    matched_alt = int((ok & ~ok_primary).sum())
-    if skip_graze:
-        ok |= graze
-    err_rgb = np.abs(gpu_rgba[:, :3] - ref["rgba"][:, :3]).max(axis=1)
-    err_a = np.abs(gpu_rgba[:, 3] - ref["rgba"][:, 3])
+        ok1 |= has & stage1(ref["alt_rgba"][:, a], ref["alt_gbuf"][:, a], ref["alt_gind"][:, a])
+        e_alt = np.abs(gpu_rgba[:, :3] - ref["alt_rgba"][:, a, :3]).max(axis=1)
+        e2e = np.where(has, np.minimum(e2e, e_alt), e2e)
+
+    ok = ok1.copy()
+    info = {"pixels": P}
+    if check_rgb:
+        shaded, gap = oracle.shade_gbuffer(gpu_gbuf, gpu_rgba[:, 3], cam, pixels, tabs,
+                                           params=params, gind=gpu_gind, vis=vis)
+        err2 = np.abs(gpu_rgba[:, :3] - shaded).max(axis=1)
+        tie = gap < TIE_GAP
+        ok2 = tie | (err2 <= TOL_RGB)
+        ok &= ok2
+        info.update({
+            "fail_shade": int((~ok2).sum()),
+            "face_ties": int(tie.sum()),
+            "max_err_shade": float(err2[~tie].max(initial=0.0)),
+            "e2e_over_1e-4": int((e2e > TOL_RGB).sum()),
+            "max_err_e2e": float(e2e.max(initial=0.0)),
+            "p99_err_e2e": float(np.percentile(e2e, 99)) if P else 0.0,
+        })
     clear = ref["stat"][:, 2] == 0
-    well = clear & (sens * tol_g <= tol_rgb)
-    info = {
-        "pixels": P,
+    err_a = np.abs(gpu_rgba[:, 3] - ref["rgba"][:, 3])
+    err_g = np.abs(gpu_gbuf - ref["gbuf"]).max(axis=1)
+    info.update({
         "fail": int((~ok).sum()),
+        "fail_blend": int((~ok1).sum()),
         "ambiguous": int((~clear).sum()),
-        "matched_alternate": matched_alt,
-        "ill_conditioned": int((clear & ~well).sum()),
-        "over_strict_rgb_tol": int((err_rgb > tol_rgb).sum()),
-        "max_err_rgb_well_conditioned": float(err_rgb[well].max(initial=0.0)),
-        "p99_err_rgb": float(np.percentile(err_rgb[clear], 99)) if clear.any() else 0.0,
+        "matched_alternate": int((ok1 & ~ok1_primary).sum()),
         "max_err_alpha_unambiguous": float(err_a[clear].max(initial=0.0)),
-    }
-    if skip_graze:
-        info["grazing_excluded"] = int(graze.sum())
-    if gpu_gbuf is not None:
-        err_g = np.abs(gpu_gbuf - ref["gbuf"]).max(axis=1)
-        info["max_err_gbuf_unambiguous"] = float(err_g[clear].max(initial=0.0))
-        info["p99_err_gbuf"] = float(np.percentile(err_g[clear], 99)) if clear.any() else 0.0
+        "max_err_gbuf_unambiguous": float(err_g[clear & gb_mask].max(initial=0.0)),
+    })
     if gpu_gind is not None:
         err_i = np.abs(gpu_gind - ref["gind"]).max(axis=1)
         info["max_err_gind_unambiguous"] = float(err_i[clear].max(initial=0.0))
+    if skip_graze:
+        info["grazing_off_gbuf_bar"] = int(graze.sum())
     return ok, info
+
+
+def e2e_bound(info):
+    """The end-to-end count bar: at most 0.5% of the checked pixels (at least 2) may differ
+    from the oracle's RGB by more than 1e-4."""
+    return info["e2e_over_1e-4"] <= max(2, E2E_FRAC * info["pixels"])
 
 
 def gather(out, v, pixels):

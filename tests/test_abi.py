@@ -110,11 +110,11 @@ def test_host_side_argument_errors():
     assert L.ts_brdf_lut(0, 16, None, None) == -1
     assert L.ts_env_bwd_workspace(0, 8, 8, ctypes.byref(out)) == -1
     assert L.ts_env_bwd_workspace(2, 8, 8, ctypes.byref(out)) == 0 and out.value >= 2 * 64 * 12 * 36
-    assert L.ts_env_bwd(1, 8, 8, None, None, None, None, None, None, 0, ctypes.c_float(0.0),
-                        None, None, None) == -1
+    assert L.ts_env_bwd(1, 8, 8, None, None, None, None, None, None, None, 0,
+                        ctypes.c_float(0.0), None, None, None) == -1
     # beta other than 0 or 1 is refused before anything else is looked at
-    assert L.ts_env_bwd(1, 8, 8, None, None, None, None, None, None, 0, ctypes.c_float(0.5),
-                        None, None, None) == -1
+    assert L.ts_env_bwd(1, 8, 8, None, None, None, None, None, None, None, 0,
+                        ctypes.c_float(0.5), None, None, None) == -1
     assert b"beta must be 0" in L.ts_last_error()
 
 

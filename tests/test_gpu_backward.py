@@ -256,13 +256,17 @@ def test_autograd_function_matches_runner():
 
 # ------------------------------------------------------------ environment-table gradients
 
-def _env_ref(sc, cams, pix_list, ds, tabs):
+def _env_ref(sc, cams, pix_list, ds, tabs, vis_list=None):
     """Summed float64 reference of the table gradients over views, and their spread under
-    +-2^-23 moves of the splat parameters (taps at a texel boundary)."""
+    +-2^-23 moves of the splat parameters (taps at a texel boundary). vis_list: per view the
+    visibility of the listed pixels (scenes with the indirect term), or None."""
+    if vis_list is None:
+        vis_list = [None] * len(cams)
+
     def total(scene):
         irr, spec = 0.0, None
-        for cam, pix, d in zip(cams, pix_list, ds):
-            r = og.grads(scene, cam, pix, d, tabs, env=True)
+        for cam, pix, d, pv in zip(cams, pix_list, ds, vis_list):
+            r = og.grads(scene, cam, pix, d, tabs, env=True, vis=pv)
             irr = irr + r["irr"]
             spec = r["spec"] if spec is None else [a + b for a, b in zip(spec, r["spec"])]
         return [irr] + spec
@@ -274,11 +278,12 @@ def _env_ref(sc, cams, pix_list, ds, tabs):
     return ref, spread
 
 
-def _gpu_env_grads(sc, cams, W, H, d_rgba, beta_twice=False):
+def _gpu_env_grads(sc, cams, W, H, d_rgba, beta_twice=False, vis=None):
     P = _pkg()
     from paper_2506_13348_amd.autograd import EnvBackward
     ds = P.DeviceScene.from_dict(sc, device="cuda")
-    plan = P.RenderPlan(ds, cams, W, H, gbuf=True, aux=True)
+    plan = P.RenderPlan(ds, cams, W, H, gbuf=True, aux=True,
+                        vis=None if vis is None else torch.as_tensor(vis).cuda())
     plan.run()
     plan.check()
     eb = EnvBackward(plan)
@@ -369,6 +374,38 @@ def test_env_grads_sq300k_training_batch_sampled():
     ref, spread = _env_ref(sc, cams[:3], pix_v, ds, tabs)
     g, _, _ = _gpu_env_grads(sc, cams, 800, 800, d_all)
     _compare_env(g, ref, spread, "env sq300k")
+
+
+def test_env_grads_with_indirect_term_and_visibility():
+    """A frame shaded with the indirect term and mixed visibility: the specular levels receive
+    V (F0 A + B) dL/dC through their lookups (the direct light is weighted by V in Eq. 12),
+    the irradiance cube what it receives without the term. Two ragged crops against the
+    float64 reference with the same visibility."""
+    sc = synth.make_scene("sq300k_train", n=3000, env_res=16)
+    sc["env_levels"] = 3
+    sc["sh"] = synth.indirect_sh(np.random.default_rng(51), 3000, 2)
+    sc["sh_degree"] = 2
+    cams = [synth.crop_camera(c, 330, 340, 45, 37) for c in synth.config_cameras("sq300k_train")[:2]]
+    tabs = oracle.tables(sc["env"], sc["env_levels"])
+    pix = oracle.all_pixels(45, 37)
+    vis = synth.visibility(np.random.default_rng(52), 2, 37, 45)
+    rng = np.random.default_rng(53)
+    d_all = np.zeros((2, 37, 45, 4))
+    ds, vs = [], []
+    for v, cam in enumerate(cams):
+        li = oracle.indirect_eval(sc, cam, sc["sh"], sc["sh_degree"])
+        pv = vis[v][pix[:, 1], pix[:, 0]].astype(np.float64)
+        ref_f = oracle.render(sc, cam, pixels=pix, tabs=tabs, lind=li, vis=pv)
+        d, d4 = _upstream(rng, ref_f, (37, 45, 4))
+        d_all[v] = d4
+        ds.append(d)
+        vs.append(pv)
+    ref, spread = _env_ref(sc, cams, [pix, pix], ds, tabs, vis_list=vs)
+    g, _, _ = _gpu_env_grads(sc, cams, 45, 37, d_all, vis=vis)
+    _compare_env(g, ref, spread, "env indirect+vis")
+    # the visibility matters: the specular levels' reference differs from the V = 1 one
+    ref1, _ = _env_ref(sc, cams, [pix, pix], ds, tabs, vis_list=[np.ones(len(pix))] * 2)
+    assert np.abs(ref1[1] - ref[1]).max() > 0.1 * np.abs(ref[1]).max()
 
 
 # ------------------------------------------------------------ indirect-term gradients

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import synth
-from parity import TOL_RGB, gather, gather_ind, pixel_match, sample_pixels
+from parity import TOL_RGB, e2e_bound, gather, gather_ind, pixel_match, sample_pixels
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -120,12 +120,13 @@ def _frame_parity(sc, cam, out, vis, v=0, pixels=None, name="frame", max_fail=0)
     ref = oracle.render(sc, cam, pixels=pixels, lind=li, vis=pv)
     rgba, gb = gather(out, v, pixels)
     gi = gather_ind(out, v, pixels)
-    ok, info = pixel_match(rgba, gb, ref, gpu_gind=gi)
+    tabs = oracle.tables(sc["env"], sc["env_levels"])
+    ok, info = pixel_match(rgba, gb, ref, cam, pixels, tabs, gpu_gind=gi, vis=pv)
     _print(name, info)
     for b in np.nonzero(~ok)[0][:5]:
         print("  fail", pixels[b], "gpu", rgba[b], "ref", ref["rgba"][b], "stat", ref["stat"][b])
     assert info["fail"] <= max_fail, info
-    assert info["over_strict_rgb_tol"] <= max(2, 0.005 * info["pixels"]), info
+    assert e2e_bound(info), info
     assert gi is None or np.abs(ref["gind"]).max() > 0.1
     return info
 
@@ -163,7 +164,7 @@ def test_indirect_full_size_sampled():
     sc = _with_sh(synth.make_scene("sq100k"), 3)
     cams = synth.config_cameras("sq100k")
     vis = synth.visibility(np.random.default_rng(8), 64, 800, 800)
-    ds, out = _render(sc, cams, 800, 800, vis=vis)
+    ds, out = _render(sc, cams, 800, 800, vis=vis, gbuf=True)
     rng = np.random.default_rng(9)
     for v in (0, 37):
         pix = sample_pixels(rng, 800, 800, 160)

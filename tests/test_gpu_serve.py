@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 import synth
-from parity import gather, pixel_match, sample_pixels
+from parity import e2e_bound, gather, pixel_match, sample_pixels
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -57,12 +57,17 @@ def test_requests_in_the_mix_equal_requests_alone():
         n_exact += int(torch.equal(alone, r.output))
     print(f"[serve] {len(reqs)} requests, {n_exact} bit-identical alone vs mix, stats {srv.stats}")
     assert n_exact == len(reqs)
-    # two of them against the oracle
+    # two of them against the oracle: the same request rendered with G-buffers gives the
+    # served RGBA bit for bit, and its G-buffer and shading pass the two-stage check
     for r in reqs[:2]:
+        full = P.render(scenes[r.scene], [r.cam], r.width, r.height, gbuf=True)
+        assert torch.equal(full["rgba"][0], r.output)
         pix = sample_pixels(np.random.default_rng(r.rid), r.width, r.height, 40)
         ref = oracle.render(raw[r.scene], r.cam, pixels=pix)
-        ok, info = pixel_match(r.output.double().cpu().numpy()[pix[:, 1], pix[:, 0]], None, ref)
-        assert info["fail"] == 0, info
+        rgba, gb = gather(full, 0, pix)
+        tabs = oracle.tables(raw[r.scene]["env"], raw[r.scene]["env_levels"])
+        ok, info = pixel_match(rgba, gb, ref, r.cam, pix, tabs)
+        assert info["fail"] == 0 and e2e_bound(info), info
 
 
 def test_pair_overflow_is_rerendered():

@@ -1,6 +1,6 @@
 """Pins of the oracle's texture variants: two-component tangent normals (Sec. 3.5.1),
 per-chart texture resolution and trilinear filtering over a box-filtered mip chain (the
-adaptive allocation and mipmapping of Sec. 6).
+adaptive allocation and mipmapping of Sec. 5).
 
 Expected values come from other routes: unit normals rebuilt from two components against the
 three-component render; for a splat parallel to the image plane the texture coordinate is
