@@ -511,31 +511,40 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_ranges(const uint32_t* __re
 
 using namespace ts;
 
-extern "C" int ts_bin_sort(int32_t n_views, int32_t width, int32_t height, int32_t n,
-                           const int32_t* rect, const uint32_t* depth_key, void* ws,
-                           size_t ws_bytes, int64_t pair_capacity, int32_t* sorted_ids,
-                           int32_t* tile_ranges, int32_t* pair_ids, int64_t* n_pairs,
-                           int32_t* status, hipStream_t stream) {
+namespace ts {
+
+// Argument checks of ts_bin_sort and its scratch-array variant (no workspace involved).
+static int bin_sort_check(const char* who, int32_t n_views, int32_t width, int32_t height,
+                          int32_t n, const int32_t* rect, const uint32_t* depth_key,
+                          int64_t pair_capacity, const int32_t* sorted_ids,
+                          const int32_t* tile_ranges, const int32_t* pair_ids,
+                          const int64_t* n_pairs, const int32_t* status) {
     if (n_views < 1 || width < 1 || height < 1 || n < 0 || pair_capacity < 0 || !tile_ranges ||
         !n_pairs || !status || (n > 0 && (!rect || !depth_key || !sorted_ids)) ||
         (pair_capacity > 0 && !pair_ids)) {
-        set_error("ts_bin_sort: bad argument");
+        set_error("%s: bad argument", who);
         return TS_E_ARG;
     }
     if (pair_capacity > 0x7FFFFFFFLL) {
-        set_error("ts_bin_sort: pair_capacity above 2^31-1");
+        set_error("%s: pair_capacity above 2^31-1", who);
         return TS_E_ARG;
     }
+    if (tiles_x(width) + 1 > kBinLdsWords / 2) {
+        set_error("%s: %d tiles per row exceed the per-view limit", who, tiles_x(width));
+        return TS_E_ARG;
+    }
+    return TS_OK;
+}
+
+// The kernels of ts_bin_sort on a checked argument set and a workspace of at least
+// binsort_layout(...).total bytes. Every workspace word the kernels read is written by an
+// earlier kernel of the same call, so the workspace needs no clearing.
+static int bin_sort_enqueue(int32_t n_views, int32_t width, int32_t height, int32_t n,
+                            const int32_t* rect, const uint32_t* depth_key, char* w,
+                            int64_t pair_capacity, int32_t* sorted_ids, int32_t* tile_ranges,
+                            int32_t* pair_ids, int64_t* n_pairs, int32_t* status,
+                            hipStream_t stream) {
     BinSortLayout L = binsort_layout(n_views, n, width, height);
-    if (!ws || ws_bytes < L.total) {
-        set_error("ts_bin_sort: workspace %zu < %zu bytes", ws_bytes, L.total);
-        return TS_E_WORKSPACE;
-    }
-    if (L.ntx + 1 > kBinLdsWords / 2) {
-        set_error("ts_bin_sort: %d tiles per row exceed the per-view limit", L.ntx);
-        return TS_E_ARG;
-    }
-    char* w = (char*)ws;
     uint32_t* keys_a = (uint32_t*)(w + L.off_keys_a);
     uint32_t* keys_b = (uint32_t*)(w + L.off_keys_b);
     int32_t* vals_a = (int32_t*)(w + L.off_vals_a);
@@ -587,4 +596,23 @@ extern "C" int ts_bin_sort(int32_t n_views, int32_t width, int32_t height, int32
         hipLaunchKernelGGL(k_bin_fill, dim3(L.n_chunks * n_views), dim3(kWave), lds_fill, stream,
                            a, L.nty);
     return launch_check("ts_bin_sort(bin)");
+}
+
+}  // namespace ts
+
+extern "C" int ts_bin_sort(int32_t n_views, int32_t width, int32_t height, int32_t n,
+                           const int32_t* rect, const uint32_t* depth_key, void* ws,
+                           size_t ws_bytes, int64_t pair_capacity, int32_t* sorted_ids,
+                           int32_t* tile_ranges, int32_t* pair_ids, int64_t* n_pairs,
+                           int32_t* status, hipStream_t stream) {
+    int rc = bin_sort_check("ts_bin_sort", n_views, width, height, n, rect, depth_key,
+                            pair_capacity, sorted_ids, tile_ranges, pair_ids, n_pairs, status);
+    if (rc != TS_OK) return rc;
+    const size_t need = binsort_layout(n_views, n, width, height).total;
+    if (!ws || ws_bytes < need) {
+        set_error("ts_bin_sort: workspace %zu < %zu bytes", ws_bytes, need);
+        return TS_E_WORKSPACE;
+    }
+    return bin_sort_enqueue(n_views, width, height, n, rect, depth_key, (char*)ws, pair_capacity,
+                            sorted_ids, tile_ranges, pair_ids, n_pairs, status, stream);
 }
