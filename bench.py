@@ -37,23 +37,105 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(scene, cam, n_pix=200000, seed=0):
-    """The FP64 oracle on a bounded random sample of pixels of one view (tables precomputed)."""
-    import numpy as np
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_fwd(scene, cam, pix, threads, tabs=None):
+    """Seconds and contributing evaluations of the oracle forward on pixels pix."""
     import oracle
-    tabs = oracle.tables(scene["env"], scene["env_levels"])
-    rng = np.random.default_rng(seed)
-    pix = np.stack([rng.integers(0, cam["width"], n_pix), rng.integers(0, cam["height"], n_pix)],
-                   1).astype(np.int32)
+    oracle.set_threads(threads)
     t0 = time.perf_counter()
     out = oracle.render(scene, cam, pixels=pix, tabs=tabs)
-    dt = time.perf_counter() - t0
+    return time.perf_counter() - t0, float(out["stat"][:, 0].sum())
+
+
+def _oracle_fwd_bwd(scene, cam, pix, threads, tabs):
+    """Seconds of the float64 forward + backward (dense autograd reference) on pixels pix."""
+    import numpy as np
+    import torch
+    from oracle import grad as og
+    torch.set_num_threads(threads)
+    d = np.random.default_rng(1).normal(size=(len(pix), 4))
+    t0 = time.perf_counter()
+    og.grads(scene, cam, pix, d, tabs)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(scene, cam, n_pix=200000, seed=0):
+    """The FP64 oracle timed on the host cores. Headline value: the forward on a bounded random
+    sample of pixels of one view of the headline scene (tables precomputed), every thread.
+    Beside it (about 20 s more of oracle work): the same view on one core, the 2k-splat
+    128x128 frame in full, a pixel sample of the 1M-splat unbounded frame, and forward +
+    backward (the float64 reference gradients) on the 64x64 crop of 500 splats and on a pixel
+    sample of a 300k-splat training view."""
+    import numpy as np
+    import oracle
+    import synth
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = oracle.set_threads(threads)
+    tabs = oracle.tables(scene["env"], scene["env_levels"])
+    rng = np.random.default_rng(seed)
+
+    def sample(c, k):
+        return np.stack([rng.integers(0, c["width"], k), rng.integers(0, c["height"], k)],
+                        1).astype(np.int32)
+
+    pix = sample(cam, n_pix)
+    dt, ev = _oracle_fwd(scene, cam, pix, threads, tabs)
+    detail = {}
+    k1 = 3000
+    dt1, ev1 = _oracle_fwd(scene, cam, pix[:k1], 1, tabs)
+    detail["sq100k_view0_fwd_1core"] = {"pixels": k1, "s": round(dt1, 2),
+                                        "mpix_per_s": round(k1 / dt1 / 1e6, 6),
+                                        "evals_per_s": round(ev1 / dt1, 1)}
+    s1 = synth.make_scene("shell2k")
+    c1 = synth.config_cameras("shell2k")[0]
+    t1 = oracle.tables(s1["env"], s1["env_levels"])
+    full = oracle.all_pixels(c1["width"], c1["height"])
+    for th in (threads, 1):
+        d1, e1 = _oracle_fwd(s1, c1, full, th, t1)
+        detail[f"shell2k_frame_fwd_{th}threads"] = {"ms_per_frame": round(d1 * 1e3, 2),
+                                                    "mpix_per_s": round(len(full) / d1 / 1e6, 4),
+                                                    "evals_per_s": round(e1 / d1, 1)}
+    s4 = synth.make_scene("field1m")
+    c4 = synth.config_cameras("field1m")[0]
+    t4 = oracle.tables(s4["env"], s4["env_levels"])
+    k4 = 2000
+    d4, e4 = _oracle_fwd(s4, c4, sample(c4, k4), threads, t4)
+    detail["field1m_fwd_sample"] = {"pixels": k4, "of": "1600x1064, 1M splats", "s": round(d4, 2),
+                                    "mpix_per_s": round(k4 / d4 / 1e6, 6),
+                                    "evals_per_s": round(e4 / d4, 1)}
+    del s4
+    s3 = synth.make_scene("sq300k_train")
+    c3 = synth.config_cameras("sq300k_train")[0]
+    t3 = oracle.tables(s3["env"], s3["env_levels"])
+    crop, ccam = synth.fd_crop_scene(s3, c3, 368, 368, 64, 64, n_keep=500)
+    cpix = oracle.all_pixels(64, 64)
+    for th in (threads, 1):
+        dc = _oracle_fwd_bwd(crop, ccam, cpix, th, t3)
+        detail[f"crop64_500splats_fwd_bwd_{th}threads"] = {
+            "s": round(dc, 3), "mpix_per_s": round(len(cpix) / dc / 1e6, 5)}
+    k3 = 32
+    d3 = _oracle_fwd_bwd(s3, c3, sample(c3, k3), threads, t3)
+    detail["sq300k_view0_fwd_bwd_sample"] = {"pixels": k3, "of": "800x800, 300k splats",
+                                             "s": round(d3, 2),
+                                             "mpix_per_s": round(k3 / d3 / 1e6, 8)}
+    oracle.set_threads(threads)
     return {"value": round(n_pix / dt / 1e6, 6), "unit": "Mpix/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{n_pix} random pixels of orbit view 0 (800x800, 100k splats), "
                       f"{dt:.1f} s, shading tables precomputed",
-            "evals_per_s": round(float(out["stat"][:, 0].sum()) / dt, 1)}
+            "evals_per_s": round(ev / dt, 1),
+            "host": {"cpu_model": _cpu_model(), "cpus_visible": os.cpu_count()},
+            "detail": detail}
 
 
 FWD_BWD_WORKLOADS = {
@@ -377,11 +459,18 @@ def bench_tab3(steps=5):
     return out
 
 
-def bench_serving(duration, rate=200.0, warm=1.0):
+def bench_serving(duration, rate=200.0, warm=3.0, saturation=300):
     """Serving: 4 resident scenes (50k, 200k, 500k superquadric splats, 1M height-field
-    splats; T=8), a seeded Poisson stream at `rate` req/s, scene uniform, resolution uniform
-    over {256^2, 512^2, 800^2, 1920x1080}, random orbit cameras. The continuous-batching
-    server (4 stream slots, graph replays) against the plain one-at-a-time renderer."""
+    splats; T=8), a seeded Poisson stream at `rate` req/s for `duration` s (latencies of the
+    first `warm` s excluded), scene uniform, resolution uniform over {256^2, 512^2, 800^2,
+    1920x1080}, random orbit cameras. Three ways of serving the same stream: the
+    continuous-batching server (front parts on prep streams, each batch rendered by one
+    persistent launch replayed from a graph), the per-request server (one graph replay of the
+    whole path per request, 4 streams), and the plain renderer one request at a time. Then a
+    closed loop (`saturation` requests all arriving at once) gives each one's saturation
+    throughput. The plan-cache budget is 1.25x the bytes of one plan per (scene, resolution),
+    so it binds: second plan instances are made on demand until it is reached, then idle
+    plans are evicted."""
     import numpy as np
     import torch
 
@@ -406,25 +495,54 @@ def bench_serving(duration, rate=200.0, warm=1.0):
         for (W, H) in synth.SERVING_RESOLUTIONS:
             samples[(s, W, H)] = [synth.serving_camera(geos[s], W, H, srng.uniform(0, 2 * np.pi),
                                                        srng.uniform(0, 40)) for _ in range(3)]
-    srv = Server(scenes, slots=4, mem_budget=48 << 30, capacity_samples=samples)
-    srv.prepare([(k, v[0]) for k, v in samples.items()], per_key=2)
-    log(f"serving plans ready in {time.perf_counter() - t0:.1f}s: {srv.stats}")
+    capacity, budget = None, None
+    servers = {}
+    for mode in ("batch", "request"):
+        srv = Server(scenes, slots=4, mem_budget=1 << 62, capacity_samples=samples, mode=mode)
+        if capacity is not None:
+            srv.capacity = dict(capacity)
+        for k in samples:
+            srv._capacity(*k)
+        capacity = dict(srv.capacity)
+        if budget is None:
+            budget = int(1.25 * sum(srv._plan_size(*k) for k in samples))
+        srv.mem_budget = budget
+        srv.prepare([(k, v[0]) for k, v in samples.items()], per_key=1)
+        servers[mode] = srv
+        log(f"{mode} server plans ready in {time.perf_counter() - t0:.1f}s: {srv.stats}")
 
-    def fresh():
+    def fresh(closed=False):
+        if closed:
+            return [Request(i, 0.0, s, wh[0], wh[1], cams[i])
+                    for i, (t, s, wh, az, el) in enumerate(trace[:saturation])]
         return [Request(i, t, s, wh[0], wh[1], cams[i]) for i, (t, s, wh, az, el) in enumerate(trace)]
 
-    reqs = srv.serve(fresh())
-    rep = latency_report([r for r in reqs if r.arrival >= warm])
-    log(f"server: {rep}")
-    seq = serve_sequential(scenes, fresh(), srv.capacity)
-    rep_seq = latency_report([r for r in seq if r.arrival >= warm])
+    out = {"workload": f"4 resident scenes (50k/200k/500k/1M splats, T=8), Poisson {rate:g} req/s "
+                       f"for {duration:g} s (first {warm:g} s excluded from the latencies), "
+                       "resolutions 256^2/512^2/800^2/1920x1080, random orbit cameras; "
+                       f"closed loop: the first {saturation} requests all at t=0",
+           "plan_budget_bytes": budget}
+    for mode, srv in servers.items():
+        reqs = srv.serve(fresh())
+        rep = latency_report(reqs, warm)
+        log(f"{mode} server: {rep}")
+        sat = latency_report(srv.serve(fresh(closed=True)))
+        log(f"{mode} server, closed loop: {sat}")
+        out[f"server_{mode}"] = rep
+        out[f"server_{mode}_saturation_mpix_per_s"] = sat["mpix_per_s"]
+        out[f"server_{mode}_stats"] = dict(srv.stats)
+    del servers
+    torch.cuda.empty_cache()
+    seq = serve_sequential(scenes, fresh(), capacity)
+    rep_seq = latency_report(seq, warm)
     log(f"sequential: {rep_seq}")
-    return {"workload": f"4 resident scenes (50k/200k/500k/1M splats, T=8), Poisson {rate:g} req/s "
-                        f"for {duration:g} s (first {warm:g} s excluded), resolutions 256^2/512^2/"
-                        "800^2/1920x1080, random orbit cameras",
-            "server": rep, "sequential_plain": rep_seq,
-            "p99_speedup": round(rep_seq["p99_ms"] / rep["p99_ms"], 2),
-            "server_stats": srv.stats}
+    sat_seq = latency_report(serve_sequential(scenes, fresh(closed=True), capacity))
+    out["sequential_plain"] = rep_seq
+    out["sequential_plain_saturation_mpix_per_s"] = sat_seq["mpix_per_s"]
+    out["p99_speedup_batch_vs_sequential"] = round(rep_seq["p99_ms"] / out["server_batch"]["p99_ms"], 2)
+    out["saturation_speedup_batch_vs_sequential"] = round(
+        out["server_batch_saturation_mpix_per_s"] / sat_seq["mpix_per_s"], 2)
+    return out
 
 
 def calibration_copy(dev):
@@ -447,7 +565,7 @@ def main():
     ap.add_argument("--no-fwd-bwd", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-tab3", action="store_true")
-    ap.add_argument("--serving-seconds", type=float, default=5.0)
+    ap.add_argument("--serving-seconds", type=float, default=30.0)
     ap.add_argument("--profile-train", action="store_true",
                     help="only a few forward+backward steps of the 300k-splat training batch "
                          "(for counter collection)")

@@ -232,6 +232,58 @@ int ts_raster_fwd(int32_t n_views, int32_t width, int32_t height, const ts_camer
                   hipStream_t stream);
 
 /*
+ * Batched forward renders for serving (test-time rendering from resident atlases, Sec. 3.4 and
+ * Supp. Sec. 1): the ts_raster_fwd work of several jobs, each with its own scene, views,
+ * resolution and outputs, in one launch of a fixed persistent grid (every compute unit's
+ * resident workgroups). The (job, view, tile) work items are cut into one contiguous range
+ * per XCD; workgroups take items from their XCD's queue, then from the others, until all are
+ * done. Each job's output is the one ts_raster_fwd gives for the same arguments (the same
+ * per-tile code). The grid does not depend on the batch, so a single captured graph of
+ * ts_raster_batch serves every batch written into its table.
+ *
+ * A job is a shaded render on the default atlas path: sampler TS_SAMPLER_BILINEAR,
+ * tex_format TS_TEX_RGBN3, no chart table, no indirect term.
+ */
+typedef struct ts_raster_job {
+    int32_t n_views, width, height, n;   /* as ts_raster_fwd                               */
+    const ts_camera* cams;               /* device [n_views]                               */
+    const float* rec;                    /* device, from ts_preprocess                     */
+    const int32_t* tile_ranges;          /* device, from ts_bin_sort                       */
+    const int32_t* pair_ids;             /* device, from ts_bin_sort                       */
+    int64_t pair_capacity;
+    const float* atlas;                  /* device [n_charts][T][T][8]                     */
+    ts_params params;                    /* by value (see the restriction above)           */
+    ts_env env;                          /* by value: the job's shading tables (device)    */
+    float* rgba;                         /* device [n_views][H][W][4] out                  */
+    float* t_final;                      /* device [n_views][H][W] out, or NULL            */
+} ts_raster_job;
+
+/* Bytes of a batch table (host copy and device copy alike); it holds up to 64 jobs. */
+size_t ts_raster_batch_table_bytes(void);
+
+/*
+ * ts_raster_batch_encode — host only: checks jobs[0..n_jobs) (the checks of ts_raster_fwd) and
+ * writes the batch table to `table` (host memory of ts_raster_batch_table_bytes() bytes, e.g.
+ * pinned, that the caller then copies to a device table). n_jobs = 0 gives an empty batch.
+ * Errors: TS_E_ARG (a job's arguments, n_jobs outside 0..64, table too small, more than 2^31-1
+ *         tiles), TS_E_UNSUPPORTED (a job off the default atlas path or without rgba/env).
+ */
+int ts_raster_batch_encode(const ts_raster_job* jobs, int32_t n_jobs, void* table,
+                           size_t table_bytes);
+
+/*
+ * ts_raster_batch — renders every job of a device batch table in one persistent launch.
+ *   table  device copy of a table written by ts_raster_batch_encode; read when the kernel
+ *          runs, so a graph replay renders whatever the table holds at that time
+ *   queue  device [16] uint32 work counters, zero before the first call (e.g. from a zeroed
+ *          allocation); each launch leaves them zero for the next. Launches that share a queue
+ *          must not overlap (use one queue per concurrently running launch).
+ * The launch allocates nothing and never synchronises the host.
+ * Errors: TS_E_ARG (null table or queue), TS_E_LAUNCH.
+ */
+int ts_raster_batch(const void* table, uint32_t* queue, hipStream_t stream);
+
+/*
  * ts_shade — deferred split-sum shading of given G-buffers (Eq. 10-12): with N^ = N/|N|
  * (the view vector if |N| = 0), w_o the unit vector to the camera,
  * w_r = 2 (N^.w_o) N^ - w_o, level = clamp(R,0,1) (L-1):

@@ -58,7 +58,7 @@ def lib():
             L = ctypes.CDLL(_LIB)
             for name in ["or_irradiance", "or_prefilter", "or_brdf_lut", "or_render", "or_shade",
                          "or_cube_sample", "or_cube_texels", "or_lut_sample", "or_splat_setup",
-                         "or_sh_basis", "or_indirect_eval"]:
+                         "or_sh_basis", "or_indirect_eval", "or_set_threads"]:
                 getattr(L, name).restype = ctypes.c_int
             _lib = L
     return _lib
@@ -66,6 +66,11 @@ def lib():
 
 def _p(a):
     return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def set_threads(n=0):
+    """Host threads of the oracle's OpenMP loops (n > 0 sets them); returns the count in use."""
+    return int(lib().or_set_threads(int(n)))
 
 
 def _f32(a):

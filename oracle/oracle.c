@@ -46,6 +46,7 @@
  * re-rendered with that decision flipped, and both results are returned.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -891,4 +892,11 @@ int or_indirect_eval(int n, const float* means, const float* quats, const float*
         for (int c = 0; c < 3; c++) out[3 * (size_t)k + c] = acc[c] > 0 ? acc[c] : 0.0;
     }
     return 0;
+}
+
+/* Thread count of the OpenMP loops above (n > 0 sets it); returns the count in effect. Used
+   only to time the oracle on a given number of host cores. */
+int or_set_threads(int n) {
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
 }

@@ -5,6 +5,6 @@ Python here only marshals arguments: `_ffi` mirrors the C entry points one to on
 keeps scenes and buffers on the device and enqueues the kernels."""
 from . import _ffi
 from ._ffi import lib
-from .render import DeviceScene, EnvTables, RenderPlan, cameras_tensor, render
+from .render import BatchRaster, DeviceScene, EnvTables, RenderPlan, cameras_tensor, render
 
-__all__ = ["DeviceScene", "EnvTables", "RenderPlan", "cameras_tensor", "render", "lib", "_ffi"]
+__all__ = ["BatchRaster", "DeviceScene", "EnvTables", "RenderPlan", "cameras_tensor", "render", "lib", "_ffi"]

@@ -34,6 +34,13 @@ class TsEnv(ctypes.Structure):
                 ("irr", c_void_p), ("irr_res", c_int32), ("lut", c_void_p), ("lut_res", c_int32)]
 
 
+class TsRasterJob(ctypes.Structure):
+    _fields_ = [("n_views", c_int32), ("width", c_int32), ("height", c_int32), ("n", c_int32),
+                ("cams", c_void_p), ("rec", c_void_p), ("tile_ranges", c_void_p),
+                ("pair_ids", c_void_p), ("pair_capacity", c_int64), ("atlas", c_void_p),
+                ("params", TsParams), ("env", TsEnv), ("rgba", c_void_p), ("t_final", c_void_p)]
+
+
 _SIGS = {
     "ts_workspace_size": [c_int32, c_int32, c_int32, c_int32, c_int32, ctypes.POINTER(c_size_t)],
     "ts_preprocess": [c_int32, c_int32, c_int32, c_void_p, ctypes.POINTER(TsParams), c_int32,
@@ -71,9 +78,12 @@ _SIGS = {
                        c_void_p],
     "ts_atlas_mips": [c_void_p, c_int32, c_int32, c_void_p, c_int32, c_int64, c_int32, c_void_p],
     "ts_locality_perm_workspace": [c_int32, ctypes.POINTER(c_size_t)],
+    "ts_raster_batch_encode": [ctypes.POINTER(TsRasterJob), c_int32, c_void_p, c_size_t],
+    "ts_raster_batch": [c_void_p, c_void_p, c_void_p],
 }
 
-EXPORTS = tuple(_SIGS) + ("ts_last_error",)
+_SIZE_FNS = ("ts_raster_batch_table_bytes",)
+EXPORTS = tuple(_SIGS) + ("ts_last_error",) + _SIZE_FNS
 
 _lib = None
 
@@ -92,6 +102,9 @@ def lib():
             f.restype = c_int32
         L.ts_last_error.restype = ctypes.c_char_p
         L.ts_last_error.argtypes = []
+        for name in _SIZE_FNS:
+            getattr(L, name).restype = c_size_t
+            getattr(L, name).argtypes = []
         _lib = L
     return _lib
 
@@ -170,6 +183,37 @@ def ts_bin_sort(n_views, width, height, n, rect, depth_key, ws, pair_capacity, s
                              ws.numel() * ws.element_size(), pair_capacity, ptr(sorted_ids),
                              ptr(tile_ranges), ptr(pair_ids), ptr(n_pairs), ptr(status),
                              stream_handle(stream)), "ts_bin_sort")
+
+
+def ts_raster_batch_table_bytes():
+    return int(lib().ts_raster_batch_table_bytes())
+
+
+def make_raster_job(n_views, width, height, cams, params, n, rec, tile_ranges, pair_ids,
+                    pair_capacity, atlas, env, rgba, t_final=None):
+    """A ts_raster_job of device tensors (the caller keeps them alive while the job is used)."""
+    j = TsRasterJob()
+    j.n_views, j.width, j.height, j.n = int(n_views), int(width), int(height), int(n)
+    j.cams, j.rec, j.tile_ranges = ptr(cams), ptr(rec), ptr(tile_ranges)
+    j.pair_ids, j.pair_capacity, j.atlas = ptr(pair_ids), int(pair_capacity), ptr(atlas)
+    j.params, j.env = params, env
+    j.rgba, j.t_final = ptr(rgba), ptr(t_final)
+    return j
+
+
+def ts_raster_batch_encode(jobs, table):
+    """Encode a list of TsRasterJob into `table` (a host uint8 tensor, e.g. pinned)."""
+    arr = (TsRasterJob * max(len(jobs), 1))(*jobs)
+    if table.is_cuda or not table.is_contiguous():
+        raise ValueError("the batch table is encoded in contiguous host memory")
+    _check(lib().ts_raster_batch_encode(arr, len(jobs), ctypes.c_void_p(table.data_ptr()),
+                                        table.numel() * table.element_size()),
+           "ts_raster_batch_encode")
+
+
+def ts_raster_batch(table, queue, stream=None):
+    _check(lib().ts_raster_batch(ptr(table), ptr(queue), stream_handle(stream)),
+           "ts_raster_batch")
 
 
 def ts_raster_fwd(n_views, width, height, cams, params, n, rec, tile_ranges, pair_ids,

@@ -8,6 +8,15 @@
 // evaluation well conditioned. The hit is in front of the camera iff n.mu and n.d share a
 // sign; all coefficients are multiplied by sign(n.mu) so that the test becomes den > 0.
 // The per-splat set-up runs in double precision; records are stored as float32.
+//
+// The camera's rotation W arrives in float32 and is orthogonal only to rounding (~1e-7),
+// while a pixel's ray is defined in the world as W^T d (with origin o = -W^T t). The camera
+// frame is therefore taken as the one in which those rays are d: points map by A = W^{-T}
+// (p_cam = A (p - o) = A p + t) and the vectors that enter dot products with rays (the
+// normal and the in-plane axes, as covectors) by W. With g_u = W t_u, g_v = W t_v, n = W n_w
+// the numerators take the general form a_u = (n.mu) g_u - (mu.g_u) n (and likewise a_v),
+// equal to the cross products above for an orthonormal frame. (Mapping points by W instead
+// shifts (u,v) by about 1e-7 / |cos| of the ray-normal angle, visible on near edge-on splats.)
 #include <math.h>
 
 #include "ts_internal.h"
@@ -28,16 +37,32 @@ struct PreArgs {
     uint32_t* depth_key;
 };
 
-__device__ inline void cross3(const double* a, const double* b, double* c) {
-    c[0] = a[1] * b[2] - a[2] * b[1];
-    c[1] = a[2] * b[0] - a[0] * b[2];
-    c[2] = a[0] * b[1] - a[1] * b[0];
-}
 __device__ inline double dot3(const double* a, const double* b) {
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
 __device__ void preprocess_one(const PreArgs& a, int64_t gid, float4* r4);
+
+// A = W^{-T} of a 3x3 row-major matrix: its cofactor matrix over its determinant.
+__device__ inline void cam_points_map(const double* W, double* A) {
+    double C[9] = {W[4] * W[8] - W[5] * W[7], W[5] * W[6] - W[3] * W[8], W[3] * W[7] - W[4] * W[6],
+                   W[2] * W[7] - W[1] * W[8], W[0] * W[8] - W[2] * W[6], W[1] * W[6] - W[0] * W[7],
+                   W[1] * W[5] - W[2] * W[4], W[2] * W[3] - W[0] * W[5], W[0] * W[4] - W[1] * W[3]};
+    double id = 1.0 / (W[0] * C[0] + W[1] * C[1] + W[2] * C[2]);
+    for (int i = 0; i < 9; i++) A[i] = C[i] * id;
+}
+
+// a_u = (n.mu) g_u - (mu.g_u) n and a_v = (n.mu) g_v - (mu.g_v) n: with a pixel ray d,
+// u = a_u.d / (s_u n.d) and v = a_v.d / (s_v n.d) (a_u.mu = a_v.mu = 0).
+__device__ inline void plane_numerators(const double* nc, const double* mc, double nmu,
+                                        const double* gu, const double* gv, double* au,
+                                        double* av) {
+    double mgu = dot3(mc, gu), mgv = dot3(mc, gv);
+    for (int i = 0; i < 3; i++) {
+        au[i] = nmu * gu[i] - mgu * nc[i];
+        av[i] = nmu * gv[i] - mgv * nc[i];
+    }
+}
 
 // Records leave through LDS: each thread builds its 7 float4 there, then the workgroup
 // writes its 256 consecutive records (28 KB) with consecutive lanes on consecutive float4s
@@ -77,9 +102,11 @@ __device__ void preprocess_one(const PreArgs& a, int64_t gid, float4* r4) {
     float op = a.opac[k];
     bool keep = z > (double)a.near_z && op >= a.amin;
 
+    // A = W^{-T} (cofactor matrix over the determinant): camera-frame points
+    double A[9];
+    cam_points_map(Wr, A);
     double mc[3];
-    for (int i = 0; i < 3; i++) mc[i] = Wr[i * 3 + 0] * mu[0] + Wr[i * 3 + 1] * mu[1] + Wr[i * 3 + 2] * mu[2] + t[i];
-    mc[2] = z;
+    for (int i = 0; i < 3; i++) mc[i] = A[i * 3 + 0] * mu[0] + A[i * 3 + 1] * mu[1] + A[i * 3 + 2] * mu[2] + t[i];
 
     // rotation of the normalised quaternion; columns t_u, t_v, n
     double q[4] = {a.quats[4 * k + 0], a.quats[4 * k + 1], a.quats[4 * k + 2], a.quats[4 * k + 3]};
@@ -89,11 +116,14 @@ __device__ void preprocess_one(const PreArgs& a, int64_t gid, float4* r4) {
     double R[9] = {1 - 2 * (y * y + zq * zq), 2 * (x * y - w * zq), 2 * (x * zq + w * y),
                    2 * (x * y + w * zq), 1 - 2 * (x * x + zq * zq), 2 * (y * zq - w * x),
                    2 * (x * zq - w * y), 2 * (y * zq + w * x), 1 - 2 * (x * x + y * y)};
-    double tu[3], tv[3], nc[3];
+    // covectors g_u, g_v, n (map by W) and in-plane point displacements t_u, t_v (map by A)
+    double gu[3], gv[3], nc[3], tu[3], tv[3];
     for (int i = 0; i < 3; i++) {
-        tu[i] = Wr[i * 3 + 0] * R[0] + Wr[i * 3 + 1] * R[3] + Wr[i * 3 + 2] * R[6];
-        tv[i] = Wr[i * 3 + 0] * R[1] + Wr[i * 3 + 1] * R[4] + Wr[i * 3 + 2] * R[7];
+        gu[i] = Wr[i * 3 + 0] * R[0] + Wr[i * 3 + 1] * R[3] + Wr[i * 3 + 2] * R[6];
+        gv[i] = Wr[i * 3 + 0] * R[1] + Wr[i * 3 + 1] * R[4] + Wr[i * 3 + 2] * R[7];
         nc[i] = Wr[i * 3 + 0] * R[2] + Wr[i * 3 + 1] * R[5] + Wr[i * 3 + 2] * R[8];
+        tu[i] = A[i * 3 + 0] * R[0] + A[i * 3 + 1] * R[3] + A[i * 3 + 2] * R[6];
+        tv[i] = A[i * 3 + 0] * R[1] + A[i * 3 + 1] * R[4] + A[i * 3 + 2] * R[7];
     }
     // facing sign in world space: +1 if n.(o - mu) >= 0, o = -W^T t
     double o[3];
@@ -110,11 +140,10 @@ __device__ void preprocess_one(const PreArgs& a, int64_t gid, float4* r4) {
     if (keep) {
         key = __float_as_uint((float)z);
         double fx = cam.fx, fy = cam.fy, cx = cam.cx, cy = cam.cy;
-        double iz = 1.0 / z;
+        double iz = 1.0 / mc[2];
         double px = fx * mc[0] * iz + cx, py = fy * mc[1] * iz + cy;
         double Au[3], Bv[3];
-        cross3(tv, mc, Au);
-        cross3(mc, tu, Bv);
+        plane_numerators(nc, mc, nmu, gu, gv, Au, Bv);
         double sg = nmu > 0 ? 1.0 : -1.0;
         double ux = sg * Au[0] / (su * fx), uy = sg * Au[1] / (su * fy);
         double vx = sg * Bv[0] / (sv * fx), vy = sg * Bv[1] / (sv * fy);

@@ -22,6 +22,10 @@
 // table); 3 the same with trilinear sampling over each chart's mip chain, the level taken from
 // the pixel's footprint on the splat (derivatives of the closed-form (u,v) along the image
 // axes: du/dX = (u_x - u w_x) / den, and likewise for v and Y).
+#include <string.h>
+
+#include <mutex>
+
 #include "eval.h"
 #include "shade.h"
 #include "texture.h"
@@ -55,21 +59,24 @@ struct RasterArgs {
 constexpr int kBatch = 192;   // records staged per batch (a multiple of 64)
 static_assert(kBatch % kWave == 0, "the batch is walked in rows of 64");
 
+// Waves per SIMD of the raster kernels: at most 80 VGPRs and a 22.5 KB record batch give six
+// workgroups per CU (measured faster than 5 waves with 256-record batches). The indirect
+// variant carries three more accumulators and needs more than 80 VGPRs: 5 waves per SIMD, no
+// spills; trilinear sampling (two texel levels in flight) 4.
 template <int kSamp, bool kInd>
-// 6 waves per SIMD: at most 80 VGPRs and a 22.5 KB record batch, so six workgroups fit a CU
-// (measured faster than 5 waves with 256-record batches). The indirect variant carries three
-// more accumulators and needs more than 80 VGPRs: 5 waves per SIMD, no spills; trilinear
-// sampling (two texel levels in flight) 4.
-__global__ __launch_bounds__(256, kSamp == 3 ? 4 : (kInd ? 5 : 6)) void k_raster_fwd(RasterArgs a) {
+constexpr int raster_waves() { return kSamp == 3 ? 4 : (kInd ? 5 : 6); }
+
+// The whole render of tile t of view v: front-to-back walk of its list, G-buffer blend,
+// outputs and the fused shading. Every thread of the workgroup calls it with the same (v, t);
+// it leaves the staging arrays free (its last step is a barrier), so a workgroup can render
+// several tiles in a row.
+template <int kSamp, bool kInd>
+__device__ __forceinline__ void raster_tile(const RasterArgs& a, int v, int t) {
     constexpr bool kTextured = kSamp != 1;
     __shared__ float4 srec[kBatch * kRec4];
     __shared__ uint32_t smask[kBatch];
     __shared__ float4 slind[kInd ? kBatch : 1];
     __shared__ int2 schart[kSamp >= 2 ? kBatch : 1];   // chart entries of the variant paths
-    const int g = gridDim.x;
-    const int bid = xcd_remap(blockIdx.x, g);
-    const int v = bid / a.n_tiles;
-    const int t = bid - v * a.n_tiles;
     const int tx = t % a.ntx, ty = t / a.ntx;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int bx = tx * kTile + (w & 1) * 8, by = ty * kTile + (w >> 1) * 8;
@@ -248,6 +255,15 @@ __global__ __launch_bounds__(256, kSamp == 3 ? 4 : (kInd ? 5 : 6)) void k_raster
     }
 }
 
+// One 256-thread workgroup per (view, tile); workgroup ids remapped so that each XCD takes a
+// contiguous run of tiles of one view (shared L2).
+template <int kSamp, bool kInd>
+__global__ __launch_bounds__(256, (raster_waves<kSamp, kInd>())) void k_raster_fwd(RasterArgs a) {
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int v = bid / a.n_tiles;
+    raster_tile<kSamp, kInd>(a, v, bid - v * a.n_tiles);
+}
+
 struct ShadeArgs {
     int V, W, H;
     const ts_camera* cams;
@@ -304,42 +320,40 @@ static int env_from(const ts_env* e, EnvDev& d, const char* who) {
     return TS_OK;
 }
 
-}  // namespace ts
-
-using namespace ts;
-
-extern "C" int ts_raster_fwd(int32_t n_views, int32_t width, int32_t height, const ts_camera* cams,
-                             const ts_params* params, int32_t n, const float* rec,
-                             const int32_t* tile_ranges, const int32_t* pair_ids,
-                             int64_t pair_capacity, const float* atlas, const ts_env* env,
-                             float* rgba, float* gbuf, float* t_final, int32_t* n_contrib,
-                             int32_t* n_blend, const float* lind, const float* vis,
-                             float* gbuf_ind, hipStream_t stream) {
+// Checks the arguments of one forward render and fills its kernel arguments; `samp` is the
+// texture path (template kSamp of k_raster_fwd). Nothing is enqueued.
+static int make_raster_args(const char* who, int32_t n_views, int32_t width, int32_t height,
+                            const ts_camera* cams, const ts_params* params, int32_t n,
+                            const float* rec, const int32_t* tile_ranges,
+                            const int32_t* pair_ids, int64_t pair_capacity, const float* atlas,
+                            const ts_env* env, float* rgba, float* gbuf, float* t_final,
+                            int32_t* n_contrib, int32_t* n_blend, const float* lind,
+                            const float* vis, float* gbuf_ind, RasterArgs& a, int& samp) {
     if (n_views < 1 || width < 1 || height < 1 || n < 0 || !params || !cams || !tile_ranges ||
         (n > 0 && (!atlas || !rec || !pair_ids))) {
-        set_error("ts_raster_fwd: bad argument");
+        set_error("%s: bad argument", who);
         return TS_E_ARG;
     }
     if (params->tex_res < 1 || params->tex_res > 32) {
-        set_error("ts_raster_fwd: tex_res %d outside 1..32", params->tex_res);
+        set_error("%s: tex_res %d outside 1..32", who, params->tex_res);
         return TS_E_ARG;
     }
     if (params->sampler == TS_SAMPLER_HARDWARE) {
-        set_error("ts_raster_fwd: texture-unit sampling is not available on gfx950 (no image "
-                  "instructions for this target)");
+        set_error("%s: texture-unit sampling is not available on gfx950 (no image "
+                  "instructions for this target)", who);
         return TS_E_UNSUPPORTED;
     }
     if (params->sampler != TS_SAMPLER_BILINEAR && params->sampler != TS_SAMPLER_CONSTANT &&
         params->sampler != TS_SAMPLER_TRILINEAR) {
-        set_error("ts_raster_fwd: unknown sampler %d", params->sampler);
+        set_error("%s: unknown sampler %d", who, params->sampler);
         return TS_E_ARG;
     }
     if (params->sampler == TS_SAMPLER_CONSTANT && params->tex_res != 1) {
-        set_error("ts_raster_fwd: the constant sampler needs tex_res 1 (got %d)", params->tex_res);
+        set_error("%s: the constant sampler needs tex_res 1 (got %d)", who, params->tex_res);
         return TS_E_ARG;
     }
     if (params->tex_format != TS_TEX_RGBN3 && params->tex_format != TS_TEX_RGBN2) {
-        set_error("ts_raster_fwd: unknown tex_format %d", params->tex_format);
+        set_error("%s: unknown tex_format %d", who, params->tex_format);
         return TS_E_ARG;
     }
     // the atlas variants: another texel layout, a chart table or trilinear sampling
@@ -347,27 +361,27 @@ extern "C" int ts_raster_fwd(int32_t n_views, int32_t width, int32_t height, con
                          params->sampler == TS_SAMPLER_TRILINEAR;
     if (variant && !params->chart_table &&
         (params->tex_res & (params->tex_res - 1)) != 0) {
-        set_error("ts_raster_fwd: atlas variants need a power-of-two tex_res (got %d)",
+        set_error("%s: atlas variants need a power-of-two tex_res (got %d)", who,
                   params->tex_res);
         return TS_E_ARG;
     }
     if (params->chart_table && params->atlas_texels <= 0) {
-        set_error("ts_raster_fwd: chart_table needs atlas_texels");
+        set_error("%s: chart_table needs atlas_texels", who);
         return TS_E_ARG;
     }
     if ((rgba != nullptr) != (env != nullptr)) {
-        set_error("ts_raster_fwd: rgba and env must be given together");
+        set_error("%s: rgba and env must be given together", who);
         return TS_E_ARG;
     }
     if (!lind && (vis || gbuf_ind)) {
-        set_error("ts_raster_fwd: vis and gbuf_ind need lind (the indirect term)");
+        set_error("%s: vis and gbuf_ind need lind (the indirect term)", who);
         return TS_E_ARG;
     }
     if (vis && !rgba) {
-        set_error("ts_raster_fwd: vis is a shading input and needs rgba and env");
+        set_error("%s: vis is a shading input and needs rgba and env", who);
         return TS_E_ARG;
     }
-    RasterArgs a = {};
+    a = RasterArgs{};
     a.V = n_views; a.W = width; a.H = height; a.n = n;
     a.ntx = tiles_x(width);
     a.n_tiles = a.ntx * tiles_y(height);
@@ -378,7 +392,7 @@ extern "C" int ts_raster_fwd(int32_t n_views, int32_t width, int32_t height, con
     for (int c = 0; c < 3; c++) a.sc.bg[c] = params->bg[c];
     a.shade = env != nullptr;
     if (env) {
-        int rc = env_from(env, a.env, "ts_raster_fwd");
+        int rc = env_from(env, a.env, who);
         if (rc != TS_OK) return rc;
     }
     a.rec = (const float4*)rec;
@@ -403,13 +417,111 @@ extern "C" int ts_raster_fwd(int32_t n_views, int32_t width, int32_t height, con
     a.tex.chart_texels = tri ? chain_texels(params->tex_res)
                              : (unsigned)(params->tex_res * params->tex_res);
     a.tex.fmt = params->tex_format;
-    int64_t blocks = (int64_t)n_views * a.n_tiles;
-    if (blocks > 0x7FFFFFFF) {
-        set_error("ts_raster_fwd: too many tiles");
+    if ((int64_t)n_views * a.n_tiles > 0x7FFFFFFF) {
+        set_error("%s: too many tiles", who);
         return TS_E_ARG;
     }
-    const dim3 grid((unsigned)blocks), block(256);
-    const int samp = tri ? 3 : variant ? 2 : params->sampler == TS_SAMPLER_CONSTANT ? 1 : 0;
+    samp = tri ? 3 : variant ? 2 : params->sampler == TS_SAMPLER_CONSTANT ? 1 : 0;
+    return TS_OK;
+}
+
+// ---- batched persistent launch -------------------------------------------------------------
+// The renders of several jobs (each a ts_raster_fwd call on the default atlas path: its own
+// scene, views, resolution and outputs) in one launch of a fixed grid. The (job, view, tile)
+// work items are numbered job by job and cut into kXcd contiguous ranges, one queue each;
+// a workgroup takes items from the queue of its XCD (the hardware deals workgroups to the
+// XCDs round-robin) and then from the others in turn, so each XCD mostly works on adjacent
+// tiles of one job and every workgroup keeps working while any queue holds items. The grid
+// and the kernel do not depend on the batch, so one captured graph serves every batch.
+constexpr int kBatchMaxJobs = 64;
+constexpr int kBatchQueueWords = 16;   // kXcd counters, the exit count, spare
+
+struct BatchTable {
+    int32_t n_jobs;
+    int32_t pad[3];
+    int32_t item_end[kBatchMaxJobs];   // inclusive prefix sums of n_views * n_tiles
+    RasterArgs job[kBatchMaxJobs];
+};
+
+// Next work item for this workgroup (thread 0 only), or -1 when every queue is empty.
+// `k` is the number of queues this workgroup has found empty so far (it never returns to
+// them).
+__device__ inline int batch_pop(uint32_t* queue, int total, int xcd, int& k) {
+    for (; k < kXcd; k++) {
+        int q = (xcd + k) % kXcd;
+        int lo = (int)((int64_t)q * total / kXcd), hi = (int)((int64_t)(q + 1) * total / kXcd);
+        if (hi <= lo) continue;
+        uint32_t i = atomicAdd(&queue[q], 1u);
+        if ((int64_t)lo + i < hi) return lo + (int)i;
+    }
+    return -1;
+}
+
+template <int kSamp, bool kInd>
+__global__ __launch_bounds__(256, (raster_waves<kSamp, kInd>())) void k_raster_batch(
+    const BatchTable* __restrict__ tab, uint32_t* __restrict__ queue) {
+    __shared__ int s_item[2];
+    const int n_jobs = tab->n_jobs;
+    const int total = n_jobs > 0 ? tab->item_end[n_jobs - 1] : 0;
+    const int xcd = blockIdx.x % kXcd;
+    int k = 0;
+    for (int it = 0;; it++) {
+        // double-buffered broadcast: slot it&1 is rewritten two iterations later, after the
+        // next barrier, by which time every thread has read it
+        if (threadIdx.x == 0) s_item[it & 1] = batch_pop(queue, total, xcd, k);
+        __syncthreads();
+        const int item = __builtin_amdgcn_readfirstlane(s_item[it & 1]);
+        if (item < 0) break;
+        int j = 0;
+        while (j < n_jobs - 1 && item >= tab->item_end[j]) j++;
+        const int local = item - (j > 0 ? tab->item_end[j - 1] : 0);
+        const RasterArgs& a = tab->job[j];
+        const int v = local / a.n_tiles;
+        raster_tile<kSamp, kInd>(a, v, local - v * a.n_tiles);
+    }
+    // the last workgroup to leave clears the counters for the next launch
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&queue[kXcd], 1u) == gridDim.x - 1) {
+            for (int q = 0; q <= kXcd; q++) atomicExch(&queue[q], 0u);
+        }
+    }
+}
+
+// Grid of the batched launch: every CU's resident workgroups, once per device.
+static int batch_grid(int dev) {
+    static std::mutex mu;
+    static int grid[64];
+    if (dev < 0 || dev >= 64) return 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!grid[dev]) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus < 1)
+            return 0;
+        grid[dev] = cus * raster_waves<0, false>();
+    }
+    return grid[dev];
+}
+
+}  // namespace ts
+
+using namespace ts;
+
+extern "C" int ts_raster_fwd(int32_t n_views, int32_t width, int32_t height, const ts_camera* cams,
+                             const ts_params* params, int32_t n, const float* rec,
+                             const int32_t* tile_ranges, const int32_t* pair_ids,
+                             int64_t pair_capacity, const float* atlas, const ts_env* env,
+                             float* rgba, float* gbuf, float* t_final, int32_t* n_contrib,
+                             int32_t* n_blend, const float* lind, const float* vis,
+                             float* gbuf_ind, hipStream_t stream) {
+    RasterArgs a;
+    int samp = 0;
+    int rc = make_raster_args("ts_raster_fwd", n_views, width, height, cams, params, n, rec,
+                              tile_ranges, pair_ids, pair_capacity, atlas, env, rgba, gbuf,
+                              t_final, n_contrib, n_blend, lind, vis, gbuf_ind, a, samp);
+    if (rc != TS_OK) return rc;
+    const dim3 grid((unsigned)((int64_t)n_views * a.n_tiles)), block(256);
     if (lind) {
         switch (samp) {
             case 0: hipLaunchKernelGGL((k_raster_fwd<0, true>), grid, block, 0, stream, a); break;
@@ -426,6 +538,63 @@ extern "C" int ts_raster_fwd(int32_t n_views, int32_t width, int32_t height, con
         }
     }
     return launch_check("ts_raster_fwd");
+}
+
+extern "C" size_t ts_raster_batch_table_bytes(void) { return sizeof(BatchTable); }
+
+extern "C" int ts_raster_batch_encode(const ts_raster_job* jobs, int32_t n_jobs, void* table,
+                                      size_t table_bytes) {
+    if (!table || table_bytes < sizeof(BatchTable) || n_jobs < 0 || n_jobs > kBatchMaxJobs ||
+        (n_jobs > 0 && !jobs)) {
+        set_error("ts_raster_batch_encode: bad argument (table of %zu bytes needed, 0..%d jobs)",
+                  sizeof(BatchTable), kBatchMaxJobs);
+        return TS_E_ARG;
+    }
+    BatchTable* t = (BatchTable*)table;
+    memset(t, 0, sizeof(BatchTable));
+    int64_t total = 0;
+    for (int j = 0; j < n_jobs; j++) {
+        const ts_raster_job& J = jobs[j];
+        int samp = 0;
+        int rc = make_raster_args("ts_raster_batch_encode", J.n_views, J.width, J.height, J.cams,
+                                  &J.params, J.n, J.rec, J.tile_ranges, J.pair_ids,
+                                  J.pair_capacity, J.atlas, &J.env, J.rgba, nullptr, J.t_final,
+                                  nullptr, nullptr, nullptr, nullptr, nullptr, t->job[j], samp);
+        if (rc != TS_OK) return rc;
+        if (samp != 0 || !J.rgba) {
+            set_error("ts_raster_batch_encode: job %d is not a shaded render on the default "
+                      "atlas path (bilinear, 8-float texels, no chart table)", j);
+            return TS_E_UNSUPPORTED;
+        }
+        total += (int64_t)J.n_views * t->job[j].n_tiles;
+        if (total > 0x7FFFFFFF) {
+            set_error("ts_raster_batch_encode: more than 2^31-1 tiles in the batch");
+            return TS_E_ARG;
+        }
+        t->item_end[j] = (int32_t)total;
+    }
+    t->n_jobs = n_jobs;
+    return TS_OK;
+}
+
+extern "C" int ts_raster_batch(const void* table, uint32_t* queue, hipStream_t stream) {
+    if (!table || !queue) {
+        set_error("ts_raster_batch: bad argument");
+        return TS_E_ARG;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        set_error("ts_raster_batch: no current device");
+        return TS_E_LAUNCH;
+    }
+    const int g = batch_grid(dev);
+    if (g < 1) {
+        set_error("ts_raster_batch: cannot read the compute-unit count of device %d", dev);
+        return TS_E_LAUNCH;
+    }
+    hipLaunchKernelGGL((k_raster_batch<0, false>), dim3(g), dim3(256), 0, stream,
+                       (const BatchTable*)table, queue);
+    return launch_check("ts_raster_batch");
 }
 
 extern "C" int ts_shade(int32_t n_views, int32_t width, int32_t height, const ts_camera* cams,

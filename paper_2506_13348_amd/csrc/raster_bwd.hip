@@ -657,12 +657,6 @@ __global__ __launch_bounds__(64) void k_bwd_gather(int V, int n, int T, const in
     }
 }
 
-__device__ inline void dcross(const double* a, const double* b, double* c) {
-    c[0] = a[1] * b[2] - a[2] * b[1];
-    c[1] = a[2] * b[0] - a[0] * b[2];
-    c[2] = a[0] * b[1] - a[1] * b[0];
-}
-
 // Chain rule of the projection set-up (see k_preprocess), double precision, views in order.
 __global__ __launch_bounds__(256) void k_bwd_params(int V, int n, const ts_camera* __restrict__ cams,
                                                     const float* __restrict__ means,
@@ -694,19 +688,33 @@ __global__ __launch_bounds__(256) void k_bwd_params(int V, int n, const ts_camer
             for (int j = 0; j < 3; j++) Wr[i * 3 + j] = cam.w2c[i * 4 + j];
             t[i] = cam.w2c[i * 4 + 3];
         }
-        double mc[3], tu[3], tv[3], nc[3];
+        // the set-up of ts_preprocess: camera-frame points by A = W^{-T}, covectors by W
+        double A[9];
+        {
+            const double* M = Wr;
+            double C[9] = {M[4] * M[8] - M[5] * M[7], M[5] * M[6] - M[3] * M[8], M[3] * M[7] - M[4] * M[6],
+                           M[2] * M[7] - M[1] * M[8], M[0] * M[8] - M[2] * M[6], M[1] * M[6] - M[0] * M[7],
+                           M[1] * M[5] - M[2] * M[4], M[2] * M[3] - M[0] * M[5], M[0] * M[4] - M[1] * M[3]};
+            double id = 1.0 / (M[0] * C[0] + M[1] * C[1] + M[2] * C[2]);
+            for (int i = 0; i < 9; i++) A[i] = C[i] * id;
+        }
+        double mc[3], gu[3], gv[3], nc[3];
         for (int i = 0; i < 3; i++) {
-            mc[i] = Wr[i * 3] * mu[0] + Wr[i * 3 + 1] * mu[1] + Wr[i * 3 + 2] * mu[2] + t[i];
-            tu[i] = Wr[i * 3] * R[0] + Wr[i * 3 + 1] * R[3] + Wr[i * 3 + 2] * R[6];
-            tv[i] = Wr[i * 3] * R[1] + Wr[i * 3 + 1] * R[4] + Wr[i * 3 + 2] * R[7];
+            mc[i] = A[i * 3] * mu[0] + A[i * 3 + 1] * mu[1] + A[i * 3 + 2] * mu[2] + t[i];
+            gu[i] = Wr[i * 3] * R[0] + Wr[i * 3 + 1] * R[3] + Wr[i * 3 + 2] * R[6];
+            gv[i] = Wr[i * 3] * R[1] + Wr[i * 3 + 1] * R[4] + Wr[i * 3 + 2] * R[7];
             nc[i] = Wr[i * 3] * R[2] + Wr[i * 3 + 1] * R[5] + Wr[i * 3 + 2] * R[8];
         }
         double fx = cam.fx, fy = cam.fy;
         double nmu = nc[0] * mc[0] + nc[1] * mc[1] + nc[2] * mc[2];
         double sg = nmu > 0 ? 1.0 : -1.0;
+        double mgu = mc[0] * gu[0] + mc[1] * gu[1] + mc[2] * gu[2];
+        double mgv = mc[0] * gv[0] + mc[1] * gv[1] + mc[2] * gv[2];
         double Au[3], Bv[3];
-        dcross(tv, mc, Au);
-        dcross(mc, tu, Bv);
+        for (int i = 0; i < 3; i++) {
+            Au[i] = nmu * gu[i] - mgu * nc[i];
+            Bv[i] = nmu * gv[i] - mgv * nc[i];
+        }
         double iz = 1.0 / mc[2];
         double g_px = gr[0], g_py = gr[1], g_ux = gr[2], g_uy = gr[3], g_vx = gr[4], g_vy = gr[5];
         double g_wx = gr[6], g_wy = gr[7], g_w0 = gr[8];
@@ -717,7 +725,8 @@ __global__ __launch_bounds__(256) void k_bwd_params(int V, int n, const ts_camer
         double nwd = R[2] * (o[0] - mu[0]) + R[5] * (o[1] - mu[1]) + R[8] * (o[2] - mu[2]);
         double sigma = nwd >= 0.0 ? 1.0 : -1.0;
         for (int k = 0; k < 9; k++) dR[k] += sigma * gr[10 + k];
-        double dmc[3] = {0, 0, 0}, dtu[3] = {0, 0, 0}, dtv[3] = {0, 0, 0}, dnc[3] = {0, 0, 0};
+        double dmc[3] = {0, 0, 0}, dgu[3] = {0, 0, 0}, dgv[3] = {0, 0, 0}, dnc[3] = {0, 0, 0};
+        double dnmu = 0.0;
         // px = fx mc0/mc2 + cx, py = fy mc1/mc2 + cy
         dmc[0] += g_px * fx * iz;
         dmc[1] += g_py * fy * iz;
@@ -727,28 +736,38 @@ __global__ __launch_bounds__(256) void k_bwd_params(int V, int n, const ts_camer
         double dB[3] = {sg * g_vx / (sv * fx), sg * g_vy / (sv * fy), 0.0};
         dsu += -(g_ux * sg * Au[0] / (su * fx) + g_uy * sg * Au[1] / (su * fy)) / su;
         dsv += -(g_vx * sg * Bv[0] / (sv * fx) + g_vy * sg * Bv[1] / (sv * fy)) / sv;
-        // Au = tv x mc: dtv += mc x dA, dmc += dA x tv ; Bv = mc x tu: dmc += tu x dB, dtu += dB x mc
-        double c[3];
-        dcross(mc, dA, c); for (int i = 0; i < 3; i++) dtv[i] += c[i];
-        dcross(dA, tv, c); for (int i = 0; i < 3; i++) dmc[i] += c[i];
-        dcross(tu, dB, c); for (int i = 0; i < 3; i++) dmc[i] += c[i];
-        dcross(dB, mc, c); for (int i = 0; i < 3; i++) dtu[i] += c[i];
-        // wx = sg nc0/fx, wy = sg nc1/fy, w0 = sg (nc.mc)/mc2
+        // Au = nmu gu - (mc.gu) nc, Bv = nmu gv - (mc.gv) nc
+        {
+            double dAg = dA[0] * gu[0] + dA[1] * gu[1] + dA[2] * gu[2];
+            double dBg = dB[0] * gv[0] + dB[1] * gv[1] + dB[2] * gv[2];
+            double dAn = dA[0] * nc[0] + dA[1] * nc[1] + dA[2] * nc[2];
+            double dBn = dB[0] * nc[0] + dB[1] * nc[1] + dB[2] * nc[2];
+            dnmu += dAg + dBg;
+            for (int i = 0; i < 3; i++) {
+                dgu[i] += nmu * dA[i] - dAn * mc[i];
+                dgv[i] += nmu * dB[i] - dBn * mc[i];
+                dmc[i] += -dAn * gu[i] - dBn * gv[i];
+                dnc[i] += -mgu * dA[i] - mgv * dB[i];
+            }
+        }
+        // wx = sg nc0/fx, wy = sg nc1/fy, w0 = sg nmu/mc2
         dnc[0] += sg * g_wx / fx;
         dnc[1] += sg * g_wy / fy;
-        for (int i = 0; i < 3; i++) {
-            dnc[i] += sg * g_w0 * mc[i] * iz;
-            dmc[i] += sg * g_w0 * nc[i] * iz;
-        }
+        dnmu += sg * g_w0 * iz;
         dmc[2] += -sg * g_w0 * nmu * iz * iz;
-        // camera frame -> world: tu = W R[:,0], ...; mc = W mu + t
+        // nmu = nc.mc
+        for (int i = 0; i < 3; i++) {
+            dnc[i] += dnmu * mc[i];
+            dmc[i] += dnmu * nc[i];
+        }
+        // camera frame -> world: gu = W R[:,0], gv = W R[:,1], nc = W R[:,2]; mc = A mu + t
         for (int j = 0; j < 3; j++) {
             double wtu = 0, wtv = 0, wnc = 0, wmc = 0;
             for (int i = 0; i < 3; i++) {
-                wtu += Wr[i * 3 + j] * dtu[i];
-                wtv += Wr[i * 3 + j] * dtv[i];
+                wtu += Wr[i * 3 + j] * dgu[i];
+                wtv += Wr[i * 3 + j] * dgv[i];
                 wnc += Wr[i * 3 + j] * dnc[i];
-                wmc += Wr[i * 3 + j] * dmc[i];
+                wmc += A[i * 3 + j] * dmc[i];
             }
             dR[j * 3 + 0] += wtu;
             dR[j * 3 + 1] += wtv;

@@ -267,6 +267,46 @@ class RenderPlan:
         self._front()
         self.raster()
 
+    def front(self):
+        """Enqueue the steps before the raster (preprocess, indirect term, bin/sort)."""
+        self._front()
+
+    @staticmethod
+    def bytes_for(scene, n_views, width, height, pair_capacity, shade=True, gbuf=False,
+                  aux=False):
+        """Device bytes a plan of these arguments allocates (visibility input not counted)."""
+        V, n = int(n_views), max(scene.n, 1)
+        n_tiles = ((width + F.TILE - 1) // F.TILE) * ((height + F.TILE - 1) // F.TILE)
+        plane = V * width * height
+        shade = bool(shade) and scene.tables is not None
+        ind = getattr(scene, "sh", None) is not None
+        b = V * n * (F.REC_FLOATS * 4 + 16 + 4 + 4)            # rec, rect, depth_key, sorted_ids
+        b += (F.ts_workspace_size(F.TS_OP_BIN_SORT, V, scene.n, width, height) + 3) // 4 * 4
+        b += V * n_tiles * 8 + max(int(pair_capacity), 1) * 4 + 8 + 4 + V * 64
+        b += plane * 16 if shade else 0
+        b += plane * 32 if (gbuf or not shade) else 0
+        b += plane * 4 if (aux or gbuf or not shade) else 0
+        b += plane * 8 if aux else 0
+        b += V * n * 16 if ind else 0
+        b += plane * 12 if ind and (gbuf or not shade) else 0
+        return int(b)
+
+    def batchable(self):
+        """Whether the raster of this plan can join a batched launch (ts_raster_batch)."""
+        p = self.params
+        return (self.shade and not self.indirect and p.sampler == F.SAMPLER_BILINEAR
+                and p.tex_format == F.TEX_RGBN3 and not p.chart_table)
+
+    def raster_job(self):
+        """This plan's raster + shading as a ts_raster_job for a batched launch (default atlas
+        path, shaded, no indirect term)."""
+        if not self.shade or self.indirect:
+            raise ValueError("batched renders are shaded renders without the indirect term")
+        sc = self.scene
+        return F.make_raster_job(self.V, self.W, self.H, self.cams, self.params, sc.n, self.rec,
+                                 self.tile_ranges, self.pair_ids, self.cap, sc.atlas,
+                                 sc.tables.struct, self.rgba, self.t_final)
+
     def check(self):
         """Synchronise and verify the pair lists fit; returns the pair count."""
         (self.stream or torch.cuda.current_stream()).synchronize()
@@ -291,6 +331,53 @@ class RenderPlan:
         if self.lind is not None:
             out["lind"] = self.lind.view(V, -1, 4)[:, :self.scene.n]
         return out
+
+
+class BatchRaster:
+    """Batched persistent raster launches from a ring of job tables.
+
+    Slot i owns a pinned host table, its device copy and a work-queue buffer; launch(i, jobs)
+    encodes the jobs, copies the table to the device and renders the whole batch in one
+    launch (optionally by replaying a graph captured once per slot: the launch does not depend
+    on the batch). A slot may be reused once the stream has finished its previous batch."""
+
+    def __init__(self, device="cuda", slots=2, use_graphs=True):
+        nb = F.ts_raster_batch_table_bytes()
+        self.device = torch.device(device)
+        self.host = [torch.empty(nb, dtype=torch.uint8).pin_memory() for _ in range(slots)]
+        self.table = [torch.empty(nb, dtype=torch.uint8, device=self.device) for _ in range(slots)]
+        # work counters: zero before the first launch, left zero by every launch
+        self.queue = [torch.zeros(16, dtype=torch.int32, device=self.device) for _ in range(slots)]
+        self.graphs = [None] * slots
+        if use_graphs:
+            for i in range(slots):
+                self.graphs[i] = self._capture(i)
+
+    def _capture(self, i):
+        # an empty batch first (a plain launch, outside any capture), then the capture
+        F.ts_raster_batch_encode([], self.host[i])
+        self.table[i].copy_(self.host[i])
+        F.ts_raster_batch(self.table[i], self.queue[i])
+        torch.cuda.synchronize(self.device)
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream(self.device)
+        with torch.cuda.stream(s):
+            g.capture_begin(capture_error_mode="thread_local")
+            F.ts_raster_batch(self.table[i], self.queue[i], s)
+            g.capture_end()
+        s.synchronize()
+        return g
+
+    def launch(self, i, jobs, stream=None):
+        """Render `jobs` (ts_raster_job structs) in one launch on `stream` (current if None)."""
+        F.ts_raster_batch_encode(jobs, self.host[i])
+        stream = stream or torch.cuda.current_stream(self.device)
+        with torch.cuda.stream(stream):
+            self.table[i].copy_(self.host[i], non_blocking=True)
+            if self.graphs[i] is not None:
+                self.graphs[i].replay()
+            else:
+                F.ts_raster_batch(self.table[i], self.queue[i], stream)
 
 
 def render(scene: DeviceScene, cams, width, height, params=None, shade=True, gbuf=False,

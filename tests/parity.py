@@ -131,3 +131,15 @@ def sample_pixels(rng, width, height, n, tile=16):
     seams = np.stack([np.minimum(tx * tile + 15, width - 1), np.minimum(ty * tile, height - 1)], 1)
     corners = np.array([[0, 0], [width - 1, 0], [0, height - 1], [width - 1, height - 1]])
     return np.unique(np.concatenate([px, seams, corners]), axis=0).astype(np.int32)
+
+
+def report_failures(ok, pixels, gpu_rgba, gpu_gbuf, ref, limit=8):
+    """Print the failing pixels (position, oracle flags, HIP and oracle values) for the log."""
+    bad = np.nonzero(~np.asarray(ok))[0]
+    for b in bad[:limit]:
+        print(f"pixel {tuple(int(c) for c in pixels[b])} stat {ref['stat'][b].tolist()}\n"
+              f"  hip rgba {np.round(gpu_rgba[b], 7).tolist()} oracle {np.round(ref['rgba'][b], 7).tolist()}\n"
+              f"  hip gbuf {np.round(gpu_gbuf[b], 7).tolist()}\n"
+              f"  oracle   {np.round(ref['gbuf'][b], 7).tolist()}", flush=True)
+    if len(bad) > limit:
+        print(f"... {len(bad) - limit} more failing pixels", flush=True)

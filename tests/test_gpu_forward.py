@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import synth
-from parity import TOL_RGB, e2e_bound, gather, pixel_match, sample_pixels
+from parity import TOL_RGB, e2e_bound, gather, pixel_match, report_failures, sample_pixels
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -333,6 +333,50 @@ def test_locality_packing_is_a_relabelling():
     ra = P.render(a, cams, 160, 120)["rgba"]
     rb = P.render(b, cams, 160, 120)["rgba"]
     assert torch.equal(ra, rb)
+
+
+def _morton_perm(means):
+    """Chart order by the 30-bit Morton code of the centres on a 1024^3 grid over their float32
+    bounding box (x in bit 0 of each triple), stable for equal codes; perm[k] = rank of k."""
+    m = np.asarray(means, np.float32)
+    lo, hi = m.min(0), m.max(0)
+    ext = np.maximum(hi - lo, np.float32(1e-30))
+    f = (m - lo) / ext
+    q = np.minimum(np.maximum(f * np.float32(1024.0), np.float32(0.0)), np.float32(1023.0))
+    q = q.astype(np.uint32)
+    code = np.zeros(len(m), np.uint64)
+    for b in range(10):
+        for c in range(3):
+            code |= ((q[:, c] >> b) & 1).astype(np.uint64) << np.uint64(3 * b + c)
+    order = np.argsort(code, kind="stable")
+    perm = np.empty(len(m), np.int64)
+    perm[order] = np.arange(len(m))
+    return perm
+
+
+def test_locality_permutation_is_the_morton_order_and_renders_like_the_oracle():
+    """ts_locality_perm equals a CPU Morton ordering bit for bit, and the image rendered from
+    the permuted atlas (charts moved, indirection buffer = the permutation) passes the
+    two-stage check against the oracle given that same atlas and indirection."""
+    P = _pkg()
+    sc = synth.make_scene("sq100k", n=20000, env_res=16)
+    b = P.DeviceScene.from_dict(sc, device="cuda", locality=True)
+    perm = b.chart_of.cpu().numpy()
+    np.testing.assert_array_equal(perm, _morton_perm(sc["means"]))
+    atlas = b.atlas.view(20000, sc["tex_res"], sc["tex_res"], 8).cpu().numpy()
+    np.testing.assert_array_equal(atlas[perm], sc["textures"])
+    packed = dict(sc, textures=atlas, chart_of=perm.astype(np.int32))
+    cams = synth.orbit_cameras(2, 160, 120)
+    out = P.render(b, cams, 160, 120, gbuf=True)
+    for v, cam in enumerate(cams):
+        pix = sample_pixels(np.random.default_rng(40 + v), 160, 120, 150)
+        ref = oracle.render(packed, cam, pixels=pix)
+        rgba, gb = gather(out, v, pix)
+        tabs = oracle.tables(sc["env"], sc["env_levels"])
+        ok, info = pixel_match(rgba, gb, ref, cam, pix, tabs)
+        report_failures(ok, pix, rgba, gb, ref)
+        print(f"locality view {v}: {info}", flush=True)
+        assert info["fail"] == 0 and e2e_bound(info), info
 
 
 # ------------------------------------------------------------------------------ maximum sizes

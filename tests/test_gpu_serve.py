@@ -1,11 +1,12 @@
-"""The render server on an MI355X: requests overlapping on the device through replayed HIP
-graphs give the same image as each request rendered alone (and as the oracle)."""
+"""The render server on an MI355X: requests overlapping on the device (batched into persistent
+launches, or one graph replay per request) give the same image as each request rendered alone
+(and as the oracle); a memory budget that binds evicts idle plans and keeps every result."""
 import numpy as np
 import pytest
 
 import oracle
 import synth
-from parity import e2e_bound, gather, pixel_match, sample_pixels
+from parity import e2e_bound, gather, pixel_match, report_failures, sample_pixels
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -32,9 +33,11 @@ def _trace(rng, n, res):
     return out
 
 
-def test_requests_in_the_mix_equal_requests_alone():
+@pytest.mark.parametrize("mode", ["batch", "request"])
+def test_requests_in_the_mix_equal_requests_alone(mode):
     import paper_2506_13348_amd as P
     from paper_2506_13348_amd.serve import Request, Server
+    print(f"serve mix, mode {mode}", flush=True)
     raw, scenes = _scenes()
     rng = np.random.default_rng(5)
     res = [(64, 64), (96, 80), (128, 128)]
@@ -42,12 +45,15 @@ def test_requests_in_the_mix_equal_requests_alone():
     samples = {}
     for t, s, (W, H), cam in trace:
         samples.setdefault((s, W, H), []).append(cam)
-    srv = Server(scenes, slots=4, capacity_samples=samples, keep_outputs=True)
+    srv = Server(scenes, slots=4, capacity_samples=samples, keep_outputs=True, mode=mode)
     srv.prepare([((s, W, H), c[0]) for (s, W, H), c in samples.items()], per_key=2)
     reqs = [Request(i, t, s, wh[0], wh[1], cam) for i, (t, s, wh, cam) in enumerate(trace)]
     srv.serve(reqs, realtime=False)
     torch.cuda.synchronize()
     assert srv.stats["max_inflight"] >= 2, srv.stats
+    if mode == "batch":
+        # all requests arrive at once: some launch carried several of them
+        assert srv.stats["max_batch_size"] >= 2 and srv.stats["batches"] < len(reqs), srv.stats
     assert srv.stats["graph_replays"] >= len(reqs) - srv.stats["overflow_retries"]
     n_exact = 0
     for r in reqs:
@@ -67,7 +73,40 @@ def test_requests_in_the_mix_equal_requests_alone():
         rgba, gb = gather(full, 0, pix)
         tabs = oracle.tables(raw[r.scene]["env"], raw[r.scene]["env_levels"])
         ok, info = pixel_match(rgba, gb, ref, r.cam, pix, tabs)
+        print(info)
+        report_failures(ok, pix, rgba, gb, ref)
         assert info["fail"] == 0 and e2e_bound(info), info
+
+
+def test_a_binding_memory_budget_evicts_idle_plans():
+    """A budget of about two plans over six (scene, resolution) keys: idle plans are evicted
+    least recently used first, resident plan bytes never exceed the budget, and every request
+    still equals the same request rendered alone."""
+    import paper_2506_13348_amd as P
+    from paper_2506_13348_amd.serve import Request, Server, plan_bytes
+    raw, scenes = _scenes()
+    rng = np.random.default_rng(8)
+    res = [(64, 64), (96, 80), (128, 128)]
+    trace = _trace(rng, 30, res)
+    samples = {}
+    for t, s, (W, H), cam in trace:
+        samples.setdefault((s, W, H), []).append(cam)
+    srv = Server(scenes, slots=2, capacity_samples=samples, keep_outputs=True, mode="batch")
+    sizes = {k: srv._plan_size(*k) for k in samples}
+    srv.mem_budget = 2 * max(sizes.values()) + 1024
+    reqs = [Request(i, t, s, wh[0], wh[1], cam) for i, (t, s, wh, cam) in enumerate(trace)]
+    srv.serve(reqs, realtime=False)
+    torch.cuda.synchronize()
+    print(f"[serve budget] budget {srv.mem_budget} stats {srv.stats}", flush=True)
+    assert srv.stats["evictions"] > 0
+    assert srv.stats["max_resident"] <= srv.mem_budget
+    # the byte count a plan is admitted with is the bytes it holds
+    for ps in srv.plans.values():
+        for p in ps:
+            assert p.nbytes == plan_bytes(p.plan) == sizes[p.key]
+    for r in reqs:
+        alone = P.render(scenes[r.scene], [r.cam], r.width, r.height)["rgba"][0]
+        assert torch.equal(alone, r.output)
 
 
 def test_pair_overflow_is_rerendered():

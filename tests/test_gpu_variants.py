@@ -151,7 +151,7 @@ def test_variants_full_size_sampled():
     cams = synth.config_cameras("sq100k")
     P = _pkg()
     ds = P.DeviceScene.from_dict(sc, device="cuda", tex_format=1, mips=True)
-    out = P.render(ds, cams, 800, 800)
+    out = P.render(ds, cams, 800, 800, gbuf=True)
     torch.cuda.synchronize()
     rng = np.random.default_rng(5)
     osc = _oracle_scene(sc, fmt=1, tri=True)
