@@ -169,6 +169,29 @@ int ts_bin_sort(int32_t n_views, int32_t width, int32_t height, int32_t n,
                 int32_t* pair_ids, int64_t* n_pairs, int32_t* status, hipStream_t stream);
 
 /*
+ * ts_bin_sort_noalloc — ts_bin_sort for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same kernels
+ * and outputs, with the scratch taken from a static device array of the library instead of a
+ * workspace argument. Arguments as ts_bin_sort without ws/ws_bytes; inputs and outputs are
+ * still the caller's.
+ *   - Allocates nothing (no hipMalloc/hipFree, no allocating library call). The array is
+ *     ts_bin_sort_noalloc_max_bytes() = 128 MiB per GPU, held from the library's load until
+ *     the process ends; its device address is looked up on the first call on each device.
+ *   - A call whose scratch (ts_workspace_size(TS_OP_BIN_SORT, ...)) exceeds that size returns
+ *     TS_E_WORKSPACE and enqueues nothing.
+ *   - Every call on one GPU shares that GPU's array: calls that overlap on one GPU (concurrent
+ *     streams, or host threads) race and must be serialised by the caller. Each call writes
+ *     every scratch word it reads before reading it, so no clearing is needed between calls.
+ * Errors: TS_E_ARG (as ts_bin_sort), TS_E_WORKSPACE (scratch above the maximum), TS_E_LAUNCH
+ *         (no current device, symbol lookup or launch failure).
+ */
+int ts_bin_sort_noalloc(int32_t n_views, int32_t width, int32_t height, int32_t n,
+                        const int32_t* rect, const uint32_t* depth_key, int64_t pair_capacity,
+                        int32_t* sorted_ids, int32_t* tile_ranges, int32_t* pair_ids,
+                        int64_t* n_pairs, int32_t* status, hipStream_t stream);
+size_t ts_bin_sort_noalloc_max_bytes(void);
+
+/*
  * ts_indirect_eval — per (view, splat) indirect radiance l_ind from per-splat spherical
  * harmonics (Sec. 3.5-3.6: indirect light encoded per primitive with SH, blended by Eq. 9
  * and mixed into the specular term by Eq. 12). With d the unit direction from camera v's

@@ -48,6 +48,8 @@ _SIGS = {
                       c_void_p, c_void_p],
     "ts_bin_sort": [c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_size_t,
                     c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
+    "ts_bin_sort_noalloc": [c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_int64,
+                            c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
     "ts_raster_fwd": [c_int32, c_int32, c_int32, c_void_p, ctypes.POINTER(TsParams), c_int32,
                       c_void_p, c_void_p, c_void_p, c_int64, c_void_p, ctypes.POINTER(TsEnv),
                       c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
@@ -82,7 +84,7 @@ _SIGS = {
     "ts_raster_batch": [c_void_p, c_void_p, c_void_p],
 }
 
-_SIZE_FNS = ("ts_raster_batch_table_bytes",)
+_SIZE_FNS = ("ts_bin_sort_noalloc_max_bytes", "ts_raster_batch_table_bytes")
 EXPORTS = tuple(_SIGS) + ("ts_last_error",) + _SIZE_FNS
 
 _lib = None
@@ -183,6 +185,18 @@ def ts_bin_sort(n_views, width, height, n, rect, depth_key, ws, pair_capacity, s
                              ws.numel() * ws.element_size(), pair_capacity, ptr(sorted_ids),
                              ptr(tile_ranges), ptr(pair_ids), ptr(n_pairs), ptr(status),
                              stream_handle(stream)), "ts_bin_sort")
+
+
+def ts_bin_sort_noalloc(n_views, width, height, n, rect, depth_key, pair_capacity, sorted_ids,
+                        tile_ranges, pair_ids, n_pairs, status, stream=None):
+    _check(lib().ts_bin_sort_noalloc(n_views, width, height, n, ptr(rect), ptr(depth_key),
+                                     pair_capacity, ptr(sorted_ids), ptr(tile_ranges),
+                                     ptr(pair_ids), ptr(n_pairs), ptr(status),
+                                     stream_handle(stream)), "ts_bin_sort_noalloc")
+
+
+def ts_bin_sort_noalloc_max_bytes():
+    return int(lib().ts_bin_sort_noalloc_max_bytes())
 
 
 def ts_raster_batch_table_bytes():

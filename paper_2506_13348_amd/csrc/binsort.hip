@@ -7,6 +7,8 @@
 // tile; a column scan over chunks plus a scan over tiles gives every (chunk, tile) its write
 // offset; a second pass over each chunk, in order, writes the splat ids. Each pair is written
 // once (4 bytes) and the order inside every list is the depth order by construction.
+#include <mutex>
+
 #include "binsort_layout.h"
 #include "sort_kernels.h"
 #include "ts_internal.h"
@@ -614,5 +616,66 @@ extern "C" int ts_bin_sort(int32_t n_views, int32_t width, int32_t height, int32
         return TS_E_WORKSPACE;
     }
     return bin_sort_enqueue(n_views, width, height, n, rect, depth_key, (char*)ws, pair_capacity,
+                            sorted_ids, tile_ranges, pair_ids, n_pairs, status, stream);
+}
+
+// ---- ts_bin_sort_noalloc: the same kernels on a library-owned scratch array ----------------
+// A file-scope device array replaces the caller's workspace. In host code `scratch` is only a
+// host-side stand-in for the symbol, so its device address (one per GPU: each device holds its
+// own copy of the array) is taken once per device with hipGetSymbolAddress and only that
+// address is passed to kernels.
+constexpr size_t kNoAllocScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+namespace ts {
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static char* g_scratch_ptr[kMaxDevices];   // device address of `scratch` per device, or null
+
+// Device address of the scratch array on the current device (looked up on the first call per
+// device, under a lock); null with the error set on failure.
+static char* scratch_on_current_device(const char* who) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        set_error("%s: no current device (or device index above %d)", who, kMaxDevices - 1);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("%s: hipGetSymbolAddress(scratch) failed: %s", who, hipGetErrorString(e));
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = (char*)p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace ts
+
+extern "C" size_t ts_bin_sort_noalloc_max_bytes(void) { return kNoAllocScratchBytes; }
+
+extern "C" int ts_bin_sort_noalloc(int32_t n_views, int32_t width, int32_t height, int32_t n,
+                                   const int32_t* rect, const uint32_t* depth_key,
+                                   int64_t pair_capacity, int32_t* sorted_ids,
+                                   int32_t* tile_ranges, int32_t* pair_ids, int64_t* n_pairs,
+                                   int32_t* status, hipStream_t stream) {
+    int rc = bin_sort_check("ts_bin_sort_noalloc", n_views, width, height, n, rect, depth_key,
+                            pair_capacity, sorted_ids, tile_ranges, pair_ids, n_pairs, status);
+    if (rc != TS_OK) return rc;
+    const size_t need = binsort_layout(n_views, n, width, height).total;
+    if (need > kNoAllocScratchBytes) {
+        set_error("ts_bin_sort_noalloc: this call needs %zu bytes of scratch, above the %zu-byte "
+                  "static array (use ts_bin_sort with a workspace)", need, kNoAllocScratchBytes);
+        return TS_E_WORKSPACE;
+    }
+    char* w = scratch_on_current_device("ts_bin_sort_noalloc");
+    if (!w) return TS_E_LAUNCH;
+    // every scratch word the kernels read is written earlier in the same call, so the
+    // contents left by a previous call need no clearing
+    return bin_sort_enqueue(n_views, width, height, n, rect, depth_key, w, pair_capacity,
                             sorted_ids, tile_ranges, pair_ids, n_pairs, status, stream);
 }

@@ -58,6 +58,11 @@ def test_host_side_argument_errors():
     assert b"needs rgba" in L.ts_last_error()
     assert L.ts_indirect_eval(1, one, 10, one, one, one, 4, one, None) == -1
     assert b"degree" in L.ts_last_error()
+    # the no-alloc bin sort refuses, on the host, a call whose scratch exceeds its static array
+    assert L.ts_bin_sort_noalloc(64, 1920, 1080, 1000000, one, one, 16, one, one, one, one, one,
+                                 None) == -2
+    assert b"static array" in L.ts_last_error()
+    assert L.ts_bin_sort_noalloc(0, 16, 16, 10, one, one, 16, one, one, one, one, one, None) == -1
     assert L.ts_indirect_eval(0, one, 10, one, one, one, 3, one, None) == -1
     assert L.ts_indirect_eval(2, one, 10, None, one, one, 3, one, None) == -1
     assert L.ts_indirect_eval(2, one, 0, None, None, None, 3, None, None) == 0
