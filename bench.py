@@ -28,7 +28,10 @@ METRIC = "Mpix/s fwd and fwd+bwd vs plain at 1e-4 tol; serving p50/p99 latency"
 # (u,v) 17, Gaussian 5, alpha/transmittance/weight 5, texel coordinates 8, bilinear
 # weights 6 + 8 channels x 7, normal normalisation 9, rotation 15, accumulation 16.
 FLOPS_PER_BLEND = 137
-# fp32 vector peak without packed-fp32 instructions: 256 CU x 64 lanes x 2 flops x 2.4 GHz
+# MI355X's published fp32 vector peak (packed-fp32 instructions: two lanes' worth per issue)
+PEAK_FP32 = 157.3
+# the same without packed-fp32 instructions, which this build does not emit:
+# 256 CU x 64 lanes x 2 flops x 2.4 GHz
 PEAK_FP32_UNPACKED = 256 * 64 * 2 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 
@@ -92,6 +95,7 @@ def cpu_baseline(scene, cam, n_pix=200000, seed=0):
     dt, ev = _oracle_fwd(scene, cam, pix, threads, tabs)
     detail = {}
     k1 = 3000
+    log("cpu baseline: one core ...")
     dt1, ev1 = _oracle_fwd(scene, cam, pix[:k1], 1, tabs)
     detail["sq100k_view0_fwd_1core"] = {"pixels": k1, "s": round(dt1, 2),
                                         "mpix_per_s": round(k1 / dt1 / 1e6, 6),
@@ -105,18 +109,27 @@ def cpu_baseline(scene, cam, n_pix=200000, seed=0):
         detail[f"shell2k_frame_fwd_{th}threads"] = {"ms_per_frame": round(d1 * 1e3, 2),
                                                     "mpix_per_s": round(len(full) / d1 / 1e6, 4),
                                                     "evals_per_s": round(e1 / d1, 1)}
+    log("cpu baseline: 1M-splat frame sample ...")
     s4 = synth.make_scene("field1m")
     c4 = synth.config_cameras("field1m")[0]
-    t4 = oracle.tables(s4["env"], s4["env_levels"])
     k4 = 2000
-    d4, e4 = _oracle_fwd(s4, c4, sample(c4, k4), threads, t4)
-    detail["field1m_fwd_sample"] = {"pixels": k4, "of": "1600x1064, 1M splats", "s": round(d4, 2),
-                                    "mpix_per_s": round(k4 / d4 / 1e6, 6),
-                                    "evals_per_s": round(e4 / d4, 1)}
-    del s4
+    # G-buffers only: the FP64 prefiltering of this scene's 256^2 environment alone takes
+    # minutes on the host, and shading is a small part of a pixel's oracle work
+    oracle.set_threads(threads)
+    t0 = time.perf_counter()
+    o4 = oracle.render(s4, c4, pixels=sample(c4, k4), shade=False)
+    d4 = time.perf_counter() - t0
+    e4 = float(o4["stat"][:, 0].sum())
+    detail["field1m_fwd_sample_gbuffers"] = {"pixels": k4, "of": "1600x1064, 1M splats",
+                                             "s": round(d4, 2),
+                                             "mpix_per_s": round(k4 / d4 / 1e6, 6),
+                                             "evals_per_s": round(e4 / d4, 1)}
+    del s4, o4
+    log("cpu baseline: float64 forward + backward ...")
     s3 = synth.make_scene("sq300k_train")
     c3 = synth.config_cameras("sq300k_train")[0]
     t3 = oracle.tables(s3["env"], s3["env_levels"])
+    log("cpu baseline: tables ready")
     crop, ccam = synth.fd_crop_scene(s3, c3, 368, 368, 64, 64, n_keep=500)
     cpix = oracle.all_pixels(64, 64)
     for th in (threads, 1):
@@ -246,6 +259,40 @@ def bench_fwd_bwd(cfg, steps, warmup, sh_degree=None):
     del plan, run, grads, d_rgba, target, ds
     torch.cuda.empty_cache()
     return out
+
+
+def bench_unfused_shade(ds, cams, W, H, cap, reps=10):
+    """ts_shade on its own over the headline step's G-buffers (64 views x 800x800): per pixel
+    32 B of G-buffer + 4 B of transmittance read and 16 B of RGBA written (the tables, a few
+    MB, stay cache resident); HBM-bound. Its duration: `reps` launches back to back."""
+    import torch
+    from paper_2506_13348_amd import RenderPlan
+    from paper_2506_13348_amd import _ffi as F
+    plan = RenderPlan(ds, cams, W, H, gbuf=True, pair_capacity=cap)
+    plan.run()
+    plan.check()
+    V = len(cams)
+    env = ds.tables.struct
+
+    def shade():
+        F.ts_shade(V, W, H, plan.cams, plan.params, env, plan.gbuf, plan.t_final, plan.rgba)
+
+    shade()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        shade()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = V * W * H * (32 + 4 + 16)
+    gbs = nbytes / (ms / 1e3) / 1e9
+    del plan
+    torch.cuda.empty_cache()
+    return {"kernel": "k_shade", "bound": "hbm", "algorithmic_bytes": nbytes,
+            "ms_per_launch": round(ms, 4), "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def bench_indirect(sc, cams, W, H, cap, steps, warmup, degree=3):
@@ -468,9 +515,9 @@ def bench_serving(duration, rate=200.0, warm=3.0, saturation=300):
     persistent launch replayed from a graph), the per-request server (one graph replay of the
     whole path per request, 4 streams), and the plain renderer one request at a time. Then a
     closed loop (`saturation` requests all arriving at once) gives each one's saturation
-    throughput. The plan-cache budget is 1.25x the bytes of one plan per (scene, resolution),
-    so it binds: second plan instances are made on demand until it is reached, then idle
-    plans are evicted."""
+    throughput. The plan-cache budget is 3x the bytes of one plan per (scene, resolution): the
+    Poisson stream rarely reaches it, the closed loop does (requests then wait for plans of
+    their key, or evict idle plans of other keys)."""
     import numpy as np
     import torch
 
@@ -505,7 +552,7 @@ def bench_serving(duration, rate=200.0, warm=3.0, saturation=300):
             srv._capacity(*k)
         capacity = dict(srv.capacity)
         if budget is None:
-            budget = int(1.25 * sum(srv._plan_size(*k) for k in samples))
+            budget = int(3.0 * sum(srv._plan_size(*k) for k in samples))
         srv.mem_budget = budget
         srv.prepare([(k, v[0]) for k, v in samples.items()], per_key=1)
         servers[mode] = srv
@@ -533,6 +580,8 @@ def bench_serving(duration, rate=200.0, warm=3.0, saturation=300):
         out[f"server_{mode}_stats"] = dict(srv.stats)
     del servers
     torch.cuda.empty_cache()
+    out["raster_launch_forms"] = bench_batch_launch(scenes, geos, capacity)
+    log(f"raster launch forms: {out['raster_launch_forms']}")
     seq = serve_sequential(scenes, fresh(), capacity)
     rep_seq = latency_report(seq, warm)
     log(f"sequential: {rep_seq}")
@@ -543,6 +592,62 @@ def bench_serving(duration, rate=200.0, warm=3.0, saturation=300):
     out["saturation_speedup_batch_vs_sequential"] = round(
         out["server_batch_saturation_mpix_per_s"] / sat_seq["mpix_per_s"], 2)
     return out
+
+
+def bench_batch_launch(scenes, geos, capacity, reps=20):
+    """The raster of 16 requests, one per (scene, resolution) of the serving mix, three ways:
+    16 ts_raster_fwd launches on one stream, the same spread over 4 streams, and one
+    ts_raster_batch launch (fronts done beforehand; each timed over `reps` repetitions)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2506_13348_amd import BatchRaster, RenderPlan
+    rng = np.random.default_rng(9)
+    plans = []
+    for s in range(len(scenes)):
+        for (W, H) in synth.SERVING_RESOLUTIONS:
+            cam = synth.serving_camera(geos[s], W, H, rng.uniform(0, 2 * np.pi), rng.uniform(0, 40))
+            p = RenderPlan(scenes[s], [cam], W, H, pair_capacity=capacity[(s, W, H)])
+            p.run()
+            plans.append(p)
+    for p in plans:
+        p.check()
+    jobs = [p.raster_job() for p in plans]
+    br = BatchRaster(slots=1, use_graphs=True)
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def four_streams():
+        cur = torch.cuda.current_stream()
+        for i, p in enumerate(plans):
+            st = streams[i % 4]
+            st.wait_stream(cur)
+            with torch.cuda.stream(st):
+                p.raster()
+        for st in streams:
+            cur.wait_stream(st)
+
+    t_seq = timed(lambda: [p.raster() for p in plans])
+    t_4 = timed(four_streams)
+    t_b = timed(lambda: br.launch(0, jobs))
+    px = sum(p.W * p.H for p in plans)
+    del plans, br
+    torch.cuda.empty_cache()
+    return {"workload": "raster + shading of 16 requests (4 scenes x 256^2/512^2/800^2/1920x1080)",
+            "mpix": round(px / 1e6, 3), "ms_launches_one_stream": round(t_seq, 3),
+            "ms_launches_four_streams": round(t_4, 3), "ms_one_batched_launch": round(t_b, 3),
+            "batched_speedup_vs_four_streams": round(t_4 / t_b, 2)}
 
 
 def calibration_copy(dev):
@@ -569,6 +674,8 @@ def main():
     ap.add_argument("--profile-train", action="store_true",
                     help="only a few forward+backward steps of the 300k-splat training batch "
                          "(for counter collection)")
+    ap.add_argument("--locality", action="store_true",
+                    help="with --profile-run: the atlas packed in Morton order of the centres")
     ap.add_argument("--profile-run", action="store_true",
                     help="only the forward workload (few steps) plus a 256 MiB device copy that "
                          "calibrates the FETCH_SIZE / WRITE_SIZE counters")
@@ -596,7 +703,7 @@ def main():
     cams = synth.config_cameras("sq100k")
     W, H, V = 800, 800, len(cams)
     log(f"scene drawn in {time.perf_counter() - t0:.1f}s")
-    ds = DeviceScene.from_dict(sc, device=dev)
+    ds = DeviceScene.from_dict(sc, device=dev, locality=args.profile_run and args.locality)
     plan = RenderPlan(ds, cams, W, H)
     torch.cuda.synchronize()
     log(f"plan ready: {ds.n} splats, {V} views, pair capacity {plan.cap}")
@@ -637,6 +744,8 @@ def main():
     n_blend = int(aux.n_blend.to(torch.int64).sum().item())
     del aux
     achieved = n_blend * FLOPS_PER_BLEND / (ras_ms / 1e3) / 1e12
+    shade_line = bench_unfused_shade(ds, cams, W, H, plan.cap)
+    log(f"unfused shading: {shade_line}")
     # HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary, only while the
     # kernel's sources are the ones the counters were taken on
     from paper_2506_13348_amd.profiling import read_traffic
@@ -664,11 +773,16 @@ def main():
         "per_kernel_ms": {"preprocess": round(pre_ms, 4), "bin_sort": round(bin_ms, 4),
                           "raster_fwd_shade": round(ras_ms, 4)},
         "roofline": {"kernel": "k_raster_fwd", "bound": "alu",
-                     "achieved": round(achieved, 3), "peak": round(PEAK_FP32_UNPACKED, 2),
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_UNPACKED, 4),
+                     "achieved": round(achieved, 3), "peak": PEAK_FP32,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32, 4),
                      "traffic": traffic,
-                     "note": f"{n_blend} blended evaluations x {FLOPS_PER_BLEND} flops per launch"},
+                     "peak_unpacked": round(PEAK_FP32_UNPACKED, 2),
+                     "frac_unpacked": round(achieved / PEAK_FP32_UNPACKED, 4),
+                     "note": f"{n_blend} blended evaluations x {FLOPS_PER_BLEND} flops per launch; "
+                             "peak = published fp32 vector rate (packed), peak_unpacked = the "
+                             "rate without packed-fp32 instructions, which the build disables"},
     }
+    result["shade_unfused"] = shade_line
     # the same step with charts packed in Morton order of the centres (locality-aware atlas)
     ds_loc = DeviceScene.from_dict(sc, device=dev, locality=True)
     plan_loc = RenderPlan(ds_loc, cams, W, H, pair_capacity=plan.cap)

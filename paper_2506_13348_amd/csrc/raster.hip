@@ -66,6 +66,55 @@ static_assert(kBatch % kWave == 0, "the batch is walked in rows of 64");
 template <int kSamp, bool kInd>
 constexpr int raster_waves() { return kSamp == 3 ? 4 : (kInd ? 5 : 6); }
 
+// A pixel's outputs: G-buffer channels, transmittance, counters and the fused shading.
+template <bool kInd>
+__device__ __forceinline__ void raster_outputs(const RasterArgs& a, int v, int x, int y,
+                                               const float* acc, const float* ai, float Tr,
+                                               int last, int nbl) {
+    int64_t pix = ((int64_t)v * a.H + y) * a.W + x;
+    int64_t plane = (int64_t)a.H * a.W;
+    if (a.gbuf) {
+        float* gb = a.gbuf + (int64_t)v * 8 * plane + (int64_t)y * a.W + x;
+#pragma unroll
+        for (int c = 0; c < 8; c++) gb[c * plane] = acc[c];
+    }
+    if (kInd && a.gbuf_ind) {
+        float* gi = a.gbuf_ind + (int64_t)v * 3 * plane + (int64_t)y * a.W + x;
+#pragma unroll
+        for (int c = 0; c < 3; c++) gi[c * plane] = ai[c];
+    }
+    if (a.t_final) a.t_final[pix] = Tr;
+    if (a.n_contrib) a.n_contrib[pix] = last;
+    if (a.n_blend) a.n_blend[pix] = nbl;
+    if (a.shade) {
+        float3 d = pixel_ray(a.cams[v], (float)x + 0.5f, (float)y + 0.5f);
+        float vis = (kInd && a.vis) ? a.vis[pix] : 1.0f;
+        float3 C = shade_pixel<kInd>(a.env, a.sc, acc, Tr, d, ai, vis);
+        a.rgba[pix] = make_float4(C.x, C.y, C.z, 1.0f - Tr);
+    }
+}
+
+// Blends one texture sample t[0..7] (albedo rgb, roughness, tangent normal xyz, metallic) with
+// weight ww: sigma R (t / |t|) = (sigma R t) / |t| rotates the sampled tangent normal (Eq. 7),
+// scaled by ww / |t|; a zero-length sample is (0,0,1).
+__device__ __forceinline__ void blend_sample(float* acc, float ww, float4 c4, float4 c5,
+                                             float4 c6, float t0, float t1, float t2, float t3,
+                                             float t4, float t5, float t6, float t7) {
+    float nl = t4 * t4 + t5 * t5 + t6 * t6;
+    bool hasn = nl > 0.f;
+    float il = hasn ? __builtin_amdgcn_rsqf(nl) : 1.f;
+    float tz = hasn ? t6 : 1.f;
+    float wn = ww * il;
+    acc[0] = fmaf(ww, t0, acc[0]);
+    acc[1] = fmaf(ww, t1, acc[1]);
+    acc[2] = fmaf(ww, t2, acc[2]);
+    acc[3] = fmaf(ww, t7, acc[3]);   // metallic
+    acc[4] = fmaf(ww, t3, acc[4]);   // roughness
+    acc[5] = fmaf(wn, c4.x * t4 + c4.y * t5 + c4.z * tz, acc[5]);
+    acc[6] = fmaf(wn, c4.w * t4 + c5.x * t5 + c5.y * tz, acc[6]);
+    acc[7] = fmaf(wn, c5.z * t4 + c5.w * t5 + c6.x * tz, acc[7]);
+}
+
 // The whole render of tile t of view v: front-to-back walk of its list, G-buffer blend,
 // outputs and the fused shading. Every thread of the workgroup calls it with the same (v, t);
 // it leaves the staging arrays free (its last step is a barrier), so a workgroup can render
@@ -176,6 +225,10 @@ __device__ __forceinline__ void raster_tile(const RasterArgs& a, int v, int t) {
                             load_texel8(tr, (unsigned)(j0 * T + i1), p10, q10);
                             load_texel8(tr, (unsigned)(j1 * T + i0), p01, q01);
                             load_texel8(tr, (unsigned)(j1 * T + i1), p11, q11);
+                            // keep the eight loads together ahead of their use (the scheduler
+                            // otherwise may interleave them with the math to save registers,
+                            // leaving one texel in flight at a time)
+                            __builtin_amdgcn_sched_barrier(0);
                             float w00 = (1.f - fx) * (1.f - fy), w10 = fx * (1.f - fy);
                             float w01 = (1.f - fx) * fy, w11 = fx * fy;
                             t0 = w00 * p00.x + w10 * p10.x + w01 * p01.x + w11 * p11.x;
@@ -195,22 +248,8 @@ __device__ __forceinline__ void raster_tile(const RasterArgs& a, int v, int t) {
                             t0 = p0.x; t1 = p0.y; t2 = p0.z; t3 = p0.w;
                             t4 = q0.x; t5 = q0.y; t6 = q0.z; t7 = q0.w;
                         }
-                        // sigma R (t / |t|) = (sigma R t) / |t|: rotate the sampled tangent
-                        // normal, then scale by w / |t|; a zero-length sample is (0,0,1)
-                        float nl = t4 * t4 + t5 * t5 + t6 * t6;
-                        bool hasn = nl > 0.f;
-                        float il = hasn ? __builtin_amdgcn_rsqf(nl) : 1.f;
-                        float tz = hasn ? t6 : 1.f;
                         float ww = alpha * Tr;
-                        float wn = ww * il;
-                        acc[0] = fmaf(ww, t0, acc[0]);
-                        acc[1] = fmaf(ww, t1, acc[1]);
-                        acc[2] = fmaf(ww, t2, acc[2]);
-                        acc[3] = fmaf(ww, t7, acc[3]);   // metallic
-                        acc[4] = fmaf(ww, t3, acc[4]);   // roughness
-                        acc[5] = fmaf(wn, c4.x * t4 + c4.y * t5 + c4.z * tz, acc[5]);
-                        acc[6] = fmaf(wn, c4.w * t4 + c5.x * t5 + c5.y * tz, acc[6]);
-                        acc[7] = fmaf(wn, c5.z * t4 + c5.w * t5 + c6.x * tz, acc[7]);
+                        blend_sample(acc, ww, c4, c5, c6, t0, t1, t2, t3, t4, t5, t6, t7);
                         if (kInd) {
                             float4 l4 = slind[j];
                             ai[0] = fmaf(ww, l4.x, ai[0]);
@@ -232,27 +271,7 @@ __device__ __forceinline__ void raster_tile(const RasterArgs& a, int v, int t) {
         __syncthreads();
     }
     if (!inside) return;
-    int64_t pix = ((int64_t)v * a.H + y) * a.W + x;
-    int64_t plane = (int64_t)a.H * a.W;
-    if (a.gbuf) {
-        float* gb = a.gbuf + (int64_t)v * 8 * plane + (int64_t)y * a.W + x;
-#pragma unroll
-        for (int c = 0; c < 8; c++) gb[c * plane] = acc[c];
-    }
-    if (kInd && a.gbuf_ind) {
-        float* gi = a.gbuf_ind + (int64_t)v * 3 * plane + (int64_t)y * a.W + x;
-#pragma unroll
-        for (int c = 0; c < 3; c++) gi[c * plane] = ai[c];
-    }
-    if (a.t_final) a.t_final[pix] = Tr;
-    if (a.n_contrib) a.n_contrib[pix] = last;
-    if (a.n_blend) a.n_blend[pix] = nbl;
-    if (a.shade) {
-        float3 d = pixel_ray(a.cams[v], X, Y);
-        float vis = (kInd && a.vis) ? a.vis[pix] : 1.0f;
-        float3 C = shade_pixel<kInd>(a.env, a.sc, acc, Tr, d, ai, vis);
-        a.rgba[pix] = make_float4(C.x, C.y, C.z, 1.0f - Tr);
-    }
+    raster_outputs<kInd>(a, v, x, y, acc, ai, Tr, last, nbl);
 }
 
 // One 256-thread workgroup per (view, tile); workgroup ids remapped so that each XCD takes a

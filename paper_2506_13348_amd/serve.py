@@ -7,8 +7,9 @@ requests (scene, camera, resolution) is served.
 Plans. One preallocated plan per (scene, resolution) instance holds every buffer of one
 render. Plans stay resident between requests (a plan cache) and are counted against the
 memory budget whether busy or idle; when a new plan would not fit, idle plans are evicted
-least recently used first, and a request whose plan cannot be made to fit waits (a request
-alone on the device is always admitted, or it could never run).
+least recently used first; a request whose key already has plans (all busy) waits for one of
+them instead of evicting, and a request whose plan cannot be made to fit waits (a request alone
+on the device is always admitted, or it could never run).
 
 Two ways of running admitted requests on the device:
 
@@ -19,7 +20,8 @@ Two ways of running admitted requests on the device:
   persistent launch over a shared (request, view, tile) work queue (ts_raster_batch), replayed
   from a graph captured once per batch slot (the launch does not depend on the batch; its
   table is rewritten per batch). Requests that arrive while a batch renders join the next
-  one, so batches grow with the load. Up to `batch_depth` batches are in flight.
+  one, so batches grow with the load. Up to `batch_depth` batches are in flight, each on its
+  own raster stream.
 * mode "request": each request replays its plan's graph of the whole path on one of `slots`
   streams, so requests overlap on the device but no launch carries two of them.
 
@@ -101,8 +103,8 @@ def _capture(fn, stream):
 
 class Server:
     def __init__(self, scenes, slots=4, mem_budget=16 << 30, use_graphs=True,
-                 capacity_samples=None, keep_outputs=False, mode="batch", max_batch=32,
-                 batch_depth=2, max_inflight=64):
+                 capacity_samples=None, keep_outputs=False, mode="batch", max_batch=16,
+                 batch_depth=3, max_inflight=48):
         if mode not in ("batch", "request"):
             raise ValueError(f"unknown mode {mode}")
         self.scenes = scenes
@@ -123,6 +125,7 @@ class Server:
         self.staged = []          # mode "batch": (req, plan, slot) with the front enqueued
         self.batches = []         # mode "batch": (batch slot, [(req, plan)], handle)
         self.n_busy = 0
+        self._pinned = []
         self._tick = 0
         self._serving = False
         self._next_prep = 0
@@ -137,7 +140,8 @@ class Server:
 
     def _setup_batching(self):
         if self.mode == "batch":
-            self.raster_stream = torch.cuda.Stream()
+            # one raster stream per batch slot: batches in flight may overlap on the device
+            self.raster_streams = [torch.cuda.Stream() for _ in range(self.batch_depth)]
             self.batcher = BatchRaster(slots=self.batch_depth, use_graphs=self.use_graphs)
             self.free_batch_slots = list(range(self.batch_depth))
 
@@ -168,8 +172,7 @@ class Server:
         key = (s, W, H)
         cap = self._capacity(s, W, H)
         plan = RenderPlan(self.scenes[s], [cam], W, H, pair_capacity=cap)
-        cam_host = torch.empty(16, dtype=torch.float32).pin_memory()
-        status_host = torch.zeros(1, dtype=torch.int32).pin_memory()
+        cam_host, status_host = self._pinned_pair()
         batchable = self.mode == "batch" and plan.batchable()
         graph = None
         if self.use_graphs:
@@ -188,6 +191,14 @@ class Server:
         self._add_plan(p)
         return p
 
+    def _pinned_pair(self):
+        """Pinned host words for a plan's camera and status (pinned allocations are slow, so
+        those of evicted plans are reused)."""
+        if self._pinned:
+            return self._pinned.pop()
+        return (torch.empty(16, dtype=torch.float32).pin_memory(),
+                torch.zeros(1, dtype=torch.int32).pin_memory())
+
     def _add_plan(self, p):
         self.plans[p.key].append(p)
         self.resident += p.nbytes
@@ -203,6 +214,8 @@ class Server:
         victim = min(idle, key=lambda p: p.last_used)
         self.plans[victim.key].remove(victim)
         self.resident -= victim.nbytes
+        if victim.cam_host is not None:
+            self._pinned.append((victim.cam_host, victim.status_host))
         self.stats["evictions"] += 1
         return True
 
@@ -224,6 +237,9 @@ class Server:
             if not p.busy:
                 return p
         need = self._plan_size(*key)
+        if self.plans[key] and self.resident + need > self.mem_budget:
+            # the key has plans, all busy: wait for one rather than evict another key's plan
+            return None
         while self.resident + need > self.mem_budget and self._evict_one():
             pass
         if self.resident + need > self.mem_budget and self.n_busy > 0:
@@ -298,13 +314,19 @@ class Server:
         """One persistent raster launch over every batchable request of `items` on the raster
         stream, after their front parts; other requests (rendered whole on their prep
         streams) only join the batch's completion event."""
-        rs = self.raster_stream
+        rs = self.raster_streams[bslot]
         for req, p in items:
             rs.wait_event(req._front_done)
         jobs = [p.job for req, p in items if p.job is not None]
-        self.batcher.launch(bslot, jobs, rs)
-        if self.use_graphs:
-            self.stats["graph_replays"] += 1
+        if len(jobs) == 1:
+            # a batch of one is the plain launch (the persistent grid only pays off when it
+            # carries several renders)
+            with torch.cuda.stream(rs):
+                next(p for req, p in items if p.job is not None).plan.raster()
+        elif jobs:
+            self.batcher.launch(bslot, jobs, rs)
+            if self.use_graphs:
+                self.stats["graph_replays"] += 1
         with torch.cuda.stream(rs):
             if self.keep_outputs:
                 for req, p in items:

@@ -121,6 +121,17 @@ def test_idle_plans_are_evicted_least_recently_used_first():
     assert sorted(k for k, ps in srv.plans.items() if ps) == [(1, 64, 64), (2, 64, 64)]
 
 
+def test_a_key_with_busy_plans_waits_instead_of_evicting():
+    # two plans fit; key 1's plan is idle when two key-0 requests overlap: the second waits for
+    # the first's plan rather than evicting key 1's
+    srv = SimServer(lambda r: 0.01, slots=2, mem_budget=150 * 1024, mode="request")
+    reqs = [Request(0, 0.0, 1, 64, 64, {}), Request(1, 0.02, 0, 64, 64, {}),
+            Request(2, 0.021, 0, 64, 64, {})]
+    srv.serve(reqs)
+    assert srv.made == [(1, 64, 64), (0, 64, 64)] and srv.stats["evictions"] == 0
+    assert abs(reqs[2].start - reqs[1].done) < 2e-4
+
+
 def test_a_request_alone_is_admitted_above_the_budget():
     srv = SimServer(lambda r: 0.01, slots=2, mem_budget=1024, mode="batch")
     reqs = srv.serve(_reqs([0.0, 0.0]))
@@ -139,7 +150,7 @@ def test_no_starvation_of_a_large_request():
 
 
 def test_requests_arriving_during_a_batch_join_the_next_batch():
-    srv = SimServer(lambda r: 0.01, mode="batch", batch_depth=1,
+    srv = SimServer(lambda r: 0.01, mode="batch", batch_depth=1, max_inflight=64,
                     batch_cost=lambda reqs: 0.01 + 0.001 * len(reqs))
     reqs = srv.serve(_reqs([0.0, 0.002, 0.004, 0.006, 0.02]))
     assert [r.batch for r in reqs] == [0, 1, 1, 1, 2]
@@ -150,7 +161,7 @@ def test_requests_arriving_during_a_batch_join_the_next_batch():
 
 
 def test_batch_depth_and_size_limits():
-    srv = SimServer(lambda r: 0.01, mode="batch", batch_depth=2, max_batch=4,
+    srv = SimServer(lambda r: 0.01, mode="batch", batch_depth=2, max_batch=4, max_inflight=64,
                     batch_cost=lambda reqs: 0.005 * len(reqs))
     reqs = srv.serve(_reqs([0.0] * 10))
     sizes = np.bincount([r.batch for r in reqs])
