@@ -499,6 +499,29 @@ int ts_atlas_mips(float* atlas, int32_t n_charts, int32_t tex_res, const int32_t
                   int32_t max_log2, int64_t atlas_texels, int32_t tex_format, hipStream_t stream);
 
 /*
+ * ts_atlas_pack_charts — the atlas of per-chart resolutions (Sec. 5: adaptive texture
+ * resolution per primitive): primitive k gets a chart of 2^log2_side[k] texels a side, the
+ * charts back to back in primitive order (each followed by room for its mip chain when
+ * mips != 0, which is then built as by ts_atlas_mips), and chart_table[k] = (texel offset of
+ * the chart's level 0, log2 side) for ts_params.chart_table.
+ *   texels     [n_texels][8] level-0 texels of all primitives back to back in primitive
+ *              order (primitive k's 4^log2_side[k] texels row-major), channels as ts_atlas_pack
+ *   log2_side  [n] int32 (device), clamped to 0..max_log2; max_log2 <= 5 bounds the mip passes
+ *   ws         scratch of ts_atlas_charts_workspace(n) bytes
+ *   chart_table [n][2] int32 out (device)
+ *   atlas      out, atlas_texels texels of 8 (or 7, tex_format TS_TEX_RGBN2) floats; the caller
+ *              sizes it as sum_k 4^l_k (or (4^(l_k+1) - 1)/3 with mips); charts past it, or at
+ *              offsets past 2^31-1, are left out (their table entry's offset is then -1 or past
+ *              atlas_texels, which the renderer samples as zero)
+ * Errors: TS_E_ARG, TS_E_WORKSPACE, TS_E_LAUNCH.
+ */
+int ts_atlas_pack_charts(const float* texels, int64_t n_texels, int32_t n, const int32_t* log2_side,
+                         int32_t max_log2, int32_t tex_format, int32_t mips, void* ws,
+                         size_t ws_bytes, int32_t* chart_table, float* atlas, int64_t atlas_texels,
+                         hipStream_t stream);
+int ts_atlas_charts_workspace(int32_t n, size_t* bytes);
+
+/*
  * ts_locality_perm — a chart permutation that stores the textures of nearby primitives next to
  * each other (the packing the paper leaves open, Sec. 4.4): perm[k] = rank of splat k in the
  * Morton (Z-order) sequence of its centre on a 1024^3 grid over the centres' bounding box,

@@ -80,6 +80,9 @@ _SIGS = {
                        c_void_p],
     "ts_atlas_mips": [c_void_p, c_int32, c_int32, c_void_p, c_int32, c_int64, c_int32, c_void_p],
     "ts_locality_perm_workspace": [c_int32, ctypes.POINTER(c_size_t)],
+    "ts_atlas_pack_charts": [c_void_p, c_int64, c_int32, c_void_p, c_int32, c_int32, c_int32,
+                             c_void_p, c_size_t, c_void_p, c_void_p, c_int64, c_void_p],
+    "ts_atlas_charts_workspace": [c_int32, ctypes.POINTER(c_size_t)],
     "ts_raster_batch_encode": [ctypes.POINTER(TsRasterJob), c_int32, c_void_p, c_size_t],
     "ts_raster_batch": [c_void_p, c_void_p, c_void_p],
 }
@@ -197,6 +200,19 @@ def ts_bin_sort_noalloc(n_views, width, height, n, rect, depth_key, pair_capacit
 
 def ts_bin_sort_noalloc_max_bytes():
     return int(lib().ts_bin_sort_noalloc_max_bytes())
+
+
+def ts_atlas_pack_charts(texels, n, log2_side, max_log2, tex_format, mips, chart_table, atlas,
+                         atlas_texels, stream=None):
+    """texels: device [n_texels, 8] level-0 texels of all primitives back to back."""
+    out = c_size_t(0)
+    _check(lib().ts_atlas_charts_workspace(n, ctypes.byref(out)), "ts_atlas_charts_workspace")
+    ws = torch.empty(max(int(out.value), 8), dtype=torch.uint8, device=atlas.device)
+    _check(lib().ts_atlas_pack_charts(ptr(texels), texels.shape[0], n, ptr(log2_side), max_log2,
+                                      tex_format, mips, ptr(ws), ws.numel(), ptr(chart_table),
+                                      ptr(atlas), atlas_texels, stream_handle(stream)),
+           "ts_atlas_pack_charts")
+    return ws
 
 
 def ts_raster_batch_table_bytes():

@@ -75,6 +75,79 @@ __global__ __launch_bounds__(256) void k_atlas_level(float* __restrict__ atlas, 
     for (int q = 0; q < C; q++) out[q] = 0.25f * ((a[q] + b[q]) + (d[q] + e[q]));
 }
 
+// Per-chart resolutions, set-up of the chart table: one workgroup scans the charts in order
+// (chunks of 1024 with a carried sum): table[k] = (texel offset of chart k's level 0 in the
+// atlas, log2 side clamped to 0..max_log2), the charts back to back, each with room for its
+// mip chain when `mips`; src_off[k] = offset of primitive k's level-0 texels in the input
+// (sides^2 back to back).
+constexpr int kChartScan = 1024;
+
+__global__ __launch_bounds__(kChartScan) void k_chart_table(const int32_t* __restrict__ log2_side,
+                                                            int n, int max_log2, int mips,
+                                                            int2* __restrict__ table,
+                                                            int64_t* __restrict__ src_off) {
+    __shared__ int64_t sa[kChartScan], sb[kChartScan];
+    int64_t carry_a = 0, carry_b = 0;
+    const int tid = threadIdx.x;
+    for (int c0 = 0; c0 < n; c0 += kChartScan) {
+        const int k = c0 + tid;
+        const int l = k < n ? min(max(log2_side[k], 0), max_log2) : 0;
+        const int64_t side = (int64_t)1 << l;
+        const int64_t a = k < n ? (mips ? (int64_t)chain_texels((int)side) : side * side) : 0;
+        const int64_t b = k < n ? side * side : 0;
+        sa[tid] = a;
+        sb[tid] = b;
+        __syncthreads();
+        for (int o = 1; o < kChartScan; o <<= 1) {
+            int64_t ya = tid >= o ? sa[tid - o] : 0, yb = tid >= o ? sb[tid - o] : 0;
+            __syncthreads();
+            sa[tid] += ya;
+            sb[tid] += yb;
+            __syncthreads();
+        }
+        if (k < n) {
+            const int64_t ea = carry_a + sa[tid] - a;
+            // offsets past int32 are marked invalid (-1): the chart then samples as zero
+            table[k] = make_int2(ea <= 0x7FFFFFFFLL ? (int)ea : -1, l);
+            src_off[k] = carry_b + sb[tid] - b;
+        }
+        carry_a += sa[kChartScan - 1];
+        carry_b += sb[kChartScan - 1];
+        __syncthreads();
+    }
+    if (tid == 0) src_off[n] = carry_b;
+}
+
+// One thread per input level-0 texel: its primitive by binary search over src_off, then the
+// copy into that chart's level 0 in the target layout (charts past atlas_texels are skipped).
+__global__ __launch_bounds__(256) void k_chart_copy(const float* __restrict__ texels,
+                                                    int64_t n_texels, int n,
+                                                    const int64_t* __restrict__ src_off,
+                                                    const int2* __restrict__ table, int fmt,
+                                                    int64_t atlas_texels,
+                                                    float* __restrict__ atlas) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_texels || i >= src_off[n]) return;
+    int lo = 0, hi = n - 1;   // the last k with src_off[k] <= i
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (src_off[mid] <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    const int2 e = table[lo];
+    const int64_t o = i - src_off[lo];
+    if (e.x < 0 || e.x + o >= atlas_texels) return;
+    const float* src = texels + i * 8;
+    const int C = fmt ? 7 : 8;
+    float* dst = atlas + ((int64_t)e.x + o) * C;
+    if (fmt) {
+        for (int q = 0; q < 6; q++) dst[q] = src[q];
+        dst[6] = src[7];
+    } else {
+        for (int q = 0; q < 8; q++) dst[q] = src[q];
+    }
+}
+
 static int launch_levels(float* atlas, int n_charts, int T, const int2* table, int max_log2,
                          int64_t atlas_texels, int fmt, hipStream_t stream) {
     for (int l = 1; l <= max_log2; l++) {
@@ -128,4 +201,45 @@ extern "C" int ts_atlas_mips(float* atlas, int32_t n_charts, int32_t tex_res,
     launch_levels(atlas, n_charts, tex_res, (const int2*)chart_table, L, atlas_texels, tex_format,
                   stream);
     return launch_check("ts_atlas_mips");
+}
+
+extern "C" int ts_atlas_charts_workspace(int32_t n, size_t* bytes) {
+    if (!bytes || n < 0) {
+        set_error("ts_atlas_charts_workspace: bad argument");
+        return TS_E_ARG;
+    }
+    *bytes = ((size_t)n + 1) * sizeof(int64_t);
+    return TS_OK;
+}
+
+extern "C" int ts_atlas_pack_charts(const float* texels, int64_t n_texels, int32_t n,
+                                    const int32_t* log2_side, int32_t max_log2, int32_t tex_format,
+                                    int32_t mips, void* ws, size_t ws_bytes, int32_t* chart_table,
+                                    float* atlas, int64_t atlas_texels, hipStream_t stream) {
+    if (n < 0 || n_texels < 0 || atlas_texels < 0 || max_log2 < 0 || max_log2 > kMaxTexLog2 ||
+        (tex_format != TS_TEX_RGBN3 && tex_format != TS_TEX_RGBN2)) {
+        set_error("ts_atlas_pack_charts: bad argument (n=%d format=%d)", n, tex_format);
+        return TS_E_ARG;
+    }
+    if (n == 0) return TS_OK;
+    if (!log2_side || !chart_table || !atlas || (n_texels > 0 && !texels)) {
+        set_error("ts_atlas_pack_charts: null array");
+        return TS_E_ARG;
+    }
+    if (!ws || ws_bytes < ((size_t)n + 1) * sizeof(int64_t)) {
+        set_error("ts_atlas_pack_charts: workspace %zu < %zu bytes", ws_bytes,
+                  ((size_t)n + 1) * sizeof(int64_t));
+        return TS_E_WORKSPACE;
+    }
+    int64_t* src_off = (int64_t*)ws;
+    hipLaunchKernelGGL(k_chart_table, dim3(1), dim3(kChartScan), 0, stream, log2_side, n,
+                       max_log2, mips, (int2*)chart_table, src_off);
+    if (n_texels > 0)
+        hipLaunchKernelGGL(k_chart_copy, dim3((unsigned)((n_texels + 255) / 256)), dim3(256), 0,
+                           stream, texels, n_texels, n, src_off, (const int2*)chart_table,
+                           tex_format, atlas_texels, atlas);
+    if (mips)
+        launch_levels(atlas, n, 1, (const int2*)chart_table, max_log2, atlas_texels, tex_format,
+                      stream);
+    return launch_check("ts_atlas_pack_charts");
 }

@@ -4,9 +4,11 @@
 //
 // Tile lists without sorting (tile, depth) pairs: the depth-sorted splats of a view are cut
 // into chunks; one wavefront per chunk counts, in LDS, how many of its splats cover each
-// tile; a column scan over chunks plus a scan over tiles gives every (chunk, tile) its write
-// offset; a second pass over each chunk, in order, writes the splat ids. Each pair is written
-// once (4 bytes) and the order inside every list is the depth order by construction.
+// tile; the sum over chunks and a scan over tiles give every tile's list range; then one
+// workgroup per (view, super-tile of 8x8 tiles) streams the view's rectangles in depth order
+// and writes the lists of its 64 tiles, 256 splats at a time, each tile's entries of a batch
+// at consecutive addresses. Each pair is written once (4 bytes) and the order inside every
+// list is the depth order by construction.
 #include <mutex>
 
 #include "binsort_layout.h"
@@ -284,22 +286,13 @@ struct BinArgs {
     const int32_t* sorted;   // [V][n]
     const int4* rect;        // [V][n]
     uint32_t* counts;        // [V][n_chunks][n_tiles]
-    const int32_t* ranges;   // [V][n_tiles][2] (fill)
-    int32_t* pair_ids;
-    int64_t cap;
 };
 
-// LDS words the count and fill kernels may use (64 KB); grids taller than that are done in
-// bands of tile rows, each a pass over the chunk's splats.
+// LDS words the count kernel may use (64 KB); grids taller than that are counted in bands of
+// tile rows, each a pass over the chunk's splats.
 constexpr int kBinLdsWords = 16384;
-// The fill asks for at least 16 KB of LDS, so at most 10 chunk waves share a CU (160 KB):
-// fewer tile lists are written at once and more of the partially written 128-byte lines are
-// completed in the L2 before they leave it (measured on the 64-view sq100k step: 2.36 ms for
-// ts_bin_sort at 16 waves per CU, 2.27 at 6, 2.14 at 8, 2.09 at 10, 2.16 at 12).
-constexpr size_t kFillMinLds = 16 * 1024;
 
 __host__ __device__ inline int count_band_rows(int ntx) { return max(1, kBinLdsWords / (ntx + 1) - 1); }
-__host__ __device__ inline int fill_band_rows(int ntx) { return max(1, kBinLdsWords / ntx); }
 
 // Counts per (view, chunk, tile): one wavefront per chunk adds each splat's rectangle into an
 // LDS difference grid ((ntx+1) x (rows+1): +1 at (x0,y0) and (x1,y1), -1 at (x1,y0) and
@@ -347,53 +340,180 @@ __global__ __launch_bounds__(kWave) void k_bin_count(BinArgs a, int nty) {
     }
 }
 
-// Ordered fill: one wavefront per (view, chunk) walks its splats in depth order; the lanes
-// cover the splat's rectangle in 8x8 tile blocks; LDS cursors per tile give each entry its slot.
-// Grids with more tiles than LDS words are filled in bands of tile rows (a pass each).
-__global__ __launch_bounds__(kWave) void k_bin_fill(BinArgs a, int nty) {
-    extern __shared__ uint32_t cur[];
-    // every chunk of a view on the same XCD: the chunks write interleaved short runs of the
-    // same tile lists, whose cache lines are then completed in one L2
+// Ordered fill by super-tiles of 8x8 tiles. One workgroup per (view, super-tile, group of
+// chunks) streams the group's splats in depth order (their rectangles, packed and gathered
+// once by k_bin_gather_rects, and ids; 1024 per step with the next step's loads in flight),
+// keeps those touching its 64 tiles (appended in order to an LDS ring with a 64-bit tile mask
+// each) and, 256 at a time, ranks them per tile with one ballot per (wave, tile): a splat's
+// slot in tile b's list is the tile's cursor plus the earlier waves' counts plus the lanes
+// below it in the ballot; the cursor starts at the tile's list start plus the chunk prefix of
+// the group's first chunk. A tile's entries of a batch land at consecutive addresses (whole
+// cache lines from one workgroup) instead of one 4-byte write per (chunk, tile) run; every
+// list comes out in depth order, the same lists as a per-splat append. Views with few
+// super-tiles are split into several chunk groups so that the grid still fills the chip.
+constexpr int kSt = 8;                      // super-tile side in tiles (64 tiles: one mask bit each)
+constexpr int kFillThreads = 256;
+constexpr int kFillWaves = kFillThreads / kWave;
+constexpr int kFillUnroll = 4;              // splats per thread and step
+constexpr int kFillSpan = kFillThreads * kFillUnroll;
+constexpr int kFillRing = 2048;             // >= 255 waiting + kFillSpan appended, power of two
+constexpr int kFillTargetGroups = 4096;     // workgroups the grid aims at
+static_assert(kFillRing >= kFillThreads - 1 + kFillSpan && (kFillRing & (kFillRing - 1)) == 0,
+              "the ring holds the entries of a step plus an unprocessed remainder");
+
+__global__ __launch_bounds__(256) void k_bin_gather_rects(const int32_t* __restrict__ sorted,
+                                                          const int4* __restrict__ rect,
+                                                          int64_t vn, int n,
+                                                          uint2* __restrict__ srect) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= vn) return;
+    int64_t v = i / n;
+    int4 r = rect[v * n + sorted[i]];
+    // tile coordinates are below 8192 (rows of more tiles are refused): 16 bits each
+    bool empty = r.z <= r.x || r.w <= r.y;
+    srect[i] = empty ? make_uint2(0u, 0u)
+                     : make_uint2((uint32_t)r.x | ((uint32_t)r.z << 16),
+                                  (uint32_t)r.y | ((uint32_t)r.w << 16));
+}
+
+// Tile mask of a packed rectangle within the super-tile at (tx0, ty0) of tw x th tiles
+// (bit 8 y + x for tile (x, y) of the super-tile); 0 if they do not meet.
+__device__ inline uint64_t super_tile_mask(uint2 r, int tx0, int ty0, int tw, int th) {
+    const int x0 = max((int)(r.x & 0xFFFFu) - tx0, 0), x1 = min((int)(r.x >> 16) - tx0, tw);
+    const int y0 = max((int)(r.y & 0xFFFFu) - ty0, 0), y1 = min((int)(r.y >> 16) - ty0, th);
+    if (x1 <= x0 || y1 <= y0) return 0ull;
+    const uint64_t row = ((1ull << (x1 - x0)) - 1ull) << x0;            // 1..8 bits
+    const uint64_t rows = (0x0101010101010101ull >> (8 * (kSt - (y1 - y0)))) << (8 * y0);
+    return row * rows;   // the row pattern in each selected byte (no carries: row < 256)
+}
+
+// Ranks and writes ring entries [head, head + count) (count <= kFillThreads).
+__device__ inline void fill_st_batch(int head, int count, const int32_t* cid,
+                                     const uint64_t* cmask, uint64_t (*wball)[64],
+                                     uint32_t (*wbase)[64], uint32_t* cursor,
+                                     int32_t* __restrict__ pair_ids, int64_t cap) {
+    const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
+    const int e = (head + tid) & (kFillRing - 1);
+    const uint64_t m = tid < count ? cmask[e] : 0ull;
+    const int id = tid < count ? cid[e] : 0;
+    for (int b = 0; b < 64; b++) {
+        uint64_t bb = __ballot((m >> b) & 1ull);
+        if (lane == 0) wball[w][b] = bb;
+    }
+    __syncthreads();
+    if (tid < 64) {
+        uint32_t p = cursor[tid];
+        for (int k = 0; k < kFillWaves; k++) {
+            wbase[k][tid] = p;
+            p += (uint32_t)__popcll(wball[k][tid]);
+        }
+        cursor[tid] = p;
+    }
+    __syncthreads();
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    uint64_t mm = m;
+    while (mm) {
+        int b = __builtin_ctzll(mm);
+        mm &= mm - 1;
+        uint32_t pos = wbase[w][b] + (uint32_t)__popcll(wball[w][b] & below);
+        if ((int64_t)pos < cap) pair_ids[pos] = id;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kFillThreads) void k_bin_fill_st(
+    int n, int chunk, int n_chunks, int groups, int ntx, int nty, int nsx, int n_st,
+    const int32_t* __restrict__ sorted, const uint2* __restrict__ srect,
+    const uint32_t* __restrict__ prefix, const int32_t* __restrict__ ranges,
+    int32_t* __restrict__ pair_ids, int64_t cap) {
+    __shared__ uint32_t cursor[64];
+    __shared__ int32_t cid[kFillRing];
+    __shared__ uint64_t cmask[kFillRing];
+    __shared__ uint64_t wball[kFillWaves][64];
+    __shared__ uint32_t wbase[kFillWaves][64];
+    __shared__ uint32_t wtot[kFillUnroll][kFillWaves];
+    // the workgroups of a view on the same XCD: they stream the same rectangles
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
-    int v = bid / a.n_chunks, c = bid - v * a.n_chunks, lane = threadIdx.x;
-    const uint32_t* row = a.counts + ((int64_t)v * a.n_chunks + c) * a.n_tiles;
-    const int32_t* rg = a.ranges + (int64_t)v * a.n_tiles * 2;
-    int i0 = c * a.chunk, i1 = min(a.n, i0 + a.chunk);
-    const int32_t* sv = a.sorted + (int64_t)v * a.n;
-    const int4* rv = a.rect + (int64_t)v * a.n;
-    const int lx = lane & 7, ly = lane >> 3;
-    const int band = fill_band_rows(a.ntx);
-    for (int ya = 0; ya < nty; ya += band) {
-        const int yb = min(nty, ya + band);
-        const int t0 = ya * a.ntx;
-        for (int t = t0 + lane; t < yb * a.ntx; t += kWave) cur[t - t0] = (uint32_t)rg[2 * t] + row[t];
-        __syncthreads();
-        for (int b = i0; b < i1; b += kWave) {
-            int m = min(kWave, i1 - b);
-            int id = lane < m ? sv[b + lane] : 0;
-            int4 r = lane < m ? rv[id] : make_int4(0, 0, 0, 0);
-            for (int j = 0; j < m; j++) {
-                int x0 = __builtin_amdgcn_readlane(r.x, j), y0 = __builtin_amdgcn_readlane(r.y, j);
-                int x1 = __builtin_amdgcn_readlane(r.z, j), y1 = __builtin_amdgcn_readlane(r.w, j);
-                y0 = max(y0, ya);
-                y1 = min(y1, yb);
-                if (x1 <= x0 || y1 <= y0) continue;
-                int sid = __builtin_amdgcn_readlane(id, j);
-                for (int by = y0; by < y1; by += 8) {
-                    for (int bx = x0; bx < x1; bx += 8) {
-                        int tx = bx + lx, ty = by + ly;
-                        if (tx < x1 && ty < y1) {
-                            int t = ty * a.ntx + tx - t0;
-                            uint32_t p = cur[t];
-                            cur[t] = p + 1;
-                            if ((int64_t)p < a.cap) a.pair_ids[p] = sid;
-                        }
-                    }
-                }
-            }
+    const int per_view = n_st * groups;
+    const int v = bid / per_view, rem = bid - v * per_view;
+    const int st = rem / groups, g = rem - st * groups;
+    const int sy = st / nsx, sx = st - sy * nsx;
+    const int tx0 = sx * kSt, ty0 = sy * kSt;
+    const int tw = min(kSt, ntx - tx0), th = min(kSt, nty - ty0);
+    const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
+    const int cpg = (n_chunks + groups - 1) / groups;
+    const int c0 = min(n_chunks, g * cpg), c1 = min(n_chunks, c0 + cpg);
+    const int i0 = min(n, c0 * chunk), i1 = min(n, c1 * chunk);
+    if (i0 >= i1) return;   // the whole workgroup leaves together
+    const int64_t n_tiles = (int64_t)ntx * nty;
+    if (tid < 64) {
+        const int lx = tid % kSt, ly = tid / kSt;
+        uint32_t c = 0u;
+        if (lx < tw && ly < th) {
+            const int64_t t = (int64_t)(ty0 + ly) * ntx + tx0 + lx;
+            c = (uint32_t)ranges[2 * ((int64_t)v * n_tiles + t)] +
+                prefix[((int64_t)v * n_chunks + c0) * n_tiles + t];
+        }
+        cursor[tid] = c;
+    }
+    const uint2* sr = srect + (int64_t)v * n;
+    const int32_t* sv = sorted + (int64_t)v * n;
+    // head and count of the waiting entries (the same values in every thread)
+    int head = 0, nc = 0;
+    uint2 nr[kFillUnroll];
+    int nid[kFillUnroll];
+#pragma unroll
+    for (int u = 0; u < kFillUnroll; u++) {
+        const int i = i0 + u * kFillThreads + tid;
+        nr[u] = i < i1 ? sr[i] : make_uint2(0u, 0u);
+        nid[u] = i < i1 ? sv[i] : 0;
+    }
+    for (int b0 = i0; b0 < i1; b0 += kFillSpan) {
+        uint64_t m[kFillUnroll];
+        int id[kFillUnroll];
+#pragma unroll
+        for (int u = 0; u < kFillUnroll; u++) {
+            m[u] = super_tile_mask(nr[u], tx0, ty0, tw, th);
+            id[u] = nid[u];
+        }
+        // the next step's rectangles and ids in flight while this step is ranked and written
+#pragma unroll
+        for (int u = 0; u < kFillUnroll; u++) {
+            const int i = b0 + kFillSpan + u * kFillThreads + tid;
+            nr[u] = i < i1 ? sr[i] : make_uint2(0u, 0u);
+            nid[u] = i < i1 ? sv[i] : 0;
+        }
+        // append the hits in list order: sub-step u, then wave, then lane
+        uint64_t hit[kFillUnroll];
+#pragma unroll
+        for (int u = 0; u < kFillUnroll; u++) {
+            hit[u] = __ballot(m[u] != 0ull);
+            if (lane == 0) wtot[u][w] = (uint32_t)__popcll(hit[u]);
         }
         __syncthreads();
+        int base = head + nc;
+#pragma unroll
+        for (int u = 0; u < kFillUnroll; u++) {
+            int mine = base;
+            for (int k = 0; k < kFillWaves; k++) {
+                mine += k < w ? (int)wtot[u][k] : 0;
+                base += (int)wtot[u][k];
+            }
+            if (m[u]) {
+                const int pos = (mine + (int)lanes_below(hit[u])) & (kFillRing - 1);
+                cid[pos] = id[u];
+                cmask[pos] = m[u];
+            }
+        }
+        nc = base - head;   // fewer than 256 waited, at most kFillSpan were added
+        __syncthreads();
+        while (nc >= kFillThreads) {
+            fill_st_batch(head, kFillThreads, cid, cmask, wball, wbase, cursor, pair_ids, cap);
+            head = (head + kFillThreads) & (kFillRing - 1);
+            nc -= kFillThreads;
+        }
     }
+    if (nc > 0) fill_st_batch(head, nc, cid, cmask, wball, wbase, cursor, pair_ids, cap);
 }
 
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int64_t m, uint32_t x) {
@@ -569,11 +689,8 @@ static int bin_sort_enqueue(int32_t n_views, int32_t width, int32_t height, int3
     }
     BinArgs a;
     a.n = n; a.n_chunks = L.n_chunks; a.chunk = L.chunk; a.ntx = L.ntx; a.n_tiles = L.n_tiles;
-    a.sorted = sorted_ids; a.rect = (const int4*)rect; a.counts = counts; a.ranges = tile_ranges;
-    a.pair_ids = pair_ids; a.cap = pair_capacity;
+    a.sorted = sorted_ids; a.rect = (const int4*)rect; a.counts = counts;
     size_t lds_count = (size_t)(L.ntx + 1) * (min(L.nty, count_band_rows(L.ntx)) + 1) * 4;
-    size_t lds_fill = (size_t)L.ntx * min(L.nty, fill_band_rows(L.ntx)) * 4;
-    if (lds_fill < kFillMinLds) lds_fill = kFillMinLds;
     if (n > 0) {
         hipLaunchKernelGGL(k_bin_count, dim3(L.n_chunks * n_views), dim3(kWave), lds_count,
                            stream, a, L.nty);
@@ -594,9 +711,19 @@ static int bin_sort_enqueue(int32_t n_views, int32_t width, int32_t height, int3
                        pair_capacity, n_pairs, status);
     hipLaunchKernelGGL(k_scan_ranges, dim3(nsb), dim3(kScanBlock), 0, stream, totals, m,
                        block_sums, tile_ranges);
-    if (n > 0)
-        hipLaunchKernelGGL(k_bin_fill, dim3(L.n_chunks * n_views), dim3(kWave), lds_fill, stream,
-                           a, L.nty);
+    if (n > 0) {
+        // the sort's key buffers are free now: the packed rectangles in depth order go there
+        uint2* srect = (uint2*)keys_a;
+        const int64_t vn = (int64_t)n_views * n;
+        hipLaunchKernelGGL(k_bin_gather_rects, dim3((unsigned)((vn + 255) / 256)), dim3(256), 0,
+                           stream, sorted_ids, (const int4*)rect, vn, n, srect);
+        const int nsx = (L.ntx + kSt - 1) / kSt, nsy = (L.nty + kSt - 1) / kSt;
+        const int64_t units = (int64_t)n_views * nsx * nsy;
+        const int groups = (int)max((int64_t)1, min((int64_t)L.n_chunks, kFillTargetGroups / units));
+        hipLaunchKernelGGL(k_bin_fill_st, dim3((unsigned)(units * groups)), dim3(kFillThreads), 0,
+                           stream, n, L.chunk, L.n_chunks, groups, L.ntx, L.nty, nsx, nsx * nsy,
+                           sorted_ids, srect, counts, tile_ranges, pair_ids, pair_capacity);
+    }
     return launch_check("ts_bin_sort(bin)");
 }
 

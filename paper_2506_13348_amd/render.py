@@ -128,30 +128,26 @@ class DeviceScene:
 
     def _adaptive_atlas(self, texels, log2):
         """Charts of per-splat sides 2^log2[k] (with their mip chains when self.mips), packed
-        back to back in splat order; the chart table holds (level-0 texel offset, log2)."""
+        back to back in splat order on the GPU by ts_atlas_pack_charts; the chart table holds
+        (level-0 texel offset, log2 side). Only the atlas size is worked out here."""
         n = self.n
+        log2 = np.asarray(log2, np.int32)
         sides = 1 << log2.astype(np.int64)
         chain = (4 * sides * sides - 1) // 3 if self.mips else sides * sides
-        offs = np.concatenate([[0], np.cumsum(chain)])[:-1]
         total = int(chain.sum()) if n else 1
         C = 7 if self.tex_format else 8
-        host = np.zeros((max(total, 1), C), np.float32)
-        src = np.concatenate([[0], np.cumsum(sides * sides)])
-        lv0 = texels.reshape(-1, 8)
-        if self.tex_format:
-            lv0 = np.concatenate([lv0[:, 0:6], lv0[:, 7:8]], 1)
-        for k in range(n):
-            m = int(sides[k] * sides[k])
-            host[offs[k]:offs[k] + m] = lv0[src[k]:src[k] + m]
-        self.atlas = torch.as_tensor(host.reshape(-1)).to(self.device)
-        table = np.stack([offs, log2], 1).astype(np.int32)
-        self.chart_table = torch.as_tensor(table).to(self.device).contiguous()
+        self.atlas = torch.zeros(max(total, 1) * C, device=self.device, dtype=torch.float32)
+        self.chart_table = torch.zeros((max(n, 1), 2), device=self.device, dtype=torch.int32)
         self.atlas_texels = total
         self.chart_of = torch.arange(n, device=self.device, dtype=torch.int32)
         self.tex_res = int(sides.max()) if n else 1
-        if self.mips and n:
-            F.ts_atlas_mips(self.atlas, n, self.tex_res, self.chart_table,
-                            int(log2.max()), total, self.tex_format)
+        if n:
+            lv0 = _dev(np.asarray(texels, np.float32).reshape(-1, 8), self.device)
+            ws = F.ts_atlas_pack_charts(lv0, n, _dev(log2, self.device), int(log2.max()),
+                                        self.tex_format, int(self.mips), self.chart_table,
+                                        self.atlas, total)
+            torch.cuda.current_stream(self.device).synchronize()
+            del lv0, ws
 
     @classmethod
     def from_dict(cls, sc, device="cuda", **kw):

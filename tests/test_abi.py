@@ -58,6 +58,8 @@ def test_host_side_argument_errors():
     assert b"needs rgba" in L.ts_last_error()
     assert L.ts_indirect_eval(1, one, 10, one, one, one, 4, one, None) == -1
     assert b"degree" in L.ts_last_error()
+    assert L.ts_atlas_pack_charts(one, 4, 2, one, 6, 0, 0, one, 64, one, one, 4, None) == -1
+    assert L.ts_atlas_pack_charts(one, 4, 2, one, 2, 0, 0, one, 8, one, one, 4, None) == -2
     # the no-alloc bin sort refuses, on the host, a call whose scratch exceeds its static array
     assert L.ts_bin_sort_noalloc(64, 1920, 1080, 1000000, one, one, 16, one, one, one, one, one,
                                  None) == -2

@@ -100,6 +100,40 @@ def test_mip_chain_is_the_block_mean():
             s //= 2
 
 
+@pytest.mark.parametrize("fmt,mips", [(0, False), (1, False), (0, True), (1, True)])
+def test_chart_atlas_packed_on_the_gpu(fmt, mips):
+    """ts_atlas_pack_charts: chart table = (exclusive sum of the charts' sizes, log2 side) in
+    primitive order, level 0 = the primitive's texels in the target layout, and with mips
+    level 1 = the 2x2 block means of level 0."""
+    P = _pkg()
+    rng = np.random.default_rng(7 + fmt + 2 * mips)
+    n = 300
+    log2 = rng.integers(0, 6, n).astype(np.int32)
+    sides = 1 << log2.astype(np.int64)
+    flat = rng.uniform(-1, 1, size=(int((sides * sides).sum()), 8)).astype(np.float32)
+    sc = synth.make_scene("shell2k", n=n)
+    ds = P.DeviceScene.from_dict(dict(sc, textures=flat), device="cuda", chart_log2=log2,
+                                 tex_format=fmt, mips=mips)
+    torch.cuda.synchronize()
+    C = 7 if fmt else 8
+    chain = (4 * sides * sides - 1) // 3 if mips else sides * sides
+    offs = np.concatenate([[0], np.cumsum(chain)])[:-1]
+    table = ds.chart_table.cpu().numpy()
+    np.testing.assert_array_equal(table[:, 0], offs)
+    np.testing.assert_array_equal(table[:, 1], log2)
+    atlas = ds.atlas.view(-1, C).cpu().numpy()
+    src = np.concatenate([[0], np.cumsum(sides * sides)])
+    lv0 = _n2(flat) if fmt else flat
+    for k in range(n):
+        m = int(sides[k] ** 2)
+        np.testing.assert_array_equal(atlas[offs[k]:offs[k] + m], lv0[src[k]:src[k] + m])
+        if mips and sides[k] > 1:
+            s0 = int(sides[k])
+            l1 = atlas[offs[k] + m:offs[k] + m + m // 4].reshape(s0 // 2, s0 // 2, C)
+            ref = lv0[src[k]:src[k] + m].astype(np.float64).reshape(s0 // 2, 2, s0 // 2, 2, C)
+            np.testing.assert_allclose(l1, ref.mean(axis=(1, 3)), rtol=1e-6, atol=1e-7)
+
+
 def test_two_component_normals_full_frame():
     sc = synth.make_scene("shell2k")
     cam = synth.config_cameras("shell2k")[0]
