@@ -115,10 +115,22 @@ typedef struct ts_env {
     int32_t lut_res;
 } ts_env;
 
-/* Workspace sizing (host only). op: TS_OP_BIN_SORT. Writes the byte count to *bytes. */
+/* Workspace sizing (host only): the scratch bytes of one call, written to *bytes.
+     TS_OP_BIN_SORT       ts_bin_sort          (n_views, n, width, height)
+     TS_OP_RASTER_BWD     ts_raster_bwd        (n_views, n, pair_capacity)
+     TS_OP_ENV_BWD        ts_env_bwd           (n_views, width, height)
+     TS_OP_LOCALITY_PERM  ts_locality_perm     (n)
+     TS_OP_ATLAS_CHARTS   ts_atlas_pack_charts (n)
+   Arguments an op does not use are ignored. The per-op functions below give the same sizes.
+   Errors: TS_E_ARG (unknown op, null bytes, negative sizes, n_views < 1 or width/height < 1
+   where the op uses them). */
 #define TS_OP_BIN_SORT 1
+#define TS_OP_RASTER_BWD 2
+#define TS_OP_ENV_BWD 3
+#define TS_OP_LOCALITY_PERM 4
+#define TS_OP_ATLAS_CHARTS 5
 int ts_workspace_size(int32_t op, int32_t n_views, int32_t n, int32_t width, int32_t height,
-                      size_t* bytes);
+                      int64_t pair_capacity, size_t* bytes);
 
 /*
  * ts_preprocess — per view and per splat: camera-space frame, depth, facing sign, the

@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtexsplat.so")
 
 TS_OK = 0
-TS_OP_BIN_SORT = 1
+TS_OP_BIN_SORT, TS_OP_RASTER_BWD, TS_OP_ENV_BWD, TS_OP_LOCALITY_PERM, TS_OP_ATLAS_CHARTS = 1, 2, 3, 4, 5
 REC_FLOATS = 28
 TILE = 16
 
@@ -42,7 +42,8 @@ class TsRasterJob(ctypes.Structure):
 
 
 _SIGS = {
-    "ts_workspace_size": [c_int32, c_int32, c_int32, c_int32, c_int32, ctypes.POINTER(c_size_t)],
+    "ts_workspace_size": [c_int32, c_int32, c_int32, c_int32, c_int32, c_int64,
+                          ctypes.POINTER(c_size_t)],
     "ts_preprocess": [c_int32, c_int32, c_int32, c_void_p, ctypes.POINTER(TsParams), c_int32,
                       c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                       c_void_p, c_void_p],
@@ -167,9 +168,10 @@ def make_env(spec, spec_res, levels, irr, irr_res, lut, lut_res):
 # one wrapper per C entry point, same names
 # --------------------------------------------------------------------------------------
 
-def ts_workspace_size(op, n_views, n, width, height):
+def ts_workspace_size(op, n_views, n, width, height, pair_capacity=0):
     out = c_size_t(0)
-    _check(lib().ts_workspace_size(op, n_views, n, width, height, ctypes.byref(out)),
+    _check(lib().ts_workspace_size(op, n_views, n, width, height, pair_capacity,
+                                   ctypes.byref(out)),
            "ts_workspace_size")
     return int(out.value)
 

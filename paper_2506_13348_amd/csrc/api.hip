@@ -143,19 +143,35 @@ extern "C" int ts_locality_perm(const float* means, int32_t n, void* ws, size_t 
 
 extern "C" const char* ts_last_error(void) { return g_err; }
 
+extern "C" int ts_raster_bwd_workspace(int32_t n_views, int32_t n, int64_t pair_capacity,
+                                       size_t* bytes);
+extern "C" int ts_env_bwd_workspace(int32_t n_views, int32_t width, int32_t height,
+                                    size_t* bytes);
+extern "C" int ts_atlas_charts_workspace(int32_t n, size_t* bytes);
+
 extern "C" int ts_workspace_size(int32_t op, int32_t n_views, int32_t n, int32_t width,
-                                 int32_t height, size_t* bytes) {
-    if (!bytes || n_views < 1 || n < 0 || width < 1 || height < 1) {
+                                 int32_t height, int64_t pair_capacity, size_t* bytes) {
+    if (!bytes || n < 0) {
         set_error("ts_workspace_size: bad argument");
         return TS_E_ARG;
     }
-    if (op != TS_OP_BIN_SORT) {
-        set_error("ts_workspace_size: unknown op %d", op);
-        return TS_E_ARG;
+    switch (op) {
+        case TS_OP_BIN_SORT: {
+            if (n_views < 1 || width < 1 || height < 1) {
+                set_error("ts_workspace_size: bad argument");
+                return TS_E_ARG;
+            }
+            *bytes = binsort_layout(n_views, n, width, height).total;
+            return TS_OK;
+        }
+        case TS_OP_RASTER_BWD: return ts_raster_bwd_workspace(n_views, n, pair_capacity, bytes);
+        case TS_OP_ENV_BWD: return ts_env_bwd_workspace(n_views, width, height, bytes);
+        case TS_OP_LOCALITY_PERM: return ts_locality_perm_workspace(n, bytes);
+        case TS_OP_ATLAS_CHARTS: return ts_atlas_charts_workspace(n, bytes);
+        default:
+            set_error("ts_workspace_size: unknown op %d", op);
+            return TS_E_ARG;
     }
-    BinSortLayout L = binsort_layout(n_views, n, width, height);
-    *bytes = L.total;
-    return TS_OK;
 }
 
 extern "C" int ts_atlas_pack(const float* textures, int32_t n, int32_t tex_res,

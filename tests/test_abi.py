@@ -36,10 +36,20 @@ def test_host_side_argument_errors():
     from paper_2506_13348_amd import _ffi
     L = _ffi.lib()
     out = ctypes.c_size_t(0)
-    assert L.ts_workspace_size(1, 0, 10, 16, 16, ctypes.byref(out)) == -1
-    assert L.ts_workspace_size(7, 1, 10, 16, 16, ctypes.byref(out)) == -1
+    assert L.ts_workspace_size(1, 0, 10, 16, 16, 0, ctypes.byref(out)) == -1
+    assert L.ts_workspace_size(7, 1, 10, 16, 16, 0, ctypes.byref(out)) == -1
     assert b"unknown op" in L.ts_last_error()
-    assert L.ts_workspace_size(1, 2, 1000, 64, 48, ctypes.byref(out)) == 0 and out.value > 0
+    assert L.ts_workspace_size(1, 2, 1000, 64, 48, 0, ctypes.byref(out)) == 0 and out.value > 0
+    # every op's size equals its own sizing function's
+    ref = ctypes.c_size_t(0)
+    assert L.ts_workspace_size(2, 3, 500, 0, 0, 12345, ctypes.byref(out)) == 0
+    assert L.ts_raster_bwd_workspace(3, 500, 12345, ctypes.byref(ref)) == 0 and ref.value == out.value
+    assert L.ts_workspace_size(3, 2, 0, 64, 48, 0, ctypes.byref(out)) == 0
+    assert L.ts_env_bwd_workspace(2, 64, 48, ctypes.byref(ref)) == 0 and ref.value == out.value
+    assert L.ts_workspace_size(4, 1, 777, 1, 1, 0, ctypes.byref(out)) == 0
+    assert L.ts_locality_perm_workspace(777, ctypes.byref(ref)) == 0 and ref.value == out.value
+    assert L.ts_workspace_size(5, 1, 777, 1, 1, 0, ctypes.byref(out)) == 0
+    assert L.ts_atlas_charts_workspace(777, ctypes.byref(ref)) == 0 and ref.value == out.value
     p = _ffi.make_params(8)
     assert L.ts_preprocess(0, 16, 16, None, ctypes.byref(p), 10, *([None] * 8), None) == -1
     p.tex_res = 64
