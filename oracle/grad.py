@@ -70,6 +70,46 @@ def _bilinear(flat, base, H, W, X, Y):
     return (1 - fy) * ((1 - fx) * v00 + fx * v10) + fy * ((1 - fx) * v01 + fx * v11)
 
 
+def _bilinear_var(flat, base, side, X, Y):
+    """Bilinear samples of square images in flat [K, C], image m of side[m] texels starting at
+    row base[m] (per-sample long tensors), at texel coordinates X, Y (centres at integers),
+    clamp-to-edge."""
+    x0 = torch.floor(X.detach())
+    y0 = torch.floor(Y.detach())
+    fx, fy = X - x0, Y - y0
+    top = side - 1
+    i0 = torch.minimum(torch.clamp(x0.long(), min=0), top)
+    i1 = torch.minimum(torch.clamp(x0.long() + 1, min=0), top)
+    j0 = torch.minimum(torch.clamp(y0.long(), min=0), top)
+    j1 = torch.minimum(torch.clamp(y0.long() + 1, min=0), top)
+    v00, v10 = flat[base + j0 * side + i0], flat[base + j0 * side + i1]
+    v01, v11 = flat[base + j1 * side + i0], flat[base + j1 * side + i1]
+    fx, fy = fx[:, None], fy[:, None]
+    return (1 - fy) * ((1 - fx) * v00 + fx * v10) + fy * ((1 - fx) * v01 + fx * v11)
+
+
+def _mip_chain(flat, off0, log2):
+    """Every chart's box-filtered mip chain (Sec. 5 mipmapping: level l texel = mean of the
+    2^l x 2^l level-0 texels it covers), built from the level-0 texels in flat [K, 8] (chart c
+    at row off0[c], 2^log2[c] a side) with differentiable means. Returns the chain texels
+    [K', 8] and offs [n_charts, 6] (row of level l of chart c, -1 past its last level)."""
+    n = len(off0)
+    offs = np.full((n, 6), -1, np.int64)
+    parts, rows = [], 0
+    for lg in np.unique(log2):
+        cs = np.nonzero(log2 == lg)[0]
+        side = 1 << int(lg)
+        idx = torch.as_tensor(off0[cs][:, None] + np.arange(side * side)[None], dtype=torch.long)
+        lv = flat[idx].reshape(len(cs), side, side, 8)
+        for l in range(int(lg) + 1):
+            sl, b = side >> l, 1 << l
+            m = lv.reshape(len(cs), sl, b, sl, b, 8).mean(dim=(2, 4))
+            offs[cs, l] = rows + np.arange(len(cs)) * sl * sl
+            parts.append(m.reshape(-1, 8))
+            rows += len(cs) * sl * sl
+    return torch.cat(parts, 0), offs
+
+
 def _cube_lookup(cube, d):
     """cube [6, r, r, 3] float64 tensor, directions d [M,3] -> [M,3]."""
     r = cube.shape[1]
@@ -169,12 +209,21 @@ def _shade(g, A, dirs, tabs, bg, gind=None, vis=None):
 
 
 def render_dense(means, quats, scales, opac, textures, chart_of, cam, pixels, tabs=None,
-                 params=None, sh=None, degree=0, vis=None, tex_format=0):
+                 params=None, sh=None, degree=0, vis=None, tex_format=0, chart_table=None,
+                 trilinear=False, info=None):
     """Differentiable render of pixels [P,2]. Tensors are float64 (leaves may require grad).
     Returns rgba [P,4] and gbuf [P,8] (albedo 3, metallic, roughness, normal 3); with sh
     ([N,(degree+1)^2,3]) the indirect term is on (vis [P] visibility, default 1) and gbuf has
     the blended L_ind as channels 8..10. tex_format 1: two-component tangent normals, n_z
-    rebuilt as sqrt(max(0, 1 - n_x^2 - n_y^2)) after filtering (texel channel 6 unused)."""
+    rebuilt as sqrt(max(0, 1 - n_x^2 - n_y^2)) after filtering (texel channel 6 unused).
+    chart_table [n_charts, 2] (level-0 texel offset, log2 side): per-chart resolutions, the
+    textures then a flat [texels, 8] array (Sec. 5, adaptive resolution). trilinear: filter
+    over each chart's box-filtered mip chain at the level lambda = log2(T rho), rho the larger
+    of the pixel's texture-space steps along the image axes (derivatives of the exact
+    ray-plane (u,v)); lambda <= 0 samples level 0, past the last level the last level, else
+    levels floor(lambda) and floor(lambda)+1 blend by the fraction, which carries gradient
+    through rho to the geometry (Sec. 5, mipmapping). info: a dict that receives the number
+    of blended samples at level 0 alone, blending two levels and at the last level alone."""
     p = dict(DEFAULT_PARAMS)
     if params:
         p.update(params)
@@ -233,11 +282,61 @@ def render_dense(means, quats, scales, opac, textures, chart_of, cam, pixels, ta
     pi, ki = blended_o.nonzero(as_tuple=True)
     k = torch.as_tensor(order)[ki]
     uu, vv = u[pi, k], v[pi, k]
-    T = textures.shape[1]
-    X = (uu + S) / (2 * S) * T - 0.5
-    Y = (vv + S) / (2 * S) * T - 0.5
-    chart = torch.as_tensor(np.asarray(chart_of)).long()[k]
-    tx = _bilinear(textures.reshape(-1, 8), chart * T * T, T, T, X, Y)        # [B, 8]
+    chart = np.asarray(chart_of, np.int64)[k.numpy()]
+    flat = textures.reshape(-1, 8)
+    if chart_table is None:
+        T = textures.shape[1]
+        nch = len(textures)
+        off0 = np.arange(nch, dtype=np.int64) * T * T
+        log2 = np.full(nch, int(round(math.log2(T))), np.int64)
+    else:
+        ct = np.asarray(chart_table, np.int64).reshape(-1, 2)
+        off0, log2 = ct[:, 0], ct[:, 1]
+    side_b = torch.as_tensor(1 << log2[chart], dtype=torch.long)
+    s_tex = (uu + S) / (2 * S)
+    t_tex = (vv + S) / (2 * S)
+    if not trilinear:
+        sf = side_b.to(DT)
+        tx = _bilinear_var(flat, torch.as_tensor(off0[chart]), side_b, s_tex * sf - 0.5,
+                           t_tex * sf - 0.5)                                    # [B, 8]
+    else:
+        chain, offs = _mip_chain(flat, off0, log2)
+        # footprint: d(s,t)/dX and d(s,t)/dY from the ray derivative d'(X) = column X of the
+        # camera-to-world rotation over f, lambda' = -lambda (d'.n)/(d.n), P' = lambda' d +
+        # lambda d'
+        Rc2w = Wr.T
+        lam_b, den_b, d_b = lam[pi, k], den[pi, k], dirs[pi]
+        steps = []
+        for ax, f in ((0, fx), (1, fy)):
+            dd = Rc2w[:, ax] / f
+            dlam = -lam_b * (nrm[k] @ dd) / den_b
+            dP = lam_b[:, None] * dd[None] + dlam[:, None] * d_b
+            ju = (dP * tu[k]).sum(1) / scales[k, 0] / (2 * S)
+            jv = (dP * tv[k]).sum(1) / scales[k, 1] / (2 * S)
+            steps.append(torch.sqrt(ju * ju + jv * jv))
+        rho = torch.maximum(steps[0], steps[1])
+        lamb = torch.log2(side_b.to(DT) * rho)
+        Lc = torch.as_tensor(log2[chart], dtype=torch.long)
+        lv = lamb.detach()
+        l0 = torch.where(lv > 0, torch.floor(lv).long(), torch.zeros_like(Lc))
+        last = l0 >= Lc
+        blend = (lv > 0) & ~last
+        la = torch.where(last, Lc, l0)
+        lb = torch.where(blend, l0 + 1, la)
+        fb = torch.where(blend, lamb - torch.floor(lv), torch.zeros_like(lamb))
+        offs_t = torch.as_tensor(offs)
+        cb = torch.as_tensor(chart, dtype=torch.long)
+
+        def level_sample(l):
+            sl = side_b >> l
+            sf = sl.to(DT)
+            return _bilinear_var(chain, offs_t[cb, l], sl, s_tex * sf - 0.5, t_tex * sf - 0.5)
+
+        if info is not None:
+            info.update(level0=int((lv <= 0).sum()), blend=int(blend.sum()),
+                        last=int(((lv > 0) & last).sum()))
+        va, vb = level_sample(la), level_sample(lb)
+        tx = (1 - fb)[:, None] * va + fb[:, None] * vb
     nt = tx[:, 4:7]
     if tex_format == 1:
         r2 = 1 - tx[:, 4] * tx[:, 4] - tx[:, 5] * tx[:, 5]
@@ -288,7 +387,9 @@ def grads(scene, cam, pixels, d_rgba, tabs=None, params=None, env=False, vis=Non
     rgba, gbuf = render_dense(leaves["means"], leaves["quats"], leaves["scales"], leaves["opac"],
                               leaves["textures"], scene["chart_of"], cam, pixels, t, params,
                               sh=leaves.get("sh"), degree=int(scene.get("sh_degree", 0)),
-                              vis=vis, tex_format=int(scene.get("tex_format", 0)))
+                              vis=vis, tex_format=int(scene.get("tex_format", 0)),
+                              chart_table=scene.get("chart_table"),
+                              trilinear=bool(scene.get("trilinear", False)))
     loss = (rgba * torch.as_tensor(np.asarray(d_rgba), dtype=DT)).sum()
     loss.backward()
     out = {k: leaves[k].grad.detach().numpy() for k in leaves}

@@ -6,7 +6,11 @@
   crosses a support edge, the alpha cut-off or the termination threshold changes the h and
   h/2 differences; such parameters are skipped and counted);
 * with constant textures, the texel gradients of a splat summed over its T x T texels equal
-  the gradient of the same attribute rendered with 1x1 textures (the untextured primitive).
+  the gradient of the same attribute rendered with 1x1 textures (the untextured primitive);
+* with per-chart resolutions (a table-addressed flat atlas) and with trilinear filtering over
+  the box-filtered mip chain (on a zoomed-out crop whose samples blend levels), the forward
+  equals the C oracle's and every parameter group's gradient equals central differences;
+  a level fraction taken without gradient fails the trilinear case.
 """
 import numpy as np
 import pytest
@@ -309,3 +313,121 @@ def test_two_component_gradients_match_central_differences(fd_case):
             assert abs(d1 - gg[idx]) <= 2e-5 * scale + 1e-7, (name, idx, d1, gg[idx])
             checked += 1
     assert checked >= 9 and skipped <= 3, (checked, skipped)
+
+
+# ------------------------------------------- per-chart resolutions and trilinear filtering
+
+def _charted(sub, seed=11):
+    """The crop scene with each chart box-downsampled to its own side (1 to 8 texels) in a
+    table-addressed flat atlas."""
+    tex = np.asarray(sub["textures"], np.float32)
+    n, T = tex.shape[0], tex.shape[1]
+    rng = np.random.default_rng(seed)
+    log2 = rng.integers(0, int(np.log2(T)) + 1, size=n)
+    parts, table, off = [], np.zeros((n, 2), np.int32), 0
+    for c in range(n):
+        s = 1 << int(log2[c])
+        b = T // s
+        lv = tex[c].reshape(s, b, s, b, 8).mean(axis=(1, 3)).astype(np.float32)
+        parts.append(lv.reshape(-1, 8))
+        table[c] = (off, log2[c])
+        off += s * s
+    return dict(sub, textures=np.concatenate(parts), chart_table=table)
+
+
+def _variant_loss(sc, crop, pix, d, tabs, name, idx, val):
+    leaves = {k: torch.tensor(np.asarray(sc[k], np.float32), dtype=torch.float64)
+              for k in ("means", "quats", "scales", "opac", "textures")}
+    leaves[name].view(-1)[idx] = val
+    rgba, _ = og.render_dense(leaves["means"], leaves["quats"], leaves["scales"], leaves["opac"],
+                              leaves["textures"], sc["chart_of"], crop, pix, tabs,
+                              chart_table=sc.get("chart_table"),
+                              trilinear=bool(sc.get("trilinear", False)))
+    return float((rgba * torch.as_tensor(d)).sum())
+
+
+@pytest.fixture(scope="module")
+def tri_case():
+    """The training view zoomed out ten times (focal lengths / 10) and cropped to 64x64 around
+    its centre, the 1500 nearest splats: most samples there cover several texels per pixel,
+    so trilinear filtering blends levels, where the full-resolution crop only magnifies."""
+    sc = synth.make_scene("sq300k_train", n=20000, env_res=32)
+    sc["env_levels"] = 3
+    cam = dict(synth.config_cameras("sq300k_train")[0])
+    cam["fx"], cam["fy"] = cam["fx"] / 10, cam["fy"] / 10
+    sub, crop = synth.fd_crop_scene(sc, cam, 368, 368, 64, 64, n_keep=1500)
+    tabs = oracle.tables(sub["env"], sub["env_levels"])
+    pix = oracle.all_pixels(64, 64)
+    d = np.random.default_rng(2).normal(size=(len(pix), 4))
+    return sub, crop, tabs, pix, d
+
+
+VARIANTS = {"charts": dict(tri=False, charts=True), "trilinear": dict(tri=True, charts=False),
+            "charts+trilinear": dict(tri=True, charts=True)}
+
+
+@pytest.mark.parametrize("variant", list(VARIANTS))
+def test_variant_forward_matches_c_oracle(fd_case, tri_case, variant):
+    """Per-chart resolutions (flat table-addressed atlas) and trilinear filtering over the
+    box-filtered chain: the differentiable reference equals the C oracle's forward."""
+    v = VARIANTS[variant]
+    sub, crop, tabs, pix, d = tri_case if v["tri"] else fd_case
+    sc = _charted(sub) if v["charts"] else dict(sub)
+    sc["trilinear"] = v["tri"]
+    ref = oracle.render(sc, crop, pixels=pix, tabs=tabs)
+    g = og.grads(sc, crop, pix, d, tabs)
+    np.testing.assert_allclose(g["rgba"], ref["rgba"], atol=1e-10)
+    np.testing.assert_allclose(g["gbuf"], ref["gbuf"], atol=1e-12)
+    # the variant changes the image (it is not the plain uniform bilinear render)
+    base = oracle.render(sub, crop, pixels=pix, tabs=tabs)
+    assert np.abs(base["gbuf"] - ref["gbuf"]).max() > 1e-4
+    assert g["textures"].shape == np.asarray(sc["textures"]).shape
+
+
+def test_trilinear_crop_exercises_every_level_rule(tri_case):
+    """The trilinear pins below are meaningful only if the crop has samples below level 0's
+    threshold, blending two levels, and clamped at the last level; count them from the
+    footprint the reference differentiates."""
+    sub, crop, tabs, pix, d = tri_case
+    sc = dict(sub, trilinear=True)
+    leaves = {k: torch.tensor(np.asarray(sc[k], np.float32), dtype=torch.float64)
+              for k in ("means", "quats", "scales", "opac", "textures")}
+    stats = {}
+    og.render_dense(leaves["means"], leaves["quats"], leaves["scales"], leaves["opac"],
+                    leaves["textures"], sc["chart_of"], crop, pix, tabs, trilinear=True,
+                    info=stats)
+    print(stats)
+    assert stats["blend"] > 10000 and stats["level0"] > 10000 and stats["last"] > 0, stats
+
+
+@pytest.mark.parametrize("variant", list(VARIANTS))
+def test_variant_gradients_match_central_differences(fd_case, tri_case, variant):
+    """Gradients of every parameter group under the variant against central differences;
+    with trilinear filtering the centres, rotations and scales also move the level (the
+    blend fraction lambda - floor(lambda) carries gradient through the footprint)."""
+    v = VARIANTS[variant]
+    sub, crop, tabs, pix, d = tri_case if v["tri"] else fd_case
+    sc = _charted(sub) if v["charts"] else dict(sub)
+    sc["trilinear"] = v["tri"]
+    g = og.grads(sc, crop, pix, d, tabs)
+    rng = np.random.default_rng(13)
+    checked, skipped = 0, 0
+    for name in ("means", "quats", "scales", "opac", "textures"):
+        arr = np.asarray(sc[name], np.float64).reshape(-1)
+        gg = g[name].reshape(-1)
+        cand = np.argsort(-np.abs(gg))[:40]
+        picks = list(rng.choice(cand, 4, replace=False)) + list(rng.integers(0, len(arr), 1))
+        for idx in picks:
+            x0 = arr[idx]
+            h = 1e-7 * max(1.0, abs(x0))
+            f = lambda dx: _variant_loss(sc, crop, pix, d, tabs, name, idx, x0 + dx)
+            d1 = (f(h) - f(-h)) / (2 * h)
+            d2 = (f(h / 2) - f(-h / 2)) / h
+            scale = max(abs(gg[idx]), 1e-3 * np.abs(gg).max(), 1e-8)
+            if abs(d1 - d2) > 1e-4 * scale:
+                skipped += 1
+                continue
+            assert abs(d1 - gg[idx]) <= 2e-5 * scale + 1e-7, (name, idx, d1, gg[idx])
+            checked += 1
+    print(f"{variant}: checked {checked}, skipped {skipped}")
+    assert checked >= 18 and skipped <= 5, (checked, skipped)
