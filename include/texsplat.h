@@ -356,7 +356,7 @@ int ts_shade(int32_t n_views, int32_t width, int32_t height, const ts_camera* ca
  *   ws       scratch, at least ts_raster_bwd_workspace(n_views, n, pair_capacity) bytes
  *   partials scratch for per-(tile entry, 8x8 block) partial sums, partial_capacity floats;
  *            if it is too small, *status is set to 2 and the gradients are incomplete
- *            (re-run with a larger buffer). A frame needs about 24 + 8 * (texels touched)
+ *            (re-run with a larger buffer). A frame needs about 24 + 8 * (level-0 texels touched)
  *            floats per (entry, 8x8 block) with a blended pixel; each 8x8 block of the frame
  *            takes the buffer in chunks of 2048 floats, so up to that much more per block.
  *            At most 2^34 floats (TS_E_ARG above).
@@ -366,17 +366,25 @@ int ts_shade(int32_t n_views, int32_t width, int32_t height, const ts_camera* ca
  *   partial_used [1] int64 device word or NULL: floats the frame asked for (also on overflow)
  *   beta     0: overwrite the gradient outputs; 1: add to them
  *   d_means [n,3], d_quats [n,4], d_scales [n,2], d_opac [n] out
- *   d_atlas  out, in the atlas layout of params->tex_format: [n_charts][T][T][8], or
- *            [n_charts][T][T][7] for TS_TEX_RGBN2 (two-component normals, Sec. 3.5.1: the
- *            rebuilt n_z's gradient goes to n_x and n_y through n_z = sqrt(1 - n_x^2 - n_y^2))
+ *   d_atlas  out, in the layout of atlas (params->tex_format, chart table, mip chains):
+ *            [n_charts][T][T][8], or [n_charts][T][T][7] for TS_TEX_RGBN2 (two-component
+ *            normals, Sec. 3.5.1: the rebuilt n_z's gradient goes to n_x and n_y through
+ *            n_z = sqrt(1 - n_x^2 - n_y^2)); with a chart table each splat's chart at its
+ *            table offset. The gradient is w.r.t. the level-0 texels: with
+ *            TS_SAMPLER_TRILINEAR a level-l texel's share reaches the 2^l x 2^l level-0 texels
+ *            it is the box mean of (weight 4^-l), the chain's coarser levels are written as
+ *            zero gradient, and the blend fraction's gradient reaches the geometry through the
+ *            level lambda = log2(T rho) (Sec. 5). Each chart belongs to one splat (as the atlas
+ *            packers make it); texels of no splat's chart, and charts outside the atlas, are
+ *            not written
  *   lind, vis, gbuf_ind   the indirect term of the forward (as given to / written by
  *            ts_raster_fwd), or NULL for the plain shading; with lind the shading adjoint
  *            takes the specular radiance V Lspec + (1 - V) L_ind and
  *   d_lind   [n_views][n][4] out: dL/dl_ind per (view, splat) (rgb, 0), the input of
  *            ts_indirect_bwd (written, not accumulated)
- * Errors: TS_E_ARG (also gbuf_ind or d_lind missing with lind, or given without it),
- *         TS_E_WORKSPACE, TS_E_LAUNCH, TS_E_UNSUPPORTED (chart tables, trilinear sampling:
- *         rendered forward only).
+ * Errors: TS_E_ARG (also gbuf_ind or d_lind missing with lind, or given without it; the
+ *         constant sampler; the forward's atlas checks), TS_E_WORKSPACE, TS_E_LAUNCH,
+ *         TS_E_UNSUPPORTED (the hardware sampler).
  */
 int ts_raster_bwd(int32_t n_views, int32_t width, int32_t height, const ts_camera* cams,
                   const ts_params* params, int32_t n, const float* means, const float* quats,

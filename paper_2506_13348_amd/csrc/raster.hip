@@ -195,13 +195,7 @@ __device__ __forceinline__ void raster_tile(const RasterArgs& a, int v, int t) {
                         if (kSamp >= 2) {
                             float lr = 0.f;
                             if (kSamp == 3) {
-                                float4 c1 = rp[1], c2 = rp[2], c3 = rp[3];
-                                float dux = (c1.z - u * c3.x) * e.inv, duy = (c1.w - u * c3.y) * e.inv;
-                                float dvx = (c2.y - vv * c3.x) * e.inv, dvy = (c2.z - vv * c3.y) * e.inv;
-                                float ax = fmaf(dux, dux, dvx * dvx), ay = fmaf(duy, duy, dvy * dvy);
-                                // log2 rho = log2 max(|d(u,v)/dX|, |d(u,v)/dY|) - log2(2 S)
-                                lr = 0.5f * __builtin_amdgcn_logf(fmaxf(ax, ay)) -
-                                     __builtin_amdgcn_logf(2.0f * a.S);
+                                lr = footprint(rp[1], rp[2], rp[3], u, vv, e.inv, a.S).lr;
                             }
                             float tt[8];
                             int2 ce = schart[j];

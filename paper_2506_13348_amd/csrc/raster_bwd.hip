@@ -11,7 +11,12 @@
 //        dL/dalpha_i = T_i (g . x_i) - (sum_{j>i} w_j g . x_j + dL/dT_final T_final) / (1 - alpha_i)
 //    and the chain through alpha = o G(u,v), the bilinear texture sample at (u,v), the normal
 //    normalisation and rotation (Eq. 2-9), down to the 9 coefficients of the closed-form (u,v),
-//    the opacity and sigma R. Each wave (8x8 pixels) sums its pixels' contributions for one
+//    the opacity and sigma R. On the atlas variants (per-chart sides from a chart table,
+//    trilinear sampling over the box-filtered chain) the sample is taken as the forward takes
+//    it; with trilinear sampling the blend fraction of two levels also carries gradient through
+//    the level lambda = log2 T_c + log2 rho to the footprint, i.e. to the (u,v) coefficients
+//    and the pixel's (u,v), and a level-l texel's gradient reaches the 2^l x 2^l level-0 texels
+//    it is the mean of, each with weight 4^-l (the chain is derived from level 0). Each wave (8x8 pixels) sums its pixels' contributions for one
 //    splat in a fixed lane order and writes one partial — 19 geometric values and the window
 //    of texels it touched — into the partial buffer and records where in the pair's
 //    splat-major slot row. No value is accumulated with
@@ -20,7 +25,8 @@
 //    blended splat's l_ind joins g . x_i, and its partial carries 3 more sums, w dL/dL_ind.
 // 3. k_bwd_gather: per splat, the partials of its (view, tile, quadrant) entries summed in a
 //    fixed order (its slot rows are contiguous) -> per-view record gradients and the splat's
-//    texel gradients (and, with the indirect term, dL/dl_ind per view and splat).
+//    level-0 texel gradients (and, with the indirect term, dL/dl_ind per view and splat); the
+//    coarser levels of a chain get none (they are not parameters).
 // 4. k_bwd_params: per splat, in double precision, the record gradients of every view chained
 //    through the projection set-up to the splat parameters.
 #include "eval.h"
@@ -38,6 +44,56 @@ template <bool kInd> constexpr int geo_n() { return kInd ? kGeo + 3 : kGeo; }
 template <bool kInd> constexpr int hdr_n() { return kInd ? 32 : kHdr; }
 constexpr int kBwdBatch = 128;
 constexpr int kEnt = 16;          // LDS floats per lane entry: taps (4 ints), fx, fy, q[8], pad 2
+// atlas variants: taps, fx, fy of two levels, their weights over 4^level, the two levels, q[8]
+constexpr int kEntVar = 24;
+// texture paths of the backward: 0 the default atlas (uniform charts, level-0 bilinear), 1 a
+// chart table with level-0 bilinear, 2 trilinear over each chart's chain (table or uniform)
+template <int kVar> constexpr int ent_n() { return kVar ? kEntVar : kEnt; }
+// resident waves per SIMD: the variants hold a second level's texels and a larger LDS entry
+template <int kVar> constexpr int bwd_waves() { return kVar ? 3 : 4; }
+
+// bits lo..hi of a 32-bit mask (0 <= lo <= hi <= 31)
+__device__ inline unsigned bit_range(int lo, int hi) {
+    unsigned top = hi >= 31 ? 0xFFFFFFFFu : ((2u << hi) - 1u);
+    return top & ~((1u << lo) - 1u);
+}
+
+// The four texels of a bilinear footprint on one level (first texel of the level at lo,
+// Tl a side): v[tap][channel], taps 00, 10, 01, 11.
+template <int kFmt>
+__device__ inline void fetch_taps(__amdgpu_buffer_rsrc_t r, unsigned lo, int Tl, const Taps& k,
+                                  float (&v)[4][8]) {
+    float4 p[4], q[4];
+    fetch_texel(r, kFmt, lo + (unsigned)(k.j0 * Tl + k.i0), p[0], q[0]);
+    fetch_texel(r, kFmt, lo + (unsigned)(k.j0 * Tl + k.i1), p[1], q[1]);
+    fetch_texel(r, kFmt, lo + (unsigned)(k.j1 * Tl + k.i0), p[2], q[2]);
+    fetch_texel(r, kFmt, lo + (unsigned)(k.j1 * Tl + k.i1), p[3], q[3]);
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+        v[t][0] = p[t].x; v[t][1] = p[t].y; v[t][2] = p[t].z; v[t][3] = p[t].w;
+        v[t][4] = q[t].x; v[t][5] = q[t].y; v[t][6] = q[t].z; v[t][7] = q[t].w;
+    }
+}
+
+__device__ inline void bilerp_taps(const Taps& k, const float (&v)[4][8], float (&o)[8]) {
+    float w00 = (1.f - k.fx) * (1.f - k.fy), w10 = k.fx * (1.f - k.fy);
+    float w01 = (1.f - k.fx) * k.fy, w11 = k.fx * k.fy;
+#pragma unroll
+    for (int c = 0; c < 8; c++) o[c] = w00 * v[0][c] + w10 * v[1][c] + w01 * v[2][c] + w11 * v[3][c];
+}
+
+// dL/d(texel coordinates) of one level's bilinear sample for the sample gradient q:
+// with D_t = q . v_t, d/dfx = (1-fy)(D10 - D00) + fy (D11 - D01), d/dfy likewise.
+__device__ inline void bilerp_coord_grad(const Taps& k, const float (&v)[4][8], const float (&q)[8],
+                                         float& gX, float& gY) {
+    float D[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 4; t++)
+#pragma unroll
+        for (int c = 0; c < 8; c++) D[t] = fmaf(q[c], v[t][c], D[t]);
+    gX = (1.f - k.fy) * (D[1] - D[0]) + k.fy * (D[3] - D[2]);
+    gY = (1.f - k.fx) * (D[2] - D[0]) + k.fx * (D[3] - D[1]);
+}
 constexpr int kChunk = 2048;      // floats of the partial buffer a wave takes at a time
 
 struct BwdArgs {
@@ -65,6 +121,7 @@ struct BwdArgs {
     const float4* lind;      // [V][n] per (view, splat) l_ind (indirect term) or null
     const float* gind;       // [V][3][H][W] the forward's blended L_ind
     const float* vis;        // [V][H][W] visibility or null (V = 1)
+    TexArgs tex;             // atlas description of the variant paths
 };
 
 // Texel formats: kFmt 0 = 8 floats (normal xyz), 1 = 7 floats (normal xy, n_z rebuilt as
@@ -74,13 +131,14 @@ struct BwdArgs {
 // record loads measured faster than 3 waves with more registers; also for the indirect
 // variant (three more sums and the L_ind channel), whose few register spills at 4 waves cost
 // less than the fourth wave gains (training step with the indirect term 37.4 -> 33.0 ms)
-template <bool kInd, int kFmt>
-__global__ __launch_bounds__(256, 4) void k_raster_bwd(BwdArgs a) {
+template <bool kInd, int kFmt, int kVar>
+__global__ __launch_bounds__(256, (bwd_waves<kVar>())) void k_raster_bwd(BwdArgs a) {
     constexpr int kGeoN = geo_n<kInd>();
     constexpr int kHdrN = hdr_n<kInd>();
+    constexpr int kEntN = ent_n<kVar>();
     __shared__ float4 srec[kBwdBatch * kRec4];
     __shared__ float4 slind[kInd ? kBwdBatch : 1];
-    __shared__ float ent[4][kWave * kEnt];
+    __shared__ float ent[4][kWave * kEntN];
     __shared__ int smax[4];
     __shared__ uint32_t smask[kBwdBatch];
     __shared__ int32_t sslot[kBwdBatch];
@@ -186,9 +244,193 @@ __global__ __launch_bounds__(256, 4) void k_raster_bwd(BwdArgs a) {
             if (blm == 0) continue;
             float geo[kGeoN];
             int i0 = 0x7fffffff, i1 = -1, j0 = 0x7fffffff, j1 = -1;   // texel taps (blended)
+            unsigned wmx = 0u, wmy = 0u;   // variants: level-0 columns and rows touched
 #pragma unroll
             for (int k = 0; k < kGeoN; k++) geo[k] = 0.f;
-            if (bl) {
+            if (bl && kVar != 0) {
+                float4 c1 = r[1], c2 = r[2], c3 = r[3], c4 = r[4], c5 = r[5], c6 = r[6];
+                int chart = __builtin_amdgcn_readfirstlane(__float_as_int(c6.y));
+                float dx = ev.dx - c6.z, dy = ev.dy - c6.w;
+                // the chart's entry (the same for the wave), its level(s) and taps as the
+                // forward takes them
+                const int2 ce = chart_entry<kVar == 2>(a.tex, chart);
+                const bool cok = ce.y >= 0;
+                const int Lc = cok ? ce.y : 0;
+                const int Tc = 1 << Lc;
+                constexpr unsigned tb = kFmt ? 28u : 32u;
+                const unsigned n_tex =
+                    cok ? (kVar == 2 ? chain_texels(Tc) : (unsigned)(Tc * Tc)) : 0u;
+                __amdgpu_buffer_rsrc_t tr = __builtin_amdgcn_make_buffer_rsrc(
+                    (void*)(a.tex.atlas + (int64_t)(unsigned)ce.x * tb), (short)0,
+                    (int)(n_tex * tb), 0x00020000);
+                Footprint fp = {};
+                Levels lv = {0, 0, 0.f, false};
+                if (kVar == 2) {
+                    fp = footprint(c1, c2, c3, u, vv, inv, a.S);
+                    lv = mip_levels(Lc, fp.lr);
+                }
+                const Taps ka = bilinear_taps(Tc >> lv.la, u, vv, a.S);
+                float va[4][8], vb[4][8], sa[8], sb[8];
+                fetch_taps<kFmt>(tr, level_offset(Tc, lv.la), Tc >> lv.la, ka, va);
+                Taps kb = ka;
+                if (lv.blend) {
+                    kb = bilinear_taps(Tc >> lv.lb, u, vv, a.S);
+                    fetch_taps<kFmt>(tr, level_offset(Tc, lv.lb), Tc >> lv.lb, kb, vb);
+                }
+                bilerp_taps(ka, va, sa);
+                float tv[8];
+                if (lv.blend) {
+                    bilerp_taps(kb, vb, sb);
+#pragma unroll
+                    for (int c = 0; c < 8; c++) tv[c] = fmaf(lv.f, sb[c] - sa[c], sa[c]);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 8; c++) tv[c] = sa[c];
+                }
+                if (kFmt == 1) tv[6] = sqrtf(fmaxf(0.f, 1.f - tv[4] * tv[4] - tv[5] * tv[5]));
+                float nl = tv[4] * tv[4] + tv[5] * tv[5] + tv[6] * tv[6];
+                float nh[3], il = 0.f;
+                bool hasn = nl > 0.f;
+                if (hasn) {
+                    il = rsqrtf(nl);
+                    nh[0] = tv[4] * il; nh[1] = tv[5] * il; nh[2] = tv[6] * il;
+                } else {
+                    nh[0] = 0.f; nh[1] = 0.f; nh[2] = 1.f;
+                }
+                float sR[9] = {c4.x, c4.y, c4.z, c4.w, c5.x, c5.y, c5.z, c5.w, c6.x};
+                float nw[3];
+                for (int i = 0; i < 3; i++) nw[i] = sR[3 * i] * nh[0] + sR[3 * i + 1] * nh[1] + sR[3 * i + 2] * nh[2];
+                float r1m = 1.0f / (1.0f - alpha);
+                float Tb = Tr * r1m;
+                float wgt = alpha * Tb;
+                float cdot = gx[0] * tv[0] + gx[1] * tv[1] + gx[2] * tv[2] + gx[3] * tv[7] +
+                             gx[4] * tv[3] + gx[5] * nw[0] + gx[6] * nw[1] + gx[7] * nw[2];
+                if (kInd) {
+                    float4 l4 = slind[j];
+                    cdot += gli[0] * l4.x + gli[1] * l4.y + gli[2] * l4.z;
+                }
+                float dalpha = Tb * cdot - (accum + dLdTf * Tf) * r1m;
+                accum = fmaf(wgt, cdot, accum);
+                Tr = Tb;
+                float q[8];
+                q[0] = wgt * gx[0]; q[1] = wgt * gx[1]; q[2] = wgt * gx[2];
+                q[3] = wgt * gx[4];
+                q[7] = wgt * gx[3];
+                float dnw[3] = {wgt * gx[5], wgt * gx[6], wgt * gx[7]};
+                float dnh[3];
+                for (int k = 0; k < 3; k++) dnh[k] = sR[k] * dnw[0] + sR[3 + k] * dnw[1] + sR[6 + k] * dnw[2];
+                if (hasn) {
+                    float pp = nh[0] * dnh[0] + nh[1] * dnh[1] + nh[2] * dnh[2];
+                    q[4] = (dnh[0] - nh[0] * pp) * il;
+                    q[5] = (dnh[1] - nh[1] * pp) * il;
+                    q[6] = (dnh[2] - nh[2] * pp) * il;
+                } else {
+                    q[4] = q[5] = q[6] = 0.f;
+                }
+                if (kFmt == 1) {
+                    if (tv[6] > 0.f) {
+                        float r6 = q[6] / tv[6];
+                        q[4] -= r6 * tv[4];
+                        q[5] -= r6 * tv[5];
+                    }
+                    q[6] = 0.f;
+                }
+                for (int i = 0; i < 3; i++)
+                    for (int k = 0; k < 3; k++) geo[10 + 3 * i + k] = dnw[i] * nh[k];
+                float gu = 0.f, gv = 0.f, go = 0.f;
+                if (ev.oG < a.amax) {
+                    go = dalpha * ev.G;
+                    gu = -dalpha * ev.oG * u;
+                    gv = -dalpha * ev.oG * vv;
+                }
+                // through each level's bilinear weights (texel coordinate = u T_l/(2S) + ...)
+                const float wa = lv.blend ? 1.f - lv.f : 1.f;
+                {
+                    float gX, gY;
+                    bilerp_coord_grad(ka, va, q, gX, gY);
+                    const float sca = (float)(Tc >> lv.la) / (2.0f * a.S);
+                    gu = fmaf(wa * gX, sca, gu);
+                    gv = fmaf(wa * gY, sca, gv);
+                }
+                float g_ux = 0.f, g_uy = 0.f, g_vx = 0.f, g_vy = 0.f, g_wx = 0.f, g_wy = 0.f;
+                float g_w0 = 0.f, g_px = 0.f, g_py = 0.f;
+                if (lv.blend) {
+                    float gX, gY;
+                    bilerp_coord_grad(kb, vb, q, gX, gY);
+                    const float scb = (float)(Tc >> lv.lb) / (2.0f * a.S);
+                    gu = fmaf(lv.f * gX, scb, gu);
+                    gv = fmaf(lv.f * gY, scb, gv);
+                    // the blend fraction f = lambda - floor(lambda): dL/dlambda = q . (s_b - s_a),
+                    // lambda = L_c + 0.5 log2 max(ax, ay) - log2(2S)
+                    float glam = 0.f;
+#pragma unroll
+                    for (int c = 0; c < 8; c++) glam = fmaf(q[c], sb[c] - sa[c], glam);
+                    const float m = fmaxf(fp.ax, fp.ay);
+                    const float gm = glam * (0.5f * 1.44269504088896341f) / m;
+                    float gdux = 0.f, gduy = 0.f, gdvx = 0.f, gdvy = 0.f;
+                    if (fp.ax >= fp.ay) {
+                        gdux = 2.f * fp.dux * gm;
+                        gdvx = 2.f * fp.dvx * gm;
+                    } else {
+                        gduy = 2.f * fp.duy * gm;
+                        gdvy = 2.f * fp.dvy * gm;
+                    }
+                    // du/dX = (ux - u wx) inv, du/dY = (uy - u wy) inv, dv/dX, dv/dY likewise
+                    g_ux = gdux * inv;
+                    g_uy = gduy * inv;
+                    g_vx = gdvx * inv;
+                    g_vy = gdvy * inv;
+                    g_wx = -(gdux * u + gdvx * vv) * inv;
+                    g_wy = -(gduy * u + gdvy * vv) * inv;
+                    gu -= (gdux * c3.x + gduy * c3.y) * inv;
+                    gv -= (gdvx * c3.x + gdvy * c3.y) * inv;
+                    // inv = 1/den, den = wx dx + wy dy + w0
+                    const float gden = -(gdux * fp.dux + gduy * fp.duy + gdvx * fp.dvx +
+                                         gdvy * fp.dvy) * inv;
+                    g_wx = fmaf(gden, dx, g_wx);
+                    g_wy = fmaf(gden, dy, g_wy);
+                    g_w0 = gden;
+                    g_px = -gden * c3.x;
+                    g_py = -gden * c3.y;
+                }
+                float e = -(gu * u + gv * vv) * inv;
+                geo[2] = fmaf(gu * dx, inv, g_ux);
+                geo[3] = fmaf(gu * dy, inv, g_uy);
+                geo[4] = fmaf(gv * dx, inv, g_vx);
+                geo[5] = fmaf(gv * dy, inv, g_vy);
+                geo[6] = fmaf(e, dx, g_wx);
+                geo[7] = fmaf(e, dy, g_wy);
+                geo[8] = e + g_w0;
+                geo[0] = -(gu * c1.z + gv * c2.y) * inv - e * c3.x + g_px;
+                geo[1] = -(gu * c1.w + gv * c2.z) * inv - e * c3.y + g_py;
+                geo[9] = go;
+                if (kInd) {
+                    geo[kGeo + 0] = wgt * gli[0];
+                    geo[kGeo + 1] = wgt * gli[1];
+                    geo[kGeo + 2] = wgt * gli[2];
+                }
+                // level-0 texels under the taps of each level (a level-l texel is the mean of
+                // a 2^l x 2^l block of level 0)
+                wmx = bit_range(ka.i0 << lv.la, ((ka.i1 + 1) << lv.la) - 1);
+                wmy = bit_range(ka.j0 << lv.la, ((ka.j1 + 1) << lv.la) - 1);
+                if (lv.blend) {
+                    wmx |= bit_range(kb.i0 << lv.lb, ((kb.i1 + 1) << lv.lb) - 1);
+                    wmy |= bit_range(kb.j0 << lv.lb, ((kb.j1 + 1) << lv.lb) - 1);
+                }
+                float* me = E + (int)lanes_below(blm) * kEntN;
+                me[0] = __int_as_float(ka.i0); me[1] = __int_as_float(ka.i1);
+                me[2] = __int_as_float(ka.j0); me[3] = __int_as_float(ka.j1);
+                me[4] = ka.fx; me[5] = ka.fy;
+                me[6] = __int_as_float(kb.i0); me[7] = __int_as_float(kb.i1);
+                me[8] = __int_as_float(kb.j0); me[9] = __int_as_float(kb.j1);
+                me[10] = kb.fx; me[11] = kb.fy;
+                me[12] = ldexpf(wa, -2 * lv.la);
+                me[13] = lv.blend ? ldexpf(lv.f, -2 * lv.lb) : 0.f;
+                me[14] = __int_as_float(lv.la); me[15] = __int_as_float(lv.lb);
+#pragma unroll
+                for (int c = 0; c < 8; c++) me[16 + c] = q[c];
+            }
+            if (bl && kVar == 0) {
                 float4 c1 = r[1], c2 = r[2], c3 = r[3], c4 = r[4], c5 = r[5], c6 = r[6];
                 int chart = __builtin_amdgcn_readfirstlane(__float_as_int(c6.y));
                 // offsets from the exact projected centre (head + low part)
@@ -323,7 +565,7 @@ __global__ __launch_bounds__(256, 4) void k_raster_bwd(BwdArgs a) {
                     geo[kGeo + 2] = wgt * gli[2];
                 }
                 // lane entry, at the lane's rank among the blended lanes
-                float* me = E + (int)lanes_below(blm) * kEnt;
+                float* me = E + (int)lanes_below(blm) * kEntN;
                 me[0] = __int_as_float(i0); me[1] = __int_as_float(i1);
                 me[2] = __int_as_float(j0); me[3] = __int_as_float(j1);
                 me[4] = fx; me[5] = fy;
@@ -333,7 +575,13 @@ __global__ __launch_bounds__(256, 4) void k_raster_bwd(BwdArgs a) {
             // window of texels touched by this wave: OR over the blended lanes of bit masks of
             // their tap columns and rows (at least one lane is blended here; i1 >= i0, j1 >= j0)
             int wi0, wj0, wi1, wj1;
-            if (T <= 16) {
+            if (kVar != 0) {
+                unsigned mx = wave_or_dpp(wmx), my = wave_or_dpp(wmy);
+                wi0 = __builtin_ctz(mx);
+                wi1 = 31 - __builtin_clz(mx);
+                wj0 = __builtin_ctz(my);
+                wj1 = 31 - __builtin_clz(my);
+            } else if (T <= 16) {
                 unsigned mk = bl ? (1u << i0) | (1u << i1) | (0x10000u << j0) | (0x10000u << j1) : 0u;
                 unsigned m = wave_or_dpp(mk);
                 wi0 = __builtin_ctz(m & 0xFFFFu);
@@ -416,15 +664,34 @@ __global__ __launch_bounds__(256, 4) void k_raster_bwd(BwdArgs a) {
                 int ti = wi0 + (tt % wi), tj = wj0 + (tt / wi);
                 float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                 for (int p = grp; p < nbw; p += ngrp) {
-                    const float* pe = E + p * kEnt;
-                    int pi0 = __float_as_int(pe[0]), pi1 = __float_as_int(pe[1]);
-                    int pj0 = __float_as_int(pe[2]), pj1 = __float_as_int(pe[3]);
-                    float pfx = pe[4], pfy = pe[5];
-                    float wxp = (ti == pi0 ? 1.f - pfx : 0.f) + (ti == pi1 ? pfx : 0.f);
-                    float wyp = (tj == pj0 ? 1.f - pfy : 0.f) + (tj == pj1 ? pfy : 0.f);
-                    float wq = wxp * wyp;
+                    const float* pe = E + p * kEntN;
+                    if (kVar == 0) {
+                        int pi0 = __float_as_int(pe[0]), pi1 = __float_as_int(pe[1]);
+                        int pj0 = __float_as_int(pe[2]), pj1 = __float_as_int(pe[3]);
+                        float pfx = pe[4], pfy = pe[5];
+                        float wxp = (ti == pi0 ? 1.f - pfx : 0.f) + (ti == pi1 ? pfx : 0.f);
+                        float wyp = (tj == pj0 ? 1.f - pfy : 0.f) + (tj == pj1 ? pfy : 0.f);
+                        float wq = wxp * wyp;
 #pragma unroll
-                    for (int c = 0; c < 8; c++) acc[c] = fmaf(wq, pe[6 + c], acc[c]);
+                        for (int c = 0; c < 8; c++) acc[c] = fmaf(wq, pe[6 + c], acc[c]);
+                    } else {
+                        // level-0 texel (ti, tj) lies under level-l texel (ti >> l, tj >> l)
+                        float wq = 0.f;
+#pragma unroll
+                        for (int b = 0; b < 2; b++) {
+                            const float* pb = pe + 6 * b;
+                            int l = __float_as_int(pe[14 + b]);
+                            int si = ti >> l, sj = tj >> l;
+                            float pfx = pb[4], pfy = pb[5];
+                            float wxp = (si == __float_as_int(pb[0]) ? 1.f - pfx : 0.f) +
+                                        (si == __float_as_int(pb[1]) ? pfx : 0.f);
+                            float wyp = (sj == __float_as_int(pb[2]) ? 1.f - pfy : 0.f) +
+                                        (sj == __float_as_int(pb[3]) ? pfy : 0.f);
+                            wq = fmaf(pe[12 + b], wxp * wyp, wq);
+                        }
+#pragma unroll
+                        for (int c = 0; c < 8; c++) acc[c] = fmaf(wq, pe[16 + c], acc[c]);
+                    }
                 }
                 for (int sft = L; sft < kWave; sft <<= 1) {
 #pragma unroll
@@ -534,8 +801,9 @@ __global__ void k_copy_u64(const unsigned long long* src, int64_t* dst) { *dst =
 // of 64 texels. The entries are taken 64 at a time: lane e looks up entry e's slot and window
 // (so those dependent loads overlap), then the entries are summed one after another in order,
 // their slot and window read from the owning lane.
-template <bool kInd, int kFmt>
-__global__ __launch_bounds__(64) void k_bwd_gather(int V, int n, int T, const int4* __restrict__ rect,
+template <bool kInd, int kFmt, int kVar>
+__global__ __launch_bounds__(64) void k_bwd_gather(int V, int n, int T, TexArgs tex,
+                                                   const int4* __restrict__ rect,
                                                    const int64_t* __restrict__ start,
                                                    int64_t cap,
                                                    const int32_t* __restrict__ slots,
@@ -549,12 +817,24 @@ __global__ __launch_bounds__(64) void k_bwd_gather(int V, int n, int T, const in
     constexpr int kHdrN = hdr_n<kInd>();
     if (status[0] != 0) return;   // incomplete partials: leave the outputs untouched
     int s = blockIdx.x, lane = threadIdx.x;
-    int TT = T * T;
-    float* dch = d_atlas + (int64_t)chart_of[s] * TT * (kFmt ? 7 : 8);
+    constexpr int C = kFmt ? 7 : 8;
+    // the splat's chart: level-0 texel offset and side (a chart outside the atlas samples as 0
+    // and takes no texel gradient)
+    int Tg = T;
+    int64_t cbase = (int64_t)chart_of[s] * T * T;
+    bool cok = true;
+    if (kVar != 0) {
+        int2 ce = chart_entry<kVar == 2>(tex, chart_of[s]);
+        cok = ce.y >= 0;
+        Tg = cok ? 1 << ce.y : 1;
+        cbase = (unsigned)ce.x;
+    }
+    int TT = Tg * Tg;
+    float* dch = d_atlas + cbase * C;
     for (int t0 = 0; t0 < TT; t0 += kWave) {
         int tt = t0 + lane;
-        int ti = tt % T, tj = tt / T;
-        bool own = tt < TT;
+        int ti = tt % Tg, tj = tt / Tg;
+        bool own = cok && tt < TT;
         float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         for (int v = 0; v < V; v++) {
             int4 r = rect[(int64_t)v * n + s];
@@ -654,6 +934,12 @@ __global__ __launch_bounds__(64) void k_bwd_gather(int V, int n, int T, const in
                 for (int c = 0; c < 7; c++) d7[c] = beta != 0.f ? v7[c] + beta * d7[c] : v7[c];
             }
         }
+    }
+    // the chain's coarser levels are derived from level 0: no gradient of their own
+    if (kVar == 2 && cok) {
+        const int64_t end = (int64_t)chain_texels(Tg) * C;
+        for (int64_t i = (int64_t)TT * C + lane; i < end; i += kWave)
+            dch[i] = beta != 0.f ? beta * dch[i] : 0.f;
     }
 }
 
@@ -825,17 +1111,37 @@ extern "C" int ts_raster_bwd_workspace(int32_t n_views, int32_t n, int64_t pair_
     return TS_OK;
 }
 
-template <bool kInd, int kFmt>
+template <bool kInd, int kFmt, int kVar>
 static void launch_bwd(const BwdArgs& a, int n_views, int n_tiles, int n, int T, const int32_t* rect,
                        const int64_t* start, int64_t pair_capacity, const int32_t* slots,
                        const float* partials, const int32_t* chart_of, const int32_t* status,
                        float beta, float* rec_grad, float* d_atlas, float* d_lind,
                        hipStream_t stream) {
-    hipLaunchKernelGGL((k_raster_bwd<kInd, kFmt>), dim3(n_views * n_tiles), dim3(256), 0, stream,
-                       a);
-    hipLaunchKernelGGL((k_bwd_gather<kInd, kFmt>), dim3(n), dim3(64), 0, stream, n_views, n, T,
-                       (const int4*)rect, start, pair_capacity, slots, partials, chart_of, status,
-                       beta, rec_grad, d_atlas, d_lind);
+    hipLaunchKernelGGL((k_raster_bwd<kInd, kFmt, kVar>), dim3(n_views * n_tiles), dim3(256), 0,
+                       stream, a);
+    hipLaunchKernelGGL((k_bwd_gather<kInd, kFmt, kVar>), dim3(n), dim3(64), 0, stream, n_views, n,
+                       T, a.tex, (const int4*)rect, start, pair_capacity, slots, partials, chart_of,
+                       status, beta, rec_grad, d_atlas, d_lind);
+}
+
+template <bool kInd, int kFmt>
+static void launch_bwd_var(int var, const BwdArgs& a, int n_views, int n_tiles, int n, int T,
+                           const int32_t* rect, const int64_t* start, int64_t pair_capacity,
+                           const int32_t* slots, const float* partials, const int32_t* chart_of,
+                           const int32_t* status, float beta, float* rec_grad, float* d_atlas,
+                           float* d_lind, hipStream_t stream) {
+    if (var == 2)
+        launch_bwd<kInd, kFmt, 2>(a, n_views, n_tiles, n, T, rect, start, pair_capacity, slots,
+                                  partials, chart_of, status, beta, rec_grad, d_atlas, d_lind,
+                                  stream);
+    else if (var == 1)
+        launch_bwd<kInd, kFmt, 1>(a, n_views, n_tiles, n, T, rect, start, pair_capacity, slots,
+                                  partials, chart_of, status, beta, rec_grad, d_atlas, d_lind,
+                                  stream);
+    else
+        launch_bwd<kInd, kFmt, 0>(a, n_views, n_tiles, n, T, rect, start, pair_capacity, slots,
+                                  partials, chart_of, status, beta, rec_grad, d_atlas, d_lind,
+                                  stream);
 }
 
 extern "C" int ts_raster_bwd(int32_t n_views, int32_t width, int32_t height, const ts_camera* cams,
@@ -862,17 +1168,24 @@ extern "C" int ts_raster_bwd(int32_t n_views, int32_t width, int32_t height, con
         set_error("ts_raster_bwd: tex_res %d outside 1..32", params->tex_res);
         return TS_E_ARG;
     }
-    if (params->sampler != TS_SAMPLER_BILINEAR) {
-        set_error("ts_raster_bwd: only the bilinear sampler is differentiated (T = 1 textures "
-                  "give the untextured primitive)");
-        return params->sampler == TS_SAMPLER_HARDWARE || params->sampler == TS_SAMPLER_TRILINEAR
-                   ? TS_E_UNSUPPORTED : TS_E_ARG;
+    if (params->sampler != TS_SAMPLER_BILINEAR && params->sampler != TS_SAMPLER_TRILINEAR) {
+        set_error("ts_raster_bwd: the bilinear and trilinear samplers are differentiated (T = 1 "
+                  "textures give the untextured primitive)");
+        return params->sampler == TS_SAMPLER_HARDWARE ? TS_E_UNSUPPORTED : TS_E_ARG;
     }
-    if ((params->tex_format != TS_TEX_RGBN3 && params->tex_format != TS_TEX_RGBN2) ||
-        params->chart_table) {
-        set_error("ts_raster_bwd: per-chart resolutions (chart tables) are rendered forward "
-                  "only");
-        return params->chart_table ? TS_E_UNSUPPORTED : TS_E_ARG;
+    if (params->tex_format != TS_TEX_RGBN3 && params->tex_format != TS_TEX_RGBN2) {
+        set_error("ts_raster_bwd: unknown tex_format %d", params->tex_format);
+        return TS_E_ARG;
+    }
+    const bool tri = params->sampler == TS_SAMPLER_TRILINEAR;
+    if (tri && !params->chart_table && (params->tex_res & (params->tex_res - 1)) != 0) {
+        set_error("ts_raster_bwd: trilinear sampling needs a power-of-two tex_res (got %d)",
+                  params->tex_res);
+        return TS_E_ARG;
+    }
+    if (params->chart_table && params->atlas_texels <= 0) {
+        set_error("ts_raster_bwd: chart_table needs atlas_texels");
+        return TS_E_ARG;
     }
     if (lind && (!gbuf_ind || !d_lind)) {
         set_error("ts_raster_bwd: the indirect term needs gbuf_ind and d_lind");
@@ -929,23 +1242,32 @@ extern "C" int ts_raster_bwd(int32_t n_views, int32_t width, int32_t height, con
     a.rect = (const int4*)rect; a.start = (const int64_t*)start;
     a.part = partials; a.part_cap = partial_capacity; a.part_top = top; a.status = status;
     a.lind = (const float4*)lind; a.gind = gbuf_ind; a.vis = vis;
+    a.tex.atlas = (const char*)atlas;
+    a.tex.table = (const int2*)params->chart_table;
+    a.tex.atlas_texels = params->atlas_texels;
+    a.tex.T = params->tex_res;
+    a.tex.L = ilog2(params->tex_res);
+    a.tex.chart_texels = tri ? chain_texels(params->tex_res)
+                             : (unsigned)(params->tex_res * params->tex_res);
+    a.tex.fmt = params->tex_format;
+    const int var = tri ? 2 : params->chart_table ? 1 : 0;
     const bool xy = params->tex_format == TS_TEX_RGBN2;
     if (lind && xy)
-        launch_bwd<true, 1>(a, n_views, n_tiles, n, params->tex_res, rect, start, pair_capacity,
-                            slots, partials, chart_of, status, beta, rec_grad, d_atlas, d_lind,
-                            stream);
+        launch_bwd_var<true, 1>(var, a, n_views, n_tiles, n, params->tex_res, rect, start,
+                                pair_capacity, slots, partials, chart_of, status, beta, rec_grad,
+                                d_atlas, d_lind, stream);
     else if (lind)
-        launch_bwd<true, 0>(a, n_views, n_tiles, n, params->tex_res, rect, start, pair_capacity,
-                            slots, partials, chart_of, status, beta, rec_grad, d_atlas, d_lind,
-                            stream);
+        launch_bwd_var<true, 0>(var, a, n_views, n_tiles, n, params->tex_res, rect, start,
+                                pair_capacity, slots, partials, chart_of, status, beta, rec_grad,
+                                d_atlas, d_lind, stream);
     else if (xy)
-        launch_bwd<false, 1>(a, n_views, n_tiles, n, params->tex_res, rect, start, pair_capacity,
-                             slots, partials, chart_of, status, beta, rec_grad, d_atlas, nullptr,
-                             stream);
+        launch_bwd_var<false, 1>(var, a, n_views, n_tiles, n, params->tex_res, rect, start,
+                                 pair_capacity, slots, partials, chart_of, status, beta, rec_grad,
+                                 d_atlas, nullptr, stream);
     else
-        launch_bwd<false, 0>(a, n_views, n_tiles, n, params->tex_res, rect, start, pair_capacity,
-                             slots, partials, chart_of, status, beta, rec_grad, d_atlas, nullptr,
-                             stream);
+        launch_bwd_var<false, 0>(var, a, n_views, n_tiles, n, params->tex_res, rect, start,
+                                 pair_capacity, slots, partials, chart_of, status, beta, rec_grad,
+                                 d_atlas, nullptr, stream);
     hipLaunchKernelGGL(k_bwd_params, dim3((n + 255) / 256), dim3(256), 0, stream, n_views, n, cams,
                        means, quats, scales, (const int4*)rect, (const float*)rec_grad,
                        (const int32_t*)status, beta, d_means, d_quats, d_scales, d_opac);

@@ -44,19 +44,83 @@ __device__ inline void fetch_texel(__amdgpu_buffer_rsrc_t r, int fmt, unsigned t
     }
 }
 
-// Bilinear on level l of a chart of side Tc at local (u,v) (s = (u+S)/(2S)): texel centres at
-// (i+1/2)/T_l, clamp-to-edge inside the chart (Eq. 5-6).
-__device__ inline void bilinear_level(__amdgpu_buffer_rsrc_t r, int fmt, int Tc, int l, float u,
-                                      float v, float S, float* o) {
-    const int Tl = Tc >> l;
+// The four taps of bilinear filtering on a level of Tl texels a side at local (u,v)
+// (s = (u+S)/(2S)): texel centres at (i+1/2)/T_l, clamp-to-edge inside the chart (Eq. 5-6).
+struct Taps {
+    int i0, i1, j0, j1;
+    float fx, fy;
+};
+
+__device__ inline Taps bilinear_taps(int Tl, float u, float v, float S) {
+    Taps k;
     const float sc = (float)Tl / (2.0f * S), off = 0.5f * (float)Tl - 0.5f;
     float sx = fmaf(u, sc, off), sy = fmaf(v, sc, off);
     float fx0 = floorf(sx), fy0 = floorf(sy);
-    float fx = sx - fx0, fy = sy - fy0;
+    k.fx = sx - fx0;
+    k.fy = sy - fy0;
     int i0 = (int)fx0, j0 = (int)fy0;
-    int i1 = min(max(i0 + 1, 0), Tl - 1), j1 = min(max(j0 + 1, 0), Tl - 1);
-    i0 = min(max(i0, 0), Tl - 1);
-    j0 = min(max(j0, 0), Tl - 1);
+    k.i1 = min(max(i0 + 1, 0), Tl - 1);
+    k.j1 = min(max(j0 + 1, 0), Tl - 1);
+    k.i0 = min(max(i0, 0), Tl - 1);
+    k.j0 = min(max(j0, 0), Tl - 1);
+    return k;
+}
+
+// Footprint of the pixel on the splat: the image-axis derivatives of the closed-form
+// (u,v) = (ux dx + uy dy + u0, vx dx + vy dy + v0) / (wx dx + wy dy + w0) (record rows c1..c3,
+// inv = 1/den of the pixel), d(u,v)/dX = (ux - u wx, vx - v wx) inv and likewise along Y, and
+// lr = log2 rho = log2 max(|d(u,v)/dX|, |d(u,v)/dY|) - log2(2S): rho in units of the whole
+// chart, so a chart of side T_c takes level lambda = log2 T_c + lr (Sec. 5, mipmapping).
+struct Footprint {
+    float dux, duy, dvx, dvy, ax, ay, lr;
+};
+
+__device__ inline Footprint footprint(float4 c1, float4 c2, float4 c3, float u, float v,
+                                      float inv, float S) {
+    Footprint f;
+    f.dux = (c1.z - u * c3.x) * inv;
+    f.duy = (c1.w - u * c3.y) * inv;
+    f.dvx = (c2.y - v * c3.x) * inv;
+    f.dvy = (c2.z - v * c3.y) * inv;
+    f.ax = fmaf(f.dux, f.dux, f.dvx * f.dvx);
+    f.ay = fmaf(f.duy, f.duy, f.dvy * f.dvy);
+    f.lr = 0.5f * __builtin_amdgcn_logf(fmaxf(f.ax, f.ay)) - __builtin_amdgcn_logf(2.0f * S);
+    return f;
+}
+
+// Levels of trilinear sampling on a chain of levels 0..L at lambda = L + lr: lambda <= 0 (or
+// undefined) level 0 alone; past the last level, level L alone; else levels floor(lambda) and
+// floor(lambda)+1 blended by the fraction f.
+struct Levels {
+    int la, lb;
+    float f;
+    bool blend;
+};
+
+__device__ inline Levels mip_levels(int L, float lr) {
+    Levels m = {0, 0, 0.f, false};
+    float lam = (float)L + lr;
+    if (lam > 0.f) {
+        int l0 = (int)floorf(lam);
+        if (l0 >= L) {
+            m.la = m.lb = L;
+        } else {
+            m.la = l0;
+            m.lb = l0 + 1;
+            m.f = lam - (float)l0;
+            m.blend = true;
+        }
+    }
+    return m;
+}
+
+// Bilinear on level l of a chart of side Tc at local (u,v).
+__device__ inline void bilinear_level(__amdgpu_buffer_rsrc_t r, int fmt, int Tc, int l, float u,
+                                      float v, float S, float* o) {
+    const int Tl = Tc >> l;
+    const Taps k = bilinear_taps(Tl, u, v, S);
+    const int i0 = k.i0, i1 = k.i1, j0 = k.j0, j1 = k.j1;
+    const float fx = k.fx, fy = k.fy;
     const unsigned lo = level_offset(Tc, l);
     float4 p00, q00, p10, q10, p01, q01, p11, q11;
     fetch_texel(r, fmt, lo + (unsigned)(j0 * Tl + i0), p00, q00);
@@ -103,20 +167,15 @@ __device__ inline void sample_chart(const TexArgs& ta, int2 ce, float u, float v
     if (!kTri) {
         bilinear_level(r, ta.fmt, Tc, 0, u, v, S, t);
     } else {
-        float lam = (float)L + lr;
-        if (!(lam > 0.f)) {
-            bilinear_level(r, ta.fmt, Tc, 0, u, v, S, t);
+        const Levels m = mip_levels(L, lr);
+        if (!m.blend) {
+            bilinear_level(r, ta.fmt, Tc, m.la, u, v, S, t);
         } else {
-            int l0 = (int)floorf(lam);
-            if (l0 >= L) {
-                bilinear_level(r, ta.fmt, Tc, L, u, v, S, t);
-            } else {
-                float f = lam - (float)l0, t1[8];
-                bilinear_level(r, ta.fmt, Tc, l0, u, v, S, t);
-                bilinear_level(r, ta.fmt, Tc, l0 + 1, u, v, S, t1);
+            float t1[8];
+            bilinear_level(r, ta.fmt, Tc, m.la, u, v, S, t);
+            bilinear_level(r, ta.fmt, Tc, m.lb, u, v, S, t1);
 #pragma unroll
-                for (int q = 0; q < 8; q++) t[q] = fmaf(f, t1[q] - t[q], t[q]);
-            }
+            for (int q = 0; q < 8; q++) t[q] = fmaf(m.f, t1[q] - t[q], t[q]);
         }
     }
     if (ta.fmt) t[6] = sqrtf(fmaxf(0.f, 1.f - t[4] * t[4] - t[5] * t[5]));

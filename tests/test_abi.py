@@ -94,10 +94,14 @@ def test_host_side_argument_errors():
              one, one, 0.0, one, one, one, one, one] + list(ind) + [None]
         assert L.ts_raster_bwd(*args) == -1
         assert msg in L.ts_last_error(), L.ts_last_error()
-    # backward of the atlas variants: chart tables are refused (forward only), an unknown
-    # texel format is an argument error
-    for kw, code, msg in ((dict(chart_table=16), -4, b"forward only"),
-                          (dict(tex_format=3), -1, b"forward only")):
+    # backward of the atlas variants: a chart table needs atlas_texels, trilinear sampling on
+    # uniform charts a power-of-two side; an unknown texel format and the constant sampler are
+    # argument errors, the hardware sampler is unsupported
+    for kw, code, msg in ((dict(chart_table=16), -1, b"needs atlas_texels"),
+                          (dict(tex_format=3), -1, b"unknown tex_format"),
+                          (dict(sampler=_ffi.SAMPLER_TRILINEAR, tex_res=6), -1, b"power-of-two"),
+                          (dict(sampler=_ffi.SAMPLER_CONSTANT, tex_res=1), -1, b"differentiated"),
+                          (dict(sampler=_ffi.SAMPLER_HARDWARE), -4, b"differentiated")):
         q = _ffi.make_params(8)
         for k, v in kw.items():
             setattr(q, k, v)

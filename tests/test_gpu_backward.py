@@ -715,3 +715,143 @@ def test_xy_normals_with_indirect_term_grads_fd_crop(fd_case):
     g = list(grads)
     g[4] = g[4].view(dsc.n, T, T, 7)
     _compare_ind(g, _seven(ref), "xy normals + indirect fd crop")
+
+
+# ------------------------------- atlas variants: per-chart resolutions, trilinear sampling
+
+def _charted(sub, seed=11):
+    """The crop scene with each chart box-downsampled to its own side (1 to T texels), level-0
+    texels back to back in splat order, and the table of (level-0 offset, log2 side)."""
+    tex = np.asarray(sub["textures"], np.float32)
+    n, T = tex.shape[0], tex.shape[1]
+    log2 = np.random.default_rng(seed).integers(0, int(np.log2(T)) + 1, size=n).astype(np.int32)
+    parts, table, off = [], np.zeros((n, 2), np.int32), 0
+    for c in range(n):
+        s = 1 << int(log2[c])
+        b = T // s
+        parts.append(tex[c].reshape(s, b, s, b, 8).mean(axis=(1, 3)).astype(np.float32)
+                     .reshape(-1, 8))
+        table[c] = (off, log2[c])
+        off += s * s
+    return np.concatenate(parts), table, log2
+
+
+def _zoomed_crop():
+    """The training view with focal lengths / 10, a 64x64 crop at its centre and its 1500
+    nearest splats: samples there cover several texels per pixel, so trilinear sampling blends
+    levels (and some reach the last level)."""
+    sc = synth.make_scene("sq300k_train", n=20000, env_res=32)
+    sc["env_levels"] = 3
+    cam = dict(synth.config_cameras("sq300k_train")[0])
+    cam["fx"], cam["fy"] = cam["fx"] / 10, cam["fy"] / 10
+    return synth.fd_crop_scene(sc, cam, 368, 368, 64, 64, n_keep=1500)
+
+
+def _variant_case(sub, fmt, charts, tri):
+    """(reference scene for oracle/grad.py, C-oracle scene, DeviceScene keyword arguments,
+    device-side texture input) of one variant of the crop scene."""
+    ref_sc = dict(sub, trilinear=tri, tex_format=fmt)
+    kw = dict(tex_format=fmt, mips=tri)
+    dev_sc = dict(sub)
+    if charts:
+        flat, table, log2 = _charted(sub)
+        ref_sc.update(textures=flat, chart_table=table)
+        kw["chart_log2"] = log2
+        dev_sc["textures"] = flat
+    c_sc = dict(ref_sc, textures=_n2(ref_sc["textures"]) if fmt else ref_sc["textures"])
+    return ref_sc, c_sc, kw, dev_sc
+
+
+def _gpu_grads_variant(dev_sc, kw, cams, W, H, d_rgba):
+    """GPU gradients with the texel gradients taken out of the atlas layout: level 0 of each
+    splat's chart, in the reference's layout (8 channels, channel 6 zero with 7-float texels);
+    the chain's coarser levels must hold exact zeros."""
+    P = _pkg()
+    from paper_2506_13348_amd.autograd import BackwardRunner
+    ds = P.DeviceScene.from_dict(dev_sc, device="cuda", **kw)
+    plan = P.RenderPlan(ds, cams, W, H, gbuf=True, aux=True)
+    plan.run()
+    plan.check()
+    grads = tuple(torch.zeros_like(t) for t in (ds.means, ds.quats, ds.scales, ds.opac))
+    grads = grads + (torch.full_like(ds.atlas, 7.0),)     # every atlas texel must be written
+    BackwardRunner(plan).run(torch.as_tensor(np.asarray(d_rgba, np.float32)).cuda().contiguous(),
+                             grads)
+    torch.cuda.synchronize()
+    out = {k: g.double().cpu().numpy() for k, g in zip(NAMES[:4], grads[:4])}
+    C = 7 if kw.get("tex_format", 0) else 8
+    ga = grads[4].double().cpu().numpy().reshape(-1, C)
+    chart_of = ds.chart_of.cpu().numpy()
+    mips = kw.get("mips", False)
+    if ds.chart_table is not None:
+        tab = ds.chart_table.cpu().numpy()
+        ents = [(int(tab[c, 0]), 1 << int(tab[c, 1])) for c in chart_of]
+    else:
+        T = ds.tex_res
+        stride = (4 * T * T - 1) // 3 if mips else T * T
+        ents = [(int(c) * stride, T) for c in chart_of]
+    lv0, coarse = [], []
+    for off, side in ents:
+        lv0.append(ga[off:off + side * side])
+        if mips:
+            coarse.append(ga[off + side * side:off + (4 * side * side - 1) // 3])
+    lv0 = np.concatenate(lv0)
+    if C == 7:
+        lv0 = np.concatenate([lv0[:, :6], np.zeros((len(lv0), 1)), lv0[:, 6:]], 1)
+    if coarse:
+        assert all(np.all(c == 0) for c in coarse), "coarser chain levels got a gradient"
+    out["textures"] = lv0
+    return out
+
+
+def _variant_compare(sub, crop, fmt, charts, tri, seed, name):
+    ref_sc, c_sc, kw, dev_sc = _variant_case(sub, fmt, charts, tri)
+    tabs = oracle.tables(sub["env"], sub["env_levels"])
+    pix = oracle.all_pixels(64, 64)
+    ref_f = oracle.render(c_sc, crop, pixels=pix, tabs=tabs)
+    d, d4 = _upstream(np.random.default_rng(seed), ref_f, (1, 64, 64, 4))
+    ref, spread = _reference(ref_sc, [crop], pix, [d], tabs)
+    ref = dict(ref, textures=ref["textures"].reshape(-1, 8))
+    spread = dict(spread, textures=spread["textures"].reshape(-1, 8))
+    g = _gpu_grads_variant(dev_sc, kw, [crop], 64, 64, d4)
+    _compare(g, ref, name, spread)
+
+
+@pytest.mark.parametrize("fmt", [0, 1])
+def test_chart_table_grads_fd_crop(fd_case, fmt):
+    """Per-chart sides 1..8 in one table-addressed atlas (level-0 bilinear) on the 64x64 crop."""
+    sub, crop = fd_case
+    _variant_compare(sub, crop, fmt, True, False, 101 + fmt, f"chart table fmt={fmt}")
+
+
+@pytest.mark.parametrize("fmt,charts", [(0, False), (1, False), (0, True), (1, True)])
+def test_trilinear_grads_zoomed_crop(fmt, charts):
+    """Trilinear sampling over each chart's box-filtered chain (uniform charts or a chart
+    table) where most samples blend two levels: the level's gradient reaches the centres,
+    rotations and scales through the footprint, and every level's texel gradient is folded
+    into level 0."""
+    sub, crop = _zoomed_crop()
+    _variant_compare(sub, crop, fmt, charts, True, 111 + fmt + 2 * charts,
+                     f"trilinear fmt={fmt} charts={charts}")
+
+
+def test_trilinear_grads_multi_view_ragged():
+    """Three ragged views of a 700-splat shell with 8-texel charts: most samples blend two
+    levels, some sit at the last level (1 texel), a few at level 0."""
+    sc = synth.make_scene("shell2k", n=700, tex_res=8)
+    cams = synth.orbit_cameras(3, 45, 37, dist=2.8, el_deg=10.0)
+    rng = np.random.default_rng(121)
+    tabs = oracle.tables(sc["env"], 1)
+    pix = oracle.all_pixels(45, 37)
+    ref_sc = dict(sc, trilinear=True)
+    d_all = np.zeros((3, 37, 45, 4))
+    ds = []
+    for v, cam in enumerate(cams):
+        ref_f = oracle.render(ref_sc, cam, pixels=pix, tabs=tabs)
+        d, d4 = _upstream(rng, ref_f, (37, 45, 4))
+        d_all[v] = d4
+        ds.append(d)
+    ref, spread = _reference(ref_sc, cams, pix, ds, tabs)
+    ref = dict(ref, textures=ref["textures"].reshape(-1, 8))
+    spread = dict(spread, textures=spread["textures"].reshape(-1, 8))
+    g = _gpu_grads_variant(sc, dict(mips=True), cams, 45, 37, d_all)
+    _compare(g, ref, "trilinear 3 views", spread)

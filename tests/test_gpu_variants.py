@@ -194,24 +194,18 @@ def test_variants_full_size_sampled():
         _frame(osc, cams[v], out, v=v, pixels=pix, name=f"sq100k xy+trilinear v{v}")
 
 
-def test_variant_backward_is_refused():
-    """Per-chart resolutions and trilinear sampling are rendered forward only (two-component
-    normals have a backward: tests/test_gpu_backward.py)."""
+def test_hardware_sampler_backward_is_refused():
+    """The texture-unit sampler has no gfx950 path, forward or backward."""
     P = _pkg()
+    from paper_2506_13348_amd import _ffi as F
+    from paper_2506_13348_amd.autograd import BackwardRunner
     sc = synth.make_scene("shell2k", n=200)
     cam = synth.config_cameras("shell2k")[0]
-    from paper_2506_13348_amd.autograd import BackwardRunner
-    log2 = synth.texture_sides(sc["scales"])
-    flat = synth.adaptive_textures(np.random.default_rng(3), log2)
-    for kw, scene, msg in ((dict(chart_log2=log2), dict(sc, textures=flat), "forward only"),
-                           (dict(mips=True), sc, "bilinear sampler")):
-        ds = P.DeviceScene.from_dict(scene, device="cuda", **kw)
-        plan = P.RenderPlan(ds, [cam], 64, 64, gbuf=True, aux=True)
-        plan.run()
-        plan.check()
-        n = ds.n
-        grads = (torch.zeros(n * 3, device="cuda"), torch.zeros(n * 4, device="cuda"),
-                 torch.zeros(n * 2, device="cuda"), torch.zeros(n, device="cuda"),
-                 torch.zeros_like(ds.atlas))
-        with pytest.raises(RuntimeError, match=msg):
-            BackwardRunner(plan).run(torch.zeros(64 * 64 * 4, device="cuda"), grads)
+    ds = P.DeviceScene.from_dict(sc, device="cuda")
+    plan = P.RenderPlan(ds, [cam], 64, 64, gbuf=True, aux=True)
+    plan.run()
+    plan.check()
+    plan.params.sampler = F.SAMPLER_HARDWARE
+    grads = tuple(torch.zeros_like(t) for t in (ds.means, ds.quats, ds.scales, ds.opac, ds.atlas))
+    with pytest.raises(RuntimeError, match="trilinear samplers are differentiated"):
+        BackwardRunner(plan).run(torch.zeros(64 * 64 * 4, device="cuda"), grads)
