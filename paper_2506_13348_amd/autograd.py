@@ -20,14 +20,20 @@ class _SceneView(SimpleNamespace):
     pass
 
 
-def _scene_view(means, quats, scales, opac, atlas, chart_of, tables, sh=None, sh_degree=0):
-    return _SceneView(device=means.device, n=int(means.shape[0]), tex_res=int(atlas.shape[1]),
-                      means=means.contiguous(), quats=quats.contiguous(),
-                      scales=scales.contiguous(), opac=opac.contiguous(),
-                      atlas=atlas.contiguous(), chart_of=chart_of.contiguous(), tables=tables,
-                      # [n_charts, T, T, 7]: two-component tangent normals
-                      tex_format=1 if atlas.dim() == 4 and atlas.shape[-1] == 7 else 0,
-                      sh=None if sh is None else sh.contiguous(), sh_degree=int(sh_degree))
+def _scene_view(means, quats, scales, opac, atlas, chart_of, tables, sh=None, sh_degree=0,
+                atlas_spec=None):
+    if atlas_spec is None:
+        # [n_charts, T, T, 8], or [n_charts, T, T, 7]: two-component tangent normals
+        spec = dict(tex_res=int(atlas.shape[1]),
+                    tex_format=1 if atlas.dim() == 4 and atlas.shape[-1] == 7 else 0)
+    else:
+        spec = dict(atlas_spec)
+    return _SceneView(device=means.device, n=int(means.shape[0]), means=means.contiguous(),
+                      quats=quats.contiguous(), scales=scales.contiguous(),
+                      opac=opac.contiguous(), atlas=atlas.contiguous(),
+                      chart_of=chart_of.contiguous(), tables=tables,
+                      sh=None if sh is None else sh.contiguous(), sh_degree=int(sh_degree),
+                      **spec)
 
 
 class BackwardRunner:
@@ -107,10 +113,10 @@ class EnvBackward:
 class TexSplatRender(torch.autograd.Function):
     @staticmethod
     def forward(ctx, means, quats, scales, opac, atlas, chart_of, cams, width, height, tables,
-                params, sh, sh_degree, vis):
+                params, sh, sh_degree, vis, atlas_spec):
         sv = _scene_view(means.detach(), quats.detach(), scales.detach(), opac.detach(),
                          atlas.detach(), chart_of, tables,
-                         None if sh is None else sh.detach(), sh_degree)
+                         None if sh is None else sh.detach(), sh_degree, atlas_spec)
         plan = RenderPlan(sv, cams, width, height, params, shade=True, gbuf=True, aux=True,
                           vis=vis)
         plan.run()
@@ -129,14 +135,19 @@ class TexSplatRender(torch.autograd.Function):
             grads = grads + (torch.empty_like(sc.sh),)
         BackwardRunner(plan).run(d_rgba.contiguous(), grads)
         d_sh = grads[5] if plan.indirect else None
-        return (*grads[:5], None, None, None, None, None, None, d_sh, None, None)
+        return (*grads[:5], None, None, None, None, None, None, d_sh, None, None, None)
 
 
 def render_rgba(means, quats, scales, opac, atlas, chart_of, cams, width, height, tables,
-                params=None, sh=None, sh_degree=0, vis=None):
+                params=None, sh=None, sh_degree=0, vis=None, atlas_spec=None):
     """[V,H,W,4] shaded RGBA + alpha, differentiable w.r.t. the first five tensors (atlas
     [n_charts,T,T,8], or [n_charts,T,T,7] with two-component tangent normals) and, with
     the indirect term (sh [n,(sh_degree+1)^2,3] per-splat SH coefficients, vis [V,H,W] optional
-    visibility), w.r.t. sh as well."""
+    visibility), w.r.t. sh as well.
+
+    atlas_spec (DeviceScene.atlas_spec()) describes any other atlas layout: per-chart sides
+    through a chart table, mip chains with trilinear sampling. The atlas gradient then has the
+    atlas's layout and is w.r.t. the level-0 texels (zero on the coarser levels of a chain,
+    which ts_atlas_mips rebuilds from level 0 after an update)."""
     return TexSplatRender.apply(means, quats, scales, opac, atlas, chart_of, cams, width, height,
-                                tables, params, sh, sh_degree, vis)
+                                tables, params, sh, sh_degree, vis, atlas_spec)

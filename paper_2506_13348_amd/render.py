@@ -88,6 +88,7 @@ class DeviceScene:
         self.device = torch.device(device)
         self.tex_format, self.mips = int(tex_format), bool(mips)
         self.chart_table, self.atlas_texels = None, 0
+        self.max_log2 = 0       # largest log2 chart side
         # indirect light: [n, (degree+1)^2, 3] SH coefficients per splat, or None
         self.sh = None if sh is None else _dev(sh, device, torch.float32)
         self.sh_degree = int(sh_degree)
@@ -101,6 +102,7 @@ class DeviceScene:
         else:
             tex = _dev(textures, device, torch.float32)
             self.tex_res = int(tex.shape[1])
+            self.max_log2 = max(self.tex_res.bit_length() - 1, 0)
             T, C = self.tex_res, (7 if self.tex_format else 8)
             chart = (4 * T * T - 1) // 3 if self.mips else T * T
             self.atlas = (torch.empty_like(tex) if not (self.tex_format or self.mips) else
@@ -141,6 +143,7 @@ class DeviceScene:
         self.atlas_texels = total
         self.chart_of = torch.arange(n, device=self.device, dtype=torch.int32)
         self.tex_res = int(sides.max()) if n else 1
+        self.max_log2 = int(log2.max()) if n else 0
         if n:
             lv0 = _dev(np.asarray(texels, np.float32).reshape(-1, 8), self.device)
             ws = F.ts_atlas_pack_charts(lv0, n, _dev(log2, self.device), int(log2.max()),
@@ -148,6 +151,19 @@ class DeviceScene:
                                         self.atlas, total)
             torch.cuda.current_stream(self.device).synchronize()
             del lv0, ws
+
+    def atlas_spec(self):
+        """How the atlas is laid out (side, texel format, mip chains, chart table), for views
+        of this scene's tensors such as autograd.render_rgba's."""
+        return dict(tex_res=self.tex_res, tex_format=self.tex_format, mips=self.mips,
+                    chart_table=self.chart_table, atlas_texels=self.atlas_texels)
+
+    def rebuild_mips(self, stream=None):
+        """Levels 1.. of every chart's chain again from its level 0 (after level 0 changed)."""
+        if not self.mips:
+            raise ValueError("the atlas holds no mip chains")
+        F.ts_atlas_mips(self.atlas, self.n, self.tex_res, self.chart_table, self.max_log2,
+                        self.atlas_texels, self.tex_format, stream)
 
     @classmethod
     def from_dict(cls, sc, device="cuda", **kw):

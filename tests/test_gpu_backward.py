@@ -855,3 +855,67 @@ def test_trilinear_grads_multi_view_ragged():
     spread = dict(spread, textures=spread["textures"].reshape(-1, 8))
     g = _gpu_grads_variant(sc, dict(mips=True), cams, 45, 37, d_all)
     _compare(g, ref, "trilinear 3 views", spread)
+
+
+@pytest.mark.parametrize("charts", [False, True])
+def test_variant_autograd_matches_runner_and_trains(charts):
+    """render_rgba over a trilinear atlas (uniform or chart table) given the scene's atlas_spec:
+    its gradients equal the runner's bit for bit, and a few gradient steps on the level-0
+    texels (chains rebuilt by ts_atlas_mips after each) bring the render back towards a target
+    rendered from the original texels."""
+    P = _pkg()
+    from paper_2506_13348_amd.autograd import BackwardRunner, render_rgba
+    sc = synth.make_scene("shell2k", n=600, tex_res=8)
+    cam = synth.orbit_cameras(1, 96, 96, dist=2.8, el_deg=10.0)[0]
+    kw = dict(mips=True)
+    dev_sc = sc
+    if charts:
+        log2 = synth.texture_sides(sc["scales"], max_log2=3)
+        dev_sc = dict(sc, textures=synth.adaptive_textures(np.random.default_rng(5), log2))
+        kw["chart_log2"] = log2
+    ds = P.DeviceScene.from_dict(dev_sc, device="cuda", **kw)
+    cams = P.cameras_tensor([cam])
+    leaves = [t.clone().requires_grad_(True) for t in (ds.means, ds.quats, ds.scales, ds.opac,
+                                                       ds.atlas)]
+    rgba = render_rgba(*leaves, ds.chart_of, cams, 96, 96, ds.tables, atlas_spec=ds.atlas_spec())
+    d4 = torch.randn(1, 96, 96, 4, device="cuda", generator=torch.Generator("cuda").manual_seed(7))
+    (rgba * d4).sum().backward()
+    plan = P.RenderPlan(ds, [cam], 96, 96, gbuf=True, aux=True)
+    plan.run()
+    plan.check()
+    grads = tuple(torch.zeros_like(t) for t in (ds.means, ds.quats, ds.scales, ds.opac, ds.atlas))
+    BackwardRunner(plan).run(d4.reshape(-1).contiguous(), grads)
+    torch.cuda.synchronize()
+    for k, leaf, ref in zip(NAMES, leaves, grads):
+        assert torch.equal(leaf.grad, ref), k
+    assert float(leaves[4].grad.abs().max()) > 0
+    # a short fit of the level-0 texels to a target from the original atlas
+    with torch.no_grad():
+        target = render_rgba(ds.means, ds.quats, ds.scales, ds.opac, ds.atlas, ds.chart_of, cams,
+                             96, 96, ds.tables, atlas_spec=ds.atlas_spec()).clone()
+        noise = torch.randn(ds.atlas.shape, device="cuda",
+                            generator=torch.Generator("cuda").manual_seed(8))
+        ds.atlas += 0.2 * noise
+        ds.rebuild_mips()
+    atlas = ds.atlas.requires_grad_(True)
+    opt = torch.optim.Adam([atlas], lr=0.02)
+    losses = []
+    for it in range(30):
+        out = render_rgba(ds.means, ds.quats, ds.scales, ds.opac, atlas, ds.chart_of, cams, 96, 96,
+                          ds.tables, atlas_spec=ds.atlas_spec())
+        loss = (out - target).square().mean()
+        opt.zero_grad()
+        loss.backward()
+        opt.step()
+        with torch.no_grad():
+            ds.rebuild_mips()
+        losses.append(float(loss.detach()))
+    print(f"[trilinear fit charts={charts}] loss {losses[0]:.3e} -> {losses[-1]:.3e}", flush=True)
+    assert losses[-1] < 0.3 * losses[0], losses
+    if not charts:
+        # the rebuilt chains are the block means of the fitted level 0
+        T, n = ds.tex_res, ds.n
+        a = ds.atlas.detach().view(n, (4 * T * T - 1) // 3, 8).double().cpu().numpy()
+        l0 = a[:, :T * T].reshape(n, T // 2, 2, T // 2, 2, 8).mean(axis=(2, 4))
+        l1 = a[:, T * T:T * T + (T // 2) ** 2].reshape(n, T // 2, T // 2, 8)
+        np.testing.assert_allclose(l1, l0, rtol=1e-5, atol=1e-6)
