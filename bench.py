@@ -160,10 +160,12 @@ FWD_BWD_WORKLOADS = {
 }
 
 
-def bench_fwd_bwd(cfg, steps, warmup, sh_degree=None):
+def bench_fwd_bwd(cfg, steps, warmup, sh_degree=None, mips=False):
     """One training step: forward of the config's batch of views, L1 loss to a seeded target,
     hand-written backward to all splat parameters. With sh_degree, the indirect term is on
-    (per-splat SH of that degree, mixed visibility) and the SH coefficients get gradients."""
+    (per-splat SH of that degree, mixed visibility) and the SH coefficients get gradients;
+    with mips, the atlas holds each chart's mip chain and sampling is trilinear (gradients to
+    the level-0 texels and, through the level, to the geometry)."""
     import numpy as np
     import torch
 
@@ -179,7 +181,7 @@ def bench_fwd_bwd(cfg, steps, warmup, sh_degree=None):
         sc["sh"] = synth.indirect_sh(np.random.default_rng(11), len(sc["opac"]), sh_degree)
         sc["sh_degree"] = sh_degree
         vis = torch.as_tensor(synth.visibility(np.random.default_rng(12), V, H, W)).cuda()
-    ds = DeviceScene.from_dict(sc, device="cuda")
+    ds = DeviceScene.from_dict(sc, device="cuda", mips=mips)
     del sc
     target = torch.as_tensor(synth.target_image(W, H, seed=1, n_views=V)).cuda()
     plan = RenderPlan(ds, cams, W, H, gbuf=True, aux=True, vis=vis)
@@ -244,6 +246,13 @@ def bench_fwd_bwd(cfg, steps, warmup, sh_degree=None):
         e1.record()
         torch.cuda.synchronize()
         ind_ms = e0.elapsed_time(e1) / 3
+    # algorithmic HBM bytes of two backward kernels, for their rooflines (k_bwd_gather's
+    # duration comes from the kernel trace, ts_env_bwd's from the events above)
+    used = int(run.used.item())
+    gather_bytes = (used * 4 + plan.cap * 16 + V * ds.n * (16 + 8) + V * ds.n * 19 * 4
+                    + ds.atlas.numel() * 4)
+    env_bytes = V * W * H * (32 + 4 + 16) + (0 if vis is None else V * W * H * 4)
+    env_gbs = env_bytes / (env_ms * 1e-3) / 1e9
     out = {"value": round(V * W * H / dt / 1e6, 2), "unit": "Mpix/s",
            "ms_per_step": round(dt * 1e3, 3), "steps": steps, "views_per_step": V,
            "width": W, "height": H, "splats": ds.n,
@@ -251,9 +260,18 @@ def bench_fwd_bwd(cfg, steps, warmup, sh_degree=None):
            "workload": FWD_BWD_WORKLOADS[cfg] + (
                "" if sh_degree is None else
                f"; indirect term: degree-{sh_degree} SH per splat, mixed visibility, gradients "
-               "to the SH coefficients too"),
+               "to the SH coefficients too") + (
+               "; trilinear sampling over each chart's box-filtered mip chain" if mips else ""),
            "env_tables_bwd_ms": round(env_ms, 3),
-           "partial_buffer_floats_used": int(run.used.item())}
+           # G-buffers, transmittance, dL/dC (and visibility) read once per pixel; the tables'
+           # gradients are a few MB
+           "env_tables_bwd_hbm": {"algorithmic_bytes": env_bytes, "achieved": round(env_gbs, 1),
+                                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": round(env_gbs / HBM_PEAK_GBS, 4)},
+           # partials and slot table read once, rectangles and offsets, record and texel
+           # gradients written once
+           "bwd_gather_algorithmic_bytes": gather_bytes,
+           "partial_buffer_floats_used": used}
     if ind_ms is not None:
         out["indirect_bwd_ms"] = round(ind_ms, 4)
     del plan, run, grads, d_rgba, target, ds
@@ -818,6 +836,9 @@ def main():
         result["fwd_bwd_indirect"] = bench_fwd_bwd("sq300k_train", max(3, K // 2), 1,
                                                    sh_degree=3)
         log(f"fwd+bwd indirect: {result['fwd_bwd_indirect']}")
+        result["fwd_bwd_trilinear"] = bench_fwd_bwd("sq300k_train", max(3, K // 2), 1,
+                                                    mips=True)
+        log(f"fwd+bwd trilinear: {result['fwd_bwd_trilinear']}")
     result["small_frame"] = bench_small_frame()
     log(f"small frame: {result['small_frame']}")
     if not args.no_tab3:
