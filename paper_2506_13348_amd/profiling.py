@@ -31,6 +31,7 @@ KERNEL_SOURCES = {
     "k_bin_fill": ["csrc/binsort.hip", "csrc/binsort_layout.h", "csrc/ts_internal.h"],
     "k_raster_bwd": ["csrc/raster_bwd.hip", "csrc/eval.h", "csrc/shade.h", "csrc/shade_bwd.h",
                      "csrc/texture.h", "csrc/ts_internal.h"],
+    "k_bwd_gather": ["csrc/raster_bwd.hip", "csrc/texture.h", "csrc/ts_internal.h"],
 }
 
 
