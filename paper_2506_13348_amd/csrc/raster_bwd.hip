@@ -75,24 +75,22 @@ __device__ inline void fetch_taps(__amdgpu_buffer_rsrc_t r, unsigned lo, int Tl,
     }
 }
 
-__device__ inline void bilerp_taps(const Taps& k, const float (&v)[4][8], float (&o)[8]) {
+// One level's bilinear sample s and its derivatives along the texel coordinates,
+// ds/dfx = (1-fy)(v10 - v00) + fy (v11 - v01) and ds/dfy likewise: all that the gradient needs
+// of the four texels once the sample's gradient q is known (dL/dfx = q . ds/dfx).
+template <int kFmt>
+__device__ inline void level_sample(__amdgpu_buffer_rsrc_t r, unsigned lo, int Tl, const Taps& k,
+                                    float (&s)[8], float (&sx)[8], float (&sy)[8]) {
+    float v[4][8];
+    fetch_taps<kFmt>(r, lo, Tl, k, v);
     float w00 = (1.f - k.fx) * (1.f - k.fy), w10 = k.fx * (1.f - k.fy);
     float w01 = (1.f - k.fx) * k.fy, w11 = k.fx * k.fy;
 #pragma unroll
-    for (int c = 0; c < 8; c++) o[c] = w00 * v[0][c] + w10 * v[1][c] + w01 * v[2][c] + w11 * v[3][c];
-}
-
-// dL/d(texel coordinates) of one level's bilinear sample for the sample gradient q:
-// with D_t = q . v_t, d/dfx = (1-fy)(D10 - D00) + fy (D11 - D01), d/dfy likewise.
-__device__ inline void bilerp_coord_grad(const Taps& k, const float (&v)[4][8], const float (&q)[8],
-                                         float& gX, float& gY) {
-    float D[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int t = 0; t < 4; t++)
-#pragma unroll
-        for (int c = 0; c < 8; c++) D[t] = fmaf(q[c], v[t][c], D[t]);
-    gX = (1.f - k.fy) * (D[1] - D[0]) + k.fy * (D[3] - D[2]);
-    gY = (1.f - k.fx) * (D[2] - D[0]) + k.fx * (D[3] - D[1]);
+    for (int c = 0; c < 8; c++) {
+        s[c] = w00 * v[0][c] + w10 * v[1][c] + w01 * v[2][c] + w11 * v[3][c];
+        sx[c] = (1.f - k.fy) * (v[1][c] - v[0][c]) + k.fy * (v[3][c] - v[2][c]);
+        sy[c] = (1.f - k.fx) * (v[2][c] - v[0][c]) + k.fx * (v[3][c] - v[1][c]);
+    }
 }
 constexpr int kChunk = 2048;      // floats of the partial buffer a wave takes at a time
 
@@ -270,17 +268,15 @@ __global__ __launch_bounds__(256, (bwd_waves<kVar>())) void k_raster_bwd(BwdArgs
                     lv = mip_levels(Lc, fp.lr);
                 }
                 const Taps ka = bilinear_taps(Tc >> lv.la, u, vv, a.S);
-                float va[4][8], vb[4][8], sa[8], sb[8];
-                fetch_taps<kFmt>(tr, level_offset(Tc, lv.la), Tc >> lv.la, ka, va);
+                float sa[8], sax[8], say[8], sb[8], sbx[8], sby[8];
+                level_sample<kFmt>(tr, level_offset(Tc, lv.la), Tc >> lv.la, ka, sa, sax, say);
                 Taps kb = ka;
                 if (lv.blend) {
                     kb = bilinear_taps(Tc >> lv.lb, u, vv, a.S);
-                    fetch_taps<kFmt>(tr, level_offset(Tc, lv.lb), Tc >> lv.lb, kb, vb);
+                    level_sample<kFmt>(tr, level_offset(Tc, lv.lb), Tc >> lv.lb, kb, sb, sbx, sby);
                 }
-                bilerp_taps(ka, va, sa);
                 float tv[8];
                 if (lv.blend) {
-                    bilerp_taps(kb, vb, sb);
 #pragma unroll
                     for (int c = 0; c < 8; c++) tv[c] = fmaf(lv.f, sb[c] - sa[c], sa[c]);
                 } else {
@@ -346,8 +342,12 @@ __global__ __launch_bounds__(256, (bwd_waves<kVar>())) void k_raster_bwd(BwdArgs
                 // through each level's bilinear weights (texel coordinate = u T_l/(2S) + ...)
                 const float wa = lv.blend ? 1.f - lv.f : 1.f;
                 {
-                    float gX, gY;
-                    bilerp_coord_grad(ka, va, q, gX, gY);
+                    float gX = 0.f, gY = 0.f;
+#pragma unroll
+                    for (int c = 0; c < 8; c++) {
+                        gX = fmaf(q[c], sax[c], gX);
+                        gY = fmaf(q[c], say[c], gY);
+                    }
                     const float sca = (float)(Tc >> lv.la) / (2.0f * a.S);
                     gu = fmaf(wa * gX, sca, gu);
                     gv = fmaf(wa * gY, sca, gv);
@@ -355,8 +355,12 @@ __global__ __launch_bounds__(256, (bwd_waves<kVar>())) void k_raster_bwd(BwdArgs
                 float g_ux = 0.f, g_uy = 0.f, g_vx = 0.f, g_vy = 0.f, g_wx = 0.f, g_wy = 0.f;
                 float g_w0 = 0.f, g_px = 0.f, g_py = 0.f;
                 if (lv.blend) {
-                    float gX, gY;
-                    bilerp_coord_grad(kb, vb, q, gX, gY);
+                    float gX = 0.f, gY = 0.f;
+#pragma unroll
+                    for (int c = 0; c < 8; c++) {
+                        gX = fmaf(q[c], sbx[c], gX);
+                        gY = fmaf(q[c], sby[c], gY);
+                    }
                     const float scb = (float)(Tc >> lv.lb) / (2.0f * a.S);
                     gu = fmaf(lv.f * gX, scb, gu);
                     gv = fmaf(lv.f * gY, scb, gv);

@@ -150,11 +150,14 @@ def test_grads_multi_view_ragged():
     _compare(_np(g), ref, "3 views", spread)
 
 
-def _full_size_sampled(cfg, n_views, per_view, seed):
+def _full_size_sampled(cfg, n_views, per_view, seed, variant=None):
     """Full-size frame(s) of a config with dL/dC nonzero only at sampled pixels: the GPU runs the
-    whole backward over every tile and view; the float64 reference needs only those pixels."""
+    whole backward over every tile and view; the float64 reference needs only those pixels.
+    variant: DeviceScene keyword arguments of an atlas variant (mips=True: trilinear)."""
     from parity import sample_pixels
     sc = synth.make_scene(cfg)
+    if variant and variant.get("mips"):
+        sc["trilinear"] = True
     cams = synth.config_cameras(cfg)
     W, H = cams[0]["width"], cams[0]["height"]
     tabs = oracle.tables(sc["env"], sc["env_levels"])
@@ -187,6 +190,11 @@ def _full_size_sampled(cfg, n_views, per_view, seed):
         alt = total(_perturbed(sc, sign, 11))
         for k in NAMES:
             spread[k] = np.maximum(spread[k], np.abs(alt[k] - ref[k]))
+    if variant:
+        flat = lambda r: dict(r, textures=r["textures"].reshape(-1, 8))
+        g = _gpu_grads_variant(sc, variant, cams, W, H, d_all)
+        _compare(g, flat(ref), f"{cfg} {variant}", flat(spread))
+        return
     g, run = _gpu_grads(sc, cams, W, H, d_all)
     _compare(_np(g), ref, cfg, spread)
 
@@ -194,6 +202,12 @@ def _full_size_sampled(cfg, n_views, per_view, seed):
 def test_grads_sq300k_training_batch_sampled():
     """The 300k-splat, 8-view 800x800 training batch through the whole backward."""
     _full_size_sampled("sq300k_train", 8, 10, 5)
+
+
+def test_grads_sq300k_training_batch_trilinear_sampled():
+    """The 300k-splat, 8-view training batch with trilinear sampling (the bench's trilinear
+    training leg) through the whole backward, checked at sampled pixels."""
+    _full_size_sampled("sq300k_train", 8, 10, 15, variant=dict(mips=True))
 
 
 def test_grads_field1m_sampled():
