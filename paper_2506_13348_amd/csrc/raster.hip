@@ -21,7 +21,10 @@
 // with bilinear sampling (two-component normals, per-chart resolutions through a chart
 // table); 3 the same with trilinear sampling over each chart's mip chain, the level taken from
 // the pixel's footprint on the splat (derivatives of the closed-form (u,v) along the image
-// axes: du/dX = (u_x - u w_x) / den, and likewise for v and Y).
+// axes: du/dX = (u_x - u w_x) / den, and likewise for v and Y); 4 and 5 are 2 and 3 on the
+// 7-float texels of two-component normals. The texel layout is a template argument because a
+// run-time choice between the two loads around every texel fetch cost up to 43% of the step
+// (per-chart sides: 32.4 against 22.6 ms).
 #include <string.h>
 
 #include <mutex>
@@ -63,8 +66,12 @@ static_assert(kBatch % kWave == 0, "the batch is walked in rows of 64");
 // workgroups per CU (measured faster than 5 waves with 256-record batches). The indirect
 // variant carries three more accumulators and needs more than 80 VGPRs: 5 waves per SIMD, no
 // spills; trilinear sampling (two texel levels in flight) 4.
+constexpr bool samp_variant(int kSamp) { return kSamp >= 2; }
+constexpr bool samp_tri(int kSamp) { return kSamp == 3 || kSamp == 5; }
+constexpr int samp_fmt(int kSamp) { return kSamp >= 4 ? 1 : 0; }
+
 template <int kSamp, bool kInd>
-constexpr int raster_waves() { return kSamp == 3 ? 4 : (kInd ? 5 : 6); }
+constexpr int raster_waves() { return samp_tri(kSamp) ? 4 : (kInd ? 5 : 6); }
 
 // A pixel's outputs: G-buffer channels, transmittance, counters and the fused shading.
 template <bool kInd>
@@ -125,7 +132,7 @@ __device__ __forceinline__ void raster_tile(const RasterArgs& a, int v, int t) {
     __shared__ float4 srec[kBatch * kRec4];
     __shared__ uint32_t smask[kBatch];
     __shared__ float4 slind[kInd ? kBatch : 1];
-    __shared__ int2 schart[kSamp >= 2 ? kBatch : 1];   // chart entries of the variant paths
+    __shared__ int2 schart[samp_variant(kSamp) ? kBatch : 1];   // chart entries (variants)
     const int tx = t % a.ntx, ty = t / a.ntx;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int bx = tx * kTile + (w & 1) * 8, by = ty * kTile + (w >> 1) * 8;
@@ -164,8 +171,9 @@ __device__ __forceinline__ void raster_tile(const RasterArgs& a, int v, int t) {
 #pragma unroll
             for (int q = 4; q < kRec4; q++) srec[tid * kRec4 + q] = src[q];
             if (kInd) slind[tid] = a.lind[(int64_t)v * a.n + id];
-            if (kSamp >= 2)
-                schart[tid] = chart_entry<kSamp == 3>(a.tex, __float_as_int(srec[tid * kRec4 + 6].y));
+            if (samp_variant(kSamp))
+                schart[tid] = chart_entry<samp_tri(kSamp)>(a.tex,
+                                                           __float_as_int(srec[tid * kRec4 + 6].y));
             qm = quad_mask_uv(r0, r1, r2, r3, tx * kTile, ty * kTile, a.S, a.amin);
         }
         if (tid < kBatch) smask[tid] = qm;
@@ -192,16 +200,17 @@ __device__ __forceinline__ void raster_tile(const RasterArgs& a, int v, int t) {
                         // the chart is the same for the whole wave: scalar base address
                         int chart = __builtin_amdgcn_readfirstlane(__float_as_int(c6.y));
                         float t0, t1, t2, t3, t4, t5, t6, t7;
-                        if (kSamp >= 2) {
+                        if (samp_variant(kSamp)) {
                             float lr = 0.f;
-                            if (kSamp == 3) {
+                            if (samp_tri(kSamp)) {
                                 lr = footprint(rp[1], rp[2], rp[3], u, vv, e.inv, a.S).lr;
                             }
                             float tt[8];
                             int2 ce = schart[j];
                             ce.x = __builtin_amdgcn_readfirstlane(ce.x);
                             ce.y = __builtin_amdgcn_readfirstlane(ce.y);
-                            sample_chart<kSamp == 3>(a.tex, ce, u, vv, a.S, lr, tt);
+                            sample_chart<samp_tri(kSamp), samp_fmt(kSamp)>(a.tex, ce, u, vv, a.S,
+                                                                           lr, tt);
                             t0 = tt[0]; t1 = tt[1]; t2 = tt[2]; t3 = tt[3];
                             t4 = tt[4]; t5 = tt[5]; t6 = tt[6]; t7 = tt[7];
                         } else if (kTextured) {
@@ -435,6 +444,7 @@ static int make_raster_args(const char* who, int32_t n_views, int32_t width, int
         return TS_E_ARG;
     }
     samp = tri ? 3 : variant ? 2 : params->sampler == TS_SAMPLER_CONSTANT ? 1 : 0;
+    if (samp >= 2 && params->tex_format == TS_TEX_RGBN2) samp += 2;
     return TS_OK;
 }
 
@@ -540,14 +550,18 @@ extern "C" int ts_raster_fwd(int32_t n_views, int32_t width, int32_t height, con
             case 0: hipLaunchKernelGGL((k_raster_fwd<0, true>), grid, block, 0, stream, a); break;
             case 1: hipLaunchKernelGGL((k_raster_fwd<1, true>), grid, block, 0, stream, a); break;
             case 2: hipLaunchKernelGGL((k_raster_fwd<2, true>), grid, block, 0, stream, a); break;
-            default: hipLaunchKernelGGL((k_raster_fwd<3, true>), grid, block, 0, stream, a); break;
+            case 3: hipLaunchKernelGGL((k_raster_fwd<3, true>), grid, block, 0, stream, a); break;
+            case 4: hipLaunchKernelGGL((k_raster_fwd<4, true>), grid, block, 0, stream, a); break;
+            default: hipLaunchKernelGGL((k_raster_fwd<5, true>), grid, block, 0, stream, a); break;
         }
     } else {
         switch (samp) {
             case 0: hipLaunchKernelGGL((k_raster_fwd<0, false>), grid, block, 0, stream, a); break;
             case 1: hipLaunchKernelGGL((k_raster_fwd<1, false>), grid, block, 0, stream, a); break;
             case 2: hipLaunchKernelGGL((k_raster_fwd<2, false>), grid, block, 0, stream, a); break;
-            default: hipLaunchKernelGGL((k_raster_fwd<3, false>), grid, block, 0, stream, a); break;
+            case 3: hipLaunchKernelGGL((k_raster_fwd<3, false>), grid, block, 0, stream, a); break;
+            case 4: hipLaunchKernelGGL((k_raster_fwd<4, false>), grid, block, 0, stream, a); break;
+            default: hipLaunchKernelGGL((k_raster_fwd<5, false>), grid, block, 0, stream, a); break;
         }
     }
     return launch_check("ts_raster_fwd");
