@@ -62,16 +62,20 @@ struct RasterArgs {
 constexpr int kBatch = 192;   // records staged per batch (a multiple of 64)
 static_assert(kBatch % kWave == 0, "the batch is walked in rows of 64");
 
-// Waves per SIMD of the raster kernels: at most 80 VGPRs and a 22.5 KB record batch give six
-// workgroups per CU (measured faster than 5 waves with 256-record batches). The indirect
-// variant carries three more accumulators and needs more than 80 VGPRs: 5 waves per SIMD, no
-// spills; trilinear sampling (two texel levels in flight) 4.
+// Waves per SIMD of the raster kernels, as measured on the 64-view headline step: the default
+// path at 7 (72 VGPRs, 32 bytes of spills, a 22.5 KB record batch: seven workgroups per CU;
+// 18.30 ms against 18.63 at 6); the indirect term and the atlas variants stage more per record
+// (26 and 24 KB), which leaves room for six workgroups: 6 waves (the indirect term at 80 VGPRs,
+// 19.33 ms against 19.40 at 5); trilinear sampling (two texel levels in flight) 4 (5 was
+// slower). The batched launch keeps 6 (its own state beside the tile's).
 constexpr bool samp_variant(int kSamp) { return kSamp >= 2; }
 constexpr bool samp_tri(int kSamp) { return kSamp == 3 || kSamp == 5; }
 constexpr int samp_fmt(int kSamp) { return kSamp >= 4 ? 1 : 0; }
 
 template <int kSamp, bool kInd>
-constexpr int raster_waves() { return samp_tri(kSamp) ? 4 : (kInd ? 5 : 6); }
+constexpr int raster_waves() {
+    return samp_tri(kSamp) ? 4 : (samp_variant(kSamp) || kInd) ? 6 : 7;
+}
 
 // A pixel's outputs: G-buffer channels, transmittance, counters and the fused shading.
 template <bool kInd>
@@ -481,7 +485,7 @@ __device__ inline int batch_pop(uint32_t* queue, int total, int xcd, int& k) {
 }
 
 template <int kSamp, bool kInd>
-__global__ __launch_bounds__(256, (raster_waves<kSamp, kInd>())) void k_raster_batch(
+__global__ __launch_bounds__(256, 6) void k_raster_batch(
     const BatchTable* __restrict__ tab, uint32_t* __restrict__ queue) {
     __shared__ int s_item[2];
     const int n_jobs = tab->n_jobs;
