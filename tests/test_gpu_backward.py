@@ -933,3 +933,34 @@ def test_variant_autograd_matches_runner_and_trains(charts):
         l0 = a[:, :T * T].reshape(n, T // 2, 2, T // 2, 2, 8).mean(axis=(2, 4))
         l1 = a[:, T * T:T * T + (T // 2) ** 2].reshape(n, T // 2, T // 2, 8)
         np.testing.assert_allclose(l1, l0, rtol=1e-5, atol=1e-6)
+
+
+def test_trilinear_with_indirect_term_grads_zoomed_crop():
+    """Trilinear sampling and degree-2 SH with mixed visibility at once on the zoomed crop (the
+    backward kernel's <indirect, 8-float texel, trilinear> variant); texel gradients taken out
+    of the chain layout at level 0."""
+    sub, crop = _zoomed_crop()
+    sc = dict(_with_sh(sub, 2, 131), trilinear=True)
+    tabs = oracle.tables(sc["env"], sc["env_levels"])
+    pix = oracle.all_pixels(64, 64)
+    vis = synth.visibility(np.random.default_rng(132), 1, 64, 64)
+    d_all, ds, vs = _ind_upstream(sc, [crop], pix, vis, tabs, np.random.default_rng(133), 64, 64)
+    ref, sp = _ind_reference(sc, [crop], pix, ds, vs, tabs)
+    P = _pkg()
+    from paper_2506_13348_amd.autograd import BackwardRunner
+    dsc = P.DeviceScene.from_dict(sc, device="cuda", mips=True)
+    plan = P.RenderPlan(dsc, [crop], 64, 64, gbuf=True, aux=True, vis=torch.as_tensor(vis).cuda())
+    plan.run()
+    plan.check()
+    grads = tuple(torch.zeros_like(t) for t in (dsc.means, dsc.quats, dsc.scales, dsc.opac,
+                                                dsc.atlas, dsc.sh))
+    BackwardRunner(plan).run(torch.as_tensor(d_all.astype(np.float32)).cuda().contiguous(), grads)
+    torch.cuda.synchronize()
+    T = dsc.tex_res
+    chain = (4 * T * T - 1) // 3
+    ga = grads[4].view(dsc.n, chain, 8)
+    assert float(ga[:, T * T:].abs().max()) == 0.0
+    order = dsc.chart_of.long()
+    g = list(grads)
+    g[4] = ga[order, :T * T].reshape(dsc.n, T, T, 8)
+    _compare_ind(g, ref, "trilinear + indirect zoomed crop", sp)
