@@ -396,10 +396,20 @@ __device__ inline void fill_st_batch(int head, int count, const int32_t* cid,
     const int e = (head + tid) & (kFillRing - 1);
     const uint64_t m = tid < count ? cmask[e] : 0ull;
     const int id = tid < count ? cid[e] : 0;
-    for (int b = 0; b < 64; b++) {
-        uint64_t bb = __ballot((m >> b) & 1ull);
-        if (lane == 0) wball[w][b] = bb;
+    // the wave's 64 per-tile ballots are the transpose of the 64 x 64 bit matrix whose row l is
+    // lane l's tile mask: six stages, stage j swapping bit j of the row and column indices
+    // between lanes l and l ^ j (lane b ends with the ballot of tile b; 64 ballots took about
+    // five times the instructions)
+    uint64_t t = m;
+#pragma unroll
+    for (int j = 32; j >= 1; j >>= 1) {
+        const uint64_t lo = j == 32 ? 0x00000000FFFFFFFFull : j == 16 ? 0x0000FFFF0000FFFFull
+                          : j == 8 ? 0x00FF00FF00FF00FFull : j == 4 ? 0x0F0F0F0F0F0F0F0Full
+                          : j == 2 ? 0x3333333333333333ull : 0x5555555555555555ull;
+        const uint64_t p = __shfl_xor(t, j);
+        t = (lane & j) ? ((t & ~lo) | ((p >> j) & lo)) : ((t & lo) | ((p & lo) << j));
     }
+    wball[w][lane] = t;
     __syncthreads();
     if (tid < 64) {
         uint32_t p = cursor[tid];
