@@ -801,6 +801,17 @@ def main():
                              "rate without packed-fp32 instructions, which the build disables"},
     }
     result["shade_unfused"] = shade_line
+    # the two phases before the raster against HBM, from the same events: k_preprocess reads
+    # 40 B of parameters per splat once and writes a 112 B record, 16 B rectangle and 4 B key
+    # per (view, splat); ts_bin_sort moves its keys 4 times (16 B each way per key and pass),
+    # reads rectangles and ids (2 x 20 B per (view, splat)) and writes 4 B per list entry
+    vn = V * ds.n
+    for name, nbytes, ms in (("preprocess", 40 * ds.n + 132 * vn, pre_ms),
+                             ("bin_sort", 4 * 16 * vn + 2 * 20 * vn + 4 * n_pairs, bin_ms)):
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        result[f"{name}_hbm"] = {"algorithmic_bytes": nbytes, "ms": round(ms, 4),
+                                 "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                                 "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
     # the same step with charts packed in Morton order of the centres (locality-aware atlas)
     ds_loc = DeviceScene.from_dict(sc, device=dev, locality=True)
     plan_loc = RenderPlan(ds_loc, cams, W, H, pair_capacity=plan.cap)
