@@ -964,3 +964,76 @@ def test_trilinear_with_indirect_term_grads_zoomed_crop():
     g = list(grads)
     g[4] = ga[order, :T * T].reshape(dsc.n, T, T, 8)
     _compare_ind(g, ref, "trilinear + indirect zoomed crop", sp)
+
+
+def _window_splats(sc, cam, x0, y0, w, h, S=3.0, margin=2.0):
+    """Indices (ascending) of the splats whose support square |u|,|v| <= S can reach a pixel
+    of the window [x0, x0+w) x [y0, y0+h) of the camera: the bounding box of the square's four
+    projected corners, widened by a margin; a square with a corner at or behind the near plane
+    is kept (conservative). The other splats cannot touch the window's pixels."""
+    q = np.asarray(sc["quats"], np.float64)
+    q = q / np.linalg.norm(q, axis=1, keepdims=True)
+    w_, x, y, z = q.T
+    tu = np.stack([1 - 2 * (y * y + z * z), 2 * (x * y + w_ * z), 2 * (x * z - w_ * y)], 1)
+    tv = np.stack([2 * (x * y - w_ * z), 1 - 2 * (x * x + z * z), 2 * (y * z + w_ * x)], 1)
+    mu = np.asarray(sc["means"], np.float64)
+    s = np.asarray(sc["scales"], np.float64)
+    w2c = np.asarray(cam["w2c"], np.float64)
+    xs, ys, bad = [], [], np.zeros(len(mu), bool)
+    for a in (-S, S):
+        for b in (-S, S):
+            p = mu + a * s[:, :1] * tu + b * s[:, 1:2] * tv
+            pc = p @ w2c[:, :3].T + w2c[:, 3]
+            bad |= pc[:, 2] <= 0.2
+            zc = np.where(pc[:, 2] > 0.2, pc[:, 2], 1.0)
+            xs.append(cam["fx"] * pc[:, 0] / zc + cam["cx"])
+            ys.append(cam["fy"] * pc[:, 1] / zc + cam["cy"])
+    xs, ys = np.stack(xs), np.stack(ys)
+    hit = ((xs.max(0) >= x0 - margin) & (xs.min(0) <= x0 + w + margin) &
+           (ys.max(0) >= y0 - margin) & (ys.min(0) <= y0 + h + margin))
+    return np.nonzero(hit | bad)[0]
+
+
+def test_grads_sq300k_dense_window():
+    """The full-size 8-view sq300k training launch with dL/dC dense (every pixel) over a 64x64
+    window of two views, zero elsewhere: the partials of every splat touching the windows are
+    gathered at full size. Gradients of those splats match the float64 reference (rendered
+    from the splats that can reach the window, in their original order; with its spread under
+    +-2^-23 moves, as the other full-size tests); every other splat's gradient is exactly
+    zero."""
+    sc = synth.make_scene("sq300k_train")
+    cams = synth.config_cameras("sq300k_train")
+    W, H = cams[0]["width"], cams[0]["height"]
+    tabs = oracle.tables(sc["env"], sc["env_levels"])
+    rng = np.random.default_rng(141)
+    d_all = np.zeros((len(cams), H, W, 4))
+    pix = oracle.all_pixels(64, 64)
+    ref = {k: 0.0 for k in NAMES}
+    spread = {k: 0.0 for k in NAMES}
+    touched = np.zeros(len(sc["opac"]), bool)
+    for v, (x0, y0) in ((0, (368, 368)), (5, (300, 420))):
+        crop = synth.crop_camera(cams[v], x0, y0, 64, 64)
+        idx = _window_splats(sc, cams[v], x0, y0, 64, 64)
+        sub = {k: (val[idx] if isinstance(val, np.ndarray) and val.shape[:1] == (len(sc["opac"]),)
+                   else val) for k, val in sc.items()}
+        sub["chart_of"] = np.arange(len(idx), dtype=np.int32)
+        ref_f = oracle.render(sub, crop, pixels=pix, tabs=tabs)
+        assert (ref_f["rgba"][:, 3] > 0).mean() > 0.5
+        d, d4 = _upstream(rng, ref_f, (64, 64, 4))
+        d_all[v, y0:y0 + 64, x0:x0 + 64] = d4
+        r, sp = _reference(sub, [crop], pix, [d], tabs)
+        print(f"[dense window] view {v}: {len(idx)} splats can reach it", flush=True)
+        for k in NAMES:
+            full = np.zeros((len(sc["opac"]),) + r[k].shape[1:])
+            full[idx] = r[k]
+            ref[k] = ref[k] + full
+            full = np.zeros((len(sc["opac"]),) + r[k].shape[1:])
+            full[idx] = sp[k]
+            spread[k] = spread[k] + full
+        touched[idx] = True
+    g, run = _gpu_grads(sc, cams, W, H, d_all)
+    g = _np(g)
+    for k in NAMES:
+        assert np.all(g[k][~touched] == 0.0), k
+    _compare({k: g[k][touched] for k in NAMES}, {k: ref[k][touched] for k in NAMES},
+             "sq300k dense windows", {k: spread[k][touched] for k in NAMES})
