@@ -67,10 +67,14 @@ static_assert(kBatch % kWave == 0, "the batch is walked in rows of 64");
 // 18.30 ms against 18.63 at 6); the indirect term and the atlas variants stage more per record
 // (26 and 24 KB), which leaves room for six workgroups: 6 waves (the indirect term at 80 VGPRs,
 // 19.33 ms against 19.40 at 5); trilinear sampling (two texel levels in flight) 4 (5 was
-// slower). The batched launch keeps 6 (its own state beside the tile's).
+// slower).
 constexpr bool samp_variant(int kSamp) { return kSamp >= 2; }
 constexpr bool samp_tri(int kSamp) { return kSamp == 3 || kSamp == 5; }
 constexpr int samp_fmt(int kSamp) { return kSamp >= 4 ? 1 : 0; }
+
+// the batched launch: 6 waves per SIMD (7 measured slower there: 10.76 against 10.53 ms for
+// the raster of 16 serving requests), so a grid of 6 workgroups per CU is every resident one
+constexpr int kBatchWaves = 6;
 
 template <int kSamp, bool kInd>
 constexpr int raster_waves() {
@@ -485,7 +489,7 @@ __device__ inline int batch_pop(uint32_t* queue, int total, int xcd, int& k) {
 }
 
 template <int kSamp, bool kInd>
-__global__ __launch_bounds__(256, 6) void k_raster_batch(
+__global__ __launch_bounds__(256, kBatchWaves) void k_raster_batch(
     const BatchTable* __restrict__ tab, uint32_t* __restrict__ queue) {
     __shared__ int s_item[2];
     const int n_jobs = tab->n_jobs;
@@ -526,7 +530,7 @@ static int batch_grid(int dev) {
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             cus < 1)
             return 0;
-        grid[dev] = cus * raster_waves<0, false>();
+        grid[dev] = cus * kBatchWaves;
     }
     return grid[dev];
 }
