@@ -812,25 +812,39 @@ def main():
         result[f"{name}_hbm"] = {"algorithmic_bytes": nbytes, "ms": round(ms, 4),
                                  "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                                  "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
-    # the same step with charts packed in Morton order of the centres (locality-aware atlas)
-    ds_loc = DeviceScene.from_dict(sc, device=dev, locality=True)
-    plan_loc = RenderPlan(ds_loc, cams, W, H, pair_capacity=plan.cap)
-    for _ in range(2):
-        plan_loc.run()
-    plan_loc.check()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(K):
-        plan_loc.run()
-    e1.record()
-    torch.cuda.synchronize()
-    plan_loc.check()
-    loc_ms = e0.elapsed_time(e1) / K
+    # the same step with charts packed in Morton order of the centres (locality-aware atlas),
+    # and both packings again with the splats first shuffled into a random order (the order a
+    # scene has after densification), where chart order and space are unrelated
+    def step_ms(scene, locality):
+        ds_l = DeviceScene.from_dict(scene, device=dev, locality=locality)
+        plan_l = RenderPlan(ds_l, cams, W, H, pair_capacity=plan.cap)
+        for _ in range(2):
+            plan_l.run()
+        plan_l.check()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(K):
+            plan_l.run()
+        e1.record()
+        torch.cuda.synchronize()
+        plan_l.check()
+        del plan_l, ds_l
+        return e0.elapsed_time(e1) / K
+
+    loc_ms = step_ms(sc, True)
+    n_s = len(sc["opac"])
+    shuf = np.random.default_rng(5).permutation(n_s)
+    sc_shuf = {k: (val[shuf] if isinstance(val, np.ndarray) and val.shape[:1] == (n_s,)
+                   and k != "chart_of" else val) for k, val in sc.items()}
+    shuf_id_ms, shuf_loc_ms = step_ms(sc_shuf, False), step_ms(sc_shuf, True)
+    del sc_shuf
     result["locality_packing"] = {"ms_per_step": round(loc_ms, 3),
                                   "mpix_per_s": round(V * W * H / (loc_ms / 1e3) / 1e6, 2),
-                                  "speedup_vs_identity_packing": round(ms_step / loc_ms, 3)}
+                                  "speedup_vs_identity_packing": round(ms_step / loc_ms, 3),
+                                  "shuffled_order_identity_ms": round(shuf_id_ms, 3),
+                                  "shuffled_order_morton_ms": round(shuf_loc_ms, 3),
+                                  "shuffled_speedup": round(shuf_id_ms / shuf_loc_ms, 3)}
     log(f"locality packing: {result['locality_packing']}")
-    del plan_loc, ds_loc
     result["indirect"] = bench_indirect(sc, cams, W, H, plan.cap, K, args.warmup)
     log(f"indirect: {result['indirect']}")
     result["atlas_variants"] = bench_atlas_variants(sc, cams, W, H, plan.cap, max(3, K // 2),
