@@ -1054,3 +1054,69 @@ def test_grads_sq300k_dense_window():
         assert np.all(g[k][~touched] == 0.0), k
     _compare({k: g[k][touched] for k in NAMES}, {k: ref[k][touched] for k in NAMES},
              "sq300k dense windows", {k: spread[k][touched] for k in NAMES})
+
+
+@pytest.mark.parametrize("tri", [False, True])
+def test_chart_outside_the_atlas_backward(fd_case, tri):
+    """A chart-table entry reaching past the atlas samples as zero texels in the forward; its
+    backward gives the other parameters the gradients of that zero-texture render (the float64
+    reference with the chart's texels zeroed) and leaves the chart's texel gradients unwritten
+    (the caller's buffer keeps its contents). Trilinear on the zoomed-out crop, where the
+    moved chart's samples blend levels."""
+    sub, crop = _zoomed_crop() if tri else fd_case
+    flat, table, log2 = _charted(sub)
+    sc = dict(sub, textures=flat, chart_table=table, trilinear=tri)
+    tabs = oracle.tables(sub["env"], sub["env_levels"])
+    pix = oracle.all_pixels(64, 64)
+    # the splat whose texels matter most on the crop goes out of the atlas
+    d0 = np.random.default_rng(150).normal(size=(len(pix), 4))
+    g0 = og.grads(sc, crop, pix, d0, tabs)
+    per_chart = np.array([np.abs(g0["textures"][o:o + (1 << (2 * l))]).sum() for o, l in table])
+    k = int(np.argmax(per_chart))
+    o, l = int(table[k, 0]), int(table[k, 1])
+    ref_sc = dict(sc, textures=flat.copy())
+    ref_sc["textures"][o:o + (1 << (2 * l))] = 0.0
+    ref_f = oracle.render(ref_sc, crop, pixels=pix, tabs=tabs)
+    d, d4 = _upstream(np.random.default_rng(151), ref_f, (1, 64, 64, 4))
+    ref, spread = _reference(ref_sc, [crop], pix, [d], tabs)
+    P = _pkg()
+    from paper_2506_13348_amd.autograd import BackwardRunner
+    ds = P.DeviceScene.from_dict(dict(sub, textures=flat), device="cuda", chart_log2=log2,
+                                 mips=tri)
+    o_dev = int(ds.chart_table[k, 0])
+    ds.chart_table[k, 0] = int(ds.atlas_texels)          # past the end of the atlas
+    plan = P.RenderPlan(ds, [crop], 64, 64, gbuf=True, aux=True)
+    plan.run()
+    plan.check()
+    from parity import gather, pixel_match
+    rgba, gb = gather(plan.outputs(), 0, pix)
+    ok, info = pixel_match(rgba, gb, ref_f, crop, pix, tabs)
+    print(f"[chart outside the atlas tri={tri}] forward " + " ".join(f"{a}={b}" for a, b in
+                                                                  info.items()), flush=True)
+    assert info["fail"] == 0, info
+    grads = tuple(torch.zeros_like(t) for t in (ds.means, ds.quats, ds.scales, ds.opac))
+    grads = grads + (torch.full_like(ds.atlas, 5.0),)
+    BackwardRunner(plan).run(torch.as_tensor(d4.astype(np.float32)).cuda().contiguous(), grads)
+    torch.cuda.synchronize()
+    g = {n: t.double().cpu().numpy() for n, t in zip(NAMES[:4], grads[:4])}
+    # the chart moved out takes no texel gradient: its old place (level 0 and, with mip
+    # chains, the coarser levels) keeps the caller's contents
+    tab = ds.chart_table.cpu().numpy()
+    ga = grads[4].view(-1, 8).double().cpu().numpy()
+    C = (4 * (1 << (2 * l)) - 1) // 3 if tri else (1 << (2 * l))
+    assert np.all(ga[o_dev:o_dev + C] == 5.0), "the moved chart's texels were written"
+    lv0 = []
+    for c in range(ds.n):
+        if c == k:
+            lv0.append(np.zeros((1 << (2 * l), 8)))
+            continue
+        side = 1 << int(tab[c, 1])
+        lv0.append(ga[int(tab[c, 0]):int(tab[c, 0]) + side * side])
+        if tri:
+            coarse = ga[int(tab[c, 0]) + side * side:int(tab[c, 0]) + (4 * side * side - 1) // 3]
+            assert np.all(coarse == 0.0), "coarser chain levels got a gradient"
+    g["textures"] = np.concatenate(lv0)
+    ref = dict(ref, textures=ref["textures"].reshape(-1, 8))
+    ref["textures"][o:o + (1 << (2 * l))] = 0.0           # not a parameter the GPU writes
+    spread = dict(spread, textures=spread["textures"].reshape(-1, 8))
+    _compare(g, ref, f"chart outside the atlas tri={tri}", spread)
