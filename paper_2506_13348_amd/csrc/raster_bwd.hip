@@ -49,8 +49,11 @@ constexpr int kEntVar = 24;
 // texture paths of the backward: 0 the default atlas (uniform charts, level-0 bilinear), 1 a
 // chart table with level-0 bilinear, 2 trilinear over each chart's chain (table or uniform)
 template <int kVar> constexpr int ent_n() { return kVar ? kEntVar : kEnt; }
-// resident waves per SIMD: the variants hold a second level's texels and a larger LDS entry
-template <int kVar> constexpr int bwd_waves() { return kVar ? 3 : 4; }
+// resident waves per SIMD: 4 on every texture path, as measured on the 8-view sq300k training
+// batch (the chart table: 26.8 ms against 32.3 at 3; trilinear, whose taps are read a row at a
+// time and again after the shading adjoint so that it fits 128 registers but for a few spills:
+// 32.3 ms against 37.9 at 3; with the indirect term the compiler keeps 3)
+template <int kVar> constexpr int bwd_waves() { return 4; }
 
 // bits lo..hi of a 32-bit mask (0 <= lo <= hi <= 31)
 __device__ inline unsigned bit_range(int lo, int hi) {
@@ -91,6 +94,67 @@ __device__ inline void level_sample(__amdgpu_buffer_rsrc_t r, unsigned lo, int T
         sx[c] = (1.f - k.fy) * (v[1][c] - v[0][c]) + k.fy * (v[3][c] - v[2][c]);
         sy[c] = (1.f - k.fx) * (v[2][c] - v[0][c]) + k.fx * (v[3][c] - v[1][c]);
     }
+}
+
+// Two of a level's four taps (0-1: row j0, 2-3: row j1) as 8-channel values.
+template <int kFmt>
+__device__ __forceinline__ void fetch_row(__amdgpu_buffer_rsrc_t r, unsigned lo, int Tl,
+                                          const Taps& k, int row, float (&v)[2][8]) {
+    const int j = row ? k.j1 : k.j0;
+    float4 p[2], q[2];
+    fetch_texel(r, kFmt, lo + (unsigned)(j * Tl + k.i0), p[0], q[0]);
+    fetch_texel(r, kFmt, lo + (unsigned)(j * Tl + k.i1), p[1], q[1]);
+#pragma unroll
+    for (int t = 0; t < 2; t++) {
+        v[t][0] = p[t].x; v[t][1] = p[t].y; v[t][2] = p[t].z; v[t][3] = p[t].w;
+        v[t][4] = q[t].x; v[t][5] = q[t].y; v[t][6] = q[t].z; v[t][7] = q[t].w;
+    }
+}
+
+// One level's bilinear sample only (trilinear backward: the taps are read again once q is
+// known, so that no level's texels or derivatives stay in registers across the shading
+// adjoint; a row of two taps at a time keeps 16 of them in flight, not 32).
+template <int kFmt>
+__device__ inline void level_value(__amdgpu_buffer_rsrc_t r, unsigned lo, int Tl, const Taps& k,
+                                   float (&s)[8]) {
+    const float wx0 = 1.f - k.fx, wx1 = k.fx;
+#pragma unroll
+    for (int row = 0; row < 2; row++) {
+        float v[2][8];
+        fetch_row<kFmt>(r, lo, Tl, k, row, v);
+        const float wy = row ? k.fy : 1.f - k.fy;
+#pragma unroll
+        for (int c = 0; c < 8; c++) {
+            const float h = wx0 * v[0][c] + wx1 * v[1][c];
+            s[c] = row ? fmaf(wy, h, s[c]) : wy * h;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// With the sample's gradient q: the tap dot products D_t = q . v_t of one level, and from them
+// q . ds/dfx, q . ds/dfy and q . s (the same sums as from level_sample's outputs, reordered).
+template <int kFmt>
+__device__ inline void level_dots(__amdgpu_buffer_rsrc_t r, unsigned lo, int Tl, const Taps& k,
+                                  const float (&q)[8], float& gX, float& gY, float& qs) {
+    float D[4];
+#pragma unroll
+    for (int row = 0; row < 2; row++) {
+        float v[2][8];
+        fetch_row<kFmt>(r, lo, Tl, k, row, v);
+#pragma unroll
+        for (int t = 0; t < 2; t++) {
+            float d = 0.f;
+#pragma unroll
+            for (int c = 0; c < 8; c++) d = fmaf(q[c], v[t][c], d);
+            D[2 * row + t] = d;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    gX = (1.f - k.fy) * (D[1] - D[0]) + k.fy * (D[3] - D[2]);
+    gY = (1.f - k.fx) * (D[2] - D[0]) + k.fx * (D[3] - D[1]);
+    qs = (1.f - k.fx) * (1.f - k.fy) * D[0] + k.fx * (1.f - k.fy) * D[1] +
+         (1.f - k.fx) * k.fy * D[2] + k.fx * k.fy * D[3];
 }
 constexpr int kChunk = 2048;      // floats of the partial buffer a wave takes at a time
 
@@ -243,6 +307,7 @@ __global__ __launch_bounds__(256, (bwd_waves<kVar>())) void k_raster_bwd(BwdArgs
             float geo[kGeoN];
             int i0 = 0x7fffffff, i1 = -1, j0 = 0x7fffffff, j1 = -1;   // texel taps (blended)
             unsigned wmx = 0u, wmy = 0u;   // variants: level-0 columns and rows touched
+            bool lblend = false;           // trilinear: this lane blends two levels
 #pragma unroll
             for (int k = 0; k < kGeoN; k++) geo[k] = 0.f;
             if (bl && kVar != 0) {
@@ -266,14 +331,19 @@ __global__ __launch_bounds__(256, (bwd_waves<kVar>())) void k_raster_bwd(BwdArgs
                 if (kVar == 2) {
                     fp = footprint(c1, c2, c3, u, vv, inv, a.S);
                     lv = mip_levels(Lc, fp.lr);
+                    lblend = lv.blend;
                 }
                 const Taps ka = bilinear_taps(Tc >> lv.la, u, vv, a.S);
-                float sa[8], sax[8], say[8], sb[8], sbx[8], sby[8];
-                level_sample<kFmt>(tr, level_offset(Tc, lv.la), Tc >> lv.la, ka, sa, sax, say);
+                float sa[8], sax[8], say[8], sb[8];
+                if (kVar == 2) {
+                    level_value<kFmt>(tr, level_offset(Tc, lv.la), Tc >> lv.la, ka, sa);
+                } else {
+                    level_sample<kFmt>(tr, 0u, Tc, ka, sa, sax, say);
+                }
                 Taps kb = ka;
                 if (lv.blend) {
                     kb = bilinear_taps(Tc >> lv.lb, u, vv, a.S);
-                    level_sample<kFmt>(tr, level_offset(Tc, lv.lb), Tc >> lv.lb, kb, sb, sbx, sby);
+                    level_value<kFmt>(tr, level_offset(Tc, lv.lb), Tc >> lv.lb, kb, sb);
                 }
                 float tv[8];
                 if (lv.blend) {
@@ -341,12 +411,18 @@ __global__ __launch_bounds__(256, (bwd_waves<kVar>())) void k_raster_bwd(BwdArgs
                 }
                 // through each level's bilinear weights (texel coordinate = u T_l/(2S) + ...)
                 const float wa = lv.blend ? 1.f - lv.f : 1.f;
+                float qsa = 0.f;   // q . s_a (trilinear)
                 {
                     float gX = 0.f, gY = 0.f;
+                    if (kVar == 2) {
+                        level_dots<kFmt>(tr, level_offset(Tc, lv.la), Tc >> lv.la, ka, q, gX, gY,
+                                         qsa);
+                    } else {
 #pragma unroll
-                    for (int c = 0; c < 8; c++) {
-                        gX = fmaf(q[c], sax[c], gX);
-                        gY = fmaf(q[c], say[c], gY);
+                        for (int c = 0; c < 8; c++) {
+                            gX = fmaf(q[c], sax[c], gX);
+                            gY = fmaf(q[c], say[c], gY);
+                        }
                     }
                     const float sca = (float)(Tc >> lv.la) / (2.0f * a.S);
                     gu = fmaf(wa * gX, sca, gu);
@@ -355,20 +431,14 @@ __global__ __launch_bounds__(256, (bwd_waves<kVar>())) void k_raster_bwd(BwdArgs
                 float g_ux = 0.f, g_uy = 0.f, g_vx = 0.f, g_vy = 0.f, g_wx = 0.f, g_wy = 0.f;
                 float g_w0 = 0.f, g_px = 0.f, g_py = 0.f;
                 if (lv.blend) {
-                    float gX = 0.f, gY = 0.f;
-#pragma unroll
-                    for (int c = 0; c < 8; c++) {
-                        gX = fmaf(q[c], sbx[c], gX);
-                        gY = fmaf(q[c], sby[c], gY);
-                    }
+                    float gX, gY, qsb;
+                    level_dots<kFmt>(tr, level_offset(Tc, lv.lb), Tc >> lv.lb, kb, q, gX, gY, qsb);
                     const float scb = (float)(Tc >> lv.lb) / (2.0f * a.S);
                     gu = fmaf(lv.f * gX, scb, gu);
                     gv = fmaf(lv.f * gY, scb, gv);
                     // the blend fraction f = lambda - floor(lambda): dL/dlambda = q . (s_b - s_a),
                     // lambda = L_c + 0.5 log2 max(ax, ay) - log2(2S)
-                    float glam = 0.f;
-#pragma unroll
-                    for (int c = 0; c < 8; c++) glam = fmaf(q[c], sb[c] - sa[c], glam);
+                    const float glam = qsb - qsa;
                     const float m = fmaxf(fp.ax, fp.ay);
                     const float gm = glam * (0.5f * 1.44269504088896341f) / m;
                     float gdux = 0.f, gduy = 0.f, gdvx = 0.f, gdvy = 0.f;
@@ -659,6 +729,8 @@ __global__ __launch_bounds__(256, (bwd_waves<kVar>())) void k_raster_bwd(BwdArgs
             // group g sums entries g, g + 64/L, ... in order, then the groups are combined by
             // a fixed butterfly
             const int nbw = __builtin_popcountll(blm);
+            // the second level's weights are zero unless a lane of the wave blends two levels
+            const int nlev = (kVar == 2 && __ballot(lblend) != 0) ? 2 : 1;
             int L = 1;
             while (L < wt && L < kWave) L <<= 1;
             const int ngrp = kWave / L;
@@ -682,7 +754,7 @@ __global__ __launch_bounds__(256, (bwd_waves<kVar>())) void k_raster_bwd(BwdArgs
                         // level-0 texel (ti, tj) lies under level-l texel (ti >> l, tj >> l)
                         float wq = 0.f;
 #pragma unroll
-                        for (int b = 0; b < 2; b++) {
+                        for (int b = 0; b < nlev; b++) {
                             const float* pb = pe + 6 * b;
                             int l = __float_as_int(pe[14 + b]);
                             int si = ti >> l, sj = tj >> l;
