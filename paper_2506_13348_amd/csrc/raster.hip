@@ -66,8 +66,8 @@ static_assert(kBatch % kWave == 0, "the batch is walked in rows of 64");
 // path at 7 (72 VGPRs, 32 bytes of spills, a 22.5 KB record batch: seven workgroups per CU;
 // 18.30 ms against 18.63 at 6); the indirect term and the atlas variants stage more per record
 // (26 and 24 KB), which leaves room for six workgroups: 6 waves (the indirect term at 80 VGPRs,
-// 19.33 ms against 19.40 at 5); trilinear sampling (two texel levels in flight) 4 (5 was
-// slower).
+// 19.33 ms against 19.40 at 5; trilinear sampling at 80 VGPRs with a few spills, 23.9 ms per
+// step against 25.6 at 5 and 25.4 at 4 with 92 VGPRs).
 constexpr bool samp_variant(int kSamp) { return kSamp >= 2; }
 constexpr bool samp_tri(int kSamp) { return kSamp == 3 || kSamp == 5; }
 constexpr int samp_fmt(int kSamp) { return kSamp >= 4 ? 1 : 0; }
@@ -78,7 +78,7 @@ constexpr int kBatchWaves = 6;
 
 template <int kSamp, bool kInd>
 constexpr int raster_waves() {
-    return samp_tri(kSamp) ? 4 : (samp_variant(kSamp) || kInd) ? 6 : 7;
+    return (samp_variant(kSamp) || kInd) ? 6 : 7;
 }
 
 // A pixel's outputs: G-buffer channels, transmittance, counters and the fused shading.
