@@ -160,12 +160,13 @@ FWD_BWD_WORKLOADS = {
 }
 
 
-def bench_fwd_bwd(cfg, steps, warmup, sh_degree=None, mips=False):
+def bench_fwd_bwd(cfg, steps, warmup, sh_degree=None, mips=False, charts=False):
     """One training step: forward of the config's batch of views, L1 loss to a seeded target,
     hand-written backward to all splat parameters. With sh_degree, the indirect term is on
     (per-splat SH of that degree, mixed visibility) and the SH coefficients get gradients;
     with mips, the atlas holds each chart's mip chain and sampling is trilinear (gradients to
-    the level-0 texels and, through the level, to the geometry)."""
+    the level-0 texels and, through the level, to the geometry); with charts, each splat's
+    chart has its own side by primitive size (1..8, through a chart table)."""
     import numpy as np
     import torch
 
@@ -181,7 +182,12 @@ def bench_fwd_bwd(cfg, steps, warmup, sh_degree=None, mips=False):
         sc["sh"] = synth.indirect_sh(np.random.default_rng(11), len(sc["opac"]), sh_degree)
         sc["sh_degree"] = sh_degree
         vis = torch.as_tensor(synth.visibility(np.random.default_rng(12), V, H, W)).cuda()
-    ds = DeviceScene.from_dict(sc, device="cuda", mips=mips)
+    kw = dict(mips=mips)
+    if charts:
+        log2 = synth.texture_sides(sc["scales"], base_log2=3, max_log2=3)
+        sc["textures"] = synth.adaptive_textures(np.random.default_rng(3), log2)
+        kw["chart_log2"] = log2
+    ds = DeviceScene.from_dict(sc, device="cuda", **kw)
     del sc
     target = torch.as_tensor(synth.target_image(W, H, seed=1, n_views=V)).cuda()
     plan = RenderPlan(ds, cams, W, H, gbuf=True, aux=True, vis=vis)
@@ -261,7 +267,9 @@ def bench_fwd_bwd(cfg, steps, warmup, sh_degree=None, mips=False):
                "" if sh_degree is None else
                f"; indirect term: degree-{sh_degree} SH per splat, mixed visibility, gradients "
                "to the SH coefficients too") + (
-               "; trilinear sampling over each chart's box-filtered mip chain" if mips else ""),
+               "; trilinear sampling over each chart's box-filtered mip chain" if mips else "") + (
+               "; per-splat chart sides 1..8 by primitive size through a chart table"
+               if charts else ""),
            "env_tables_bwd_ms": round(env_ms, 3),
            # G-buffers, transmittance, dL/dC (and visibility) read once per pixel; the tables'
            # gradients are a few MB
@@ -864,6 +872,9 @@ def main():
         result["fwd_bwd_trilinear"] = bench_fwd_bwd("sq300k_train", max(3, K // 2), 1,
                                                     mips=True)
         log(f"fwd+bwd trilinear: {result['fwd_bwd_trilinear']}")
+        result["fwd_bwd_adaptive_sides"] = bench_fwd_bwd("sq300k_train", max(3, K // 2), 1,
+                                                         charts=True)
+        log(f"fwd+bwd adaptive sides: {result['fwd_bwd_adaptive_sides']}")
     result["small_frame"] = bench_small_frame()
     log(f"small frame: {result['small_frame']}")
     if not args.no_tab3:
