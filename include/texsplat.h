@@ -118,12 +118,13 @@ typedef struct ts_env {
 /* Workspace sizing (host only): the scratch bytes of one call, written to *bytes.
      TS_OP_BIN_SORT       ts_bin_sort          (n_views, n, width, height)
      TS_OP_RASTER_BWD     ts_raster_bwd        (n_views, n, pair_capacity)
-     TS_OP_ENV_BWD        ts_env_bwd           (n_views, width, height)
+     TS_OP_ENV_BWD        ts_env_bwd           (n = texels of the environment's tables:
+                                                6 irr_res^2 + 6 r_l^2 over the specular levels)
      TS_OP_LOCALITY_PERM  ts_locality_perm     (n)
      TS_OP_ATLAS_CHARTS   ts_atlas_pack_charts (n)
    Arguments an op does not use are ignored. The per-op functions below give the same sizes.
    Errors: TS_E_ARG (unknown op, null bytes, negative sizes, n_views < 1 or width/height < 1
-   where the op uses them). */
+   where the op uses them, n < 1 for TS_OP_ENV_BWD). */
 #define TS_OP_BIN_SORT 1
 #define TS_OP_RASTER_BWD 2
 #define TS_OP_ENV_BWD 3
@@ -432,29 +433,33 @@ int ts_raster_bwd_workspace(int32_t n_views, int32_t n, int64_t pair_capacity, s
  * reflected direction receive dL/dC * V (F0 A + B) weighted (1-f) and f between the levels
  * around R (L-1), each spread over 4 texels by the bilinear weights (V the pixel's
  * visibility: with the indirect term the specular radiance is V L_pref + (1 - V) L_ind).
- * Empty pixels (alpha = 0, background only) contribute nothing. Summed without
- * floating-point atomics (records sorted by texel, summed in pixel order): run-to-run
- * identical.
+ * Empty pixels (alpha = 0, background only) contribute nothing. Summed in 64-bit fixed
+ * point: each contribution x is rounded to a multiple of 2^(e+b-61), with M < 2^e the largest
+ * |x| of the call and 2^b above the number of contributions (12 per pixel), so that no sum
+ * leaves 2^61; the sums do not depend on the order of the additions (integer atomics), so
+ * the result is run-to-run identical, within M 2^(b-62) per contribution of the exact sum.
+ * A non-finite contribution makes every output texel NaN.
  *
  *   cams, env    as given to ts_raster_fwd / ts_raster_bwd
  *   gbuf, t_final  forward outputs of the same frame ([n_views][8][H][W], [n_views][H][W])
  *   d_rgba       [n_views][H][W][4] dL/d(rgb, alpha) (alpha does not reach the tables)
  *   vis          [n_views][H][W] the visibility the frame was shaded with, or NULL: V = 1
- *   ws, ws_bytes scratch, at least ts_env_bwd_workspace(n_views, width, height) bytes
- *                (about 56 bytes per pixel)
+ *   ws, ws_bytes scratch, at least ts_env_bwd_workspace(env) bytes (24 bytes per table
+ *                texel, plus 256)
  *   beta         0: overwrite the outputs; 1: add to them (any other value is TS_E_ARG)
  *   d_irr        [6][irr_res][irr_res][4] out, layout of env->irr (the 4th component is 0)
  *   d_spec       levels back to back as env->spec, [6][r_l][r_l][4] each, out
- * Errors: TS_E_ARG (null pointers, bad sizes, beta not 0 or 1, more than 2^31-1 records),
- * TS_E_WORKSPACE, TS_E_LAUNCH.
+ * Errors: TS_E_ARG (null pointers, bad sizes, beta not 0 or 1, more than 2^40
+ * contributions), TS_E_WORKSPACE, TS_E_LAUNCH.
  */
 int ts_env_bwd(int32_t n_views, int32_t width, int32_t height, const ts_camera* cams,
                const ts_env* env, const float* gbuf, const float* t_final, const float* d_rgba,
                const float* vis, void* ws, size_t ws_bytes, float beta, float* d_irr,
                float* d_spec, hipStream_t stream);
 
-/* Scratch bytes ts_env_bwd needs (host only). */
-int ts_env_bwd_workspace(int32_t n_views, int32_t width, int32_t height, size_t* bytes);
+/* Scratch bytes ts_env_bwd needs for the tables of env (host only; reads only the
+   resolutions and the level count). Errors: TS_E_ARG (null pointers, sizes < 1). */
+int ts_env_bwd_workspace(const ts_env* env, size_t* bytes);
 
 /*
  * ts_brdf_lut — the split-sum BRDF table (Sec. 3.5.4 precomputed 2D lookup; split sum of

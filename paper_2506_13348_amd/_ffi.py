@@ -72,7 +72,7 @@ _SIGS = {
     "ts_env_bwd": [c_int32, c_int32, c_int32, c_void_p, ctypes.POINTER(TsEnv), c_void_p, c_void_p,
                    c_void_p, c_void_p, c_void_p, c_size_t, ctypes.c_float, c_void_p, c_void_p,
                    c_void_p],
-    "ts_env_bwd_workspace": [c_int32, c_int32, c_int32, ctypes.POINTER(c_size_t)],
+    "ts_env_bwd_workspace": [ctypes.POINTER(TsEnv), ctypes.POINTER(c_size_t)],
     "ts_brdf_lut": [c_int32, c_int32, c_void_p, c_void_p],
     "ts_env_tables": [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p],
     "ts_atlas_pack": [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p],
@@ -265,11 +265,11 @@ def ts_indirect_eval(n_views, cams, n, means, quats, sh, sh_degree, lind, stream
            "ts_indirect_eval")
 
 
-def ts_env_bwd_workspace(n_views, width, height):
+def ts_env_bwd_workspace(env):
     out = c_size_t(0)
-    _check(lib().ts_env_bwd_workspace(n_views, width, height, ctypes.byref(out)),
+    _check(lib().ts_env_bwd_workspace(ctypes.byref(env), ctypes.byref(out)),
            "ts_env_bwd_workspace")
-    return int(out.value)
+    return out.value
 
 
 def ts_env_bwd(n_views, width, height, cams, env, gbuf, t_final, d_rgba, ws, beta, d_irr, d_spec,

@@ -94,7 +94,7 @@ class EnvBackward:
     def __init__(self, plan: RenderPlan):
         self.plan = plan
         dev = plan.scene.device
-        ws = F.ts_env_bwd_workspace(plan.V, plan.W, plan.H)
+        ws = F.ts_env_bwd_workspace(plan.scene.tables.struct)
         self.ws = torch.empty((ws + 7) // 8, device=dev, dtype=torch.int64)
         tabs = plan.scene.tables
         self.d_irr = torch.zeros_like(tabs.irr)

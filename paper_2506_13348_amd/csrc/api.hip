@@ -145,8 +145,7 @@ extern "C" const char* ts_last_error(void) { return g_err; }
 
 extern "C" int ts_raster_bwd_workspace(int32_t n_views, int32_t n, int64_t pair_capacity,
                                        size_t* bytes);
-extern "C" int ts_env_bwd_workspace(int32_t n_views, int32_t width, int32_t height,
-                                    size_t* bytes);
+namespace ts { size_t env_bwd_bytes(int64_t n_tex); }
 extern "C" int ts_atlas_charts_workspace(int32_t n, size_t* bytes);
 
 extern "C" int ts_workspace_size(int32_t op, int32_t n_views, int32_t n, int32_t width,
@@ -165,7 +164,13 @@ extern "C" int ts_workspace_size(int32_t op, int32_t n_views, int32_t n, int32_t
             return TS_OK;
         }
         case TS_OP_RASTER_BWD: return ts_raster_bwd_workspace(n_views, n, pair_capacity, bytes);
-        case TS_OP_ENV_BWD: return ts_env_bwd_workspace(n_views, width, height, bytes);
+        case TS_OP_ENV_BWD:
+            if (n < 1) {
+                set_error("ts_workspace_size: the environment's table texels n must be >= 1");
+                return TS_E_ARG;
+            }
+            *bytes = ts::env_bwd_bytes(n);
+            return TS_OK;
         case TS_OP_LOCALITY_PERM: return ts_locality_perm_workspace(n, bytes);
         case TS_OP_ATLAS_CHARTS: return ts_atlas_charts_workspace(n, bytes);
         default:

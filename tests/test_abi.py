@@ -44,8 +44,12 @@ def test_host_side_argument_errors():
     ref = ctypes.c_size_t(0)
     assert L.ts_workspace_size(2, 3, 500, 0, 0, 12345, ctypes.byref(out)) == 0
     assert L.ts_raster_bwd_workspace(3, 500, 12345, ctypes.byref(ref)) == 0 and ref.value == out.value
-    assert L.ts_workspace_size(3, 2, 0, 64, 48, 0, ctypes.byref(out)) == 0
-    assert L.ts_env_bwd_workspace(2, 64, 48, ctypes.byref(ref)) == 0 and ref.value == out.value
+    env = _ffi.TsEnv(None, 64, 5, None, 16, None, 32)
+    n_tex = 6 * 16 * 16 + sum(6 * max(64 >> l, 1) ** 2 for l in range(5))
+    assert L.ts_workspace_size(3, 2, n_tex, 64, 48, 0, ctypes.byref(out)) == 0
+    assert L.ts_env_bwd_workspace(ctypes.byref(env), ctypes.byref(ref)) == 0
+    assert ref.value == out.value and out.value >= 24 * n_tex
+    assert L.ts_workspace_size(3, 2, 0, 64, 48, 0, ctypes.byref(out)) == -1
     assert L.ts_workspace_size(4, 1, 777, 1, 1, 0, ctypes.byref(out)) == 0
     assert L.ts_locality_perm_workspace(777, ctypes.byref(ref)) == 0 and ref.value == out.value
     assert L.ts_workspace_size(5, 1, 777, 1, 1, 0, ctypes.byref(out)) == 0
@@ -129,8 +133,9 @@ def test_host_side_argument_errors():
                            None, None, None, None, None, None, None, None, None) == -1
     assert b"atlas_texels" in L.ts_last_error()
     assert L.ts_brdf_lut(0, 16, None, None) == -1
-    assert L.ts_env_bwd_workspace(0, 8, 8, ctypes.byref(out)) == -1
-    assert L.ts_env_bwd_workspace(2, 8, 8, ctypes.byref(out)) == 0 and out.value >= 2 * 64 * 12 * 36
+    assert L.ts_env_bwd_workspace(None, ctypes.byref(out)) == -1
+    bad = _ffi.TsEnv(None, 64, 0, None, 16, None, 32)
+    assert L.ts_env_bwd_workspace(ctypes.byref(bad), ctypes.byref(out)) == -1
     assert L.ts_env_bwd(1, 8, 8, None, None, None, None, None, None, None, 0,
                         ctypes.c_float(0.0), None, None, None) == -1
     # beta other than 0 or 1 is refused before anything else is looked at

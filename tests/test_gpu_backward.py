@@ -368,6 +368,44 @@ def test_env_grads_multi_view():
     _compare_env(g2, ref, spread, "env 2 views")
 
 
+def test_env_grads_fixed_point_scale_and_degenerate_upstream():
+    """The sums are taken in fixed point at a scale set by the largest contribution, so an
+    upstream scaled by a power of two scales every output texel by exactly that power; a zero
+    upstream gives exact zeros; a non-finite one makes every texel's rgb NaN. Dense upstream on the
+    8-view 800x800 batch: two calls are bit-identical."""
+    sc = synth.make_scene("sq300k_train", n=3000, env_res=16)
+    sc["env_levels"] = 3
+    cams = [synth.crop_camera(c, 330, 340, 45, 37) for c in synth.config_cameras("sq300k_train")[:2]]
+    rng = np.random.default_rng(18)
+    d = rng.normal(size=(2, 37, 45, 4))
+    g, _, eb = _gpu_env_grads(sc, cams, 45, 37, d)
+    base = [t.clone() for t in g]
+    assert any(float(t.abs().max()) > 0 for t in base)
+    dd = torch.as_tensor(d.astype(np.float32)).cuda()
+    for k in (-40, 17):
+        eb.run((dd * 2.0 ** k).contiguous())
+        torch.cuda.synchronize()
+        assert torch.equal(eb.d_irr, base[0].reshape(-1) * 2.0 ** k), k
+    eb.run(torch.zeros_like(dd))
+    torch.cuda.synchronize()
+    assert float(eb.d_irr.abs().max()) == 0.0 and float(eb.d_spec.abs().max()) == 0.0
+    bad = dd.clone()
+    ys, xs = np.nonzero(eb.plan.t_final.view(2, 37, 45)[0].cpu().numpy() < 1.0)
+    bad[0, ys[0], xs[0], 0] = float("nan")
+    eb.run(bad.contiguous())
+    torch.cuda.synchronize()
+    for t in (eb.d_irr, eb.d_spec):   # rgb of every texel; the fourth component stays 0
+        assert bool(torch.isnan(t.view(-1, 4)[:, :3]).all()) and float(t.view(-1, 4)[:, 3].abs().max()) == 0.0
+    # dense upstream over the training batch: run to run identical
+    sc = synth.make_scene("sq300k_train")
+    cams = synth.config_cameras("sq300k_train")
+    d = np.random.default_rng(19).normal(size=(len(cams), 800, 800, 4)) * 1e-6
+    g1, first, eb = _gpu_env_grads(sc, cams, 800, 800, d)
+    eb.run(torch.as_tensor(d.astype(np.float32)).cuda().contiguous())
+    torch.cuda.synchronize()
+    assert torch.equal(first[0], eb.d_irr) and torch.equal(first[1], eb.d_spec)
+
+
 def test_env_grads_sq300k_training_batch_sampled():
     """The 8-view 800x800 training batch with dL/dC at sampled pixels only."""
     from parity import sample_pixels
