@@ -16,9 +16,9 @@
 //     q = round(x 2^(61-b-e)), e = the exponent with M < 2^e and b = the bits of the record
 //     count, so that every partial sum stays below 2^61 in magnitude; the workgroup adds its q
 //     per texel in an LDS hash table (integer atomics; a texel that finds no slot within a few
-//     probes goes straight to the global table) and then adds the table into the global
-//     accumulators.
-//  3. k_env_finish: per texel, accumulator x 2^-(61-b-e) in double, rounded to float.
+//     probes goes straight to the global table) and then adds the table into one of 16 copies
+//     of the global accumulators.
+//  3. k_env_finish: per texel, the copies' sum x 2^-(61-b-e) in double, rounded to float.
 // A contribution is rounded by at most 2^(e+b-62), M 2^(b-61) relative to the largest one.
 #include "shade.h"
 #include "ts_internal.h"
@@ -30,6 +30,10 @@ constexpr int kEnvTile = 16;          // pixels a side of one k_env_accum workgr
 constexpr int kEnvSlots = 1024;       // LDS hash slots per workgroup
 constexpr int kEnvProbes = 8;         // slots tried before a texel goes to the global table
 constexpr uint32_t kNoKey = 0xFFFFFFFFu;
+// copies of the global accumulators, workgroup g adding into copy g % kEnvCopies: the integer
+// atomics on a texel that most workgroups reach (the irradiance cube's) are spread over 16
+// addresses instead of queueing on one
+constexpr int kEnvCopies = 16;
 
 struct EnvBwdArgs {
     int V, W, H, tiles_x, tiles_per_view;
@@ -41,7 +45,8 @@ struct EnvBwdArgs {
     const float* vis;        // [V][H][W] visibility or null (V = 1)
     uint32_t n_irr;          // texels of the irradiance cube (6 r^2)
     int bits;                // b: contributions of the call < 2^b
-    unsigned long long* acc; // [n_irr + n_spec][3] fixed-point sums
+    unsigned long long* acc; // [kEnvCopies][n_irr + n_spec][3] fixed-point sums
+    int64_t n_acc;           // (n_irr + n_spec) * 3: the stride between copies
     uint32_t* words;         // [0] bits of M, [1] non-finite contribution seen
 };
 
@@ -189,10 +194,22 @@ __global__ __launch_bounds__(256) void k_env_max(EnvBwdArgs a) {
         }
     }
     for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-    uint64_t anybad = __ballot(bad);
+    __shared__ float wm[4];
+    __shared__ int wb[4];
+    const int w = threadIdx.x >> 6;
+    const bool anybad = __ballot(bad) != 0;
     if ((threadIdx.x & 63) == 0) {
-        if (m > 0.f) atomicMax(&a.words[0], __float_as_uint(m));
-        if (anybad) atomicOr(&a.words[1], 1u);
+        wm[w] = m;
+        wb[w] = anybad ? 1 : 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float bm = fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]));
+        // one atomic per workgroup, and only while it can raise the maximum (a stale read
+        // costs an atomic, never a wrong result)
+        const uint32_t cur = *(volatile uint32_t*)&a.words[0];
+        if (bm > 0.f && __float_as_uint(bm) > cur) atomicMax(&a.words[0], __float_as_uint(bm));
+        if (wb[0] | wb[1] | wb[2] | wb[3]) atomicOr(&a.words[1], 1u);
     }
 }
 
@@ -207,6 +224,7 @@ __global__ __launch_bounds__(256) void k_env_accum(EnvBwdArgs a) {
         sacc[i][0] = 0ull; sacc[i][1] = 0ull; sacc[i][2] = 0ull;
     }
     __syncthreads();
+    unsigned long long* const gacc = a.acc + (int64_t)(blockIdx.x % kEnvCopies) * a.n_acc;
     int v, x, y;
     if (a.words[1] == 0u && env_pixel(a, blockIdx.x, tid, v, x, y)) {
         uint32_t ko[kEnvRec];
@@ -231,7 +249,7 @@ __global__ __launch_bounds__(256) void k_env_accum(EnvBwdArgs a) {
                     h = (h + 1) & (kEnvSlots - 1);
                 }
                 if (!placed) {
-                    unsigned long long* g = a.acc + (int64_t)key * 3;
+                    unsigned long long* g = gacc + (int64_t)key * 3;
                     for (int c = 0; c < 3; c++)
                         if (qi[c]) atomicAdd(g + c, (unsigned long long)qi[c]);
                 }
@@ -242,7 +260,7 @@ __global__ __launch_bounds__(256) void k_env_accum(EnvBwdArgs a) {
     for (int i = tid; i < kEnvSlots; i += 256) {
         const uint32_t key = skey[i];
         if (key == kNoKey) continue;
-        unsigned long long* g = a.acc + (int64_t)key * 3;
+        unsigned long long* g = gacc + (int64_t)key * 3;
         for (int c = 0; c < 3; c++)
             if (sacc[i][c]) atomicAdd(g + c, sacc[i][c]);
     }
@@ -260,7 +278,11 @@ __global__ __launch_bounds__(256) void k_env_finish(EnvBwdArgs a, int64_t n_tex,
         r[0] = r[1] = r[2] = __builtin_nanf("");
     } else {
         const double inv = 1.0 / env_scale(a);   // a power of two: exact
-        for (int c = 0; c < 3; c++) r[c] = (float)((double)(long long)a.acc[t * 3 + c] * inv);
+        for (int c = 0; c < 3; c++) {
+            unsigned long long sum = 0ull;
+            for (int k = 0; k < kEnvCopies; k++) sum += a.acc[(int64_t)k * a.n_acc + t * 3 + c];
+            r[c] = (float)((double)(long long)sum * inv);
+        }
     }
     float4* dst = t < (int64_t)a.n_irr ? d_irr + t : d_spec + (t - (int64_t)a.n_irr);
     if (beta != 0.f) {
@@ -281,9 +303,10 @@ inline int64_t env_texels(const ts_env& e, int64_t* n_irr_out) {
     return n_irr + n_spec;
 }
 
-// Accumulators (24 bytes per texel, rounded up to 256 bytes) then the two status words.
+// Accumulators (kEnvCopies x 24 bytes per texel, rounded up to 256 bytes) then the two status
+// words.
 inline size_t env_acc_bytes(int64_t n_tex) {
-    return ((size_t)n_tex * 3 * sizeof(unsigned long long) + 255) & ~(size_t)255;
+    return ((size_t)kEnvCopies * n_tex * 3 * sizeof(unsigned long long) + 255) & ~(size_t)255;
 }
 size_t env_bwd_bytes(int64_t n_tex) { return env_acc_bytes(n_tex) + 256; }
 
@@ -343,9 +366,10 @@ extern "C" int ts_env_bwd(int32_t n_views, int32_t width, int32_t height, const 
     while ((1LL << a.bits) <= m) a.bits++;
     a.acc = (unsigned long long*)ws;
     a.words = (uint32_t*)((char*)ws + env_acc_bytes(n_tex));
-    const int64_t n_acc = n_tex * 3;
-    hipLaunchKernelGGL(k_env_clear_acc, dim3((unsigned)((n_acc + 255) / 256)), dim3(256), 0,
-                       stream, a.acc, n_acc, a.words);
+    a.n_acc = n_tex * 3;
+    const int64_t n_all = a.n_acc * kEnvCopies;
+    hipLaunchKernelGGL(k_env_clear_acc, dim3((unsigned)((n_all + 255) / 256)), dim3(256), 0,
+                       stream, a.acc, n_all, a.words);
     const unsigned blocks = (unsigned)((int64_t)a.tiles_per_view * n_views);
     hipLaunchKernelGGL(k_env_max, dim3(blocks), dim3(256), 0, stream, a);
     hipLaunchKernelGGL(k_env_accum, dim3(blocks), dim3(256), 0, stream, a);
