@@ -48,7 +48,8 @@ def test_host_side_argument_errors():
     n_tex = 6 * 16 * 16 + sum(6 * max(64 >> l, 1) ** 2 for l in range(5))
     assert L.ts_workspace_size(3, 2, n_tex, 64, 48, 0, ctypes.byref(out)) == 0
     assert L.ts_env_bwd_workspace(ctypes.byref(env), ctypes.byref(ref)) == 0
-    assert ref.value == out.value and out.value >= 24 * n_tex
+    # 16 copies of three 64-bit accumulators per texel (rounded up to 256 bytes) + 256
+    assert ref.value == out.value == ((16 * 24 * n_tex + 255) & ~255) + 256
     assert L.ts_workspace_size(3, 2, 0, 64, 48, 0, ctypes.byref(out)) == -1
     assert L.ts_workspace_size(4, 1, 777, 1, 1, 0, ctypes.byref(out)) == 0
     assert L.ts_locality_perm_workspace(777, ctypes.byref(ref)) == 0 and ref.value == out.value
