@@ -406,6 +406,37 @@ def test_env_grads_fixed_point_scale_and_degenerate_upstream():
     assert torch.equal(first[0], eb.d_irr) and torch.equal(first[1], eb.d_spec)
 
 
+def test_env_grads_many_texels_per_workgroup():
+    """Random tangent normals per texel and roughness near 0 on a 64-texel environment: the
+    reflected lookups of one 16x16 pixel block reach more distinct table texels than the
+    accumulation's LDS table has slots (1024), so part of every block's contributions goes to
+    the global accumulators directly; the sums still match the float64 reference."""
+    sc = synth.make_scene("sq300k_train", n=3000, env_res=64)
+    sc["env_levels"] = 5
+    tex = np.array(sc["textures"], np.float64)
+    rng = np.random.default_rng(5)
+    nrm = rng.normal(size=tex.shape[:-1] + (3,))
+    nrm[..., 2] = np.abs(nrm[..., 2]) + 0.05
+    tex[..., 4:7] = nrm / np.linalg.norm(nrm, axis=-1, keepdims=True)
+    tex[..., 3] = 0.02
+    sc["textures"] = tex.astype(np.float32)
+    cam = synth.crop_camera(synth.config_cameras("sq300k_train")[0], 330, 340, 45, 37)
+    tabs = oracle.tables(sc["env"], sc["env_levels"])
+    pix = oracle.all_pixels(45, 37)
+    # the first 16x16 block alone reaches more texels than a workgroup's table holds
+    block = (pix[:, 0] < 16) & (pix[:, 1] < 16)
+    d0 = np.where(block[:, None], rng.normal(size=(len(pix), 4)), 0.0)
+    r0 = og.grads(sc, cam, pix, d0, tabs, env=True)
+    reached = int((np.abs(r0["irr"]).sum(-1) > 0).sum()) + sum(
+        int((np.abs(t).sum(-1) > 0).sum()) for t in r0["spec"])
+    assert reached > 1024, reached
+    ref_f = oracle.render(sc, cam, pixels=pix, tabs=tabs)
+    d, d4 = _upstream(rng, ref_f, (1, 37, 45, 4))
+    ref, spread = _env_ref(sc, [cam], [pix], [d], tabs)
+    g, _, _ = _gpu_env_grads(sc, [cam], 45, 37, d4)
+    _compare_env(g, ref, spread, "env many texels")
+
+
 def test_env_grads_sq300k_training_batch_sampled():
     """The 8-view 800x800 training batch with dL/dC at sampled pixels only."""
     from parity import sample_pixels
