@@ -437,7 +437,7 @@ int ts_raster_bwd_workspace(int32_t n_views, int32_t n, int64_t pair_capacity, s
  * point: each contribution x is rounded to a multiple of 2^(e+b-61), with M < 2^e the largest
  * |x| of the call and 2^b above the number of contributions (12 per pixel), so that no sum
  * leaves 2^61; the sums do not depend on the order of the additions (integer atomics), so
- * the result is run-to-run identical, within M 2^(b-62) per contribution of the exact sum.
+ * the result is run-to-run identical, within M 2^(b-61) per contribution of the exact sum.
  * A non-finite contribution makes every output texel NaN.
  *
  *   cams, env    as given to ts_raster_fwd / ts_raster_bwd
