@@ -444,8 +444,9 @@ int ts_raster_bwd_workspace(int32_t n_views, int32_t n, int64_t pair_capacity, s
  *   gbuf, t_final  forward outputs of the same frame ([n_views][8][H][W], [n_views][H][W])
  *   d_rgba       [n_views][H][W][4] dL/d(rgb, alpha) (alpha does not reach the tables)
  *   vis          [n_views][H][W] the visibility the frame was shaded with, or NULL: V = 1
- *   ws, ws_bytes scratch, at least ts_env_bwd_workspace(env) bytes (16 copies of 24 bytes
- *                per table texel, plus 256)
+ *   ws, ws_bytes scratch, at least ts_env_bwd_workspace(env) bytes (c copies of 24 bytes
+ *                per table texel, c = 16 or fewer so that they fit 64 MB but at least 1,
+ *                rounded up to 256 bytes, plus 256)
  *   beta         0: overwrite the outputs; 1: add to them (any other value is TS_E_ARG)
  *   d_irr        [6][irr_res][irr_res][4] out, layout of env->irr (the 4th component is 0)
  *   d_spec       levels back to back as env->spec, [6][r_l][r_l][4] each, out

@@ -16,8 +16,8 @@
 //     q = round(x 2^(61-b-e)), e = the exponent with M < 2^e and b = the bits of the record
 //     count, so that every partial sum stays below 2^61 in magnitude; the workgroup adds its q
 //     per texel in an LDS hash table (integer atomics; a texel that finds no slot within a few
-//     probes goes straight to the global table) and then adds the table into one of 16 copies
-//     of the global accumulators.
+//     probes goes straight to the global table) and then adds the table into one of up to 16
+//     copies of the global accumulators.
 //  3. k_env_finish: per texel, the copies' sum x 2^-(61-b-e) in double, rounded to float.
 // A contribution is rounded by at most 2^(e+b-62), M 2^(b-61) relative to the largest one.
 #include "shade.h"
@@ -30,10 +30,16 @@ constexpr int kEnvTile = 16;          // pixels a side of one k_env_accum workgr
 constexpr int kEnvSlots = 1024;       // LDS hash slots per workgroup
 constexpr int kEnvProbes = 8;         // slots tried before a texel goes to the global table
 constexpr uint32_t kNoKey = 0xFFFFFFFFu;
-// copies of the global accumulators, workgroup g adding into copy g % kEnvCopies: the integer
-// atomics on a texel that most workgroups reach (the irradiance cube's) are spread over 16
-// addresses instead of queueing on one
+// copies of the global accumulators, workgroup g adding into copy g % copies: the integer
+// atomics on a texel that most workgroups reach (the irradiance cube's) are spread over up to
+// 16 addresses instead of queueing on one; as many copies as fit 64 MB (at least one), so
+// large tables do not pay for clearing and reading back copies they hardly need
 constexpr int kEnvCopies = 16;
+constexpr int64_t kEnvCopyBudget = 64ll << 20;
+inline int env_copies(int64_t n_tex) {
+    const int64_t per = n_tex * 3 * (int64_t)sizeof(unsigned long long);
+    return (int)max((int64_t)1, min((int64_t)kEnvCopies, kEnvCopyBudget / max(per, (int64_t)1)));
+}
 
 struct EnvBwdArgs {
     int V, W, H, tiles_x, tiles_per_view;
@@ -45,8 +51,9 @@ struct EnvBwdArgs {
     const float* vis;        // [V][H][W] visibility or null (V = 1)
     uint32_t n_irr;          // texels of the irradiance cube (6 r^2)
     int bits;                // b: contributions of the call < 2^b
-    unsigned long long* acc; // [kEnvCopies][n_irr + n_spec][3] fixed-point sums
+    unsigned long long* acc; // [copies][n_irr + n_spec][3] fixed-point sums
     int64_t n_acc;           // (n_irr + n_spec) * 3: the stride between copies
+    int copies;              // env_copies(n_irr + n_spec)
     uint32_t* words;         // [0] bits of M, [1] non-finite contribution seen
 };
 
@@ -224,7 +231,7 @@ __global__ __launch_bounds__(256) void k_env_accum(EnvBwdArgs a) {
         sacc[i][0] = 0ull; sacc[i][1] = 0ull; sacc[i][2] = 0ull;
     }
     __syncthreads();
-    unsigned long long* const gacc = a.acc + (int64_t)(blockIdx.x % kEnvCopies) * a.n_acc;
+    unsigned long long* const gacc = a.acc + (int64_t)(blockIdx.x % a.copies) * a.n_acc;
     int v, x, y;
     if (a.words[1] == 0u && env_pixel(a, blockIdx.x, tid, v, x, y)) {
         uint32_t ko[kEnvRec];
@@ -280,7 +287,7 @@ __global__ __launch_bounds__(256) void k_env_finish(EnvBwdArgs a, int64_t n_tex,
         const double inv = 1.0 / env_scale(a);   // a power of two: exact
         for (int c = 0; c < 3; c++) {
             unsigned long long sum = 0ull;
-            for (int k = 0; k < kEnvCopies; k++) sum += a.acc[(int64_t)k * a.n_acc + t * 3 + c];
+            for (int k = 0; k < a.copies; k++) sum += a.acc[(int64_t)k * a.n_acc + t * 3 + c];
             r[c] = (float)((double)(long long)sum * inv);
         }
     }
@@ -303,10 +310,11 @@ inline int64_t env_texels(const ts_env& e, int64_t* n_irr_out) {
     return n_irr + n_spec;
 }
 
-// Accumulators (kEnvCopies x 24 bytes per texel, rounded up to 256 bytes) then the two status
+// Accumulators (env_copies x 24 bytes per texel, rounded up to 256 bytes) then the two status
 // words.
 inline size_t env_acc_bytes(int64_t n_tex) {
-    return ((size_t)kEnvCopies * n_tex * 3 * sizeof(unsigned long long) + 255) & ~(size_t)255;
+    return ((size_t)env_copies(n_tex) * n_tex * 3 * sizeof(unsigned long long) + 255) &
+           ~(size_t)255;
 }
 size_t env_bwd_bytes(int64_t n_tex) { return env_acc_bytes(n_tex) + 256; }
 
@@ -367,7 +375,8 @@ extern "C" int ts_env_bwd(int32_t n_views, int32_t width, int32_t height, const 
     a.acc = (unsigned long long*)ws;
     a.words = (uint32_t*)((char*)ws + env_acc_bytes(n_tex));
     a.n_acc = n_tex * 3;
-    const int64_t n_all = a.n_acc * kEnvCopies;
+    a.copies = env_copies(n_tex);
+    const int64_t n_all = a.n_acc * a.copies;
     hipLaunchKernelGGL(k_env_clear_acc, dim3((unsigned)((n_all + 255) / 256)), dim3(256), 0,
                        stream, a.acc, n_all, a.words);
     const unsigned blocks = (unsigned)((int64_t)a.tiles_per_view * n_views);

@@ -48,8 +48,13 @@ def test_host_side_argument_errors():
     n_tex = 6 * 16 * 16 + sum(6 * max(64 >> l, 1) ** 2 for l in range(5))
     assert L.ts_workspace_size(3, 2, n_tex, 64, 48, 0, ctypes.byref(out)) == 0
     assert L.ts_env_bwd_workspace(ctypes.byref(env), ctypes.byref(ref)) == 0
-    # 16 copies of three 64-bit accumulators per texel (rounded up to 256 bytes) + 256
+    # copies of three 64-bit accumulators per texel (16 or as many as fit 64 MB, at least 1),
+    # rounded up to 256 bytes, + 256
     assert ref.value == out.value == ((16 * 24 * n_tex + 255) & ~255) + 256
+    for big in (524_288 + 6 * 32 * 32, 8_388_608):
+        c = max(1, min(16, (64 << 20) // (24 * big)))
+        assert L.ts_workspace_size(3, 1, big, 1, 1, 0, ctypes.byref(out)) == 0
+        assert out.value == ((c * 24 * big + 255) & ~255) + 256, (big, c)
     assert L.ts_workspace_size(3, 2, 0, 64, 48, 0, ctypes.byref(out)) == -1
     assert L.ts_workspace_size(4, 1, 777, 1, 1, 0, ctypes.byref(out)) == 0
     assert L.ts_locality_perm_workspace(777, ctypes.byref(ref)) == 0 and ref.value == out.value
